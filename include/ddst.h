@@ -1,0 +1,226 @@
+/*
+ * ddst.h -- C-ABI of the MI355X solution-transfer domain-decomposition library.
+ *
+ * The library implements the data-parallel hot path of the overlapping
+ * solution-transfer DD method (Dirckx, Yesypenko, Martinsson, arXiv 2510.25991)
+ * for the finite-difference model problem of Section 2.1:
+ *
+ *     -div(kappa grad u) + b . grad u + c u = f   in the unit square / cube,
+ *                                        u = g   on its boundary,
+ *
+ * discretised on n interior nodes per axis (h = 1/(n+1)) with the 5-point /
+ * 7-point stencil.  The coefficient kappa is cellwise ((n+1)^dim cells); the
+ * coefficient of a grid edge is the mean of the 2^(dim-1) cells sharing it;
+ * convection uses centred differences.  The domain is cut along x into
+ * n_slabs equispaced slabs of m = (n+1)/n_slabs cells; the N_ds = n_slabs-1
+ * interfaces Gamma_j sit on node planes x-index j*m and carry M = n^(dim-1)
+ * nodes each (Section 2, equispaced slabs).
+ *
+ * Layouts (all arrays are caller-owned DEVICE memory unless stated):
+ *   interior nodal arrays: n^dim float64, C order, x slowest (node (i,j[,k])
+ *       with 1-based indices sits at ((i-1)*n + (j-1))[*n + (k-1)]);
+ *   kappa: (n+1)^dim float64 cells, C order (cell c spans nodes c..c+1);
+ *   g: (n+2)^dim float64 node box, C order; only boundary entries are read;
+ *   interface vectors: N_ds*M float64, interface-major (Gamma_1 first).
+ *
+ * Every call is ordered on the given HIP stream.  Calls whose return status
+ * depends on device results (pivot breakdown, ranks, convergence) synchronise
+ * the stream before returning.  No C++ exception crosses this boundary.
+ *
+ * Status codes: 0 success; DDST_ENOTCONV (+1) means outputs were written but
+ * the requested tolerance was not met; negative values are errors, and after
+ * an error the text of ddst_last_error() (thread-local) says what failed.
+ */
+#ifndef DDST_H
+#define DDST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DDST_OK = 0,
+  DDST_ENOTCONV = 1,     /* outputs written, tolerance not reached            */
+  DDST_EINVAL = -1,      /* bad shape, divisibility, NaN or kappa <= 0, NULL  */
+  DDST_ENOMEM = -2,      /* device allocation failed                          */
+  DDST_EHIP = -3,        /* a HIP runtime call failed                         */
+  DDST_EBREAKDOWN = -4,  /* non-finite or non-positive pivot in a local solve */
+  DDST_ERANK = -5,       /* HODLR rank cap exceeded                           */
+  DDST_ESTATE = -6       /* operation not available in this operator state    */
+};
+
+/* Arithmetic of the local eliminations, transfer blocks and factors. */
+enum { DDST_FP64 = 0, DDST_FP32 = 1 };
+/* Cluster tree for hierarchical compression. */
+enum { DDST_TREE_BINARY = 0, DDST_TREE_QUAD = 1 };
+/* Storage type of the compressed low-rank factors. */
+enum { DDST_FACTOR_BF16 = 0, DDST_FACTOR_FP32 = 1, DDST_FACTOR_FP64 = 2 };
+/* Which representation ddst_apply uses. */
+enum { DDST_APPLY_DENSE = 0, DDST_APPLY_HODLR = 1 };
+
+typedef struct ddst_op ddst_op_t; /* opaque, library-owned */
+
+/* The PDE operator (eq. basic of the paper, FD form of Section 2.1). */
+typedef struct {
+  int32_t dim;          /* 2 or 3                                              */
+  int32_t n;            /* interior nodes per axis, >= 3                       */
+  int32_t n_slabs;      /* >= 2, (n+1) % n_slabs == 0, m = (n+1)/n_slabs >= 2  */
+  const double *kappa;  /* device, (n+1)^dim cells, > 0; NULL means kappa = 1  */
+  double bvec[3];       /* constant convection velocity (unused entries 0)     */
+  const double *c;      /* device, n^dim nodal zeroth-order term; NULL means 0 */
+} ddst_problem_t;
+
+typedef struct {
+  int32_t precision;        /* DDST_FP64 (plain path) or DDST_FP32 (mixed path) */
+  int32_t keep_factors;     /* 1: keep the per-slab elimination factors for the
+                               solve (required by ddst_solve); 0: drop them     */
+  int32_t transpose;        /* 0: operator A; 1: build for A^T (convection
+                               reversed), used by the adjoint                  */
+  int32_t reserved;
+} ddst_build_opts_t;
+
+typedef struct {
+  int32_t tree;             /* DDST_TREE_BINARY (dim 2) or DDST_TREE_QUAD (dim 3) */
+  int32_t leaf;             /* maximum leaf cluster size, e.g. 128             */
+  int32_t oversample;       /* p, extra Gaussian samples beyond the rank, e.g. 10 */
+  int32_t max_rank;         /* rank cap per admissible block (<= 256)          */
+  int32_t factor_dtype;     /* DDST_FACTOR_BF16 / FP32 / FP64                  */
+  int32_t reserved;
+  double tol;               /* keep sigma_i > tol * ||S_{j,j'}||_2             */
+  uint64_t seed;            /* Gaussian test matrices                          */
+} ddst_compress_opts_t;
+
+typedef struct {
+  double tol;               /* target relative error of the refined solution   */
+  double inner_tol;         /* relative residual of the interface GMRES        */
+  int32_t max_iter;         /* GMRES iteration cap (unrestarted; <= 1000)      */
+  int32_t max_outer;        /* FP64 refinement passes (>= 1)                   */
+  int32_t use_hodlr;        /* 1: apply S through the compressed form          */
+  int32_t reserved;
+} ddst_solve_opts_t;
+
+typedef struct {
+  int32_t outer_iters;      /* refinement passes taken                         */
+  int32_t gmres_iters;      /* GMRES iterations summed over passes             */
+  int32_t last_gmres_iters; /* GMRES iterations of the last pass               */
+  int32_t converged;        /* 1 if the stopping rule was met                  */
+  double gmres_relres;      /* last GMRES relative residual estimate           */
+  double residual_rel;      /* ||f - A u||_2 / ||f - A 0||_2, FP64 stencil     */
+  double correction_rel;    /* ||last correction|| / ||u||                     */
+  double t_build_ms, t_compress_ms, t_solve_ms, t_adjoint_ms; /* phase times   */
+  double bytes_factors, bytes_transfer, bytes_hodlr;          /* storage       */
+  int32_t max_rank, min_rank;                                  /* HODLR ranks   */
+} ddst_stats_t;
+
+/*
+ * ddst_build_transfer -- form every dense solution-transfer block
+ *   S_{j,j'} = -R_{C_j} A_j(I_j,I_j)^{-1} A_j(I_j,J_{j,j'})   (eq. defS)
+ * of every double slab Psi_j (Section 2.5, local and global assembly), by
+ * batched block-tridiagonal elimination across the thin x direction of all
+ * slabs at once, plus the inverse of each interface Schur block
+ * T_jj (Section 2.1, eq. efewin) and, if keep_factors, the per-plane inverse
+ * Schur complements of a left-to-right sweep of every single slab.
+ * prob: host struct; its device arrays are read during the call only.
+ * opts: host struct or NULL (defaults: FP32, keep_factors=1, transpose=0).
+ * out: receives the new operator, or NULL on error.
+ * Errors: EINVAL (shape/divisibility, kappa <= 0 or non-finite, c non-finite),
+ *         ENOMEM, EHIP, EBREAKDOWN (a local elimination met a non-positive or
+ *         non-finite pivot: the local problem is degenerate, cf. the remark on
+ *         degenerate local problems in Section 2.2).
+ */
+int ddst_build_transfer(const ddst_problem_t *prob, const ddst_build_opts_t *opts,
+                        hipStream_t stream, ddst_op_t **out);
+
+/*
+ * ddst_compress -- compress every transfer block as a weak-admissibility
+ * hierarchical matrix (Section 2.4; HODLR form): on a cluster tree shared by
+ * source and target interface, every interaction between distinct children
+ * of a tree node is a low-rank block U V^T obtained from a randomized range
+ * finder with Gaussian probes (Algorithm 1, sampling step), a Householder QR
+ * and a small SVD, truncated at sigma_i > tol * ||S_{j,j'}||_2; leaves stay
+ * dense.  The dense blocks are kept (ddst_apply can use either form).
+ * Errors: EINVAL, ENOMEM, EHIP, ERANK (a block needs more than max_rank).
+ */
+int ddst_compress(ddst_op_t *op, const ddst_compress_opts_t *opts, hipStream_t stream);
+
+/*
+ * ddst_solve -- solve the FD problem through the equilibrium system
+ *   u_j - S_{j,j-1} u_{j-1} - S_{j,j+1} u_{j+1} = hhat_j   (eq. modelS)
+ * by unrestarted GMRES (Section 5), with FP64 iterative refinement on the FP64
+ * stencil residual: each pass forms r = f - A u, computes the equivalent loads
+ * of r (eq. equilib1) with the stored slab factors, solves the interface
+ * system, recovers the volume correction slab by slab and adds it in FP64.
+ * f: device n^dim (NULL means 0); g: device (n+2)^dim node box (NULL means 0).
+ * u_gamma: device N_ds*M output (interface traces), may be NULL.
+ * u_vol: device n^dim output (full solution), may be NULL.
+ * stats: host, may be NULL.
+ * Stops when the predicted relative error (correction size times the
+ * observed contraction) is <= tol, or after max_outer passes.
+ * Errors: EINVAL, ESTATE (factors dropped), ENOMEM, EHIP; ENOTCONV (+1) if
+ * GMRES hit max_iter or the stopping rule was not met.
+ */
+int ddst_solve(const ddst_op_t *op, const double *f, const double *g,
+               const ddst_solve_opts_t *opts, double *u_gamma, double *u_vol,
+               ddst_stats_t *stats, hipStream_t stream);
+
+/*
+ * ddst_adjoint -- gradient of a loss L(u) with respect to the cellwise
+ * coefficient kappa, for the solution u of ddst_solve with the same g.
+ * Solves A^T lambda = gbar through the transposed Schur structure of the
+ * slab decomposition: transposed single-slab solves, the transposed
+ * equilibrium system S^T (GMRES; (S^T)_{j,j'} = S_{j',j}^T) and the transposed
+ * interface blocks, with FP64 refinement on the A^T stencil residual.  The
+ * slab factors are recomputed (not read from the operator) when the operator
+ * holds none.  Then
+ *   dL/dkappa_c = -1/(2^(dim-1) h^2) sum_{edges (p,q) of cell c}
+ *                  (lambda_p - lambda_q)(u_p - u_q),
+ * with lambda = 0 and u = g on the boundary.
+ * u_vol: device n^dim; gbar: device n^dim (dL/du); g: as in ddst_solve;
+ * dkappa: device (n+1)^dim output (overwritten); lambda: device n^dim output
+ * or NULL.  Errors: as ddst_solve.
+ */
+int ddst_adjoint(const ddst_op_t *op, const double *u_vol, const double *g,
+                 const double *gbar, const ddst_solve_opts_t *opts, double *dkappa,
+                 double *lambda, ddst_stats_t *stats, hipStream_t stream);
+
+/* Drop the per-slab factors (frees device memory); the adjoint recomputes. */
+int ddst_release_factors(ddst_op_t *op);
+
+/* Destroy an operator; NULL is a no-op.  Synchronises the device. */
+void ddst_destroy(ddst_op_t *op);
+
+/* Text of the last error on this thread ("" if none). */
+const char *ddst_last_error(void);
+
+/* Geometry of an operator: M, N_ds, padded leading dimension, precision. */
+int ddst_op_info(const ddst_op_t *op, int32_t *M, int32_t *n_ds, int32_t *ld,
+                 int32_t *precision);
+
+/*
+ * Test hooks.
+ * ddst_get_transfer: copy S_{j,j-1} and S_{j,j+1} (1-based j) into M x M
+ *   row-major float64 device buffers (a block that does not exist -- next to
+ *   the physical boundary -- is written as zeros); either pointer may be NULL.
+ * ddst_apply: y = S x (transpose 0) or S^T x (transpose 1) for the equilibrium
+ *   matrix S = I - K, x and y device N_ds*M float64, through the dense blocks
+ *   (which = DDST_APPLY_DENSE) or the compressed form (DDST_APPLY_HODLR).
+ * ddst_loads: equivalent loads hhat (eq. equilib1) of the load f and boundary
+ *   data g, device N_ds*M output.
+ */
+int ddst_get_transfer(const ddst_op_t *op, int32_t j, double *S_left, double *S_right,
+                      hipStream_t stream);
+int ddst_apply(const ddst_op_t *op, int32_t transpose, int32_t which, const double *x,
+               double *y, hipStream_t stream);
+int ddst_loads(const ddst_op_t *op, const double *f, const double *g, double *hhat,
+               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDST_H */

@@ -1,0 +1,1055 @@
+// Host side of libddst: the C-ABI entry points of include/ddst.h.
+//
+// Build (eq. defS, Algorithms 1-2 of the paper, dense form): every single
+// slab is swept across its thin x direction by block-tridiagonal elimination,
+// all sweeps of all slabs batched into each launch.  Sweep of slab s towards
+// an interface, local planes k = 1..m-1 (plane P(k)):
+//     D_1 = A_P(1),  G_k = D_k^{-1},
+//     D_k = A_P(k) - diag(Eb(P(k))) G_{k-1} diag(Ef(P(k-1))),
+//     Y_1 = -G_1 diag(Eb(P(1))),  Y_k = -G_k diag(Eb(P(k))) Y_{k-1},
+// with Eb / Ef the couplings towards / away from the sweep's start plane.
+// At interface j (plane c = j m) the two sweeps that end there give
+//     Sigma_j = A_c - Em(c) G^L Ep(c-1) - Ep(c) G^R Em(c+1)   (= T_jj),
+//     S_{j,j-1} = Sigma_j^{-1} (-diag(Em(c)) Y^L),
+//     S_{j,j+1} = Sigma_j^{-1} (-diag(Ep(c)) Y^R).
+// The left-to-right G_k of every slab are kept for the solve.
+//
+// Solve (eq. modelS, Section 5): FP64 refinement around the DD solve
+//     r = f - A u;   z = A_II^{-1} r_I (slab sweeps);
+//     hhat = Sigma^{-1} (r_J - A_JI z);   S delta_J = hhat (GMRES, CGS2, FP64);
+//     delta_I = A_II^{-1}(r_I - A_IJ delta_J);   u += delta.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ddst;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+struct DeviceMem {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DeviceMem() = default;
+  explicit DeviceMem(size_t b) { alloc(b); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DeviceMem() { release(); }
+  DeviceMem(const DeviceMem &) = delete;
+  DeviceMem &operator=(const DeviceMem &) = delete;
+};
+
+// Bump allocator over one device allocation (256-byte aligned slices).
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t b) {
+    const size_t o = off;
+    off += (b + 255) & ~size_t(255);
+    return o;
+  }
+};
+
+// A table of plain structs staged to the device in one copy.
+struct JobTable {
+  std::vector<unsigned char> host;
+  DeviceMem dev;
+  template <typename J>
+  size_t add(const std::vector<J> &v) {
+    const size_t o = (host.size() + 63) & ~size_t(63);
+    host.resize(o + v.size() * sizeof(J));
+    if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(J));
+    return o;
+  }
+  void upload(hipStream_t s) {
+    if (host.empty()) return;
+    dev.alloc(host.size());
+    HIPCHK(hipMemcpyAsync(dev.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  }
+  template <typename J>
+  const J *at(size_t o) const {
+    return reinterpret_cast<const J *>(static_cast<unsigned char *>(dev.p) + o);
+  }
+};
+
+inline size_t esize(int prec) { return prec == DDST_FP32 ? sizeof(float) : sizeof(double); }
+
+inline void *mat(void *base, size_t idx, size_t bytes) {
+  return static_cast<unsigned char *>(base) + idx * bytes;
+}
+
+// ---- sweeps ----------------------------------------------------------------
+struct Sweep {
+  int slab;
+  int dir;      // +1 left-to-right (towards plane (s+1)m), -1 right-to-left
+  int y_index;  // index into the transfer-chain buffers, -1 if no chain
+  int work;     // index into ping-pong work buffers, -1 if stored in the factor store
+};
+
+struct SweepPlan {
+  std::vector<Sweep> sw;
+  int n_y = 0, n_work = 0;
+};
+
+// Plane (1-based) of local step k of a sweep.
+inline int sweep_plane(const ddst_op *op, const Sweep &w, int k) {
+  return w.dir > 0 ? w.slab * op->m + k : (w.slab + 1) * op->m - k;
+}
+
+struct SweepBuffers {
+  void *store = nullptr;  // factor store (n_slabs*(m-1) matrices) or null
+  void *work = nullptr;   // 2 * n_work matrices
+  void *ybuf = nullptr;   // 2 * n_y matrices
+};
+
+inline void *sweep_G(const ddst_op *op, const Sweep &w, int k, const SweepBuffers &b) {
+  if (w.work < 0) return mat(b.store, (size_t)w.slab * (op->m - 1) + (k - 1), op->mat_bytes);
+  return mat(b.work, (size_t)w.work * 2 + (k & 1), op->mat_bytes);
+}
+inline void *sweep_Y(const ddst_op *op, const Sweep &w, int k, const SweepBuffers &b) {
+  return mat(b.ybuf, (size_t)w.y_index * 2 + (k & 1), op->mat_bytes);
+}
+inline const double *Ebwd(const ddst_op *op, const Sweep &w, int plane) {
+  return (w.dir > 0 ? op->Em : op->Ep) + (size_t)plane * op->ld;
+}
+inline const double *Efwd(const ddst_op *op, const Sweep &w, int plane) {
+  return (w.dir > 0 ? op->Ep : op->Em) + (size_t)plane * op->ld;
+}
+
+// Run all sweeps of a plan, batched per local step.  Returns nothing; the
+// breakdown flag on the device records pivot failures.
+template <typename T>
+void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hipStream_t s) {
+  const int m = op->m, ld = op->ld;
+  const int nsw = (int)plan.sw.size();
+  JobTable tab;
+  std::vector<size_t> off_asm(m), off_mats(m), off_y(m);
+  std::vector<int> ny_at(m, 0);
+  for (int k = 1; k <= m - 1; ++k) {
+    std::vector<AsmJob> aj;
+    std::vector<void *> mats;
+    std::vector<GemmJob> yj;
+    for (const Sweep &w : plan.sw) {
+      const int P = sweep_plane(op, w, k);
+      AsmJob a{};
+      a.D = sweep_G(op, w, k, buf);
+      a.plane = P;
+      if (k > 1) {
+        a.G1 = sweep_G(op, w, k - 1, buf);
+        a.r1 = Ebwd(op, w, P);
+        a.c1 = Efwd(op, w, sweep_plane(op, w, k - 1));
+      }
+      aj.push_back(a);
+      mats.push_back(a.D);
+      if (w.y_index >= 0) {
+        GemmJob g{};
+        g.A = a.D;
+        g.B = (k > 1) ? sweep_Y(op, w, k - 1, buf) : nullptr;
+        g.C = sweep_Y(op, w, k, buf);
+        g.bscale = Ebwd(op, w, P);
+        yj.push_back(g);
+      }
+    }
+    off_asm[k - 1] = tab.add(aj);
+    off_mats[k - 1] = tab.add(mats);
+    off_y[k - 1] = tab.add(yj);
+    ny_at[k - 1] = (int)yj.size();
+  }
+  tab.upload(s);
+  DeviceMem gjw((size_t)nsw * kNB * ld * sizeof(T) * 2);
+  T *Rb = static_cast<T *>(gjw.p);
+  T *Cb = Rb + (size_t)nsw * kNB * ld;
+  for (int k = 1; k <= m - 1; ++k) {
+    launch_assemble<T>(tab.at<AsmJob>(off_asm[k - 1]), nsw, op->coef, op->n, op->dim, op->M,
+                       ld, s);
+    gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, Rb, Cb, op->flag, s);
+    if (ny_at[k - 1] > 0) {
+      if (k == 1)
+        launch_scale_cols<T>(tab.at<GemmJob>(off_y[0]), ny_at[0], ld, -1.0, s);
+      else
+        launch_gemm<T>(tab.at<GemmJob>(off_y[k - 1]), ny_at[k - 1], ld, -1.0, 0.0, s);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));  // keeps the job tables alive until done
+}
+
+// Left-to-right factor sweeps of every slab (no transfer chains): the part
+// of the build the solve and the adjoint need.
+SweepPlan factor_plan(const ddst_op *op) {
+  SweepPlan p;
+  for (int s = 0; s < op->n_slabs; ++s) p.sw.push_back({s, +1, -1, -1});
+  return p;
+}
+
+int check_flag(ddst_op *op, hipStream_t s, const char *what) {
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, op->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h) {
+    HIPCHK(hipMemsetAsync(op->flag, 0, sizeof(int), s));
+    return fail(DDST_EBREAKDOWN, std::string(what) +
+                                     ": non-positive or non-finite pivot in a local "
+                                     "elimination (degenerate local problem)");
+  }
+  return DDST_OK;
+}
+
+template <typename T>
+int build_impl(ddst_op *op, int keep, hipStream_t s) {
+  const int m = op->m, nsl = op->n_slabs, nds = op->n_ds;
+  SweepPlan plan;
+  int nwork = 0, ny = 0;
+  for (int sl = 0; sl < nsl; ++sl) {  // left-to-right, towards Gamma_{sl+1}
+    const bool hasY = sl >= 1 && sl <= nsl - 2;
+    plan.sw.push_back({sl, +1, hasY ? ny++ : -1, keep ? -1 : nwork++});
+  }
+  for (int sl = 1; sl < nsl; ++sl) {  // right-to-left, towards Gamma_sl
+    const bool hasY = sl <= nsl - 2;
+    plan.sw.push_back({sl, -1, hasY ? ny++ : -1, nwork++});
+  }
+  plan.n_y = ny;
+  plan.n_work = nwork;
+  SweepBuffers buf;
+  if (keep) {
+    if (hipMalloc(&op->G, (size_t)nsl * (m - 1) * op->mat_bytes) != hipSuccess) {
+      op->G = nullptr;
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    buf.store = op->G;
+  }
+  DeviceMem work((size_t)2 * nwork * op->mat_bytes);
+  DeviceMem ybuf((size_t)2 * std::max(ny, 1) * op->mat_bytes);
+  buf.work = work.p;
+  buf.ybuf = ybuf.p;
+  run_sweeps<T>(op, plan, buf, s);
+
+  // interface centres and transfer blocks
+  std::vector<AsmJob> cj;
+  std::vector<void *> smats;
+  std::vector<GemmJob> sj;
+  for (int j = 1; j <= nds; ++j) {
+    const int c = j * m;
+    const Sweep &L = plan.sw[j - 1];        // slab j-1, left-to-right
+    const Sweep &R = plan.sw[nsl + j - 1];  // slab j, right-to-left
+    AsmJob a{};
+    a.D = mat(op->Sinv, j - 1, op->mat_bytes);
+    a.plane = c;
+    a.G1 = sweep_G(op, L, m - 1, buf);
+    a.r1 = op->Em + (size_t)c * op->ld;
+    a.c1 = op->Ep + (size_t)(c - 1) * op->ld;
+    a.G2 = sweep_G(op, R, m - 1, buf);
+    a.r2 = op->Ep + (size_t)c * op->ld;
+    a.c2 = op->Em + (size_t)(c + 1) * op->ld;
+    cj.push_back(a);
+    smats.push_back(a.D);
+    if (j >= 2) {
+      GemmJob g{};
+      g.A = a.D;
+      g.B = sweep_Y(op, L, m - 1, buf);
+      g.C = mat(op->S, 2 * (j - 1) + 0, op->mat_bytes);
+      g.bscale = op->Em + (size_t)c * op->ld;
+      sj.push_back(g);
+    }
+    if (j <= nds - 1) {
+      GemmJob g{};
+      g.A = a.D;
+      g.B = sweep_Y(op, R, m - 1, buf);
+      g.C = mat(op->S, 2 * (j - 1) + 1, op->mat_bytes);
+      g.bscale = op->Ep + (size_t)c * op->ld;
+      sj.push_back(g);
+    }
+  }
+  JobTable tab;
+  const size_t oc = tab.add(cj), om = tab.add(smats), os = tab.add(sj);
+  tab.upload(s);
+  launch_assemble<T>(tab.at<AsmJob>(oc), nds, op->coef, op->n, op->dim, op->M, op->ld, s);
+  DeviceMem gjw((size_t)nds * kNB * op->ld * sizeof(T) * 2);
+  T *Rb = static_cast<T *>(gjw.p);
+  gj_invert<T>(tab.at<void *>(om), nds, op->ld, Rb, Rb + (size_t)nds * kNB * op->ld, op->flag,
+               s);
+  launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, -1.0, 0.0, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return check_flag(op, s, "ddst_build_transfer");
+}
+
+int validate_problem(const ddst_problem_t *p) {
+  if (!p) return fail(DDST_EINVAL, "problem is NULL");
+  if (p->dim != 2 && p->dim != 3) return fail(DDST_EINVAL, "dim must be 2 or 3");
+  if (p->n < 3) return fail(DDST_EINVAL, "n must be >= 3");
+  if (p->n_slabs < 2) return fail(DDST_EINVAL, "n_slabs must be >= 2");
+  if ((p->n + 1) % p->n_slabs != 0) return fail(DDST_EINVAL, "(n+1) % n_slabs != 0");
+  if ((p->n + 1) / p->n_slabs < 2) return fail(DDST_EINVAL, "slab width m must be >= 2");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->bvec[a])) return fail(DDST_EINVAL, "bvec not finite");
+  const double M = std::pow((double)p->n, p->dim - 1);
+  if (M > 65536.0) return fail(DDST_EINVAL, "interface too large (M > 65536)");
+  return DDST_OK;
+}
+
+void destroy_op(ddst_op *op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  hodlr_free(op);
+  if (op->G) (void)hipFree(op->G);
+  if (op->arena) (void)hipFree(op->arena);
+  if (op->ws) (void)hipFree(op->ws);
+  if (op->hbuf_host) (void)hipHostFree(op->hbuf_host);
+  delete op;
+}
+
+int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipStream_t s,
+                ddst_op_t **out) {
+  if (!out) return fail(DDST_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = validate_problem(prob);
+  if (st) return st;
+  ddst_build_opts_t o{DDST_FP32, 1, 0, 0};
+  if (opts) o = *opts;
+  if (o.precision != DDST_FP32 && o.precision != DDST_FP64)
+    return fail(DDST_EINVAL, "precision must be DDST_FP32 or DDST_FP64");
+  if (o.transpose != 0) return fail(DDST_EINVAL, "transpose builds are not supported");
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  ddst_op *op = new ddst_op();
+  try {
+    op->dim = prob->dim;
+    op->n = prob->n;
+    op->n_slabs = prob->n_slabs;
+    op->m = (prob->n + 1) / prob->n_slabs;
+    op->n_ds = prob->n_slabs - 1;
+    op->M = prob->dim == 2 ? prob->n : prob->n * prob->n;
+    op->ld = (op->M + kTile - 1) / kTile * kTile;
+    op->N = (size_t)op->M * op->n;
+    op->h = 1.0 / (prob->n + 1);
+    op->prec = o.precision;
+    for (int a = 0; a < 3; ++a) op->bvec[a] = prob->bvec[a];
+    op->mat_bytes = (size_t)op->ld * op->ld * esize(op->prec);
+    const size_t ncell = (size_t)std::pow((double)(op->n + 1), op->dim) + 0.5;
+    Carve cv;
+    const size_t o_kap = prob->kappa ? cv.take(ncell * 8) : 0;
+    const size_t o_c = prob->c ? cv.take(op->N * 8) : 0;
+    const size_t o_coef = cv.take((size_t)coef_slots(op->dim) * op->N * 8);
+    const size_t o_em = cv.take((size_t)(op->n + 2) * op->ld * 8);
+    const size_t o_ep = cv.take((size_t)(op->n + 2) * op->ld * 8);
+    const size_t o_si = cv.take((size_t)op->n_ds * op->mat_bytes);
+    const size_t o_s = cv.take((size_t)2 * op->n_ds * op->mat_bytes);
+    const size_t o_fl = cv.take(sizeof(int));
+    if (hipMalloc(&op->arena, cv.off) != hipSuccess) {
+      op->arena = nullptr;
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    auto at = [&](size_t o) { return static_cast<unsigned char *>(op->arena) + o; };
+    op->kappa = prob->kappa ? reinterpret_cast<double *>(at(o_kap)) : nullptr;
+    op->c = prob->c ? reinterpret_cast<double *>(at(o_c)) : nullptr;
+    op->coef = reinterpret_cast<double *>(at(o_coef));
+    op->Em = reinterpret_cast<double *>(at(o_em));
+    op->Ep = reinterpret_cast<double *>(at(o_ep));
+    op->Sinv = at(o_si);
+    op->S = at(o_s);
+    op->flag = reinterpret_cast<int *>(at(o_fl));
+    HIPCHK(hipMemsetAsync(op->flag, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(op->S, 0, (size_t)2 * op->n_ds * op->mat_bytes, s));
+    if (op->kappa) {
+      HIPCHK(hipMemcpyAsync(op->kappa, prob->kappa, ncell * 8, hipMemcpyDeviceToDevice, s));
+      launch_check_finite(op->kappa, ncell, 0.0, op->flag, s);
+    }
+    if (op->c) {
+      HIPCHK(hipMemcpyAsync(op->c, prob->c, op->N * 8, hipMemcpyDeviceToDevice, s));
+      launch_check_finite(op->c, op->N, -1.7976931348623157e308, op->flag, s);
+    }
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, op->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) {
+      destroy_op(op);
+      return fail(DDST_EINVAL, "kappa must be finite and > 0, c finite");
+    }
+    launch_setup_coef(op->kappa, op->c, op->bvec, op->dim, op->n, op->h, op->coef, nullptr, s);
+    launch_fill_couplings(op->coef, op->dim, op->n, op->M, op->ld, op->Em, op->Ep, s);
+    HIPCHK(hipGetLastError());
+    st = (op->prec == DDST_FP32) ? build_impl<float>(op, o.keep_factors ? 1 : 0, s)
+                                 : build_impl<double>(op, o.keep_factors ? 1 : 0, s);
+    if (st) {
+      destroy_op(op);
+      return st;
+    }
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    op->last_build.t_build_ms = ms;
+    op->last_build.bytes_transfer = (double)2 * op->n_ds * op->mat_bytes;
+    op->last_build.bytes_factors = op->G ? (double)op->n_slabs * (op->m - 1) * op->mat_bytes : 0;
+  } catch (...) {
+    destroy_op(op);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *out = op;
+  return DDST_OK;
+}
+
+// ---- solve ------------------------------------------------------------------
+struct SolveWs {
+  double *X, *R, *Z, *D;     // padded volumes (n*ld)
+  double *fJ, *hh, *W, *xg;  // interface vectors (n_ds*ld)
+  double *V;                 // Krylov basis (max_iter+1) * n_ds*ld
+  double *hd;                // small scalars
+  double *part;              // transposed-GEMV partial sums
+  double *nrm;               // norms
+  size_t vol, ifc;
+};
+
+void ensure_ws(ddst_op *op, size_t bytes) {
+  if (op->ws_bytes >= bytes) return;
+  if (op->ws) (void)hipFree(op->ws);
+  op->ws = nullptr;
+  op->ws_bytes = 0;
+  if (hipMalloc(&op->ws, bytes) != hipSuccess) {
+    op->ws = nullptr;
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  op->ws_bytes = bytes;
+}
+
+SolveWs carve_ws(ddst_op *op, int max_iter) {
+  const size_t vol = (size_t)op->n * op->ld, ifc = (size_t)op->n_ds * op->ld;
+  const int nchunk = std::min(op->ld / kGemvChunk, 64);
+  const size_t part = (size_t)std::max(op->n_slabs, op->n_ds) * nchunk * op->ld;
+  Carve cv;
+  size_t o[12];
+  o[0] = cv.take(vol * 8); o[1] = cv.take(vol * 8); o[2] = cv.take(vol * 8);
+  o[3] = cv.take(vol * 8);
+  o[4] = cv.take(ifc * 8); o[5] = cv.take(ifc * 8); o[6] = cv.take(ifc * 8);
+  o[7] = cv.take(ifc * 8);
+  o[8] = cv.take((size_t)(max_iter + 1) * ifc * 8);
+  o[9] = cv.take((size_t)(4 * max_iter + 16) * 8);
+  o[10] = cv.take(part * 8);
+  o[11] = cv.take(16 * 8);
+  ensure_ws(op, cv.off);
+  auto at = [&](size_t x) {
+    return reinterpret_cast<double *>(static_cast<unsigned char *>(op->ws) + x);
+  };
+  SolveWs w;
+  w.X = at(o[0]); w.R = at(o[1]); w.Z = at(o[2]); w.D = at(o[3]);
+  w.fJ = at(o[4]); w.hh = at(o[5]); w.W = at(o[6]); w.xg = at(o[7]);
+  w.V = at(o[8]); w.hd = at(o[9]); w.part = at(o[10]); w.nrm = at(o[11]);
+  w.vol = vol;
+  w.ifc = ifc;
+  return w;
+}
+
+// Slab-solve job tables: forward and backward block-Thomas sweeps of every
+// single slab with the stored left-to-right factors (or their transposes).
+//   forward  : y_k = op(G_k) (r_P(k) - e_f(k) .* y_{k-1}),  y_0 = left trace
+//   backward : z_k = y_k - op(G_k) (e_b(k) .* z_{k+1}),      z_m = right trace
+// e_f(k) = Em(P(k)), e_b(k) = Ep(P(k)) for A; Ep(P(k)-1), Em(P(k)+1) for A^T.
+struct SlabTables {
+  JobTable tab;
+  std::vector<size_t> fwd, bwd;
+  std::vector<int> nfwd, nbwd;
+};
+
+void make_slab_tables(const ddst_op *op, const void *G, const double *R, double *Vol,
+                      bool with_traces, bool transpose, SlabTables &t) {
+  const int m = op->m, ld = op->ld;
+  const size_t mb = op->mat_bytes;
+  t.fwd.assign(m, 0);
+  t.bwd.assign(m, 0);
+  t.nfwd.assign(m, 0);
+  t.nbwd.assign(m, 0);
+  for (int k = 1; k <= m - 1; ++k) {
+    std::vector<GemvJob> jf, jb;
+    for (int s = 0; s < op->n_slabs; ++s) {
+      const int P = s * m + k;
+      const void *Gk = mat(const_cast<void *>(G), (size_t)s * (m - 1) + (k - 1), mb);
+      GemvJob f{};
+      f.G = Gk;
+      f.x1 = R + (size_t)(P - 1) * ld;
+      const bool left = (k > 1) || (with_traces && s >= 1);
+      if (left) {
+        f.e = transpose ? op->Ep + (size_t)(P - 1) * ld : op->Em + (size_t)P * ld;
+        f.x2 = Vol + (size_t)(P - 2) * ld;
+      }
+      f.out = Vol + (size_t)(P - 1) * ld;
+      jf.push_back(f);
+      GemvJob b{};
+      const bool right = (k < m - 1) || (with_traces && s + 1 <= op->n_ds);
+      b.G = right ? Gk : nullptr;
+      if (right) {
+        b.e = transpose ? op->Em + (size_t)(P + 1) * ld : op->Ep + (size_t)P * ld;
+        b.x2 = Vol + (size_t)P * ld;
+      }
+      b.w = Vol + (size_t)(P - 1) * ld;
+      b.out = Vol + (size_t)(P - 1) * ld;
+      jb.push_back(b);
+    }
+    t.fwd[k] = t.tab.add(jf);
+    t.nfwd[k] = (int)jf.size();
+    if (k < m - 1 || with_traces) {
+      t.bwd[k] = t.tab.add(jb);
+      t.nbwd[k] = (int)jb.size();
+    }
+  }
+}
+
+template <typename T>
+void run_slab_solve(const ddst_op *op, const SlabTables &t, bool transpose, double *part,
+                    hipStream_t s) {
+  const int m = op->m;
+  for (int k = 1; k <= m - 1; ++k)
+    launch_gemv<T>(t.tab.at<GemvJob>(t.fwd[k]), t.nfwd[k], op->ld, op->M, transpose, 1.0, part,
+                   s);
+  for (int k = m - 1; k >= 1; --k)
+    if (t.nbwd[k] > 0)
+      launch_gemv<T>(t.tab.at<GemvJob>(t.bwd[k]), t.nbwd[k], op->ld, op->M, transpose, 1.0,
+                     part, s);
+}
+
+// Interface operator jobs: y = S x (or S^T x) for a fixed pair (x, y).
+std::vector<GemvJob> interface_jobs(const ddst_op *op, const double *x, double *y, bool trans) {
+  std::vector<GemvJob> jobs;
+  const int nds = op->n_ds, ld = op->ld;
+  const size_t mb = op->mat_bytes;
+  for (int j = 1; j <= nds; ++j) {
+    GemvJob g{};
+    if (!trans) {
+      if (j >= 2) { g.G = mat(op->S, 2 * (j - 1) + 0, mb); g.x1 = x + (size_t)(j - 2) * ld; }
+      if (j <= nds - 1) { g.G2 = mat(op->S, 2 * (j - 1) + 1, mb); g.x3 = x + (size_t)j * ld; }
+    } else {
+      if (j >= 2) { g.G = mat(op->S, 2 * (j - 2) + 1, mb); g.x1 = x + (size_t)(j - 2) * ld; }
+      if (j <= nds - 1) { g.G2 = mat(op->S, 2 * j + 0, mb); g.x3 = x + (size_t)j * ld; }
+    }
+    g.w = x + (size_t)(j - 1) * ld;
+    g.out = y + (size_t)(j - 1) * ld;
+    jobs.push_back(g);
+  }
+  return jobs;
+}
+
+std::vector<GemvJob> sinv_jobs(const ddst_op *op, const double *x, double *y) {
+  std::vector<GemvJob> jobs;
+  for (int j = 1; j <= op->n_ds; ++j) {
+    GemvJob g{};
+    g.G = mat(op->Sinv, j - 1, op->mat_bytes);
+    g.x1 = x + (size_t)(j - 1) * op->ld;
+    g.out = y + (size_t)(j - 1) * op->ld;
+    jobs.push_back(g);
+  }
+  return jobs;
+}
+
+// Unrestarted GMRES with classical Gram-Schmidt applied twice (FP64).
+// Basis vectors are padded interface vectors.  Returns iterations.
+template <typename T>
+int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int max_iter,
+          bool trans, bool hodlr, double *relres, hipStream_t s) {
+  const size_t len = w.ifc;
+  double *hh = op->hbuf_host;
+  launch_norm(rhs, len, w.nrm, s);
+  HIPCHK(hipMemcpyAsync(hh, w.nrm, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double beta = hh[0];
+  launch_fill(x, 0.0, len, s);
+  *relres = 0.0;
+  if (!(beta > 0.0)) return 0;
+  launch_scale_by_inv(w.V, rhs, w.nrm, len, s);
+  // matvec tables for every basis vector
+  JobTable tab;
+  std::vector<size_t> offs(max_iter);
+  if (!hodlr)
+    for (int k = 0; k < max_iter; ++k)
+      offs[k] = tab.add(interface_jobs(op, w.V + (size_t)k * len, w.W, trans));
+  tab.upload(s);
+  std::vector<double> H((size_t)(max_iter + 1) * max_iter, 0.0), cs(max_iter), sn(max_iter),
+      gv(max_iter + 1, 0.0);
+  gv[0] = beta;
+  int k = 0;
+  double res = 1.0;
+  for (k = 0; k < max_iter; ++k) {
+    const double *vk = w.V + (size_t)k * len;
+    if (hodlr) {
+      int st = hodlr_apply_jobs(op, vk, w.W, trans ? 1 : 0, s);
+      if (st) throw HipError("compressed apply failed");
+    } else {
+      launch_gemv<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, trans ? 1 : 0, -1.0,
+                     w.part, s);
+    }
+    launch_dots(w.V, len, k + 1, w.W, len, w.hd, s);
+    launch_mgs_update(w.W, w.V, len, k + 1, w.hd, -1.0, len, s);
+    launch_dots(w.V, len, k + 1, w.W, len, w.hd + (k + 1), s);
+    launch_mgs_update(w.W, w.V, len, k + 1, w.hd + (k + 1), -1.0, len, s);
+    launch_norm(w.W, len, w.hd + 2 * (k + 1), s);
+    launch_scale_by_inv(w.V + (size_t)(k + 1) * len, w.W, w.hd + 2 * (k + 1), len, s);
+    HIPCHK(hipMemcpyAsync(hh, w.hd, (2 * (k + 1) + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double *col = &H[(size_t)k * (max_iter + 1)];
+    for (int i = 0; i <= k; ++i) col[i] = hh[i] + hh[k + 1 + i];
+    col[k + 1] = hh[2 * (k + 1)];
+    for (int i = 0; i < k; ++i) {
+      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double r = std::hypot(col[k], col[k + 1]);
+    cs[k] = (r > 0) ? col[k] / r : 1.0;
+    sn[k] = (r > 0) ? col[k + 1] / r : 0.0;
+    col[k] = r;
+    col[k + 1] = 0.0;
+    gv[k + 1] = -sn[k] * gv[k];
+    gv[k] = cs[k] * gv[k];
+    res = std::fabs(gv[k + 1]) / beta;
+    if (res <= tol || !(hh[2 * (k + 1)] > 0.0)) {
+      ++k;
+      break;
+    }
+  }
+  if (k > max_iter) k = max_iter;
+  // back substitution R y = g, then x = V y
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double t = gv[i];
+    for (int j = i + 1; j < k; ++j) t -= H[(size_t)j * (max_iter + 1) + i] * y[j];
+    const double d = H[(size_t)i * (max_iter + 1) + i];
+    y[i] = (d != 0.0) ? t / d : 0.0;
+  }
+  std::memcpy(hh, y.data(), k * 8);
+  HIPCHK(hipMemcpyAsync(w.hd, hh, k * 8, hipMemcpyHostToDevice, s));
+  launch_mgs_update(x, w.V, len, k, w.hd, 1.0, len, s);
+  HIPCHK(hipStreamSynchronize(s));
+  *relres = res;
+  return k;
+}
+
+double dev_norm(ddst_op *op, const double *v, size_t len, double *scratch, hipStream_t s) {
+  launch_norm(v, len, scratch, s);
+  HIPCHK(hipMemcpyAsync(op->hbuf_host, scratch, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return op->hbuf_host[0];
+}
+
+void ensure_host(ddst_op *op) {
+  if (!op->hbuf_host) {
+    void *p = nullptr;
+    HIPCHK(hipHostMalloc(&p, 1 << 16, hipHostMallocDefault));
+    op->hbuf_host = static_cast<double *>(p);
+  }
+}
+
+// One DD solve of A d = r (transpose: A^T d = r) with zero boundary data,
+// writing the correction volume into w.D; returns GMRES iterations.
+template <typename T>
+int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const double *tol_inner,
+                  int max_iter, bool hodlr, double *relres, SlabTables &loads,
+                  SlabTables &recon, hipStream_t s) {
+  // z = A_II^{-1} r_I
+  run_slab_solve<T>(op, loads, trans, w.part, s);
+  // f_J = r_J - A_JI z
+  if (!trans)
+    launch_interface_rhs(w.R, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ, s);
+  else
+    launch_interface_rhs(w.R, w.Z, op->Ep, op->Em, op->n_ds, op->m, op->ld, -1, +1, w.fJ, s);
+  int it;
+  if (!trans) {
+    // hhat = Sigma^{-1} f_J ; S d_J = hhat
+    JobTable tb;
+    const size_t o = tb.add(sinv_jobs(op, w.fJ, w.hh));
+    tb.upload(s);
+    launch_gemv<T>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 0, 1.0, w.part, s);
+    it = gmres<T>(op, w, w.hh, w.xg, *tol_inner, max_iter, false, hodlr, relres, s);
+  } else {
+    // S^T mu = f_J ; d_J = Sigma^{-T} mu
+    it = gmres<T>(op, w, w.fJ, w.hh, *tol_inner, max_iter, true, hodlr, relres, s);
+    JobTable tb;
+    const size_t o = tb.add(sinv_jobs(op, w.hh, w.xg));
+    tb.upload(s);
+    launch_gemv<T>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 1, 1.0, w.part, s);
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  // traces into the correction volume, then the slab interiors
+  launch_copy_planes(w.xg, 1, 0, w.D, op->m, op->m - 1, op->n_ds, op->ld, op->M, s);
+  run_slab_solve<T>(op, recon, trans, w.part, s);
+  (void)G;
+  return it;
+}
+
+struct RefineOut {
+  int outer = 0, gm_total = 0, gm_last = 0, converged = 0;
+  double relres = 0, corr = 0, resrel = 0;
+};
+
+// FP64 refinement loop shared by the solve (A) and the adjoint (A^T).
+template <typename T>
+int refine(ddst_op *op, const void *G, const double *f, const double *g, bool trans,
+           const ddst_solve_opts_t &o, SolveWs &w, RefineOut &ro, hipStream_t s) {
+  SlabTables loads, recon;
+  make_slab_tables(op, G, w.R, w.Z, false, trans, loads);
+  make_slab_tables(op, G, w.R, w.D, true, trans, recon);
+  loads.tab.upload(s);
+  recon.tab.upload(s);
+  launch_fill(w.X, 0.0, w.vol, s);
+  launch_fill(w.Z, 0.0, w.vol, s);
+  launch_fill(w.R, 0.0, w.vol, s);  // padding of R must stay zero
+  double prev = 0.0, r0 = 0.0;
+  int status = DDST_OK;
+  for (int outer = 0; outer < o.max_outer; ++outer) {
+    launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f, trans ? nullptr : g, w.X, w.R,
+                    trans ? 1 : 0, s);
+    if (outer == 0) r0 = dev_norm(op, w.R, w.vol, w.nrm, s);
+    launch_fill(w.D, 0.0, w.vol, s);
+    double rr = 0;
+    const int it = dd_correction<T>(op, w, G, trans, &o.inner_tol, o.max_iter,
+                                    o.use_hodlr != 0, &rr, loads, recon, s);
+    ro.gm_total += it;
+    ro.gm_last = it;
+    ro.relres = rr;
+    if (rr > o.inner_tol) status = DDST_ENOTCONV;
+    launch_axpy(w.X, w.D, 1.0, w.vol, s);
+    const double dn = dev_norm(op, w.D, w.vol, w.nrm, s);
+    const double xn = dev_norm(op, w.X, w.vol, w.nrm + 1, s);
+    ro.outer = outer + 1;
+    ro.corr = (xn > 0) ? dn / xn : 0.0;
+    bool done = ro.corr <= o.tol;
+    if (outer >= 1 && prev > 0 && dn < prev) {
+      const double rho = dn / prev;
+      if (rho * ro.corr <= o.tol) done = true;
+    }
+    prev = dn;
+    if (xn == 0.0) done = true;
+    if (done) {
+      ro.converged = 1;
+      break;
+    }
+  }
+  launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f, trans ? nullptr : g, w.X, w.R,
+                  trans ? 1 : 0, s);
+  const double rf = dev_norm(op, w.R, w.vol, w.nrm, s);
+  ro.resrel = (r0 > 0) ? rf / r0 : 0.0;
+  if (!ro.converged) status = DDST_ENOTCONV;
+  return status;
+}
+
+ddst_solve_opts_t solve_defaults(const ddst_op *op) {
+  ddst_solve_opts_t o{};
+  o.tol = 1e-10;
+  o.inner_tol = (op->prec == DDST_FP32) ? 1e-7 : 1e-12;
+  o.max_iter = 300;
+  o.max_outer = 4;
+  o.use_hodlr = 0;
+  return o;
+}
+
+int check_solve_opts(const ddst_solve_opts_t &o) {
+  if (!(o.tol > 0) || !(o.inner_tol > 0)) return fail(DDST_EINVAL, "tolerances must be > 0");
+  if (o.max_iter < 1 || o.max_iter > 1000) return fail(DDST_EINVAL, "max_iter in [1, 1000]");
+  if (o.max_outer < 1 || o.max_outer > 100) return fail(DDST_EINVAL, "max_outer in [1, 100]");
+  return DDST_OK;
+}
+
+template <typename T>
+int solve_impl(ddst_op *op, const double *f, const double *g, const ddst_solve_opts_t &o,
+               double *u_gamma, double *u_vol, ddst_stats_t *st, hipStream_t s) {
+  if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
+  if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  ensure_host(op);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  SolveWs w = carve_ws(op, o.max_iter);
+  RefineOut ro;
+  const int status = refine<T>(op, op->G, f, g, false, o, w, ro, s);
+  if (u_vol) launch_unpad(w.X, u_vol, op->n, op->M, op->ld, s);
+  if (u_gamma) {
+    launch_copy_planes(w.X, op->m, op->m - 1, w.xg, 1, 0, op->n_ds, op->ld, op->M, s);
+    launch_unpad(w.xg, u_gamma, op->n_ds, op->M, op->ld, s);
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    *st = op->last_build;
+    st->outer_iters = ro.outer;
+    st->gmres_iters = ro.gm_total;
+    st->last_gmres_iters = ro.gm_last;
+    st->converged = ro.converged;
+    st->gmres_relres = ro.relres;
+    st->residual_rel = ro.resrel;
+    st->correction_rel = ro.corr;
+    st->t_solve_ms = ms;
+  }
+  return status;
+}
+
+template <typename T>
+int adjoint_impl(ddst_op *op, const double *u_vol, const double *g, const double *gbar,
+                 const ddst_solve_opts_t &o, double *dkappa, double *lambda, ddst_stats_t *st,
+                 hipStream_t s) {
+  if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  ensure_host(op);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  // factors: stored ones, or recomputed left-to-right sweeps of every slab
+  DeviceMem tmp;
+  const void *G = op->G;
+  if (!G) {
+    tmp.alloc((size_t)op->n_slabs * (op->m - 1) * op->mat_bytes);
+    SweepBuffers b;
+    b.store = tmp.p;
+    run_sweeps<T>(op, factor_plan(op), b, s);
+    const int fs = check_flag(op, s, "ddst_adjoint");
+    if (fs) return fs;
+    G = tmp.p;
+  }
+  SolveWs w = carve_ws(op, o.max_iter);
+  RefineOut ro;
+  const int status = refine<T>(op, G, gbar, nullptr, true, o, w, ro, s);
+  launch_cell_gradient(u_vol, w.X, g, op->dim, op->n, op->M, op->ld, op->h, dkappa, s);
+  if (lambda) launch_unpad(w.X, lambda, op->n, op->M, op->ld, s);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    *st = op->last_build;
+    st->outer_iters = ro.outer;
+    st->gmres_iters = ro.gm_total;
+    st->last_gmres_iters = ro.gm_last;
+    st->converged = ro.converged;
+    st->gmres_relres = ro.relres;
+    st->residual_rel = ro.resrel;
+    st->correction_rel = ro.corr;
+    st->t_adjoint_ms = ms;
+  }
+  return status;
+}
+
+template <typename Fn>
+int guarded(Fn &&fn) {
+  try {
+    return fn();
+  } catch (const std::bad_alloc &) {
+    return fail(DDST_ENOMEM, "device or host allocation failed");
+  } catch (const HipError &e) {
+    return fail(DDST_EHIP, e.what());
+  } catch (const std::exception &e) {
+    return fail(DDST_EHIP, e.what());
+  } catch (...) {
+    return fail(DDST_EHIP, "unknown error");
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+int ddst_build_transfer(const ddst_problem_t *prob, const ddst_build_opts_t *opts,
+                        hipStream_t stream, ddst_op_t **out) {
+  g_err.clear();
+  return guarded([&]() -> int { return build_entry(prob, opts, stream, out); });
+}
+
+int ddst_solve(const ddst_op_t *cop, const double *f, const double *g,
+               const ddst_solve_opts_t *opts, double *u_gamma, double *u_vol,
+               ddst_stats_t *stats, hipStream_t stream) {
+  g_err.clear();
+  if (!cop) return fail(DDST_EINVAL, "op is NULL");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  ddst_solve_opts_t o = opts ? *opts : solve_defaults(op);
+  int st = check_solve_opts(o);
+  if (st) return st;
+  return guarded([&]() -> int {
+    return op->prec == DDST_FP32 ? solve_impl<float>(op, f, g, o, u_gamma, u_vol, stats, stream)
+                                 : solve_impl<double>(op, f, g, o, u_gamma, u_vol, stats, stream);
+  });
+}
+
+int ddst_adjoint(const ddst_op_t *cop, const double *u_vol, const double *g, const double *gbar,
+                 const ddst_solve_opts_t *opts, double *dkappa, double *lambda,
+                 ddst_stats_t *stats, hipStream_t stream) {
+  g_err.clear();
+  if (!cop || !u_vol || !gbar || !dkappa)
+    return fail(DDST_EINVAL, "op, u_vol, gbar and dkappa must be non-NULL");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  ddst_solve_opts_t o = opts ? *opts : solve_defaults(op);
+  int st = check_solve_opts(o);
+  if (st) return st;
+  return guarded([&]() -> int {
+    return op->prec == DDST_FP32
+               ? adjoint_impl<float>(op, u_vol, g, gbar, o, dkappa, lambda, stats, stream)
+               : adjoint_impl<double>(op, u_vol, g, gbar, o, dkappa, lambda, stats, stream);
+  });
+}
+
+int ddst_release_factors(ddst_op_t *op) {
+  g_err.clear();
+  if (!op) return fail(DDST_EINVAL, "op is NULL");
+  if (op->G) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(op->G);
+    op->G = nullptr;
+  }
+  return DDST_OK;
+}
+
+void ddst_destroy(ddst_op_t *op) { destroy_op(op); }
+
+const char *ddst_last_error(void) { return g_err.c_str(); }
+
+int ddst_op_info(const ddst_op_t *op, int32_t *M, int32_t *n_ds, int32_t *ld,
+                 int32_t *precision) {
+  if (!op) return fail(DDST_EINVAL, "op is NULL");
+  if (M) *M = op->M;
+  if (n_ds) *n_ds = op->n_ds;
+  if (ld) *ld = op->ld;
+  if (precision) *precision = op->prec;
+  return DDST_OK;
+}
+
+int ddst_get_transfer(const ddst_op_t *op, int32_t j, double *S_left, double *S_right,
+                      hipStream_t stream) {
+  g_err.clear();
+  if (!op) return fail(DDST_EINVAL, "op is NULL");
+  if (j < 1 || j > op->n_ds) return fail(DDST_EINVAL, "interface index out of range");
+  return guarded([&]() -> int {
+    if (S_left)
+      launch_extract_block(mat(op->S, 2 * (j - 1) + 0, op->mat_bytes), op->prec, op->M, op->ld,
+                           S_left, stream);
+    if (S_right)
+      launch_extract_block(mat(op->S, 2 * (j - 1) + 1, op->mat_bytes), op->prec, op->M, op->ld,
+                           S_right, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return DDST_OK;
+  });
+}
+
+int ddst_apply(const ddst_op_t *cop, int32_t transpose, int32_t which, const double *x,
+               double *y, hipStream_t stream) {
+  g_err.clear();
+  if (!cop || !x || !y) return fail(DDST_EINVAL, "op, x and y must be non-NULL");
+  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR)
+    return fail(DDST_EINVAL, "which must be DENSE or HODLR");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  if (which == DDST_APPLY_HODLR && !hodlr_ready(op))
+    return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  return guarded([&]() -> int {
+    DeviceMem buf((size_t)op->n_ds * op->ld * 8 * 2);
+    double *xp = static_cast<double *>(buf.p), *yp = xp + (size_t)op->n_ds * op->ld;
+    launch_pad(x, xp, op->n_ds, op->M, op->ld, stream);
+    if (which == DDST_APPLY_DENSE) {
+      JobTable t;
+      const size_t o = t.add(interface_jobs(op, xp, yp, transpose != 0));
+      t.upload(stream);
+      const int nchunk = std::min(op->ld / kGemvChunk, 64);
+      DeviceMem part((size_t)op->n_ds * nchunk * op->ld * 8);
+      if (op->prec == DDST_FP32)
+        launch_gemv<float>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, transpose, -1.0,
+                           static_cast<double *>(part.p), stream);
+      else
+        launch_gemv<double>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, transpose, -1.0,
+                            static_cast<double *>(part.p), stream);
+      launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(stream));
+    } else {
+      const int st = hodlr_apply_jobs(op, xp, yp, transpose, stream);
+      if (st) return st;
+      launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(stream));
+    }
+    return DDST_OK;
+  });
+}
+
+int ddst_loads(const ddst_op_t *cop, const double *f, const double *g, double *hhat,
+               hipStream_t stream) {
+  g_err.clear();
+  if (!cop || !hhat) return fail(DDST_EINVAL, "op and hhat must be non-NULL");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped");
+  return guarded([&]() -> int {
+    SolveWs w = carve_ws(op, 1);
+    launch_fill(w.X, 0.0, w.vol, stream);
+    launch_fill(w.Z, 0.0, w.vol, stream);
+    launch_fill(w.R, 0.0, w.vol, stream);
+    launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f, g, w.X, w.R, 0, stream);
+    SlabTables loads;
+    make_slab_tables(op, op->G, w.R, w.Z, false, false, loads);
+    loads.tab.upload(stream);
+    JobTable tb;
+    const size_t o = tb.add(sinv_jobs(op, w.fJ, w.hh));
+    tb.upload(stream);
+    if (op->prec == DDST_FP32) {
+      run_slab_solve<float>(op, loads, false, w.part, stream);
+      launch_interface_rhs(w.R, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ,
+                           stream);
+      launch_gemv<float>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 0, 1.0, w.part, stream);
+    } else {
+      run_slab_solve<double>(op, loads, false, w.part, stream);
+      launch_interface_rhs(w.R, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ,
+                           stream);
+      launch_gemv<double>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 0, 1.0, w.part, stream);
+    }
+    launch_unpad(w.hh, hhat, op->n_ds, op->M, op->ld, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return DDST_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,400 @@
+// Dense batched kernels of the transfer-block build (CDNA4 / gfx950).
+//
+// * k_assemble   : plane blocks D_k = A_plane - diag(r) G diag(c) [- ...]
+//                  (the Schur complement recursion of block-tridiagonal
+//                  elimination across the thin slab direction);
+// * gj_invert    : in-place blocked Gauss-Jordan inversion without pivoting,
+//                  kNB-wide pivot blocks; each step is a rank-kNB update done
+//                  on the matrix cores (MFMA 16x16x4, FP32 or FP64);
+// * k_gemm       : batched C = alpha A diag(s) B + beta C on the matrix cores
+//                  (transfer chains Y_k = -G_k E Y_{k-1} and S = Sigma^{-1} R);
+// * k_scale_cols : C = alpha A diag(s) (first link of a transfer chain).
+//
+// All matrices are ld x ld row-major, ld a multiple of 128, padded with the
+// identity, so no kernel tests edges.  Work-group tiles are 128 x 128 with 4
+// wavefronts of 64 lanes, each owning a 64 x 64 sub-tile (4 x 4 MFMA tiles).
+#include "internal.h"
+
+namespace ddst {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct AccT;
+template <> struct AccT<float> { using type = f32x4; };
+template <> struct AccT<double> { using type = f64x4; };
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int BK = 16;           // k-depth of one LDS stage
+constexpr int LW = kTile + 16;   // LDS row width (padding spreads banks)
+
+__device__ __forceinline__ void ld8(const float *p, float *r) {
+  float4 a = *reinterpret_cast<const float4 *>(p);
+  float4 b = *reinterpret_cast<const float4 *>(p + 4);
+  r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
+  r[4] = b.x; r[5] = b.y; r[6] = b.z; r[7] = b.w;
+}
+__device__ __forceinline__ void ld8(const double *p, double *r) {
+  const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double2 v = q[i];
+    r[2 * i] = v.x;
+    r[2 * i + 1] = v.y;
+  }
+}
+
+// Map the linear work-group id so that consecutive logical tiles land on
+// the same XCD (work-groups are dispatched round-robin over the 8 XCDs):
+// tiles of one batch entry then share one L2.
+__device__ __forceinline__ int xcd_remap(int lin, int total) {
+  if ((total & 7) != 0) return lin;
+  return (lin & 7) * (total >> 3) + (lin >> 3);
+}
+
+template <typename T>
+struct Tile {
+  typename AccT<T>::type v[4][4];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[i][j][r] = T(0);
+  }
+};
+
+// acc += A[0:128, 0:K] * diag(bscale[0:K]) * B[0:K, 0:128]
+// A row-major with leading dim lda (points at the tile's first row),
+// B row-major with leading dim ldb (points at the tile's first column).
+template <typename T>
+__device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
+                                         const T *__restrict__ B, int ldb,
+                                         const double *__restrict__ bscale, int K,
+                                         T (*As)[LW], T (*Bs)[LW], Tile<T> &acc) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int ar = tid >> 1, ak = (tid & 1) * 8;    // A tile: 128 rows x 16
+  const int br = tid >> 4, bc = (tid & 15) * 8;   // B tile: 16 rows x 128
+  T ra[8], rb[8];
+  auto load = [&](int k0) {
+    ld8(A + (size_t)ar * lda + k0 + ak, ra);
+    ld8(B + (size_t)(k0 + br) * ldb + bc, rb);
+    if (bscale) {
+      const T s = (T)bscale[k0 + br];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rb[q] *= s;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[ak + q][ar] = ra[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Bs[br][bc + q] = rb[q];
+    __syncthreads();
+    if (k0 + BK < K) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T a[4], b[4];
+      const int kr = kk + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc.v[i][j] = mfma16(a[i], b[j], acc.v[i][j]);
+    }
+  }
+}
+
+// Row / column of accumulator element (i, j, r) inside the 128 x 128 tile
+// (MFMA 16x16x4 output layout: lane l holds column l%16, rows 4*(l/16)+r).
+__device__ __forceinline__ int acc_row(int i, int r) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave >> 1) * 64 + i * 16 + 4 * (lane >> 4) + r;
+}
+__device__ __forceinline__ int acc_col(int j) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave & 1) * 64 + j * 16 + (lane & 15);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(const GemmJob *__restrict__ jobs, int ld,
+                                              int tiles_per_mat, T alpha, T beta) {
+  __shared__ T As[BK][LW];
+  __shared__ T Bs[BK][LW];
+  const int total = gridDim.x;
+  const int lin = xcd_remap(blockIdx.x, total);
+  const int b = lin / tiles_per_mat;
+  const int t = lin % tiles_per_mat;
+  const int nt = ld / kTile;
+  const int bm = (t / nt) * kTile, bn = (t % nt) * kTile;
+  const GemmJob J = jobs[b];
+  const T *A = static_cast<const T *>(J.A);
+  const T *B = static_cast<const T *>(J.B);
+  T *C = static_cast<T *>(J.C);
+  Tile<T> acc;
+  acc.zero();
+  mma_tile<T>(A + (size_t)bm * ld, ld, B + bn, ld, J.bscale, ld, As, Bs, acc);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t idx = (size_t)(bm + acc_row(i, r)) * ld + bn + acc_col(j);
+        T v = alpha * acc.v[i][j][r];
+        if (beta != T(0)) v += beta * C[idx];
+        C[idx] = v;
+      }
+}
+
+// One Gauss-Jordan step, panel part.  Work-group (jt, b):
+//  * inverts the kNB x kNB pivot block P = D[p, p] in LDS (no pivoting);
+//  * R[:, jt-block] = P^{-1} D[p, jt-block]   (and P^{-1} + I when jt == p);
+//  * Cbuf[jt-block rows, :] = D[jt-block rows, p]   (copy of the old column).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats,
+                                                  T *__restrict__ Rbuf,
+                                                  T *__restrict__ Cbuf, int ld, int p,
+                                                  int *__restrict__ flag) {
+  __shared__ T P[kNB][kNB + 1];
+  __shared__ T X[kNB][kNB + 1];
+  __shared__ T colk[kNB], rowk[kNB];
+  const int b = blockIdx.y, jt = blockIdx.x, tid = threadIdx.x;
+  T *D = static_cast<T *>(mats[b]);
+  T *R = Rbuf + (size_t)b * kNB * ld;
+  T *Cb = Cbuf + (size_t)b * ld * kNB;
+  const int p0 = p * kNB, j0 = jt * kNB;
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    P[r][c] = D[(size_t)(p0 + r) * ld + p0 + c];
+    X[r][c] = D[(size_t)(p0 + r) * ld + j0 + c];
+    Cb[(size_t)(j0 + r) * kNB + c] = D[(size_t)(j0 + r) * ld + p0 + c];
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < kNB; ++k) {
+    if (tid < kNB) {
+      colk[tid] = P[tid][k];
+      rowk[tid] = P[k][tid];
+    }
+    __syncthreads();
+    const T piv = rowk[k];
+    if (!(piv > T(0)) || !isfinite((double)piv)) bad = true;
+    const T inv = T(1) / piv;
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int r = e / kNB, c = e % kNB;
+      T v;
+      if (r == k && c == k) v = inv;
+      else if (r == k) v = rowk[c] * inv;
+      else if (c == k) v = -colk[r] * inv;
+      else v = P[r][c] - colk[r] * rowk[c] * inv;
+      P[r][c] = v;
+    }
+    __syncthreads();
+  }
+  if (bad && jt == 0 && tid == 0) atomicOr(flag, 1);
+  // R tile: 64 x 64, thread -> row r = tid / 4, 16 columns
+  const int r = tid >> 2, c0 = (tid & 3) * 16;
+  T out[16];
+  if (jt == p) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[q] = P[r][c0 + q] + (r == c0 + q ? T(1) : T(0));
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[q] = T(0);
+    for (int k = 0; k < kNB; ++k) {
+      const T a = P[r][k];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) out[q] += a * X[k][c0 + q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) R[(size_t)r * ld + j0 + c0 + q] = out[q];
+}
+
+// One Gauss-Jordan step, update part: for rows outside the pivot block
+//   D[i, :] -= Cbuf[i, :] R           (column p becomes -D[i,p] P^{-1})
+// and the pivot rows take R (with P^{-1} on the diagonal block).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mats,
+                                                   const T *__restrict__ Rbuf,
+                                                   const T *__restrict__ Cbuf, int ld,
+                                                   int p, int tiles_per_mat) {
+  __shared__ T As[BK][LW];
+  __shared__ T Bs[BK][LW];
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = lin / tiles_per_mat;
+  const int t = lin % tiles_per_mat;
+  const int nt = ld / kTile;
+  const int bm = (t / nt) * kTile, bn = (t % nt) * kTile;
+  T *D = static_cast<T *>(mats[b]);
+  const T *R = Rbuf + (size_t)b * kNB * ld;
+  const T *Cb = Cbuf + (size_t)b * ld * kNB;
+  const int p0 = p * kNB;
+  Tile<T> acc;
+  acc.zero();
+  mma_tile<T>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, nullptr, kNB, As, Bs, acc);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + acc_row(i, r), col = bn + acc_col(j);
+        const size_t idx = (size_t)row * ld + col;
+        if (row >= p0 && row < p0 + kNB)
+          D[idx] = R[(size_t)(row - p0) * ld + col] - (row == col ? T(1) : T(0));
+        else
+          D[idx] = D[idx] - acc.v[i][j][r];
+      }
+}
+
+// D = A_plane - diag(r1) G1 diag(c1) - diag(r2) G2 diag(c2); one block per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ jobs,
+                                                  const double *__restrict__ coef, int n,
+                                                  int dim, int M, int ld) {
+  const AsmJob J = jobs[blockIdx.y];
+  const int r = blockIdx.x;
+  T *D = static_cast<T *>(J.D) + (size_t)r * ld;
+  if (r >= M) {
+    for (int c = threadIdx.x; c < ld; c += blockDim.x) D[c] = (c == r) ? T(1) : T(0);
+    return;
+  }
+  const size_t N = (size_t)M * n;
+  const size_t node = (size_t)(J.plane - 1) * M + r;
+  // in-plane stencil entries of row r (boundary neighbours are not in A_plane)
+  int nb_col[4];
+  double nb_val[4];
+  int nnb = 0;
+  if (dim == 2) {
+    if (r >= 1) { nb_col[nnb] = r - 1; nb_val[nnb++] = coef[3 * N + node]; }
+    if (r <= n - 2) { nb_col[nnb] = r + 1; nb_val[nnb++] = coef[4 * N + node]; }
+  } else {
+    const int y = r / n, z = r % n;
+    if (y >= 1) { nb_col[nnb] = r - n; nb_val[nnb++] = coef[3 * N + node]; }
+    if (y <= n - 2) { nb_col[nnb] = r + n; nb_val[nnb++] = coef[4 * N + node]; }
+    if (z >= 1) { nb_col[nnb] = r - 1; nb_val[nnb++] = coef[5 * N + node]; }
+    if (z <= n - 2) { nb_col[nnb] = r + 1; nb_val[nnb++] = coef[6 * N + node]; }
+  }
+  const double diag = coef[node];
+  const T *G1 = J.G1 ? static_cast<const T *>(J.G1) + (size_t)r * ld : nullptr;
+  const T *G2 = J.G2 ? static_cast<const T *>(J.G2) + (size_t)r * ld : nullptr;
+  const double s1 = G1 ? J.r1[r] : 0.0;
+  const double s2 = G2 ? J.r2[r] : 0.0;
+  for (int c = threadIdx.x; c < ld; c += blockDim.x) {
+    double v = 0.0;
+    if (c < M) {
+      if (G1) v -= s1 * (double)G1[c] * J.c1[c];
+      if (G2) v -= s2 * (double)G2[c] * J.c2[c];
+      if (c == r) v += diag;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nnb && nb_col[q] == c) v += nb_val[q];
+    }
+    D[c] = (T)v;
+  }
+}
+
+// C = alpha * A * diag(s), one block per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_cols(const GemmJob *__restrict__ jobs, int ld,
+                                                    T alpha) {
+  const GemmJob J = jobs[blockIdx.y];
+  const int r = blockIdx.x;
+  const T *A = static_cast<const T *>(J.A) + (size_t)r * ld;
+  T *C = static_cast<T *>(J.C) + (size_t)r * ld;
+  for (int c = threadIdx.x; c < ld; c += blockDim.x)
+    C[c] = alpha * A[c] * (T)J.bscale[c];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_assemble(const AsmJob *jobs, int njobs, const double *coef, int n, int dim,
+                     int M, int ld, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_assemble<T>, dim3(ld, njobs), dim3(256), 0, s, jobs, coef, n, dim, M,
+                     ld);
+}
+
+template <typename T>
+void launch_scale_cols(const GemmJob *jobs, int njobs, int ld, double alpha, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_scale_cols<T>, dim3(ld, njobs), dim3(256), 0, s, jobs, ld, (T)alpha);
+}
+
+template <typename T>
+void launch_gemm(const GemmJob *jobs, int njobs, int ld, double alpha, double beta,
+                 hipStream_t s) {
+  if (njobs <= 0) return;
+  const int tpm = (ld / kTile) * (ld / kTile);
+  hipLaunchKernelGGL(k_gemm<T>, dim3(tpm * njobs), dim3(256), 0, s, jobs, ld, tpm, (T)alpha,
+                     (T)beta);
+}
+
+template <typename T>
+void gj_invert(void *const *mats, int nmat, int ld, T *Rbuf, T *Cbuf, int *flag,
+               hipStream_t s) {
+  if (nmat <= 0) return;
+  const int nblk = ld / kNB;
+  const int tpm = (ld / kTile) * (ld / kTile);
+  for (int p = 0; p < nblk; ++p) {
+    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nblk, nmat), dim3(256), 0, s, mats, Rbuf, Cbuf,
+                       ld, p, flag);
+    hipLaunchKernelGGL(k_gj_update<T>, dim3(tpm * nmat), dim3(256), 0, s, mats, Rbuf, Cbuf,
+                       ld, p, tpm);
+  }
+}
+
+#define DDST_INST(T)                                                                      \
+  template void launch_assemble<T>(const AsmJob *, int, const double *, int, int, int, int, \
+                                   hipStream_t);                                           \
+  template void launch_scale_cols<T>(const GemmJob *, int, int, double, hipStream_t);       \
+  template void launch_gemm<T>(const GemmJob *, int, int, double, double, hipStream_t);     \
+  template void gj_invert<T>(void *const *, int, int, T *, T *, int *, hipStream_t);
+DDST_INST(float)
+DDST_INST(double)
+#undef DDST_INST
+
+}  // namespace ddst
+
+namespace ddst {
+namespace {
+template <typename T>
+__global__ void k_extract(const T *__restrict__ src, int M, int ld, double *__restrict__ dst) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)M * M) return;
+  const size_t r = e / M, c = e % M;
+  dst[e] = (double)src[r * ld + c];
+}
+}  // namespace
+
+void launch_extract_block(const void *src, int prec, int M, int ld, double *dst,
+                          hipStream_t s) {
+  const size_t len = (size_t)M * M;
+  const unsigned nb = (unsigned)((len + 255) / 256);
+  if (prec == DDST_FP32)
+    hipLaunchKernelGGL(k_extract<float>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float *>(src), M, ld, dst);
+  else
+    hipLaunchKernelGGL(k_extract<double>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const double *>(src), M, ld, dst);
+}
+}  // namespace ddst

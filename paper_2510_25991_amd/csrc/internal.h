@@ -1,0 +1,162 @@
+// Internal declarations shared by the HIP sources of libddst.
+//
+// Data layout on the device (ld = M rounded up to a multiple of 128):
+//  * every dense interface/plane matrix is ld x ld, row-major; rows/columns
+//    >= M are padding: zero coupling, identity on the diagonal, so a padded
+//    matrix inverts to blockdiag(inverse, I) and no kernel needs edge tests;
+//  * volume vectors are padded per node plane: plane i (1..n) occupies
+//    [(i-1)*ld, i*ld), entries >= M are zero;
+//  * interface vectors: interface j (1..N_ds) occupies [(j-1)*ld, j*ld).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ddst.h"
+
+struct ddst_op;
+
+namespace ddst {
+
+constexpr int kTile = 128;   // GEMM / update output tile (rows and cols)
+constexpr int kNB = 64;      // Gauss-Jordan block width
+constexpr int kGemvChunk = 32;  // rows per partial sum in the transposed GEMV
+
+// Stencil coefficient slots: coef[slot * N + node], node = interior C-order.
+// slot 0: diagonal; slot 1+2a: neighbour p - e_a; slot 2+2a: neighbour p + e_a.
+inline int coef_slots(int dim) { return 2 * dim + 1; }
+
+// One batched plane-block assembly:
+//   D = A_plane - diag(r1) G1 diag(c1) - diag(r2) G2 diag(c2)
+// (G1 / G2 may be null).  A_plane is the in-plane FD operator of node plane
+// `plane` (1-based); padding rows/cols are set to the identity.
+struct AsmJob {
+  void *D;
+  const void *G1;
+  const double *r1, *c1;
+  const void *G2;
+  const double *r2, *c2;
+  int plane;
+  int pad_;
+};
+
+// One batched GEMM job: C = alpha * A * diag(bscale) * B + beta * C
+// (all ld x ld; bscale may be null).
+struct GemmJob {
+  const void *A;
+  const void *B;
+  void *C;
+  const double *bscale;
+};
+
+// One batched GEMV job (vectors float64, matrix type T):
+//   out = w + alpha * ( op(G) (x1 - e .* x2) + op(G2) x3 )
+// any of x1, e/x2, w, G2/x3 may be null (treated as zero); G may be null
+// (then only the G2 term contributes).
+struct GemvJob {
+  const void *G;
+  const double *x1;
+  const double *e;
+  const double *x2;
+  const void *G2;
+  const double *x3;
+  const double *w;
+  double *out;
+};
+
+// ---- dense kernels (dense.hip) -------------------------------------------
+template <typename T>
+void launch_assemble(const AsmJob *jobs, int njobs, const double *coef, int n, int dim,
+                     int M, int ld, hipStream_t s);
+template <typename T>
+void launch_scale_cols(const GemmJob *jobs, int njobs, int ld, double alpha, hipStream_t s);
+template <typename T>
+void launch_gemm(const GemmJob *jobs, int njobs, int ld, double alpha, double beta,
+                 hipStream_t s);
+// In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices.
+// Rbuf: nmat*kNB*ld, Cbuf: nmat*ld*kNB workspace of T; flag: device int set
+// to 1 when a pivot is non-positive or non-finite.
+template <typename T>
+void gj_invert(void *const *mats, int nmat, int ld, T *Rbuf, T *Cbuf, int *flag,
+               hipStream_t s);
+
+// ---- vector kernels (vec.hip) --------------------------------------------
+void launch_setup_coef(const double *kappa, const double *c, const double *bvec3,
+                       int dim, int n, double h, double *coef, int *bad, hipStream_t s);
+void launch_fill_couplings(const double *coef, int dim, int n, int M, int ld,
+                           double *Em, double *Ep, hipStream_t s);
+// r = f - A_full(x; g)  (transpose: r = f - A^T x with x = 0 on the boundary,
+// g ignored).  x, r padded volumes; f unpadded n^d (nullable); g box (nullable).
+void launch_residual(const double *coef, int dim, int n, int M, int ld, const double *f,
+                     const double *g, const double *x, double *r, int transpose,
+                     hipStream_t s);
+void launch_pad(const double *src, double *dst, int rows, int M, int ld, hipStream_t s);
+void launch_unpad(const double *src, double *dst, int rows, int M, int ld, hipStream_t s);
+template <typename T>
+void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, double alpha,
+                 double *partial, hipStream_t s);
+// out_j = x_j - ... elementwise helpers for the interface right-hand sides:
+//   out[j] = v[plane_j] - a[j] .* Z[plane_j - 1] - b[j] .* Z[plane_j + 1]
+void launch_interface_rhs(const double *vol, const double *Z, const double *Ea,
+                          const double *Eb, int n_ds, int m, int ld, int a_off, int b_off,
+                          double *out, hipStream_t s);
+void launch_copy_planes(const double *src, int src_stride, int src_off, double *dst,
+                        int dst_stride, int dst_off, int count, int ld, int M,
+                        hipStream_t s);
+void launch_axpy(double *y, const double *x, double a, size_t len, hipStream_t s);
+void launch_fill(double *y, double v, size_t len, hipStream_t s);
+void launch_dots(const double *V, size_t stride, int nvec, const double *w, size_t len,
+                 double *out, hipStream_t s);
+void launch_mgs_update(double *w, const double *V, size_t stride, int nvec,
+                       const double *h, double sign, size_t len, hipStream_t s);
+void launch_norm(const double *w, size_t len, double *out, hipStream_t s);
+void launch_scale_by_inv(double *dst, const double *src, const double *nrm, size_t len,
+                         hipStream_t s);
+void launch_cell_gradient(const double *u, const double *lam, const double *g, int dim,
+                          int n, int M, int ld, double h, double *grad, hipStream_t s);
+void launch_check_finite(const double *x, size_t len, double lo_exclusive, int *bad,
+                         hipStream_t s);
+// dst (M x M float64, row-major) = src (ld x ld of the operator precision)
+void launch_extract_block(const void *src, int prec, int M, int ld, double *dst,
+                          hipStream_t s);
+
+// ---- compressed form (hodlr.hip) -----------------------------------------
+void hodlr_free(ddst_op *op);
+bool hodlr_ready(const ddst_op *op);
+int hodlr_compress(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t s);
+// y = S x or S^T x through the compressed blocks (padded interface vectors)
+int hodlr_apply_jobs(const ddst_op *op, const double *x, double *y, int transpose,
+                     hipStream_t s);
+
+}  // namespace ddst
+
+// The operator object behind the opaque C handle.
+struct ddst_op {
+  int dim = 0, n = 0, n_slabs = 0, m = 0, M = 0, ld = 0, n_ds = 0, prec = 0;
+  double h = 0;
+  double bvec[3] = {0, 0, 0};
+  size_t N = 0;          // n^dim
+  size_t mat_bytes = 0;  // ld*ld*sizeof(T)
+  // persistent device storage
+  void *arena = nullptr;      // one allocation for everything below
+  double *kappa = nullptr;    // (n+1)^dim copy (or null)
+  double *c = nullptr;        // n^dim copy (or null)
+  double *coef = nullptr;     // (2 dim + 1) * N stencil coefficients
+  double *Em = nullptr;       // (n+2) * ld coupling to plane i-1
+  double *Ep = nullptr;       // (n+2) * ld coupling to plane i+1
+  void *Sinv = nullptr;       // n_ds matrices: inverse interface Schur blocks
+  void *S = nullptr;          // 2 n_ds matrices: S_{j,j-1}, S_{j,j+1}
+  void *G = nullptr;          // n_slabs*(m-1) factor matrices (own allocation)
+  int *flag = nullptr;        // device breakdown flag
+  // compressed form (hodlr.hip)
+  struct Hodlr *hodlr = nullptr;
+  // reusable solve workspace (grown on demand)
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  double *hbuf_host = nullptr;  // pinned host staging for GMRES scalars
+  ddst_stats_t last_build{};
+};

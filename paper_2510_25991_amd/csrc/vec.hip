@@ -1,0 +1,537 @@
+// Memory-bound kernels of libddst: stencil set-up and FP64 residual, batched
+// dense matrix-vector products (slab sweeps, interface blocks), interface
+// right-hand sides, Krylov helpers and the cellwise gradient.
+//
+// The stencil follows the FD model problem: on every grid edge the
+// coefficient is the mean of the 2^(dim-1) cells sharing the edge,
+// convection uses centred differences, and boundary neighbours carry g.
+#include "internal.h"
+
+namespace ddst {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block-wide sum of 256 threads; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double kappa_at(const double *kappa, int dim, int n, int c0, int c1,
+                                           int c2) {
+  if (!kappa) return 1.0;
+  const size_t nc = (size_t)n + 1;
+  if (dim == 2) return kappa[(size_t)c0 * nc + c1];
+  return kappa[((size_t)c0 * nc + c1) * nc + c2];
+}
+
+// Mean coefficient of the edge from node p to p + e_axis (p 1-based).
+__device__ double edge_coef(const double *kappa, int dim, int n, const int *p, int axis) {
+  if (!kappa) return 1.0;
+  int base[3] = {p[0] - 1, p[1] - 1, dim == 3 ? p[2] - 1 : 0};
+  base[axis] = p[axis];  // cell index along the edge axis = node index of the lower end
+  double s = 0.0;
+  if (dim == 2) {
+    const int o = 1 - axis;  // the other axis
+    for (int t = 0; t < 2; ++t) {
+      int c[2] = {base[0], base[1]};
+      c[o] += t;
+      s += kappa_at(kappa, 2, n, c[0], c[1], 0);
+    }
+    return 0.5 * s;
+  }
+  int oa = (axis == 0) ? 1 : 0, ob = (axis == 2) ? 1 : 2;
+  for (int t = 0; t < 4; ++t) {
+    int c[3] = {base[0], base[1], base[2]};
+    c[oa] += t & 1;
+    c[ob] += t >> 1;
+    s += kappa_at(kappa, 3, n, c[0], c[1], c[2]);
+  }
+  return 0.25 * s;
+}
+
+__global__ void k_setup_coef(const double *__restrict__ kappa, const double *__restrict__ cz,
+                             double b0, double b1, double b2, int dim, int n, double h,
+                             double *__restrict__ coef) {
+  const size_t N = (dim == 2) ? (size_t)n * n : (size_t)n * n * n;
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  int p[3];
+  if (dim == 2) {
+    p[0] = (int)(node / n) + 1;
+    p[1] = (int)(node % n) + 1;
+    p[2] = 0;
+  } else {
+    p[0] = (int)(node / ((size_t)n * n)) + 1;
+    p[1] = (int)((node / n) % n) + 1;
+    p[2] = (int)(node % n) + 1;
+  }
+  const double ih2 = 1.0 / (h * h), i2h = 0.5 / h;
+  const double b[3] = {b0, b1, b2};
+  double diag = cz ? cz[node] : 0.0;
+  for (int a = 0; a < dim; ++a) {
+    const double kp = edge_coef(kappa, dim, n, p, a) * ih2;
+    int q[3] = {p[0], p[1], p[2]};
+    q[a] -= 1;
+    const double km = edge_coef(kappa, dim, n, q, a) * ih2;
+    diag += kp + km;
+    coef[(size_t)(1 + 2 * a) * N + node] = -km - b[a] * i2h;
+    coef[(size_t)(2 + 2 * a) * N + node] = -kp + b[a] * i2h;
+  }
+  coef[node] = diag;
+}
+
+// Em[i][r] = coupling of plane i to plane i-1, Ep[i][r] = to plane i+1
+// (rows 0 and n+1 and the padding stay zero).
+__global__ void k_fill_couplings(const double *__restrict__ coef, int n, int M, int ld,
+                                 size_t N, double *__restrict__ Em, double *__restrict__ Ep) {
+  const int i = blockIdx.y;  // plane 0..n+1
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += gridDim.x * blockDim.x) {
+    double em = 0.0, ep = 0.0;
+    if (i >= 1 && i <= n && r < M) {
+      const size_t node = (size_t)(i - 1) * M + r;
+      em = coef[1 * N + node];
+      ep = coef[2 * N + node];
+    }
+    Em[(size_t)i * ld + r] = em;
+    Ep[(size_t)i * ld + r] = ep;
+  }
+}
+
+// Residual r = f - A_full(x; g) (or f - A^T x), padded volume layout.
+__global__ void k_residual(const double *__restrict__ coef, int dim, int n, int M, int ld,
+                           const double *__restrict__ f, const double *__restrict__ g,
+                           const double *__restrict__ x, double *__restrict__ r,
+                           int transpose) {
+  const size_t N = (size_t)M * n;
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int i = (int)(node / M);  // 0-based plane
+  const int ip = (int)(node % M);
+  int p[3];
+  p[0] = i + 1;
+  if (dim == 2) {
+    p[1] = ip + 1;
+    p[2] = 0;
+  } else {
+    p[1] = ip / n + 1;
+    p[2] = ip % n + 1;
+  }
+  const size_t nb = (size_t)n + 2;
+  double acc = coef[node] * x[(size_t)i * ld + ip];
+  for (int a = 0; a < dim; ++a) {
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      int q[3] = {p[0], p[1], p[2]};
+      q[a] += sgn;
+      const bool inside = q[a] >= 1 && q[a] <= n;
+      const int slot = (sgn < 0) ? 1 + 2 * a : 2 + 2 * a;
+      if (inside) {
+        const size_t qi = (size_t)(q[0] - 1);
+        const size_t qip = (dim == 2) ? (size_t)(q[1] - 1)
+                                      : (size_t)(q[1] - 1) * n + (size_t)(q[2] - 1);
+        const size_t qnode = qi * M + qip;
+        const double xv = x[qi * ld + qip];
+        // A^T_{p,q} = A_{q,p}: the opposite slot of node q
+        const int oslot = (sgn < 0) ? 2 + 2 * a : 1 + 2 * a;
+        acc += (transpose ? coef[(size_t)oslot * N + qnode] : coef[(size_t)slot * N + node]) * xv;
+      } else if (!transpose && g) {
+        const size_t bidx = (dim == 2) ? (size_t)q[0] * nb + q[1]
+                                       : ((size_t)q[0] * nb + q[1]) * nb + q[2];
+        acc += coef[(size_t)slot * N + node] * g[bidx];
+      }
+    }
+  }
+  const double fv = f ? f[node] : 0.0;
+  r[(size_t)i * ld + ip] = fv - acc;
+}
+
+__global__ void k_pad(const double *__restrict__ src, double *__restrict__ dst, int rows, int M,
+                      int ld) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rows * ld) return;
+  const size_t row = e / ld, c = e % ld;
+  dst[e] = (c < (size_t)M) ? src[row * M + c] : 0.0;
+}
+
+__global__ void k_unpad(const double *__restrict__ src, double *__restrict__ dst, int rows,
+                        int M, int ld) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rows * M) return;
+  const size_t row = e / M, c = e % M;
+  dst[e] = src[row * ld + c];
+}
+
+constexpr int kGemvRowsPerWave = 4;
+constexpr int kGemvCh = 1024;
+
+template <typename T>
+__device__ __forceinline__ void ld4(const T *p, double *o);
+template <>
+__device__ __forceinline__ void ld4<float>(const float *p, double *o) {
+  float4 v = *reinterpret_cast<const float4 *>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void ld4<double>(const double *p, double *o) {
+  double2 a = reinterpret_cast<const double2 *>(p)[0];
+  double2 b = reinterpret_cast<const double2 *>(p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+
+// out[r] = w[r] + alpha * (G[r,:] (x1 - e.*x2) + G2[r,:] x3); 16 rows per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *__restrict__ jobs, int ld,
+                                                double alpha) {
+  __shared__ double xs[kGemvCh];
+  __shared__ double x3s[kGemvCh];
+  const GemvJob J = jobs[blockIdx.y];
+  const T *G = static_cast<const T *>(J.G);
+  const T *G2 = static_cast<const T *>(J.G2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.x * (4 * kGemvRowsPerWave) + wave * kGemvRowsPerWave;
+  double acc[kGemvRowsPerWave];
+#pragma unroll
+  for (int q = 0; q < kGemvRowsPerWave; ++q) acc[q] = 0.0;
+  for (int c0 = 0; c0 < ld; c0 += kGemvCh) {
+    const int cn = min(kGemvCh, ld - c0);
+    __syncthreads();
+    for (int c = threadIdx.x; c < cn; c += 256) {
+      double v = J.x1 ? J.x1[c0 + c] : 0.0;
+      if (J.e) v -= J.e[c0 + c] * J.x2[c0 + c];
+      xs[c] = v;
+      x3s[c] = (G2 && J.x3) ? J.x3[c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kGemvRowsPerWave; ++q) {
+      const size_t ro = (size_t)(row0 + q) * ld + c0;
+      double s = 0.0;
+      for (int c = lane * 4; c < cn; c += 256) {
+        double gv[4];
+        if (G) {
+          ld4<T>(G + ro + c, gv);
+          s += gv[0] * xs[c] + gv[1] * xs[c + 1] + gv[2] * xs[c + 2] + gv[3] * xs[c + 3];
+        }
+        if (G2) {
+          ld4<T>(G2 + ro + c, gv);
+          s += gv[0] * x3s[c] + gv[1] * x3s[c + 1] + gv[2] * x3s[c + 2] + gv[3] * x3s[c + 3];
+        }
+      }
+      acc[q] += s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kGemvRowsPerWave; ++q) {
+    const double s = wave_sum(acc[q]);
+    if (lane == 0) {
+      const int r = row0 + q;
+      J.out[r] = (J.w ? J.w[r] : 0.0) + alpha * s;
+    }
+  }
+}
+
+// Transposed product, partial sums over row chunks:
+// part[(job*nchunk + chunk)*ld + c] = sum_{r in chunk} G[r,c] xe[r] + G2[r,c] x3[r]
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_t_part(const GemvJob *__restrict__ jobs, int ld,
+                                                     int rows_per_chunk,
+                                                     double *__restrict__ part) {
+  extern __shared__ double sh[];
+  double *xs = sh;
+  double *x3s = sh + rows_per_chunk;
+  const int chunk = blockIdx.x, job = blockIdx.y, nchunk = gridDim.x;
+  const GemvJob J = jobs[job];
+  const T *G = static_cast<const T *>(J.G);
+  const T *G2 = static_cast<const T *>(J.G2);
+  const int r0 = chunk * rows_per_chunk;
+  for (int r = threadIdx.x; r < rows_per_chunk; r += 256) {
+    double v = J.x1 ? J.x1[r0 + r] : 0.0;
+    if (J.e) v -= J.e[r0 + r] * J.x2[r0 + r];
+    xs[r] = v;
+    x3s[r] = (G2 && J.x3) ? J.x3[r0 + r] : 0.0;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x * 4; c < ld; c += 1024) {
+    double s[4] = {0, 0, 0, 0};
+    for (int r = 0; r < rows_per_chunk; ++r) {
+      double gv[4];
+      const size_t o = (size_t)(r0 + r) * ld + c;
+      if (G) {
+        ld4<T>(G + o, gv);
+        const double xv = xs[r];
+        s[0] += gv[0] * xv; s[1] += gv[1] * xv; s[2] += gv[2] * xv; s[3] += gv[3] * xv;
+      }
+      if (G2) {
+        ld4<T>(G2 + o, gv);
+        const double xv = x3s[r];
+        s[0] += gv[0] * xv; s[1] += gv[1] * xv; s[2] += gv[2] * xv; s[3] += gv[3] * xv;
+      }
+    }
+    double *po = part + ((size_t)job * nchunk + chunk) * ld + c;
+    po[0] = s[0]; po[1] = s[1]; po[2] = s[2]; po[3] = s[3];
+  }
+}
+
+__global__ void k_gemv_t_reduce(const GemvJob *__restrict__ jobs, int ld, int nchunk,
+                                const double *__restrict__ part, double alpha) {
+  const int job = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ld) return;
+  const GemvJob J = jobs[job];
+  double s = 0.0;
+  for (int k = 0; k < nchunk; ++k) s += part[((size_t)job * nchunk + k) * ld + c];
+  J.out[c] = (J.w ? J.w[c] : 0.0) + alpha * s;
+}
+
+__global__ void k_interface_rhs(const double *__restrict__ vol, const double *__restrict__ Z,
+                                const double *__restrict__ Ea, const double *__restrict__ Eb,
+                                int n_ds, int m, int ld, int a_off, int b_off,
+                                double *__restrict__ out) {
+  const int j = blockIdx.y + 1;  // interface 1..n_ds
+  const int pl = j * m;          // node plane (1-based)
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += gridDim.x * blockDim.x) {
+    const double v = vol[(size_t)(pl - 1) * ld + r] -
+                     Ea[(size_t)(pl + a_off) * ld + r] * Z[(size_t)(pl - 2) * ld + r] -
+                     Eb[(size_t)(pl + b_off) * ld + r] * Z[(size_t)pl * ld + r];
+    out[(size_t)(j - 1) * ld + r] = v;
+  }
+}
+
+__global__ void k_copy_planes(const double *__restrict__ src, int src_stride, int src_off,
+                              double *__restrict__ dst, int dst_stride, int dst_off, int ld,
+                              int M) {
+  const int k = blockIdx.y;
+  const double *s = src + (size_t)(src_off + (size_t)k * src_stride) * ld;
+  double *d = dst + (size_t)(dst_off + (size_t)k * dst_stride) * ld;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += gridDim.x * blockDim.x)
+    d[r] = (r < M) ? s[r] : 0.0;
+}
+
+__global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, double a,
+                       size_t len) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) y[e] += a * x[e];
+}
+
+__global__ void k_fill(double *__restrict__ y, double v, size_t len) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) y[e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_dots(const double *__restrict__ V, size_t stride,
+                                              const double *__restrict__ w, size_t len,
+                                              double *__restrict__ out) {
+  __shared__ double sh[4];
+  const double *v = V + (size_t)blockIdx.x * stride;
+  double s = 0.0;
+  for (size_t e = threadIdx.x; e < len; e += 256) s += v[e] * w[e];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ void k_mgs_update(double *__restrict__ w, const double *__restrict__ V, size_t stride,
+                             int nvec, const double *__restrict__ h, double sign, size_t len) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double s = 0.0;
+  for (int i = 0; i < nvec; ++i) s += V[(size_t)i * stride + e] * h[i];
+  w[e] += sign * s;
+}
+
+__global__ __launch_bounds__(1024) void k_norm(const double *__restrict__ w, size_t len,
+                                               double *__restrict__ out) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (size_t e = threadIdx.x; e < len; e += blockDim.x) s += w[e] * w[e];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+__global__ void k_scale_by_inv(double *__restrict__ dst, const double *__restrict__ src,
+                               const double *__restrict__ nrm, size_t len) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) {
+    const double d = nrm[0];
+    dst[e] = (d > 0.0) ? src[e] / d : 0.0;
+  }
+}
+
+// dL/dkappa on cells: -1/(2^(d-1) h^2) sum_edges (lam_p - lam_q)(u_p - u_q).
+__global__ void k_cell_gradient(const double *__restrict__ u, const double *__restrict__ lam,
+                                const double *__restrict__ g, int dim, int n, int M, int ld,
+                                double h, double *__restrict__ grad) {
+  const size_t nc = (size_t)n + 1;
+  const size_t ncell = (dim == 2) ? nc * nc : nc * nc * nc;
+  const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  int c[3];
+  if (dim == 2) {
+    c[0] = (int)(cell / nc); c[1] = (int)(cell % nc); c[2] = 0;
+  } else {
+    c[0] = (int)(cell / (nc * nc)); c[1] = (int)((cell / nc) % nc); c[2] = (int)(cell % nc);
+  }
+  const size_t nb = (size_t)n + 2;
+  // corner values of the cell: node c + o, o in {0,1}^dim
+  double U[8], L[8];
+  const int ncorner = 1 << dim;
+  for (int o = 0; o < ncorner; ++o) {
+    int q[3] = {c[0] + (o & 1), c[1] + ((o >> 1) & 1), dim == 3 ? c[2] + ((o >> 2) & 1) : 0};
+    bool inside = true;
+    for (int a = 0; a < dim; ++a) inside = inside && q[a] >= 1 && q[a] <= n;
+    if (inside) {
+      const size_t ip = (dim == 2) ? (size_t)(q[1] - 1) : (size_t)(q[1] - 1) * n + (q[2] - 1);
+      U[o] = u[(size_t)(q[0] - 1) * M + ip];
+      L[o] = lam[(size_t)(q[0] - 1) * ld + ip];
+    } else {
+      const size_t bidx = (dim == 2) ? (size_t)q[0] * nb + q[1]
+                                     : ((size_t)q[0] * nb + q[1]) * nb + q[2];
+      U[o] = g ? g[bidx] : 0.0;
+      L[o] = 0.0;
+    }
+  }
+  double s = 0.0;
+  for (int o = 0; o < ncorner; ++o)
+    for (int a = 0; a < dim; ++a)
+      if (!((o >> a) & 1)) {
+        const int o2 = o | (1 << a);
+        s += (L[o] - L[o2]) * (U[o] - U[o2]);
+      }
+  grad[cell] = -s / ((double)(1 << (dim - 1)) * h * h);
+}
+
+__global__ void k_check_finite(const double *__restrict__ x, size_t len, double lo, int *bad) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) {
+    const double v = x[e];
+    if (!isfinite(v) || !(v > lo)) atomicOr(bad, 1);
+  }
+}
+
+inline unsigned nblk(size_t len, unsigned b = 256) { return (unsigned)((len + b - 1) / b); }
+
+}  // namespace
+
+void launch_setup_coef(const double *kappa, const double *c, const double *b, int dim, int n,
+                       double h, double *coef, int *, hipStream_t s) {
+  const size_t N = (dim == 2) ? (size_t)n * n : (size_t)n * n * n;
+  hipLaunchKernelGGL(k_setup_coef, dim3(nblk(N)), dim3(256), 0, s, kappa, c, b[0], b[1], b[2],
+                     dim, n, h, coef);
+}
+
+void launch_fill_couplings(const double *coef, int dim, int n, int M, int ld, double *Em,
+                           double *Ep, hipStream_t s) {
+  const size_t N = (size_t)M * n;
+  hipLaunchKernelGGL(k_fill_couplings, dim3(nblk(ld), n + 2), dim3(256), 0, s, coef, n, M, ld,
+                     N, Em, Ep);
+  (void)dim;
+}
+
+void launch_residual(const double *coef, int dim, int n, int M, int ld, const double *f,
+                     const double *g, const double *x, double *r, int transpose,
+                     hipStream_t s) {
+  const size_t N = (size_t)M * n;
+  hipLaunchKernelGGL(k_residual, dim3(nblk(N)), dim3(256), 0, s, coef, dim, n, M, ld, f, g, x,
+                     r, transpose);
+}
+
+void launch_pad(const double *src, double *dst, int rows, int M, int ld, hipStream_t s) {
+  hipLaunchKernelGGL(k_pad, dim3(nblk((size_t)rows * ld)), dim3(256), 0, s, src, dst, rows, M,
+                     ld);
+}
+
+void launch_unpad(const double *src, double *dst, int rows, int M, int ld, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpad, dim3(nblk((size_t)rows * M)), dim3(256), 0, s, src, dst, rows, M,
+                     ld);
+}
+
+template <typename T>
+void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, double alpha,
+                 double *partial, hipStream_t s) {
+  (void)M;
+  if (njobs <= 0) return;
+  if (!transpose) {
+    hipLaunchKernelGGL(k_gemv_n<T>, dim3(ld / (4 * kGemvRowsPerWave), njobs), dim3(256), 0, s,
+                       jobs, ld, alpha);
+  } else {
+    const int nchunk = (ld / kGemvChunk <= 64) ? ld / kGemvChunk : 64;
+    const int rpc = ld / nchunk;
+    hipLaunchKernelGGL(k_gemv_t_part<T>, dim3(nchunk, njobs), dim3(256),
+                       2 * rpc * sizeof(double), s, jobs, ld, rpc, partial);
+    hipLaunchKernelGGL(k_gemv_t_reduce, dim3(nblk(ld), njobs), dim3(256), 0, s, jobs, ld,
+                       nchunk, partial, alpha);
+  }
+}
+template void launch_gemv<float>(const GemvJob *, int, int, int, int, double, double *,
+                                 hipStream_t);
+template void launch_gemv<double>(const GemvJob *, int, int, int, int, double, double *,
+                                  hipStream_t);
+
+void launch_interface_rhs(const double *vol, const double *Z, const double *Ea,
+                          const double *Eb, int n_ds, int m, int ld, int a_off, int b_off,
+                          double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_interface_rhs, dim3(nblk(ld), n_ds), dim3(256), 0, s, vol, Z, Ea, Eb,
+                     n_ds, m, ld, a_off, b_off, out);
+}
+
+void launch_copy_planes(const double *src, int src_stride, int src_off, double *dst,
+                        int dst_stride, int dst_off, int count, int ld, int M, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_copy_planes, dim3(nblk(ld), count), dim3(256), 0, s, src, src_stride,
+                     src_off, dst, dst_stride, dst_off, ld, M);
+}
+
+void launch_axpy(double *y, const double *x, double a, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(nblk(len)), dim3(256), 0, s, y, x, a, len);
+}
+
+void launch_fill(double *y, double v, size_t len, hipStream_t s) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(nblk(len)), dim3(256), 0, s, y, v, len);
+}
+
+void launch_dots(const double *V, size_t stride, int nvec, const double *w, size_t len,
+                 double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(256), 0, s, V, stride, w, len, out);
+}
+
+void launch_mgs_update(double *w, const double *V, size_t stride, int nvec, const double *h,
+                       double sign, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_mgs_update, dim3(nblk(len)), dim3(256), 0, s, w, V, stride, nvec, h,
+                     sign, len);
+}
+
+void launch_norm(const double *w, size_t len, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm, dim3(1), dim3(1024), 0, s, w, len, out);
+}
+
+void launch_scale_by_inv(double *dst, const double *src, const double *nrm, size_t len,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_by_inv, dim3(nblk(len)), dim3(256), 0, s, dst, src, nrm, len);
+}
+
+void launch_cell_gradient(const double *u, const double *lam, const double *g, int dim, int n,
+                          int M, int ld, double h, double *grad, hipStream_t s) {
+  const size_t nc = (size_t)n + 1;
+  const size_t ncell = (dim == 2) ? nc * nc : nc * nc * nc;
+  hipLaunchKernelGGL(k_cell_gradient, dim3(nblk(ncell)), dim3(256), 0, s, u, lam, g, dim, n, M,
+                     ld, h, grad);
+}
+
+void launch_check_finite(const double *x, size_t len, double lo, int *bad, hipStream_t s) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_check_finite, dim3(nblk(len)), dim3(256), 0, s, x, len, lo, bad);
+}
+
+}  // namespace ddst

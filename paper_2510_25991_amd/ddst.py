@@ -1,0 +1,284 @@
+"""ctypes binding of libddst (argument marshalling only).
+
+Every step of the method runs in the HIP library; this module only passes
+device pointers of torch tensors, sizes and the current HIP stream.  It
+fails loudly when the library is not built or no GPU is present -- there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libddst.so")
+
+DDST_OK, DDST_ENOTCONV = 0, 1
+DDST_EINVAL, DDST_ENOMEM, DDST_EHIP, DDST_EBREAKDOWN, DDST_ERANK, DDST_ESTATE = -1, -2, -3, -4, -5, -6
+FP64, FP32 = 0, 1
+TREE_BINARY, TREE_QUAD = 0, 1
+FACTOR_BF16, FACTOR_FP32, FACTOR_FP64 = 0, 1, 2
+APPLY_DENSE, APPLY_HODLR = 0, 1
+
+
+class DDSTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ddst error {code}: {msg}")
+        self.code = code
+
+
+class ProblemC(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("n_slabs", ctypes.c_int32),
+                ("kappa", ctypes.c_void_p), ("bvec", ctypes.c_double * 3),
+                ("c", ctypes.c_void_p)]
+
+
+class BuildOptsC(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("keep_factors", ctypes.c_int32),
+                ("transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CompressOptsC(ctypes.Structure):
+    _fields_ = [("tree", ctypes.c_int32), ("leaf", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("max_rank", ctypes.c_int32),
+                ("factor_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class SolveOptsC(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("use_hodlr", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("gmres_iters", ctypes.c_int32),
+                ("last_gmres_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("gmres_relres", ctypes.c_double), ("residual_rel", ctypes.c_double),
+                ("correction_rel", ctypes.c_double), ("t_build_ms", ctypes.c_double),
+                ("t_compress_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("t_adjoint_ms", ctypes.c_double), ("bytes_factors", ctypes.c_double),
+                ("bytes_transfer", ctypes.c_double), ("bytes_hodlr", ctypes.c_double),
+                ("max_rank", ctypes.c_int32), ("min_rank", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_adjoint",
+           "ddst_release_factors", "ddst_destroy", "ddst_last_error", "ddst_op_info",
+           "ddst_get_transfer", "ddst_apply", "ddst_loads"]
+
+_lib = None
+
+
+def load_library(path: str = _LIB_PATH):
+    """Load libddst.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER
+    L.ddst_build_transfer.argtypes = [P(ProblemC), P(BuildOptsC), vp, P(vp)]
+    L.ddst_compress.argtypes = [vp, P(CompressOptsC), vp]
+    L.ddst_solve.argtypes = [vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
+    L.ddst_adjoint.argtypes = [vp, vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
+    L.ddst_release_factors.argtypes = [vp]
+    L.ddst_destroy.argtypes = [vp]
+    L.ddst_destroy.restype = None
+    L.ddst_last_error.argtypes = []
+    L.ddst_last_error.restype = ctypes.c_char_p
+    L.ddst_op_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+    L.ddst_get_transfer.argtypes = [vp, i32, vp, vp, vp]
+    L.ddst_apply.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.ddst_loads.argtypes = [vp, vp, vp, vp, vp]
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("ddst_destroy", "ddst_last_error"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(code, allow_notconv=False):
+    if code == DDST_OK or (allow_notconv and code == DDST_ENOTCONV):
+        return code
+    raise DDSTError(code, load_library().ddst_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(x, device="cuda"):
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+
+
+@dataclasses.dataclass
+class SolveOptions:
+    tol: float = 1e-10
+    inner_tol: Optional[float] = None      # default: 1e-7 (FP32), 1e-12 (FP64)
+    max_iter: int = 300
+    max_outer: int = 4
+    use_hodlr: bool = False
+
+
+class Operator:
+    """A built equilibrium operator (transfer blocks + slab factors) on the GPU."""
+
+    def __init__(self, dim, n, n_slabs, kappa=None, bvec=(0.0, 0.0, 0.0), c=None,
+                 precision: str = "fp32", keep_factors: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("ddst needs a ROCm GPU; no device is visible")
+        L = load_library()
+        self.dim, self.n, self.n_slabs = int(dim), int(n), int(n_slabs)
+        self.precision = precision
+        self._kappa = _dev(kappa)
+        self._c = _dev(c)
+        b = list(bvec) + [0.0] * 3
+        self._prob = ProblemC(self.dim, self.n, self.n_slabs, _ptr(self._kappa),
+                              (ctypes.c_double * 3)(*[float(v) for v in b[:3]]), _ptr(self._c))
+        opts = BuildOptsC(FP32 if precision == "fp32" else FP64, 1 if keep_factors else 0, 0, 0)
+        h = ctypes.c_void_p()
+        _check(L.ddst_build_transfer(ctypes.byref(self._prob), ctypes.byref(opts), _stream(),
+                                     ctypes.byref(h)))
+        self._h = h
+        M, nds, ld, pr = (ctypes.c_int32() for _ in range(4))
+        _check(L.ddst_op_info(self._h, ctypes.byref(M), ctypes.byref(nds), ctypes.byref(ld),
+                              ctypes.byref(pr)))
+        self.M, self.n_ds, self.ld = M.value, nds.value, ld.value
+
+    @classmethod
+    def from_problem(cls, prob, precision="fp32", keep_factors=True):
+        return cls(prob.dim, prob.n, prob.n_slabs, kappa=prob.kappa, bvec=prob.bvec, c=prob.c,
+                   precision=precision, keep_factors=keep_factors)
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().ddst_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def release_factors(self):
+        _check(load_library().ddst_release_factors(self._h))
+
+    # -- operations --------------------------------------------------------
+    def _solve_opts(self, opts: Optional[SolveOptions]):
+        o = opts or SolveOptions()
+        inner = o.inner_tol if o.inner_tol is not None else (1e-7 if self.precision == "fp32" else 1e-12)
+        return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0, 0)
+
+    def solve(self, f=None, g=None, opts: Optional[SolveOptions] = None, want_gamma=True,
+              allow_notconv=False):
+        """Returns (u_vol (n,)*dim, u_gamma (n_ds, M), stats dict)."""
+        f, g = _dev(f), _dev(g)
+        N = self.n ** self.dim
+        u = torch.empty(N, dtype=torch.float64, device="cuda")
+        ug = torch.empty(self.n_ds * self.M, dtype=torch.float64, device="cuda") if want_gamma else None
+        st = StatsC()
+        o = self._solve_opts(opts)
+        code = load_library().ddst_solve(self._h, _ptr(f), _ptr(g), ctypes.byref(o), _ptr(ug),
+                                         _ptr(u), ctypes.byref(st), _stream())
+        _check(code, allow_notconv)
+        d = st.as_dict()
+        d["status"] = code
+        return (u.view((self.n,) * self.dim),
+                None if ug is None else ug.view(self.n_ds, self.M), d)
+
+    def adjoint(self, u, gbar, g=None, opts: Optional[SolveOptions] = None, want_lambda=False,
+                allow_notconv=False):
+        """dL/dkappa on the (n+1)^dim cells for dL/du = gbar."""
+        u, gbar, g = _dev(u), _dev(gbar), _dev(g)
+        dk = torch.empty((self.n + 1) ** self.dim, dtype=torch.float64, device="cuda")
+        lam = torch.empty(self.n ** self.dim, dtype=torch.float64, device="cuda") if want_lambda else None
+        st = StatsC()
+        o = self._solve_opts(opts)
+        code = load_library().ddst_adjoint(self._h, _ptr(u), _ptr(g), _ptr(gbar), ctypes.byref(o),
+                                           _ptr(dk), _ptr(lam), ctypes.byref(st), _stream())
+        _check(code, allow_notconv)
+        d = st.as_dict()
+        d["status"] = code
+        dk = dk.view((self.n + 1,) * self.dim)
+        if want_lambda:
+            return dk, lam.view((self.n,) * self.dim), d
+        return dk, d
+
+    def transfer(self, j):
+        """(S_{j,j-1}, S_{j,j+1}) as float64 M x M tensors (zeros if absent)."""
+        a = torch.empty(self.M, self.M, dtype=torch.float64, device="cuda")
+        b = torch.empty(self.M, self.M, dtype=torch.float64, device="cuda")
+        _check(load_library().ddst_get_transfer(self._h, int(j), _ptr(a), _ptr(b), _stream()))
+        return a, b
+
+    def apply(self, x, transpose=False, which="dense"):
+        x = _dev(x).reshape(-1)
+        y = torch.empty_like(x)
+        _check(load_library().ddst_apply(self._h, 1 if transpose else 0,
+                                         APPLY_HODLR if which == "hodlr" else APPLY_DENSE,
+                                         _ptr(x), _ptr(y), _stream()))
+        return y.view(self.n_ds, self.M)
+
+    def loads(self, f=None, g=None):
+        f, g = _dev(f), _dev(g)
+        out = torch.empty(self.n_ds * self.M, dtype=torch.float64, device="cuda")
+        _check(load_library().ddst_loads(self._h, _ptr(f), _ptr(g), _ptr(out), _stream()))
+        return out.view(self.n_ds, self.M)
+
+    def compress(self, tol=1e-8, leaf=128, oversample=10, max_rank=128, tree=None,
+                 factor_dtype="bf16", seed=0):
+        tree = (TREE_BINARY if self.dim == 2 else TREE_QUAD) if tree is None else tree
+        fd = {"bf16": FACTOR_BF16, "fp32": FACTOR_FP32, "fp64": FACTOR_FP64}[factor_dtype]
+        o = CompressOptsC(tree, leaf, oversample, max_rank, fd, 0, tol, seed)
+        _check(load_library().ddst_compress(self._h, ctypes.byref(o), _stream()))
+
+
+class DDSTSolve(torch.autograd.Function):
+    """u = A(kappa)^{-1} f through the DD solver; backward by the hand-written
+    adjoint, which recomputes the slab factors (they are dropped after the
+    forward solve to keep memory at the transfer blocks only)."""
+
+    @staticmethod
+    def forward(ctx, kappa, f, n_slabs, bvec, g, precision, opts):
+        dim = kappa.dim()
+        n = kappa.shape[0] - 1
+        op = Operator(dim, n, n_slabs, kappa=kappa.detach(), bvec=bvec, precision=precision)
+        u, _, st = op.solve(f.detach(), g, opts=opts, want_gamma=False)
+        op.release_factors()
+        ctx.op, ctx.g, ctx.opts = op, g, opts
+        ctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(ctx, gbar):
+        (u,) = ctx.saved_tensors
+        dk, _ = ctx.op.adjoint(u, gbar.contiguous(), g=ctx.g, opts=ctx.opts)
+        ctx.op.close()
+        return dk, None, None, None, None, None, None
+
+
+def ddst_solve(kappa, f, n_slabs, bvec=(0.0, 0.0, 0.0), g=None, precision="fp32", opts=None):
+    return DDSTSolve.apply(kappa, f, n_slabs, tuple(bvec), g, precision, opts)

@@ -1,0 +1,266 @@
+"""Parity of the HIP path (through the C-ABI) against the CPU FP64 oracle.
+
+Tolerances (entries of transfer blocks are <= 1 in magnitude; errors are
+measured as max |GPU - oracle| / max |oracle|):
+* FP64 path: transfer blocks and loads 1e-11 -- Gauss-Jordan inversion of the
+  well-conditioned plane blocks (condition number O(10)) loses a few
+  hundred ulps over <= 64 planes;
+* FP32 path: transfer blocks 2e-4 -- the same count in units of 6e-8;
+* refined solutions: 1e-10 (FP64) and 1e-8 (mixed FP32 + FP64 refinement,
+  the accuracy target of the method's mixed-precision form);
+* adjoint gradients: 1e-8 vs the oracle's transposed sparse solve.
+"""
+import numpy as np
+import pytest
+import torch
+
+from problems import Problem, make_config, sensor_nodes, fd_directions
+from oracle import adjoint as oadj
+from oracle import dd as odd
+from oracle import fd as ofd
+
+pytestmark = pytest.mark.gpu
+
+_ORACLES = {}
+
+
+def oracle(name, prob):
+    if name not in _ORACLES:
+        _ORACLES[name] = odd.DDOracle(prob)
+    return _ORACLES[name]
+
+
+def ddst():
+    from paper_2510_25991_amd import ddst as mod
+    return mod
+
+
+CASES = {
+    # name: (problem factory) -- sizes span several 128-tiles and ragged tails
+    "cfg1": lambda: make_config("cfg1", variant=2),                 # 127^2, 8 slabs, M=127
+    "cfg2s": lambda: make_config("cfg2", n=255, n_slabs=8),         # M=255 -> ld 256, m=32
+    "cfg3s": lambda: make_config("cfg3", n=191, n_slabs=4),         # Helmholtz, M=191, m=48
+    "cfg4s": lambda: make_config("cfg4", n=23, n_slabs=4),          # 3D, M=529 -> ld 640, m=6
+    "m2": lambda: make_config("cfg2", n=7, n_slabs=4),              # minimum slab width m=2
+    "two_slabs": lambda: make_config("cfg2", n=15, n_slabs=2),      # one interface, no blocks
+}
+_PROBS = {}
+
+
+def prob(name):
+    if name not in _PROBS:
+        _PROBS[name] = CASES[name]()
+    return _PROBS[name]
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def banner(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
+@pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s", "cfg4s", "m2"])
+def test_transfer_blocks(name, precision, tol):
+    p = prob(name)
+    banner(f"transfer blocks {name} n={p.n} slabs={p.n_slabs} {precision}")
+    op = ddst().Operator.from_problem(p, precision=precision)
+    o = oracle(name, p)
+    blocks = o.all_blocks()
+    scale = max(np.abs(B).max() for B in blocks.values())
+    worst = 0.0
+    for j in range(1, p.n_ds + 1):
+        SL, SR = (t.cpu().numpy() for t in op.transfer(j))
+        refL = blocks.get((j, j - 1), np.zeros_like(SL))
+        refR = blocks.get((j, j + 1), np.zeros_like(SR))
+        worst = max(worst, np.abs(SL - refL).max() / scale, np.abs(SR - refR).max() / scale)
+    print(f"  max rel block error {worst:.3e}")
+    assert worst <= tol
+    op.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
+@pytest.mark.parametrize("name", ["cfg2s", "cfg4s"])
+def test_loads_and_apply(name, precision, tol):
+    p = prob(name)
+    banner(f"loads/apply {name} {precision}")
+    op = ddst().Operator.from_problem(p, precision=precision)
+    o = oracle(name, p)
+    hh = op.loads(p.f).cpu().numpy()
+    ref = o.loads(o.rhs())
+    assert rel(hh, ref) <= tol
+    S = o.assemble_S()
+    x = np.random.default_rng(11).standard_normal(S.shape[0])
+    y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy().ravel()
+    yt = op.apply(torch.tensor(x, device="cuda"), transpose=True).cpu().numpy().ravel()
+    assert rel(y, S @ x) <= tol
+    assert rel(yt, S.T @ x) <= tol
+    op.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+@pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s", "cfg4s", "m2", "two_slabs"])
+def test_solve_matches_global_direct(name, precision, tol):
+    p = prob(name)
+    banner(f"solve {name} {precision}")
+    ref = ofd.solve_global(p)
+    op = ddst().Operator.from_problem(p, precision=precision)
+    u, ug, st = op.solve(p.f, p.g)
+    err = rel(u.cpu().numpy().ravel(), ref)
+    o = oracle(name, p)
+    gerr = rel(ug.cpu().numpy(), o.interface_trace(ref))
+    print(f"  rel err {err:.3e} interface {gerr:.3e} outer {st['outer_iters']} "
+          f"gmres {st['gmres_iters']} resid {st['residual_rel']:.2e}")
+    assert st["converged"] == 1
+    assert err <= tol and gerr <= tol
+    op.close()
+
+
+def test_manufactured_cfg1_test1():
+    p = make_config("cfg1", variant=1)
+    banner("cfg1 manufactured exp(x) sin(y) fp32")
+    op = ddst().Operator.from_problem(p, precision="fp32")
+    u, _, st = op.solve(p.f, p.g)
+    ref = ofd.solve_global(p)
+    assert rel(u.cpu().numpy().ravel(), ref) <= 1e-8
+    xn = np.arange(1, p.n + 1) / (p.n + 1)
+    X, Y = np.meshgrid(xn, xn, indexing="ij")
+    # O(h^2) discretisation error, about 6e-7 at h = 1/128
+    assert np.abs(u.cpu().numpy() - np.exp(X) * np.sin(Y)).max() < 2e-6
+    op.close()
+
+
+def test_zero_rhs_gives_zero():
+    p = prob("cfg2s")
+    banner("zero right-hand side")
+    op = ddst().Operator.from_problem(p, precision="fp32")
+    u, ug, st = op.solve(np.zeros((p.n, p.n)))
+    assert float(u.abs().max()) == 0.0
+    op.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adjoint_matches_oracle(precision):
+    p = make_config("cfg5", n=127, n_slabs=4)
+    banner(f"adjoint cfg5-shape n=127 {precision}")
+    u_ref = ofd.solve_global(p)
+    sens = sensor_nodes(2, p.n, 64, seed=1003)
+    data = np.random.default_rng(1004).standard_normal(64) * 0.01
+    gbar = oadj.sensor_loss_grad(u_ref, sens, data, p.N)
+    gref, lref = oadj.gradient(p, u_ref, gbar)
+    op = ddst().Operator.from_problem(p, precision=precision)
+    u, _, _ = op.solve(p.f)
+    dk, lam, st = op.adjoint(u.reshape(-1), torch.tensor(gbar, device="cuda"), want_lambda=True)
+    print(f"  lambda err {rel(lam.cpu().numpy().ravel(), lref):.3e} "
+          f"grad err {rel(dk.cpu().numpy(), gref):.3e}")
+    assert rel(lam.cpu().numpy().ravel(), lref) <= 1e-8
+    assert rel(dk.cpu().numpy(), gref) <= 1e-8
+    # recomputed factors give the same gradient
+    op.release_factors()
+    dk2, st2 = op.adjoint(u.reshape(-1), torch.tensor(gbar, device="cuda"))
+    assert rel(dk2.cpu().numpy(), gref) <= 1e-8
+    op.close()
+
+
+def test_adjoint_central_differences_gpu():
+    """Central FD of the sensor loss along seeded directions, every solve on
+    the GPU (FP64 path), against the autograd backward."""
+    p = make_config("cfg5", n=63, n_slabs=4)
+    banner("adjoint vs central differences n=63")
+    dd = ddst()
+    sens = torch.tensor(sensor_nodes(2, p.n, 32, seed=1003), device="cuda")
+    kap = torch.tensor(p.kappa, device="cuda", requires_grad=True)
+    f = torch.tensor(p.f, device="cuda")
+    opts = dd.SolveOptions(tol=1e-13, max_outer=3)
+    data = torch.zeros(32, dtype=torch.float64, device="cuda")
+
+    def loss(k):
+        u = dd.ddst_solve(k, f, p.n_slabs, bvec=p.bvec, precision="fp64", opts=opts)
+        return 0.5 * ((u.reshape(-1)[sens] - data) ** 2).sum()
+
+    L = loss(kap)
+    L.backward()
+    grad = kap.grad.detach().cpu().numpy()
+    dirs = fd_directions(p.kappa.shape, 5, seed=1007)
+    eps = 1e-5 * float(np.abs(p.kappa).max())
+    with torch.no_grad():
+        for v in dirs:
+            vt = torch.tensor(v, device="cuda")
+            lp = float(loss(kap.detach() + eps * vt))
+            lm = float(loss(kap.detach() - eps * vt))
+            fdv = (lp - lm) / (2 * eps)
+            ad = float(np.sum(grad * v))
+            assert abs(fdv - ad) <= 1e-5 * abs(ad), (fdv, ad)
+
+
+def test_errors_are_reported():
+    dd = ddst()
+    banner("error paths")
+    with pytest.raises(dd.DDSTError) as e:
+        dd.Operator(2, 16, 4)  # (n+1) % n_slabs != 0
+    assert e.value.code == dd.DDST_EINVAL
+    k = np.ones((16, 16))
+    k[3, 4] = 0.0
+    with pytest.raises(dd.DDSTError) as e:
+        dd.Operator(2, 15, 4, kappa=k)
+    assert e.value.code == dd.DDST_EINVAL
+    c = np.zeros((15, 15))
+    c[2, 2] = np.nan
+    with pytest.raises(dd.DDSTError) as e:
+        dd.Operator(2, 15, 4, c=c)
+    assert e.value.code == dd.DDST_EINVAL
+    # a zeroth-order term far beyond the local spectrum makes the plane blocks
+    # indefinite: the first pivot is negative
+    with pytest.raises(dd.DDSTError) as e:
+        dd.Operator(2, 31, 2, c=-20000.0 * np.ones((31, 31)))
+    assert e.value.code == dd.DDST_EBREAKDOWN
+    # too few GMRES iterations: outputs written, status ENOTCONV
+    p = prob("cfg2s")
+    op = dd.Operator.from_problem(p, precision="fp64")
+    u, _, st = op.solve(p.f, opts=dd.SolveOptions(max_iter=2, max_outer=1), allow_notconv=True)
+    assert st["status"] == dd.DDST_ENOTCONV and bool(torch.isfinite(u).all())
+    op.release_factors()
+    with pytest.raises(dd.DDSTError) as e:
+        op.solve(p.f)
+    assert e.value.code == dd.DDST_ESTATE
+    op.close()
+
+
+def test_build_is_deterministic():
+    p = prob("cfg2s")
+    banner("determinism of the batched build")
+    dd = ddst()
+    a = dd.Operator.from_problem(p, precision="fp32")
+    b = dd.Operator.from_problem(p, precision="fp32")
+    for j in (1, 4, p.n_ds):
+        for x, y in zip(a.transfer(j), b.transfer(j)):
+            assert torch.equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_full_size_cfg2_sampled():
+    """The benchmarked workload at full size (1023^2, 32 slabs, FP32 build,
+    FP64 refinement): two sampled transfer blocks and the full solution."""
+    p = make_config("cfg2")
+    banner("full-size cfg2 1023^2 32 slabs fp32")
+    dd = ddst()
+    op = dd.Operator.from_problem(p, precision="fp32")
+    o = odd.DDOracle(p)
+    for j in (1, 16):
+        SL, SR = (t.cpu().numpy() for t in op.transfer(j))
+        refR = o.transfer_block(j, j + 1)
+        assert rel(SR, refR) <= 2e-4
+        if j > 1:
+            assert rel(SL, o.transfer_block(j, j - 1)) <= 2e-4
+    u, _, st = op.solve(p.f)
+    ref = ofd.solve_global(p)
+    err = rel(u.cpu().numpy().ravel(), ref)
+    print(f"  full cfg2 rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']} "
+          f"build {st['t_build_ms']:.1f} ms solve {st['t_solve_ms']:.1f} ms")
+    assert err <= 1e-8
+    op.close()
