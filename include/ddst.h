@@ -79,8 +79,8 @@ typedef struct {
   int32_t precision;        /* DDST_FP64 (plain path) or DDST_FP32 (mixed path) */
   int32_t keep_factors;     /* 1: keep the per-slab elimination factors for the
                                solve (required by ddst_solve); 0: drop them     */
-  int32_t transpose;        /* 0: operator A; 1: build for A^T (convection
-                               reversed), used by the adjoint                  */
+  int32_t transpose;        /* must be 0 (reserved; the adjoint works from the
+                               forward operator's transposed structure)       */
   int32_t reserved;
 } ddst_build_opts_t;
 
@@ -126,7 +126,7 @@ typedef struct {
  * T_jj (Section 2.1, eq. efewin) and, if keep_factors, the per-plane inverse
  * Schur complements of a left-to-right sweep of every single slab.
  * prob: host struct; its device arrays are read during the call only.
- * opts: host struct or NULL (defaults: FP32, keep_factors=1, transpose=0).
+ * opts: host struct or NULL (defaults: FP32, keep_factors=1).
  * out: receives the new operator, or NULL on error.
  * Errors: EINVAL (shape/divisibility, kappa <= 0 or non-finite, c non-finite),
  *         ENOMEM, EHIP, EBREAKDOWN (a local elimination met a non-positive or
@@ -218,6 +218,52 @@ int ddst_apply(const ddst_op_t *op, int32_t transpose, int32_t which, const doub
                double *y, hipStream_t stream);
 int ddst_loads(const ddst_op_t *op, const double *f, const double *g, double *hhat,
                hipStream_t stream);
+
+/*
+ * Inspection hooks for the intermediate state of the build.
+ * ddst_get_factor: G_k = D_k^{-1}, the inverse Schur complement after k
+ *   planes of the left-to-right elimination of single slab `slab`
+ *   (0-based, 0..n_slabs-1), k = 1..m-1, into an M x M float64 device buffer.
+ *   ESTATE if the factors were dropped.
+ * ddst_get_center_inverse: inverse of the interface Schur block
+ *   T_jj (eq. efewin), j = 1..N_ds, M x M float64 device buffer.
+ */
+int ddst_get_factor(const ddst_op_t *op, int32_t slab, int32_t k, double *out,
+                    hipStream_t stream);
+int ddst_get_center_inverse(const ddst_op_t *op, int32_t j, double *out, hipStream_t stream);
+
+/*
+ * Kernel unit hooks (the batched dense kernels of the build, on caller data).
+ * Matrices are `batch` contiguous ld x ld row-major device arrays of the
+ * given precision (float for DDST_FP32, double for DDST_FP64); ld must be a
+ * positive multiple of 128.
+ * ddst_test_gemm: C_b = alpha * A_b * diag(bscale_b) * B_b + beta * C_b;
+ *   bscale: device float64 batch x ld, or NULL for no scaling.
+ * ddst_test_invert: in-place inverse of every A_b by Gauss-Jordan without
+ *   pivoting; EBREAKDOWN if a pivot is non-positive or non-finite.
+ */
+int ddst_test_gemm(int32_t precision, int32_t ld, int32_t batch, const void *A, const void *B,
+                   void *C, const double *bscale, double alpha, double beta,
+                   hipStream_t stream);
+int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipStream_t stream);
+
+/*
+ * Per-kernel-class timing.  ddst_profile_enable(1) clears and starts the
+ * counters, (0) stops them.  While on, every launch of the classes below is
+ * bracketed by HIP events recorded on the stream it is launched on.
+ * ddst_profile_read returns, for one class, the number of launches, their
+ * summed duration in ms and their summed algorithmic work (flops for the
+ * matrix-core classes, bytes for the others; padding excluded).
+ */
+enum {
+  DDST_K_GJ_PANEL = 0,  /* Gauss-Jordan pivot block inverse + panel   (flops) */
+  DDST_K_GJ_UPDATE = 1, /* Gauss-Jordan rank-64 update, MFMA          (flops) */
+  DDST_K_GEMM = 2,      /* transfer chains / blocks, MFMA             (flops) */
+  DDST_K_ASSEMBLE = 3,  /* plane-block (Schur recursion) assembly     (bytes) */
+  DDST_K_GEMV = 4       /* slab sweeps and interface products         (bytes) */
+};
+int ddst_profile_enable(int32_t on);
+int ddst_profile_read(int32_t kind, int64_t *launches, double *total_ms, double *work);
 
 #ifdef __cplusplus
 }

@@ -197,12 +197,12 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
   for (int k = 1; k <= m - 1; ++k) {
     launch_assemble<T>(tab.at<AsmJob>(off_asm[k - 1]), nsw, op->coef, op->n, op->dim, op->M,
                        ld, s);
-    gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, Rb, Cb, op->flag, s);
+    gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, Rb, Cb, op->flag, s);
     if (ny_at[k - 1] > 0) {
       if (k == 1)
         launch_scale_cols<T>(tab.at<GemmJob>(off_y[0]), ny_at[0], ld, -1.0, s);
       else
-        launch_gemm<T>(tab.at<GemmJob>(off_y[k - 1]), ny_at[k - 1], ld, -1.0, 0.0, s);
+        launch_gemm<T>(tab.at<GemmJob>(off_y[k - 1]), ny_at[k - 1], ld, op->M, -1.0, 0.0, s);
     }
   }
   HIPCHK(hipGetLastError());
@@ -302,9 +302,9 @@ int build_impl(ddst_op *op, int keep, hipStream_t s) {
   launch_assemble<T>(tab.at<AsmJob>(oc), nds, op->coef, op->n, op->dim, op->M, op->ld, s);
   DeviceMem gjw((size_t)nds * kNB * op->ld * sizeof(T) * 2);
   T *Rb = static_cast<T *>(gjw.p);
-  gj_invert<T>(tab.at<void *>(om), nds, op->ld, Rb, Rb + (size_t)nds * kNB * op->ld, op->flag,
-               s);
-  launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, -1.0, 0.0, s);
+  gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, Rb, Rb + (size_t)nds * kNB * op->ld,
+               op->flag, s);
+  launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, op->M, -1.0, 0.0, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return check_flag(op, s, "ddst_build_transfer");
@@ -1048,6 +1048,103 @@ int ddst_loads(const ddst_op_t *cop, const double *f, const double *g, double *h
     launch_unpad(w.hh, hhat, op->n_ds, op->M, op->ld, stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
+    return DDST_OK;
+  });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int ddst_get_factor(const ddst_op_t *op, int32_t slab, int32_t k, double *out,
+                    hipStream_t stream) {
+  g_err.clear();
+  if (!op || !out) return fail(DDST_EINVAL, "op and out must be non-NULL");
+  if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped");
+  if (slab < 0 || slab >= op->n_slabs || k < 1 || k > op->m - 1)
+    return fail(DDST_EINVAL, "slab or plane index out of range");
+  return guarded([&]() -> int {
+    launch_extract_block(mat(op->G, (size_t)slab * (op->m - 1) + (k - 1), op->mat_bytes),
+                         op->prec, op->M, op->ld, out, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return DDST_OK;
+  });
+}
+
+int ddst_get_center_inverse(const ddst_op_t *op, int32_t j, double *out, hipStream_t stream) {
+  g_err.clear();
+  if (!op || !out) return fail(DDST_EINVAL, "op and out must be non-NULL");
+  if (j < 1 || j > op->n_ds) return fail(DDST_EINVAL, "interface index out of range");
+  return guarded([&]() -> int {
+    launch_extract_block(mat(op->Sinv, j - 1, op->mat_bytes), op->prec, op->M, op->ld, out,
+                         stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return DDST_OK;
+  });
+}
+
+int ddst_test_gemm(int32_t precision, int32_t ld, int32_t batch, const void *A, const void *B,
+                   void *C, const double *bscale, double alpha, double beta,
+                   hipStream_t stream) {
+  g_err.clear();
+  if (!A || !B || !C || batch < 1 || ld < kTile || ld % kTile != 0 ||
+      (precision != DDST_FP32 && precision != DDST_FP64))
+    return fail(DDST_EINVAL, "bad arguments");
+  return guarded([&]() -> int {
+    const size_t mb = (size_t)ld * ld * esize(precision);
+    std::vector<GemmJob> jobs;
+    for (int b = 0; b < batch; ++b) {
+      GemmJob g{};
+      g.A = mat(const_cast<void *>(A), b, mb);
+      g.B = mat(const_cast<void *>(B), b, mb);
+      g.C = mat(C, b, mb);
+      g.bscale = bscale ? bscale + (size_t)b * ld : nullptr;
+      jobs.push_back(g);
+    }
+    JobTable t;
+    const size_t o = t.add(jobs);
+    t.upload(stream);
+    if (precision == DDST_FP32)
+      launch_gemm<float>(t.at<GemmJob>(o), batch, ld, ld, alpha, beta, stream);
+    else
+      launch_gemm<double>(t.at<GemmJob>(o), batch, ld, ld, alpha, beta, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return DDST_OK;
+  });
+}
+
+int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipStream_t stream) {
+  g_err.clear();
+  if (!A || batch < 1 || ld < kTile || ld % kTile != 0 ||
+      (precision != DDST_FP32 && precision != DDST_FP64))
+    return fail(DDST_EINVAL, "bad arguments");
+  return guarded([&]() -> int {
+    const size_t mb = (size_t)ld * ld * esize(precision);
+    std::vector<void *> mats;
+    for (int b = 0; b < batch; ++b) mats.push_back(mat(A, b, mb));
+    JobTable t;
+    const size_t o = t.add(mats);
+    t.upload(stream);
+    DeviceMem fl(sizeof(int));
+    HIPCHK(hipMemsetAsync(fl.p, 0, sizeof(int), stream));
+    DeviceMem w((size_t)batch * kNB * ld * esize(precision) * 2);
+    if (precision == DDST_FP32) {
+      float *R = static_cast<float *>(w.p);
+      gj_invert<float>(t.at<void *>(o), batch, ld, ld, R, R + (size_t)batch * kNB * ld,
+                       static_cast<int *>(fl.p), stream);
+    } else {
+      double *R = static_cast<double *>(w.p);
+      gj_invert<double>(t.at<void *>(o), batch, ld, ld, R, R + (size_t)batch * kNB * ld,
+                        static_cast<int *>(fl.p), stream);
+    }
+    HIPCHK(hipGetLastError());
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, fl.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (h) return fail(DDST_EBREAKDOWN, "non-positive or non-finite pivot");
     return DDST_OK;
   });
 }

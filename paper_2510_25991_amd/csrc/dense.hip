@@ -121,11 +121,15 @@ __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
   }
 }
 
-// Row / column of accumulator element (i, j, r) inside the 128 x 128 tile
-// (MFMA 16x16x4 output layout: lane l holds column l%16, rows 4*(l/16)+r).
+// Row / column of accumulator element (i, j, r) inside the 128 x 128 tile.
+// Lane l holds column l % 16 of each 16 x 16 MFMA output; the row of
+// register r is 4*(l/16) + r for the FP32 instruction and 4*r + l/16 for
+// the FP64 one (measured on gfx950 with identity operands).
+template <typename T>
 __device__ __forceinline__ int acc_row(int i, int r) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * 64 + i * 16 + 4 * (lane >> 4) + r;
+  const int in16 = sizeof(T) == 4 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
+  return (wave >> 1) * 64 + i * 16 + in16;
 }
 __device__ __forceinline__ int acc_col(int j) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -156,7 +160,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmJob *__restrict__ jobs, 
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const size_t idx = (size_t)(bm + acc_row(i, r)) * ld + bn + acc_col(j);
+        const size_t idx = (size_t)(bm + acc_row<T>(i, r)) * ld + bn + acc_col(j);
         T v = alpha * acc.v[i][j][r];
         if (beta != T(0)) v += beta * C[idx];
         C[idx] = v;
@@ -165,15 +169,18 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmJob *__restrict__ jobs, 
 
 // One Gauss-Jordan step, panel part.  Work-group (jt, b):
 //  * inverts the kNB x kNB pivot block P = D[p, p] in LDS (no pivoting);
-//  * R[:, jt-block] = P^{-1} D[p, jt-block]   (and P^{-1} + I when jt == p);
+//  * R[:, jt-block] = P^{-1} D[p, jt-block]   (P^{-1} itself when jt == p);
 //  * Cbuf[jt-block rows, :] = D[jt-block rows, p]   (copy of the old column).
+// The jt-block of the pivot rows is staged through LDS in two halves so the
+// FP64 variant stays within 64 KB of LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats,
                                                   T *__restrict__ Rbuf,
                                                   T *__restrict__ Cbuf, int ld, int p,
                                                   int *__restrict__ flag) {
+  constexpr int H = kNB / 2;
   __shared__ T P[kNB][kNB + 1];
-  __shared__ T X[kNB][kNB + 1];
+  __shared__ T X[H][kNB + 1];
   __shared__ T colk[kNB], rowk[kNB];
   const int b = blockIdx.y, jt = blockIdx.x, tid = threadIdx.x;
   T *D = static_cast<T *>(mats[b]);
@@ -183,7 +190,6 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
   for (int e = tid; e < kNB * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
     P[r][c] = D[(size_t)(p0 + r) * ld + p0 + c];
-    X[r][c] = D[(size_t)(p0 + r) * ld + j0 + c];
     Cb[(size_t)(j0 + r) * kNB + c] = D[(size_t)(j0 + r) * ld + p0 + c];
   }
   __syncthreads();
@@ -214,23 +220,34 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
   T out[16];
   if (jt == p) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) out[q] = P[r][c0 + q] + (r == c0 + q ? T(1) : T(0));
+    for (int q = 0; q < 16; ++q) out[q] = P[r][c0 + q];
   } else {
 #pragma unroll
     for (int q = 0; q < 16; ++q) out[q] = T(0);
-    for (int k = 0; k < kNB; ++k) {
-      const T a = P[r][k];
+    for (int half = 0; half < 2; ++half) {
+      __syncthreads();
+      for (int e = tid; e < H * kNB; e += 256) {
+        const int rr = e / kNB, c = e % kNB;
+        X[rr][c] = D[(size_t)(p0 + half * H + rr) * ld + j0 + c];
+      }
+      __syncthreads();
+      for (int k = 0; k < H; ++k) {
+        const T a = P[r][half * H + k];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) out[q] += a * X[k][c0 + q];
+        for (int q = 0; q < 16; ++q) out[q] += a * X[k][c0 + q];
+      }
     }
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) R[(size_t)r * ld + j0 + c0 + q] = out[q];
 }
 
-// One Gauss-Jordan step, update part: for rows outside the pivot block
-//   D[i, :] -= Cbuf[i, :] R           (column p becomes -D[i,p] P^{-1})
-// and the pivot rows take R (with P^{-1} on the diagonal block).
+// One Gauss-Jordan step, update part (acc = Cbuf R, Cbuf = old column p):
+//   pivot rows               D[p, :] = R             (P^{-1} on the block p)
+//   other rows, column p     D[i, p] = -D[i, p] P^{-1}
+//   other rows, other cols   D[i, j] -= D[i, p] P^{-1} D[p, j]
+// The pivot column is written as -acc rather than D - (D + D P^{-1}), which
+// would add O(1) to O(|P^{-1}|) entries and lose their leading digits.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
@@ -256,10 +273,12 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = bm + acc_row(i, r), col = bn + acc_col(j);
+        const int row = bm + acc_row<T>(i, r), col = bn + acc_col(j);
         const size_t idx = (size_t)row * ld + col;
         if (row >= p0 && row < p0 + kNB)
-          D[idx] = R[(size_t)(row - p0) * ld + col] - (row == col ? T(1) : T(0));
+          D[idx] = R[(size_t)(row - p0) * ld + col];
+        else if (col >= p0 && col < p0 + kNB)
+          D[idx] = -acc.v[i][j][r];
         else
           D[idx] = D[idx] - acc.v[i][j][r];
       }
@@ -330,8 +349,11 @@ template <typename T>
 void launch_assemble(const AsmJob *jobs, int njobs, const double *coef, int n, int dim,
                      int M, int ld, hipStream_t s) {
   if (njobs <= 0) return;
+  prof_begin(KK_ASSEMBLE, s);
   hipLaunchKernelGGL(k_assemble<T>, dim3(ld, njobs), dim3(256), 0, s, jobs, coef, n, dim, M,
                      ld);
+  // reads G (and up to one more) and writes D: 2 M^2 elements per job
+  prof_end(KK_ASSEMBLE, s, 2.0 * njobs * (double)M * M * sizeof(T));
 }
 
 template <typename T>
@@ -341,25 +363,33 @@ void launch_scale_cols(const GemmJob *jobs, int njobs, int ld, double alpha, hip
 }
 
 template <typename T>
-void launch_gemm(const GemmJob *jobs, int njobs, int ld, double alpha, double beta,
+void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, double beta,
                  hipStream_t s) {
   if (njobs <= 0) return;
   const int tpm = (ld / kTile) * (ld / kTile);
+  prof_begin(KK_GEMM, s);
   hipLaunchKernelGGL(k_gemm<T>, dim3(tpm * njobs), dim3(256), 0, s, jobs, ld, tpm, (T)alpha,
                      (T)beta);
+  prof_end(KK_GEMM, s, 2.0 * njobs * (double)M * M * M);
 }
 
 template <typename T>
-void gj_invert(void *const *mats, int nmat, int ld, T *Rbuf, T *Cbuf, int *flag,
+void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, int *flag,
                hipStream_t s) {
   if (nmat <= 0) return;
   const int nblk = ld / kNB;
   const int tpm = (ld / kTile) * (ld / kTile);
-  for (int p = 0; p < nblk; ++p) {
+  // blocks that hold only identity padding need no elimination step
+  const int nreal = (M + kNB - 1) / kNB;
+  for (int p = 0; p < nreal; ++p) {
+    prof_begin(KK_GJ_PANEL, s);
     hipLaunchKernelGGL(k_gj_panel<T>, dim3(nblk, nmat), dim3(256), 0, s, mats, Rbuf, Cbuf,
                        ld, p, flag);
+    prof_end(KK_GJ_PANEL, s, 2.0 * nmat * (double)kNB * kNB * M);
+    prof_begin(KK_GJ_UPDATE, s);
     hipLaunchKernelGGL(k_gj_update<T>, dim3(tpm * nmat), dim3(256), 0, s, mats, Rbuf, Cbuf,
                        ld, p, tpm);
+    prof_end(KK_GJ_UPDATE, s, 2.0 * nmat * (double)M * M * kNB);
   }
 }
 
@@ -367,8 +397,8 @@ void gj_invert(void *const *mats, int nmat, int ld, T *Rbuf, T *Cbuf, int *flag,
   template void launch_assemble<T>(const AsmJob *, int, const double *, int, int, int, int, \
                                    hipStream_t);                                           \
   template void launch_scale_cols<T>(const GemmJob *, int, int, double, hipStream_t);       \
-  template void launch_gemm<T>(const GemmJob *, int, int, double, double, hipStream_t);     \
-  template void gj_invert<T>(void *const *, int, int, T *, T *, int *, hipStream_t);
+  template void launch_gemm<T>(const GemmJob *, int, int, int, double, double, hipStream_t); \
+  template void gj_invert<T>(void *const *, int, int, int, T *, T *, int *, hipStream_t);
 DDST_INST(float)
 DDST_INST(double)
 #undef DDST_INST

