@@ -189,16 +189,17 @@ def main():
         from problems import sensor_nodes
         op = dd.Operator(2, prob.n, prob.n_slabs, kappa=dev["kappa"], bvec=prob.bvec,
                          precision="fp32")
-        u, _, _ = op.solve(dev["f"], opts=opts, want_gamma=False)
+        u, _, _ = op.solve(dev["f"], opts=opts, want_gamma=False, allow_notconv=True)
         op.release_factors()
         gbar = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
         gbar[torch.tensor(sensor_nodes(2, prob.n, 256, seed=1003), device="cuda")] = 1.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dk, sta = op.adjoint(u.reshape(-1), gbar, opts=opts)
+        dk, sta = op.adjoint(u.reshape(-1), gbar, opts=opts, allow_notconv=True)
         torch.cuda.synchronize()
         adj = {"ms": round((time.perf_counter() - t0) * 1e3, 2),
-               "outer_iters": sta["outer_iters"], "gmres_iters": sta["gmres_iters"]}
+               "outer_iters": sta["outer_iters"], "gmres_iters": sta["gmres_iters"],
+               "converged": bool(sta["status"] == 0)}
         op.close()
     cpu, errs = (None, {})
     if not args.no_cpu:

@@ -191,13 +191,14 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
     ny_at[k - 1] = (int)yj.size();
   }
   tab.upload(s);
-  DeviceMem gjw((size_t)nsw * kNB * ld * sizeof(T) * 2);
+  DeviceMem gjw(gj_workspace_bytes(nsw, ld, sizeof(T)));
   T *Rb = static_cast<T *>(gjw.p);
   T *Cb = Rb + (size_t)nsw * kNB * ld;
+  double *Pi = reinterpret_cast<double *>(Cb + (size_t)nsw * kNB * ld);
   for (int k = 1; k <= m - 1; ++k) {
     launch_assemble<T>(tab.at<AsmJob>(off_asm[k - 1]), nsw, op->coef, op->n, op->dim, op->M,
                        ld, s);
-    gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, Rb, Cb, op->flag, s);
+    gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, Rb, Cb, Pi, op->flag, s);
     if (ny_at[k - 1] > 0) {
       if (k == 1)
         launch_scale_cols<T>(tab.at<GemmJob>(off_y[0]), ny_at[0], ld, -1.0, s);
@@ -300,10 +301,10 @@ int build_impl(ddst_op *op, int keep, hipStream_t s) {
   const size_t oc = tab.add(cj), om = tab.add(smats), os = tab.add(sj);
   tab.upload(s);
   launch_assemble<T>(tab.at<AsmJob>(oc), nds, op->coef, op->n, op->dim, op->M, op->ld, s);
-  DeviceMem gjw((size_t)nds * kNB * op->ld * sizeof(T) * 2);
+  DeviceMem gjw(gj_workspace_bytes(nds, op->ld, sizeof(T)));
   T *Rb = static_cast<T *>(gjw.p);
   gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, Rb, Rb + (size_t)nds * kNB * op->ld,
-               op->flag, s);
+               reinterpret_cast<double *>(Rb + (size_t)2 * nds * kNB * op->ld), op->flag, s);
   launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, op->M, -1.0, 0.0, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -1130,14 +1131,16 @@ int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipS
     t.upload(stream);
     DeviceMem fl(sizeof(int));
     HIPCHK(hipMemsetAsync(fl.p, 0, sizeof(int), stream));
-    DeviceMem w((size_t)batch * kNB * ld * esize(precision) * 2);
+    DeviceMem w(gj_workspace_bytes(batch, ld, esize(precision)));
     if (precision == DDST_FP32) {
       float *R = static_cast<float *>(w.p);
       gj_invert<float>(t.at<void *>(o), batch, ld, ld, R, R + (size_t)batch * kNB * ld,
+                       reinterpret_cast<double *>(R + (size_t)2 * batch * kNB * ld),
                        static_cast<int *>(fl.p), stream);
     } else {
       double *R = static_cast<double *>(w.p);
       gj_invert<double>(t.at<void *>(o), batch, ld, ld, R, R + (size_t)batch * kNB * ld,
+                        reinterpret_cast<double *>(R + (size_t)2 * batch * kNB * ld),
                         static_cast<int *>(fl.p), stream);
     }
     HIPCHK(hipGetLastError());

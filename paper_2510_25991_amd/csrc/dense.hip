@@ -72,10 +72,10 @@ struct Tile {
   }
 };
 
-// acc += A[0:128, 0:K] * diag(bscale[0:K]) * B[0:K, 0:128]
+// acc += (NEG_A ? -A : A)[0:128, 0:K] * diag(bscale[0:K]) * B[0:K, 0:128]
 // A row-major with leading dim lda (points at the tile's first row),
 // B row-major with leading dim ldb (points at the tile's first column).
-template <typename T>
+template <typename T, bool NEG_A = false>
 __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
                                          const T *__restrict__ B, int ldb,
                                          const double *__restrict__ bscale, int K,
@@ -100,7 +100,7 @@ __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[ak + q][ar] = ra[q];
+    for (int q = 0; q < 8; ++q) As[ak + q][ar] = NEG_A ? -ra[q] : ra[q];
 #pragma unroll
     for (int q = 0; q < 8; ++q) Bs[br][bc + q] = rb[q];
     __syncthreads();
@@ -167,87 +167,112 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmJob *__restrict__ jobs, 
       }
 }
 
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Elimination step K of the in-register pivot inverse, then K+1, ...: a
+// compile-time recursion so that every register index is a constant.
+template <int K>
+__device__ __forceinline__ void gj_pivot_steps(double (&col)[kNB], int c, bool &bad) {
+  if constexpr (K < kNB) {
+    const double piv = readlane_f64(col[K], K);
+    if (!(piv > 0.0) || !isfinite(piv)) bad = true;
+    const double inv = 1.0 / piv;
+    const double rk = col[K] * inv;  // this lane's entry of the scaled pivot row
+    const bool own = (c == K);
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) {
+      if (i == K) {
+        col[i] = own ? inv : rk;
+      } else {
+        const double ci = readlane_f64(col[i], K);  // pivot column entry, broadcast
+        col[i] = own ? -ci * inv : col[i] - ci * rk;
+      }
+    }
+    gj_pivot_steps<K + 1>(col, c, bad);
+  }
+}
+
+// One Gauss-Jordan step, pivot part: one wavefront per matrix inverts the
+// kNB x kNB pivot block P = D[p, p] without pivoting, in FP64, with lane c
+// holding column c of P in registers (the loops are fully unrolled so every
+// register index is static); the pivot column is broadcast with readlane.
+// FP64 throughout: the transfer blocks inherit the error of these small
+// inverses amplified by the conditioning of the interface Schur block.
+// Writes P^{-1} (row-major, FP64) to Pinv[b].
+template <typename T>
+__global__ __launch_bounds__(64) void k_gj_pivot(void *const *__restrict__ mats,
+                                                 double *__restrict__ Pinv, int ld, int p,
+                                                 int *__restrict__ flag) {
+  const int b = blockIdx.x, c = threadIdx.x;
+  const T *D = static_cast<const T *>(mats[b]);
+  const int p0 = p * kNB;
+  double col[kNB];
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) col[i] = (double)D[(size_t)(p0 + i) * ld + p0 + c];
+  bool bad = false;
+  gj_pivot_steps<0>(col, c, bad);
+  if (bad && c == 0) atomicOr(flag, 1);
+  double *out = Pinv + (size_t)b * kNB * kNB;
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) out[i * kNB + c] = col[i];
+}
+
 // One Gauss-Jordan step, panel part.  Work-group (jt, b):
-//  * inverts the kNB x kNB pivot block P = D[p, p] in LDS (no pivoting);
-//  * R[:, jt-block] = P^{-1} D[p, jt-block]   (P^{-1} itself when jt == p);
-//  * Cbuf[jt-block rows, :] = D[jt-block rows, p]   (copy of the old column).
-// The jt-block of the pivot rows is staged through LDS in two halves so the
-// FP64 variant stays within 64 KB of LDS.
+//  * R[:, jt-block] = P^{-1} D[p, jt-block] (FP64 accumulation; P^{-1} itself
+//    when jt == p);
+//  * Cbuf[jt-block rows, :] = D[jt-block rows, p] (copy of the old column).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats,
-                                                  T *__restrict__ Rbuf,
-                                                  T *__restrict__ Cbuf, int ld, int p,
-                                                  int *__restrict__ flag) {
-  constexpr int H = kNB / 2;
-  __shared__ T P[kNB][kNB + 1];
-  __shared__ T X[H][kNB + 1];
-  __shared__ T colk[kNB], rowk[kNB];
+                                                  const double *__restrict__ Pinv,
+                                                  T *__restrict__ Rbuf, T *__restrict__ Cbuf,
+                                                  int ld, int p) {
+  __shared__ double Ps[kNB][kNB + 1];
+  __shared__ T X[kNB][kNB + 1];
   const int b = blockIdx.y, jt = blockIdx.x, tid = threadIdx.x;
-  T *D = static_cast<T *>(mats[b]);
+  const T *D = static_cast<const T *>(mats[b]);
   T *R = Rbuf + (size_t)b * kNB * ld;
   T *Cb = Cbuf + (size_t)b * ld * kNB;
+  const double *Pi = Pinv + (size_t)b * kNB * kNB;
   const int p0 = p * kNB, j0 = jt * kNB;
   for (int e = tid; e < kNB * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
-    P[r][c] = D[(size_t)(p0 + r) * ld + p0 + c];
+    Ps[r][c] = Pi[e];
+    X[r][c] = D[(size_t)(p0 + r) * ld + j0 + c];
     Cb[(size_t)(j0 + r) * kNB + c] = D[(size_t)(j0 + r) * ld + p0 + c];
   }
   __syncthreads();
-  bool bad = false;
-  for (int k = 0; k < kNB; ++k) {
-    if (tid < kNB) {
-      colk[tid] = P[tid][k];
-      rowk[tid] = P[k][tid];
-    }
-    __syncthreads();
-    const T piv = rowk[k];
-    if (!(piv > T(0)) || !isfinite((double)piv)) bad = true;
-    const T inv = T(1) / piv;
-    for (int e = tid; e < kNB * kNB; e += 256) {
-      const int r = e / kNB, c = e % kNB;
-      T v;
-      if (r == k && c == k) v = inv;
-      else if (r == k) v = rowk[c] * inv;
-      else if (c == k) v = -colk[r] * inv;
-      else v = P[r][c] - colk[r] * rowk[c] * inv;
-      P[r][c] = v;
-    }
-    __syncthreads();
-  }
-  if (bad && jt == 0 && tid == 0) atomicOr(flag, 1);
-  // R tile: 64 x 64, thread -> row r = tid / 4, 16 columns
   const int r = tid >> 2, c0 = (tid & 3) * 16;
-  T out[16];
+  double out[16];
   if (jt == p) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) out[q] = P[r][c0 + q];
+    for (int q = 0; q < 16; ++q) out[q] = Ps[r][c0 + q];
   } else {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) out[q] = T(0);
-    for (int half = 0; half < 2; ++half) {
-      __syncthreads();
-      for (int e = tid; e < H * kNB; e += 256) {
-        const int rr = e / kNB, c = e % kNB;
-        X[rr][c] = D[(size_t)(p0 + half * H + rr) * ld + j0 + c];
-      }
-      __syncthreads();
-      for (int k = 0; k < H; ++k) {
-        const T a = P[r][half * H + k];
+    for (int q = 0; q < 16; ++q) out[q] = 0.0;
+    for (int k = 0; k < kNB; ++k) {
+      const double a = Ps[r][k];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) out[q] += a * X[k][c0 + q];
-      }
+      for (int q = 0; q < 16; ++q) out[q] += a * (double)X[k][c0 + q];
     }
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) R[(size_t)r * ld + j0 + c0 + q] = out[q];
+  for (int q = 0; q < 16; ++q) R[(size_t)r * ld + j0 + c0 + q] = (T)out[q];
 }
 
-// One Gauss-Jordan step, update part (acc = Cbuf R, Cbuf = old column p):
+// One Gauss-Jordan step, update part (Cbuf = old column p, R = P^{-1} D[p,:]):
 //   pivot rows               D[p, :] = R             (P^{-1} on the block p)
 //   other rows, column p     D[i, p] = -D[i, p] P^{-1}
 //   other rows, other cols   D[i, j] -= D[i, p] P^{-1} D[p, j]
-// The pivot column is written as -acc rather than D - (D + D P^{-1}), which
-// would add O(1) to O(|P^{-1}|) entries and lose their leading digits.
+// The D tile is loaded into registers before the MFMA loop (its latency
+// overlaps the panel product); the product is formed from zero and
+// subtracted once, which keeps the rounding at the scale of the update
+// rather than of D.  The pivot column is written as -acc rather than
+// D - (D + D P^{-1}), which would add O(1) to O(|P^{-1}|) entries.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
@@ -264,6 +289,17 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   const T *R = Rbuf + (size_t)b * kNB * ld;
   const T *Cb = Cbuf + (size_t)b * ld * kNB;
   const int p0 = p * kNB;
+  T dold[4][4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + acc_row<T>(i, r), col = bn + acc_col(j);
+        const bool pivcol = col >= p0 && col < p0 + kNB;
+        dold[i][j][r] = pivcol ? T(0) : D[(size_t)row * ld + col];
+      }
   Tile<T> acc;
   acc.zero();
   mma_tile<T>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, nullptr, kNB, As, Bs, acc);
@@ -277,10 +313,8 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
         const size_t idx = (size_t)row * ld + col;
         if (row >= p0 && row < p0 + kNB)
           D[idx] = R[(size_t)(row - p0) * ld + col];
-        else if (col >= p0 && col < p0 + kNB)
-          D[idx] = -acc.v[i][j][r];
         else
-          D[idx] = D[idx] - acc.v[i][j][r];
+          D[idx] = dold[i][j][r] - acc.v[i][j][r];
       }
 }
 
@@ -374,8 +408,8 @@ void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, do
 }
 
 template <typename T>
-void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, int *flag,
-               hipStream_t s) {
+void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, double *Pinv,
+               int *flag, hipStream_t s) {
   if (nmat <= 0) return;
   const int nblk = ld / kNB;
   const int tpm = (ld / kTile) * (ld / kTile);
@@ -383,8 +417,9 @@ void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, int
   const int nreal = (M + kNB - 1) / kNB;
   for (int p = 0; p < nreal; ++p) {
     prof_begin(KK_GJ_PANEL, s);
-    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nblk, nmat), dim3(256), 0, s, mats, Rbuf, Cbuf,
-                       ld, p, flag);
+    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(64), 0, s, mats, Pinv, ld, p, flag);
+    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nblk, nmat), dim3(256), 0, s, mats, Pinv, Rbuf,
+                       Cbuf, ld, p);
     prof_end(KK_GJ_PANEL, s, 2.0 * nmat * (double)kNB * kNB * M);
     prof_begin(KK_GJ_UPDATE, s);
     hipLaunchKernelGGL(k_gj_update<T>, dim3(tpm * nmat), dim3(256), 0, s, mats, Rbuf, Cbuf,
@@ -398,7 +433,8 @@ void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, int
                                    hipStream_t);                                           \
   template void launch_scale_cols<T>(const GemmJob *, int, int, double, hipStream_t);       \
   template void launch_gemm<T>(const GemmJob *, int, int, int, double, double, hipStream_t); \
-  template void gj_invert<T>(void *const *, int, int, int, T *, T *, int *, hipStream_t);
+  template void gj_invert<T>(void *const *, int, int, int, T *, T *, double *, int *,       \
+                             hipStream_t);
 DDST_INST(float)
 DDST_INST(double)
 #undef DDST_INST

@@ -94,11 +94,16 @@ template <typename T>
 void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, double beta,
                  hipStream_t s);
 // In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices.
-// Rbuf: nmat*kNB*ld, Cbuf: nmat*ld*kNB workspace of T; flag: device int set
-// to 1 when a pivot is non-positive or non-finite.
+// Rbuf: nmat*kNB*ld, Cbuf: nmat*ld*kNB workspace of T; Pinv: nmat*kNB*kNB
+// doubles; flag: device int set to 1 when a pivot is non-positive or
+// non-finite.
 template <typename T>
-void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, int *flag,
-               hipStream_t s);
+void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, double *Pinv,
+               int *flag, hipStream_t s);
+// Bytes of Gauss-Jordan workspace for nmat matrices.
+inline size_t gj_workspace_bytes(int nmat, int ld, size_t esz) {
+  return (size_t)nmat * kNB * ld * esz * 2 + (size_t)nmat * kNB * kNB * sizeof(double);
+}
 
 // ---- vector kernels (vec.hip) --------------------------------------------
 void launch_setup_coef(const double *kappa, const double *c, const double *bvec3,
