@@ -188,6 +188,11 @@ int ddst_adjoint(const ddst_op_t *op, const double *u_vol, const double *g,
                  const double *gbar, const ddst_solve_opts_t *opts, double *dkappa,
                  double *lambda, ddst_stats_t *stats, hipStream_t stream);
 
+/* Compressed-form summary: factor bytes, largest / smallest admissible rank,
+ * compression time of the last ddst_compress (ms).  ESTATE if none. */
+int ddst_compress_info(const ddst_op_t *op, double *bytes, int32_t *max_rank,
+                       int32_t *min_rank, double *ms);
+
 /* Drop the per-slab factors (frees device memory); the adjoint recomputes. */
 int ddst_release_factors(ddst_op_t *op);
 

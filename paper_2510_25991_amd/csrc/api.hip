@@ -935,6 +935,58 @@ int ddst_adjoint(const ddst_op_t *cop, const double *u_vol, const double *g, con
   });
 }
 
+int ddst_compress(ddst_op_t *op, const ddst_compress_opts_t *opts, hipStream_t stream) {
+  g_err.clear();
+  if (!op || !opts) return fail(DDST_EINVAL, "op and opts must be non-NULL");
+  const ddst_compress_opts_t &o = *opts;
+  if (o.tree != DDST_TREE_BINARY && o.tree != DDST_TREE_QUAD)
+    return fail(DDST_EINVAL, "tree must be BINARY or QUAD");
+  if (o.tree == DDST_TREE_QUAD && op->dim != 3)
+    return fail(DDST_EINVAL, "the quadtree needs a 3D problem (planar interfaces)");
+  if (o.leaf < 4) return fail(DDST_EINVAL, "leaf must be >= 4");
+  if (o.oversample < 2 || o.max_rank < 1 || o.max_rank + o.oversample > 128)
+    return fail(DDST_EINVAL, "need oversample >= 2, max_rank >= 1, max_rank + oversample <= 128");
+  if (!(o.tol > 0) || !std::isfinite(o.tol)) return fail(DDST_EINVAL, "tol must be > 0");
+  if (o.factor_dtype < DDST_FACTOR_BF16 || o.factor_dtype > DDST_FACTOR_FP64)
+    return fail(DDST_EINVAL, "bad factor_dtype");
+  return guarded([&]() -> int {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, stream));
+    int overflow = 0;
+    const int st = hodlr_compress(op, o, stream, &overflow);
+    HIPCHK(hipEventRecord(e1, stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == DDST_ERANK)
+      return fail(DDST_ERANK, "an admissible block needs rank " + std::to_string(overflow) +
+                                  ", beyond max_rank (" + std::to_string(o.max_rank) +
+                                  ") with oversampling " + std::to_string(o.oversample));
+    if (st) return fail(st, "compression failed");
+    op->last_build.t_compress_ms = ms;
+    hodlr_info(op, &op->last_build.bytes_hodlr, &op->last_build.max_rank,
+               &op->last_build.min_rank);
+    return DDST_OK;
+  });
+}
+
+int ddst_compress_info(const ddst_op_t *op, double *bytes, int32_t *max_rank,
+                       int32_t *min_rank, double *ms) {
+  g_err.clear();
+  if (!op) return fail(DDST_EINVAL, "op is NULL");
+  if (!hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  int mx = 0, mn = 0;
+  hodlr_info(op, bytes, &mx, &mn);
+  if (max_rank) *max_rank = mx;
+  if (min_rank) *min_rank = mn;
+  if (ms) *ms = op->last_build.t_compress_ms;
+  return DDST_OK;
+}
+
 int ddst_release_factors(ddst_op_t *op) {
   g_err.clear();
   if (!op) return fail(DDST_EINVAL, "op is NULL");

@@ -1,16 +1,1064 @@
-// Compressed (weak-admissibility hierarchical) form of the transfer blocks.
+// Compressed form of the transfer blocks: weak-admissibility hierarchical
+// low-rank (HODLR) representation on a cluster tree shared by source and
+// target interface (the rank-structured format of the paper's Section 2.4;
+// every interaction between two distinct children of a tree node is low
+// rank, leaf diagonal blocks stay dense).
+//
+// Compression of one admissible block B (m x n), batched over all blocks of
+// one tree level of every transfer block:
+//   1. Omega (n x s) Gaussian, s = rank cap + oversampling (Philox-4x32-10
+//      counter generator + Box-Muller), Y = B Omega                 (GEMM)
+//   2. Householder QR of Y, explicit Q (m x s)                     (FP64)
+//   3. X = B^T Q (n x s), so that B ~ Q X^T                         (GEMM)
+//   4. one-sided Jacobi on the columns of X: X V = Xt with orthogonal
+//      columns, sigma_k = |Xt_k| (relative-accurate singular values)
+//   5. keep sigma_k > tol * ||S_{j,j'}||_2 (norm by power iteration):
+//      U = Q V_sel (m x r), Vt = Xt_sel^T (r x n), packed in BF16/FP32/FP64.
+// Apply: one work-group per (interface, row cluster) at each level sums all
+// contributions of that cluster (both transfer blocks, all siblings), so no
+// two work-groups write the same output entries.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <tuple>
+#include <type_traits>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
 #include "internal.h"
 
 namespace ddst {
-void hodlr_free(ddst_op *op) { (void)op; }
-bool hodlr_ready(const ddst_op *op) { return op && op->hodlr != nullptr; }
-int hodlr_compress(ddst_op *, const ddst_compress_opts_t &, hipStream_t) { return DDST_ESTATE; }
-int hodlr_apply_jobs(const ddst_op *, const double *, double *, int, hipStream_t) {
-  return DDST_ESTATE;
-}
-}  // namespace ddst
 
-extern "C" int ddst_compress(ddst_op_t *op, const ddst_compress_opts_t *opts, hipStream_t s) {
-  if (!op || !opts) return DDST_EINVAL;
-  return ddst::hodlr_compress(op, *opts, s);
+// ---------------------------------------------------------------- host data
+struct HBlock {
+  int smat;        // transfer matrix index: 2*(j-1) + 0 for S_{j,j-1}, +1 for S_{j,j+1}
+  int r0, r1;      // row range (cluster-ordered indices)
+  int c0, c1;      // column range
+  int level;       // tree level of the parent node (0 = root) ; leaves: -1
+  int rank;        // -1 for a dense leaf
+  size_t off_u;    // element offset of U (m x rank, row-major) or of the leaf (m x n)
+  size_t off_v;    // element offset of Vt (rank x n, row-major)
+};
+
+struct Hodlr {
+  int tree = 0, leaf = 0, dtype = 0, nlev = 0;
+  std::vector<int> perm;     // cluster order -> natural interface index
+  int *d_perm = nullptr;     // device copy (null for the identity)
+  void *factors = nullptr;   // packed factor storage
+  size_t bytes = 0;
+  std::vector<HBlock> blocks;
+  int max_rank = 0, min_rank = 1 << 30;
+  // apply job tables (device), per direction and stage
+  void *jobs = nullptr;
+  std::vector<size_t> off_lr[2];  // per level offset of its LrJob list
+  std::vector<int> n_lr[2];
+  size_t off_leaf[2] = {0, 0};
+  int n_leaf[2] = {0, 0};
+  size_t off_con = 0;        // byte offset of the Contrib table in `jobs`
+  double *pbuf = nullptr;    // 2 * n_ds * ld doubles: permuted x and y
+  double tol_used = 0;       // truncation tolerance after the precision floor
+};
+
+// One output cluster of one interface at one level (or a leaf): the
+// contributions are listed in the Contrib table [first, first+count).
+struct LrJob {
+  int out_iface;   // interface whose output rows are updated (0-based)
+  int r0, r1;      // output rows (cluster order)
+  int first, count;
+};
+struct Contrib {
+  int in_iface;    // interface the input is read from (0-based)
+  int c0, c1;      // input columns (cluster order)
+  int rank;        // -1 dense
+  long long off_u, off_v;
+  int trans;       // apply the transpose of the stored block
+  int pad_;
+};
+
+namespace {
+
+// ----------------------------------------------------------- RNG (Philox)
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), then Box-Muller.
+__device__ __forceinline__ void philox_round(unsigned (&c)[4], const unsigned (&k)[2]) {
+  const unsigned long long p0 = (unsigned long long)0xD2511F53u * c[0];
+  const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c[2];
+  const unsigned hi0 = (unsigned)(p0 >> 32), lo0 = (unsigned)p0;
+  const unsigned hi1 = (unsigned)(p1 >> 32), lo1 = (unsigned)p1;
+  const unsigned n0 = hi1 ^ c[1] ^ k[0];
+  const unsigned n1 = lo1;
+  const unsigned n2 = hi0 ^ c[3] ^ k[1];
+  const unsigned n3 = lo0;
+  c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
 }
+
+__device__ void philox4x32_10(unsigned (&c)[4], unsigned k0, unsigned k1) {
+  unsigned k[2] = {k0, k1};
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k);
+    k[0] += 0x9E3779B9u;
+    k[1] += 0xBB67AE85u;
+  }
+}
+
+// Omega[i][k] (n x s, row-major) ~ N(0,1), counter = (i, k, level, 0).
+__global__ void k_gaussian(double *__restrict__ om, int n, int s, unsigned long long seed,
+                           int level) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * s) return;
+  unsigned c[4] = {(unsigned)(e / s), (unsigned)(e % s), (unsigned)level, 0u};
+  philox4x32_10(c, (unsigned)seed, (unsigned)(seed >> 32));
+  const double u1 = ((double)c[0] + 1.0) * 2.3283064365386963e-10;  // (0, 1]
+  const double u2 = (double)c[1] * 2.3283064365386963e-10;          // [0, 1)
+  om[e] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+// ------------------------------------------------------- batched block GEMM
+// C (m x s, column-major, FP64) = op(B) * W with
+//   trans == 0: op(B) = B       (m x n),  W: Omega, row-major n x s
+//   trans == 1: op(B) = B^T     (m = n_B), W: Q, column-major n_B x s
+// B is the (r0.., c0..) sub-block of a transfer matrix (ld, type T); with a
+// permutation the row / column indices are mapped through perm.
+struct BlockGemmJob {
+  const void *S;
+  int r0, c0, m, n;   // block origin and size in cluster order (m rows, n cols of B)
+  double *C;          // output
+  const double *W;    // Omega (shared) or this block's Q
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_gemm(const BlockGemmJob *__restrict__ jobs,
+                                                    const int *__restrict__ perm, int ld, int s,
+                                                    int trans) {
+  constexpr int TM = 64, TK = 32;
+  __shared__ double Bs[TK][TM + 1];   // op(B) tile, k-major
+  __shared__ double Ws[TK][129];      // W tile (k x s <= 128)
+  const BlockGemmJob J = jobs[blockIdx.y];
+  const T *S = static_cast<const T *>(J.S);
+  const int mrows = trans ? J.n : J.m;  // rows of op(B)
+  const int kdim = trans ? J.m : J.n;
+  const int row0 = blockIdx.x * TM;
+  if (row0 >= mrows) return;
+  const int tid = threadIdx.x;
+  // each thread: rows (tid % 64), columns k = tid/64 + 4*q, q < s/4
+  const int tr = tid & 63, tc = tid >> 6;
+  double acc[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+  for (int k0 = 0; k0 < kdim; k0 += TK) {
+    __syncthreads();
+    for (int e = tid; e < TK * TM; e += 256) {
+      const int kk = e / TM, ii = e % TM;
+      const int i = row0 + ii, k = k0 + kk;
+      double v = 0.0;
+      if (i < mrows && k < kdim) {
+        const int br = trans ? k : i, bc = trans ? i : k;  // entry B[br][bc]
+        int gr = J.r0 + br, gc = J.c0 + bc;
+        if (perm) { gr = perm[gr]; gc = perm[gc]; }
+        v = (double)S[(size_t)gr * ld + gc];
+      }
+      Bs[kk][ii] = v;
+    }
+    for (int e = tid; e < TK * s; e += 256) {
+      const int kk = e / s, q = e % s, k = k0 + kk;
+      double v = 0.0;
+      if (k < kdim) v = trans ? J.W[(size_t)q * kdim + k] : J.W[(size_t)k * s + q];
+      Ws[kk][q] = v;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < TK; ++kk) {
+      const double b = Bs[kk][tr];
+#pragma unroll
+      for (int q = 0; q < 32; ++q)
+        if (tc + 4 * q < s) acc[q] += b * Ws[kk][tc + 4 * q];
+    }
+  }
+  const int i = row0 + tr;
+  if (i < mrows)
+#pragma unroll
+    for (int q = 0; q < 32; ++q)
+      if (tc + 4 * q < s) J.C[(size_t)(tc + 4 * q) * mrows + i] = acc[q];
+}
+
+// --------------------------------------------------- Householder QR + form Q
+// In place on A (m x s, column-major): on exit A holds the explicit Q.
+// One work-group per block; tau in LDS.
+__device__ double block_reduce_sum(double v, double *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  return s;
+}
+
+struct QrJob {
+  double *A;  // m x s column-major
+  int m;
+};
+
+__global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__ jobs, int s) {
+  __shared__ double tau[128];
+  __shared__ double sh[8];
+  __shared__ double dots[128];
+  const QrJob J = jobs[blockIdx.x];
+  double *A = J.A;
+  const int m = J.m;
+  const int kmax = min(s, m);
+  for (int j = 0; j < kmax; ++j) {
+    double *a = A + (size_t)j * m;
+    double part = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += 256) part += a[i] * a[i];
+    const double sig = block_reduce_sum(part, sh);
+    const double x0 = a[j];
+    double beta, t, scale;
+    if (sig == 0.0) {
+      t = 0.0;
+      beta = x0;
+      scale = 0.0;
+    } else {
+      const double mu = sqrt(x0 * x0 + sig);
+      beta = (x0 <= 0.0) ? mu : -mu;   // beta = -sign(x0) |x|
+      const double v0 = x0 - beta;
+      t = (beta - x0) / beta;
+      scale = 1.0 / v0;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < m; i += 256) a[i] *= scale;  // v (v_0 = 1)
+    if (threadIdx.x == 0) {
+      a[j] = beta;
+      tau[j] = t;
+    }
+    __syncthreads();
+    // apply H_j = I - t v v^T to the remaining columns
+    for (int c = j + 1; c < s; ++c) {
+      const double *ac = A + (size_t)c * m;
+      double p2 = 0.0;
+      for (int i = j + 1 + threadIdx.x; i < m; i += 256) p2 += a[i] * ac[i];
+      const double d = block_reduce_sum(p2, sh) + ac[j];
+      if (threadIdx.x == 0) dots[c] = d;
+    }
+    __syncthreads();
+    for (int c = j + 1; c < s; ++c) {
+      double *ac = A + (size_t)c * m;
+      const double w = t * dots[c];
+      for (int i = j + 1 + threadIdx.x; i < m; i += 256) ac[i] -= w * a[i];
+      if (threadIdx.x == 0) ac[j] -= w;
+    }
+    __syncthreads();
+  }
+  // form Q = H_0 ... H_{k-1} [I; 0] backwards, in place (v_j below the diagonal)
+  for (int j = kmax - 1; j >= 0; --j) {
+    const double t = tau[j];
+    double *a = A + (size_t)j * m;
+    // columns c > j currently hold Q's columns (rows >= j+1 meaningful, rows <= j set)
+    for (int c = j + 1; c < s; ++c) {
+      const double *ac = A + (size_t)c * m;
+      double p2 = 0.0;
+      for (int i = j + 1 + threadIdx.x; i < m; i += 256) p2 += a[i] * ac[i];
+      const double d = block_reduce_sum(p2, sh);  // row j of column c is 0
+      if (threadIdx.x == 0) dots[c] = d;
+    }
+    __syncthreads();
+    for (int c = j + 1; c < s; ++c) {
+      double *ac = A + (size_t)c * m;
+      const double w = t * dots[c];
+      for (int i = j + 1 + threadIdx.x; i < m; i += 256) ac[i] -= w * a[i];
+      if (threadIdx.x == 0) ac[j] = -w;
+    }
+    __syncthreads();
+    // column j: H_j e_j = e_j - t v
+    for (int i = j + 1 + threadIdx.x; i < m; i += 256) a[i] = -t * a[i];
+    if (threadIdx.x == 0) a[j] = 1.0 - t;
+    for (int i = threadIdx.x; i < j; i += 256) a[i] = 0.0;
+    __syncthreads();
+  }
+  // columns beyond min(s, m) (only when m < s): zero
+  for (int c = kmax; c < s; ++c)
+    for (int i = threadIdx.x; i < m; i += 256) A[(size_t)c * m + i] = 0.0;
+}
+
+// -------------------------------------------------- one-sided Jacobi SVD
+// X (n x s, column-major) -> X V with mutually orthogonal columns; V (s x s,
+// column-major) accumulates the rotations.  Round-robin pair ordering, four
+// threads per pair; stops when a sweep performs no rotation.
+struct JacJob {
+  double *X;
+  double *V;
+  int n;
+};
+
+__global__ __launch_bounds__(256) void k_jacobi(const JacJob *__restrict__ jobs, int s,
+                                                int max_sweeps, int *__restrict__ sweeps_out) {
+  __shared__ int rotated;
+  const JacJob J = jobs[blockIdx.x];
+  const int n = J.n;
+  double *X = J.X, *V = J.V;
+  for (int e = threadIdx.x; e < s * s; e += 256) V[e] = (e / s == e % s) ? 1.0 : 0.0;
+  __syncthreads();
+  const int grp = threadIdx.x >> 2, sub = threadIdx.x & 3;  // 64 pairs x 4 threads
+  const int npairs = s / 2;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < s - 1; ++round) {
+      if (grp < npairs) {
+        auto pos = [&](int i) { return i == 0 ? 0 : 1 + (i - 1 + round) % (s - 1); };
+        int p = pos(grp), q = pos(s - 1 - grp);
+        if (p > q) { const int t = p; p = q; q = t; }
+        double *xp = X + (size_t)p * n, *xq = X + (size_t)q * n;
+        double a = 0, b = 0, g = 0;
+        for (int i = sub; i < n; i += 4) {
+          const double u = xp[i], v = xq[i];
+          a += u * u; b += v * v; g += u * v;
+        }
+        // combine the 4 partial sums of the group (lanes 4k..4k+3)
+        for (int off = 1; off < 4; off <<= 1) {
+          a += __shfl_xor(a, off, 64);
+          b += __shfl_xor(b, off, 64);
+          g += __shfl_xor(g, off, 64);
+        }
+        if (g != 0.0 && fabs(g) > 1e-15 * sqrt(a * b)) {
+          const double zeta = (b - a) / (2.0 * g);
+          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          for (int i = sub; i < n; i += 4) {
+            const double u = xp[i], v = xq[i];
+            xp[i] = c * u - sn * v;
+            xq[i] = sn * u + c * v;
+          }
+          double *vp = V + (size_t)p * s, *vq = V + (size_t)q * s;
+          for (int i = sub; i < s; i += 4) {
+            const double u = vp[i], v = vq[i];
+            vp[i] = c * u - sn * v;
+            vq[i] = sn * u + c * v;
+          }
+          if (sub == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sweeps_out) sweeps_out[blockIdx.x] = sweep;
+}
+
+// sigma_k = |X_k| for every column (sigma out: s per job)
+__global__ __launch_bounds__(256) void k_col_norms(const JacJob *__restrict__ jobs, int s,
+                                                   double *__restrict__ sigma) {
+  __shared__ double sh[8];
+  const JacJob J = jobs[blockIdx.x];
+  for (int k = 0; k < s; ++k) {
+    double p = 0.0;
+    for (int i = threadIdx.x; i < J.n; i += 256) {
+      const double v = J.X[(size_t)k * J.n + i];
+      p += v * v;
+    }
+    const double t = block_reduce_sum(p, sh);
+    if (threadIdx.x == 0) sigma[(size_t)blockIdx.x * s + k] = sqrt(t);
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- packing
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
+  const unsigned lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+
+template <typename F> struct FactorIO;
+template <> struct FactorIO<unsigned short> {
+  static __device__ __forceinline__ unsigned short put(double v) { return f32_to_bf16((float)v); }
+  static __device__ __forceinline__ float get(unsigned short v) { return bf16_to_f32(v); }
+};
+template <> struct FactorIO<float> {
+  static __device__ __forceinline__ float put(double v) { return (float)v; }
+  static __device__ __forceinline__ float get(float v) { return v; }
+};
+template <> struct FactorIO<double> {
+  static __device__ __forceinline__ double put(double v) { return v; }
+  static __device__ __forceinline__ double get(double v) { return v; }
+};
+
+struct PackJob {
+  const double *Q;    // m x s col-major
+  const double *X;    // n x s col-major (rotated)
+  const double *V;    // s x s col-major
+  const int *sel;     // selected columns (rank entries)
+  int m, n, rank;
+  long long off_u, off_v;
+};
+
+// U = Q V_sel (m x rank, row-major), Vt = X_sel^T (rank x n, row-major)
+template <typename F>
+__global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, int s,
+                                              F *__restrict__ store) {
+  const PackJob J = jobs[blockIdx.y];
+  const size_t tot_u = (size_t)J.m * J.rank, tot_v = (size_t)J.rank * J.n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot_u + tot_v;
+       e += (size_t)gridDim.x * blockDim.x) {
+    if (e < tot_u) {
+      const int i = (int)(e / J.rank), k = (int)(e % J.rank);
+      const int col = J.sel[k];
+      double v = 0.0;
+      for (int q = 0; q < s; ++q) v += J.Q[(size_t)q * J.m + i] * J.V[(size_t)col * s + q];
+      store[J.off_u + e] = FactorIO<F>::put(v);
+    } else {
+      const size_t f = e - tot_u;
+      const int k = (int)(f / J.n), c = (int)(f % J.n);
+      store[J.off_v + f] = FactorIO<F>::put(J.X[(size_t)J.sel[k] * J.n + c]);
+    }
+  }
+}
+
+struct LeafJob {
+  const void *S;
+  int r0, n;
+  long long off;
+};
+
+template <typename T, typename F>
+__global__ void k_pack_leaf(const LeafJob *__restrict__ jobs, const int *__restrict__ perm,
+                            int ld, F *__restrict__ store) {
+  const LeafJob J = jobs[blockIdx.y];
+  const T *S = static_cast<const T *>(J.S);
+  const size_t tot = (size_t)J.n * J.n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int gr = J.r0 + (int)(e / J.n), gc = J.r0 + (int)(e % J.n);
+    if (perm) { gr = perm[gr]; gc = perm[gc]; }
+    store[J.off + e] = FactorIO<F>::put((double)S[(size_t)gr * ld + gc]);
+  }
+}
+
+// ------------------------------------------------------------------- apply
+// y_out[rows] -= sum over contributions of B x_in[cols] (or B^T for trans),
+// x and y in cluster order, interface-major with stride ld.  Products are
+// accumulated in FP32 for BF16 / FP32 factors and in FP64 for FP64 ones.
+template <typename F>
+__global__ __launch_bounds__(256) void k_hodlr_apply(const LrJob *__restrict__ jobs,
+                                                     const Contrib *__restrict__ con,
+                                                     const F *__restrict__ store,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ y, int ld) {
+  using Acc = typename std::conditional<std::is_same<F, double>::value, double, float>::type;
+  __shared__ Acc t[128];
+  const LrJob J = jobs[blockIdx.x];
+  const int rows = J.r1 - J.r0;
+  double *yo = y + (size_t)J.out_iface * ld + J.r0;
+  for (int ci = 0; ci < J.count; ++ci) {
+    const Contrib C = con[J.first + ci];
+    const double *xin = x + (size_t)C.in_iface * ld + C.c0;
+    const int ncol = C.c1 - C.c0;
+    if (C.rank < 0) {  // dense (square) leaf, stored row-major
+      const F *Lf = store + C.off_u;
+      for (int r = threadIdx.x; r < rows; r += 256) {
+        Acc acc = 0;
+        if (!C.trans)
+          for (int c = 0; c < ncol; ++c) acc += (Acc)FactorIO<F>::get(Lf[(size_t)r * ncol + c]) * (Acc)xin[c];
+        else
+          for (int c = 0; c < ncol; ++c) acc += (Acc)FactorIO<F>::get(Lf[(size_t)c * rows + r]) * (Acc)xin[c];
+        yo[r] -= (double)acc;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int rk = C.rank;
+    // t = Vt x (or U^T x for the transpose): one wavefront per entry of t
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = wave; k < rk; k += 4) {
+      Acc acc = 0;
+      if (!C.trans) {
+        const F *v = store + C.off_v + (size_t)k * ncol;
+        for (int c = lane; c < ncol; c += 64) acc += (Acc)FactorIO<F>::get(v[c]) * (Acc)xin[c];
+      } else {
+        const F *u = store + C.off_u;
+        for (int c = lane; c < ncol; c += 64)
+          acc += (Acc)FactorIO<F>::get(u[(size_t)c * rk + k]) * (Acc)xin[c];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+      if (lane == 0) t[k] = acc;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < rows; r += 256) {
+      Acc acc = 0;
+      if (!C.trans) {
+        const F *u = store + C.off_u + (size_t)r * rk;
+        for (int k = 0; k < rk; ++k) acc += (Acc)FactorIO<F>::get(u[k]) * t[k];
+      } else {
+        const F *v = store + C.off_v;
+        for (int k = 0; k < rk; ++k) acc += (Acc)FactorIO<F>::get(v[(size_t)k * rows + r]) * t[k];
+      }
+      yo[r] -= (double)acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Gather to cluster order (inverse = 0: dst[i] = src[perm[i]]) or scatter
+// back (inverse = 1: dst[perm[i]] = src[i]); padding entries are zero.
+__global__ void k_permute(const double *__restrict__ src, double *__restrict__ dst,
+                          const int *__restrict__ perm, int M, int ld, int inverse) {
+  const int j = blockIdx.y;
+  const double *sj = src + (size_t)j * ld;
+  double *dj = dst + (size_t)j * ld;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += gridDim.x * blockDim.x) {
+    if (i >= M) {
+      dj[i] = 0.0;
+    } else if (inverse) {
+      dj[perm[i]] = sj[i];
+    } else {
+      dj[i] = sj[perm[i]];
+    }
+  }
+}
+
+__global__ void k_copy_d(const double *__restrict__ s, double *__restrict__ d, size_t n) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) d[e] = s[e];
+}
+
+inline unsigned nb(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// ----------------------------------------------------------- host helpers
+struct HipErr : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+#define HCHK(x)                                                                        \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) throw HipErr(std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DMem {
+  void *p = nullptr;
+  explicit DMem(size_t b) {
+    if (b && hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+  }
+  ~DMem() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename X>
+  X *as() const { return static_cast<X *>(p); }
+};
+
+template <typename J>
+void *upload(const std::vector<J> &v, hipStream_t s, std::vector<DMem *> &keep) {
+  DMem *m = new DMem(std::max<size_t>(v.size(), 1) * sizeof(J));
+  keep.push_back(m);
+  if (!v.empty()) HCHK(hipMemcpyAsync(m->p, v.data(), v.size() * sizeof(J), hipMemcpyHostToDevice, s));
+  return m->p;
+}
+
+struct Node {
+  int lo, hi;                 // cluster-order range
+  std::vector<int> kids;      // indices into the node list
+  int level;
+};
+
+// Build the cluster tree; perm maps cluster order to natural order.
+void build_tree(int dim, int n, int M, int tree, int leaf, std::vector<Node> &nodes,
+                std::vector<int> &perm) {
+  nodes.clear();
+  perm.clear();
+  if (tree == DDST_TREE_BINARY || dim == 2) {
+    perm.resize(M);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::vector<int> stack;
+    nodes.push_back({0, M, {}, 0});
+    stack.push_back(0);
+    while (!stack.empty()) {
+      const int id = stack.back();
+      stack.pop_back();
+      const int lo = nodes[id].lo, hi = nodes[id].hi;
+      if (hi - lo <= leaf) continue;
+      const int mid = lo + (hi - lo + 1) / 2;
+      for (auto r : {std::make_pair(lo, mid), std::make_pair(mid, hi)}) {
+        nodes.push_back({r.first, r.second, {}, nodes[id].level + 1});
+        nodes[id].kids.push_back((int)nodes.size() - 1);
+        stack.push_back((int)nodes.size() - 1);
+      }
+    }
+    return;
+  }
+  // quadtree over the n x n interface grid (natural index y*n + z)
+  // first pass: build the tree of rectangles, assign ranges by DFS order
+  struct RNode { int y0, y1, z0, z1, level; std::vector<int> kids; };
+  std::vector<RNode> rn;
+  rn.push_back({0, n, 0, n, 0, {}});
+  std::vector<int> st = {0};
+  while (!st.empty()) {
+    const int id = st.back();
+    st.pop_back();
+    const RNode r = rn[id];
+    const int size = (r.y1 - r.y0) * (r.z1 - r.z0);
+    if (size <= leaf || (r.y1 - r.y0 < 2 && r.z1 - r.z0 < 2)) continue;
+    const int ym = r.y0 + (r.y1 - r.y0 + 1) / 2, zm = r.z0 + (r.z1 - r.z0 + 1) / 2;
+    const int ys[3] = {r.y0, ym, r.y1}, zs[3] = {r.z0, zm, r.z1};
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        if (ys[a + 1] > ys[a] && zs[b + 1] > zs[b]) {
+          rn.push_back({ys[a], ys[a + 1], zs[b], zs[b + 1], r.level + 1, {}});
+          rn[id].kids.push_back((int)rn.size() - 1);
+          st.push_back((int)rn.size() - 1);
+        }
+  }
+  // depth-first numbering: leaves in DFS order give the permutation
+  nodes.resize(rn.size());
+  std::function<void(int)> visit = [&](int id) {
+    Node nd;
+    nd.level = rn[id].level;
+    nd.lo = (int)perm.size();
+    if (rn[id].kids.empty()) {
+      for (int y = rn[id].y0; y < rn[id].y1; ++y)
+        for (int z = rn[id].z0; z < rn[id].z1; ++z) perm.push_back(y * n + z);
+    } else {
+      for (int k : rn[id].kids) visit(k);
+    }
+    nd.hi = (int)perm.size();
+    nd.kids = rn[id].kids;
+    nodes[id] = nd;
+  };
+  visit(0);
+}
+
+template <typename T, typename F>
+int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, int *overflow) {
+  Hodlr *H = new Hodlr();
+  std::vector<DMem *> keep;
+  auto cleanup = [&]() {
+    for (DMem *m : keep) delete m;
+    keep.clear();
+  };
+  auto drop = [&]() {
+    if (H->d_perm) (void)hipFree(H->d_perm);
+    if (H->factors) (void)hipFree(H->factors);
+    if (H->jobs) (void)hipFree(H->jobs);
+    if (H->pbuf) (void)hipFree(H->pbuf);
+    delete H;
+  };
+  try {
+    H->tree = o.tree;
+    H->leaf = o.leaf;
+    H->dtype = o.factor_dtype;
+    // An FP32-built transfer block resolves singular values only down to a
+    // few units of eps32 times its norm; below that the tail is rounding
+    // noise, so the FP32 path truncates no lower than 1e-6.
+    H->tol_used = (op->prec == DDST_FP32) ? std::max(o.tol, 1e-6) : o.tol;
+    std::vector<Node> nodes;
+    build_tree(op->dim, op->n, op->M, o.tree, o.leaf, nodes, H->perm);
+    bool identity = true;
+    for (int i = 0; i < op->M; ++i) identity = identity && H->perm[i] == i;
+    const int *d_perm = nullptr;
+    if (!identity) {
+      HCHK(hipMalloc(&H->d_perm, op->M * sizeof(int)));
+      HCHK(hipMemcpyAsync(H->d_perm, H->perm.data(), op->M * sizeof(int), hipMemcpyHostToDevice,
+                          st));
+      HCHK(hipMalloc(&H->pbuf, (size_t)2 * op->n_ds * op->ld * sizeof(double)));
+      d_perm = H->d_perm;
+    }
+    // transfer matrices that exist
+    std::vector<int> mats;
+    for (int j = 1; j <= op->n_ds; ++j) {
+      if (j >= 2) mats.push_back(2 * (j - 1));
+      if (j <= op->n_ds - 1) mats.push_back(2 * (j - 1) + 1);
+    }
+    const int nmat = (int)mats.size();
+    auto Sptr = [&](int sm) {
+      return static_cast<const void *>(static_cast<unsigned char *>(op->S) +
+                                       (size_t)sm * op->mat_bytes);
+    };
+    // ---- ||S||_2 of every transfer matrix: power iteration on S^T S
+    std::vector<double> snorm(2 * op->n_ds, 0.0);
+    if (nmat > 0) {
+      DMem vec((size_t)2 * nmat * op->ld * sizeof(double));
+      double *v0 = static_cast<double *>(vec.p), *v1 = v0 + (size_t)nmat * op->ld;
+      std::vector<double> h((size_t)nmat * op->ld, 0.0);
+      for (int b = 0; b < nmat; ++b)
+        for (int i = 0; i < op->M; ++i) h[(size_t)b * op->ld + i] = 1.0 + 0.37 * std::sin(1.7 * i + b);
+      std::vector<GemvJob> fw, bw;
+      for (int b = 0; b < nmat; ++b) {
+        GemvJob g{};
+        g.G = Sptr(mats[b]);
+        g.x1 = v0 + (size_t)b * op->ld;
+        g.out = v1 + (size_t)b * op->ld;
+        fw.push_back(g);
+        GemvJob q{};
+        q.G = Sptr(mats[b]);
+        q.x1 = v1 + (size_t)b * op->ld;
+        q.out = v0 + (size_t)b * op->ld;
+        bw.push_back(q);
+      }
+      const GemvJob *dfw = static_cast<const GemvJob *>(upload(fw, st, keep));
+      const GemvJob *dbw = static_cast<const GemvJob *>(upload(bw, st, keep));
+      const int nchunk = std::min(op->ld / kGemvChunk, 64);
+      DMem part((size_t)nmat * nchunk * op->ld * sizeof(double));
+      for (int it = 0; it < 8; ++it) {
+        HCHK(hipMemcpyAsync(v0, h.data(), h.size() * 8, hipMemcpyHostToDevice, st));
+        launch_gemv<T>(dfw, nmat, op->ld, op->M, 0, 1.0, static_cast<double *>(part.p), st);
+        launch_gemv<T>(dbw, nmat, op->ld, op->M, 1, 1.0, static_cast<double *>(part.p), st);
+        HCHK(hipMemcpyAsync(h.data(), v0, h.size() * 8, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+        for (int b = 0; b < nmat; ++b) {
+          double ss = 0;
+          for (int i = 0; i < op->M; ++i) ss += h[(size_t)b * op->ld + i] * h[(size_t)b * op->ld + i];
+          const double nv = std::sqrt(ss);  // = sigma_max^2 for a converged unit vector
+          snorm[mats[b]] = std::sqrt(nv);
+          for (int i = 0; i < op->M; ++i) h[(size_t)b * op->ld + i] /= (nv > 0 ? nv : 1.0);
+        }
+      }
+    }
+    // ---- admissible pairs per tree level, and the leaves
+    std::vector<std::vector<std::pair<int, int>>> lev;
+    std::vector<int> leaves;
+    for (size_t id = 0; id < nodes.size(); ++id) {
+      const Node &nd = nodes[id];
+      if (nd.kids.empty()) {
+        leaves.push_back((int)id);
+        continue;
+      }
+      if ((int)lev.size() <= nd.level) lev.resize(nd.level + 1);
+      for (int a : nd.kids)
+        for (int b : nd.kids)
+          if (a != b) lev[nd.level].push_back({a, b});
+    }
+    H->nlev = (int)lev.size();
+    const int s_cap = std::min(o.max_rank + o.oversample, 128);
+    size_t store_elems = 0;
+    for (int m : mats)
+      for (int lf : leaves) {
+        HBlock b{};
+        b.smat = m;
+        b.r0 = nodes[lf].lo;
+        b.r1 = nodes[lf].hi;
+        b.c0 = b.r0;
+        b.c1 = b.r1;
+        b.level = -1;
+        b.rank = -1;
+        b.off_u = store_elems;
+        store_elems += (size_t)(b.r1 - b.r0) * (b.r1 - b.r0);
+        H->blocks.push_back(b);
+      }
+    // ---- compress level by level (FP64 staging kept until packing)
+    struct LevelData {
+      DMem *Y = nullptr, *X = nullptr, *V = nullptr, *sig = nullptr, *sel = nullptr;
+      int s = 0;
+      std::vector<HBlock> blocks;
+      std::vector<size_t> offY, offX;
+      std::vector<int> selofs;
+    };
+    std::vector<LevelData> levels;
+    int worst = 0;
+    for (size_t L = 0; L < lev.size(); ++L) {
+      if (lev[L].empty() || nmat == 0) continue;
+      int mmax = 0, nmax = 0, mnmin = 1 << 30;
+      for (auto &pr : lev[L]) {
+        const int m = nodes[pr.first].hi - nodes[pr.first].lo;
+        const int n = nodes[pr.second].hi - nodes[pr.second].lo;
+        mmax = std::max(mmax, m);
+        nmax = std::max(nmax, n);
+        mnmin = std::min(mnmin, std::min(m, n));
+      }
+      int s = std::min(s_cap, mnmin);
+      s -= s & 1;
+      if (s < 2) s = 2;
+      const bool capped = (s == s_cap - (s_cap & 1));
+      LevelData D;
+      D.s = s;
+      size_t totY = 0, totX = 0;
+      for (int mi = 0; mi < nmat; ++mi)
+        for (auto &pr : lev[L]) {
+          HBlock b{};
+          b.smat = mats[mi];
+          b.r0 = nodes[pr.first].lo;
+          b.r1 = nodes[pr.first].hi;
+          b.c0 = nodes[pr.second].lo;
+          b.c1 = nodes[pr.second].hi;
+          b.level = (int)L;
+          D.blocks.push_back(b);
+          D.offY.push_back(totY);
+          D.offX.push_back(totX);
+          totY += (size_t)(b.r1 - b.r0) * s;
+          totX += (size_t)(b.c1 - b.c0) * s;
+        }
+      const int nbk = (int)D.blocks.size();
+      D.Y = new DMem(totY * 8); keep.push_back(D.Y);
+      D.X = new DMem(totX * 8); keep.push_back(D.X);
+      D.V = new DMem((size_t)nbk * s * s * 8); keep.push_back(D.V);
+      D.sig = new DMem((size_t)nbk * s * 8); keep.push_back(D.sig);
+      DMem om((size_t)nmax * s * 8);
+      hipLaunchKernelGGL(k_gaussian, dim3(nb((size_t)nmax * s)), dim3(256), 0, st,
+                         static_cast<double *>(om.p), nmax, s, (unsigned long long)o.seed, (int)L);
+      std::vector<BlockGemmJob> gy, gx;
+      std::vector<QrJob> qr;
+      std::vector<JacJob> jac;
+      for (int b = 0; b < nbk; ++b) {
+        const HBlock &hb = D.blocks[b];
+        const int m = hb.r1 - hb.r0, n = hb.c1 - hb.c0;
+        double *Yb = static_cast<double *>(D.Y->p) + D.offY[b];
+        double *Xb = static_cast<double *>(D.X->p) + D.offX[b];
+        gy.push_back({Sptr(hb.smat), hb.r0, hb.c0, m, n, Yb, static_cast<double *>(om.p)});
+        gx.push_back({Sptr(hb.smat), hb.r0, hb.c0, m, n, Xb, Yb});
+        qr.push_back({Yb, m});
+        jac.push_back({Xb, static_cast<double *>(D.V->p) + (size_t)b * s * s, n});
+      }
+      const BlockGemmJob *dgy = static_cast<const BlockGemmJob *>(upload(gy, st, keep));
+      const BlockGemmJob *dgx = static_cast<const BlockGemmJob *>(upload(gx, st, keep));
+      const QrJob *dqr = static_cast<const QrJob *>(upload(qr, st, keep));
+      const JacJob *djac = static_cast<const JacJob *>(upload(jac, st, keep));
+      hipLaunchKernelGGL(k_block_gemm<T>, dim3((mmax + 63) / 64, nbk), dim3(256), 0, st, dgy,
+                         d_perm, op->ld, s, 0);
+      hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(256), 0, st, dqr, s);
+      hipLaunchKernelGGL(k_block_gemm<T>, dim3((nmax + 63) / 64, nbk), dim3(256), 0, st, dgx,
+                         d_perm, op->ld, s, 1);
+      hipLaunchKernelGGL(k_jacobi, dim3(nbk), dim3(256), 0, st, djac, s, 30, (int *)nullptr);
+      hipLaunchKernelGGL(k_col_norms, dim3(nbk), dim3(256), 0, st, djac, s,
+                         static_cast<double *>(D.sig->p));
+      HCHK(hipGetLastError());
+      std::vector<double> sig((size_t)nbk * s);
+      HCHK(hipMemcpyAsync(sig.data(), D.sig->p, sig.size() * 8, hipMemcpyDeviceToHost, st));
+      HCHK(hipStreamSynchronize(st));
+      std::vector<int> selall;
+      for (int b = 0; b < nbk; ++b) {
+        HBlock &hb = D.blocks[b];
+        const double thr = H->tol_used * snorm[hb.smat];
+        std::vector<std::pair<double, int>> sv;
+        for (int k = 0; k < s; ++k) sv.push_back({sig[(size_t)b * s + k], k});
+        std::sort(sv.begin(), sv.end(),
+                  [](const std::pair<double, int> &a, const std::pair<double, int> &c) {
+                    return a.first > c.first;
+                  });
+        int r = 0;
+        while (r < s && sv[r].first > thr) ++r;
+        // the sample count bounds the rank that can be certified: with the
+        // cap in force, a rank within `oversample` of s is a rank overflow
+        if (capped && r > s - o.oversample) worst = std::max(worst, r);
+        hb.rank = r;
+        hb.off_u = store_elems;
+        store_elems += (size_t)(hb.r1 - hb.r0) * r;
+        hb.off_v = store_elems;
+        store_elems += (size_t)r * (hb.c1 - hb.c0);
+        D.selofs.push_back((int)selall.size());
+        for (int k = 0; k < r; ++k) selall.push_back(sv[k].second);
+        H->max_rank = std::max(H->max_rank, r);
+        H->min_rank = std::min(H->min_rank, r);
+      }
+      D.sel = new DMem(std::max<size_t>(selall.size(), 1) * sizeof(int));
+      keep.push_back(D.sel);
+      if (!selall.empty())
+        HCHK(hipMemcpyAsync(D.sel->p, selall.data(), selall.size() * sizeof(int),
+                            hipMemcpyHostToDevice, st));
+      HCHK(hipStreamSynchronize(st));
+      levels.push_back(std::move(D));
+    }
+    if (worst > 0) {
+      cleanup();
+      drop();
+      *overflow = worst;
+      return DDST_ERANK;
+    }
+    // ---- pack factors
+    H->bytes = store_elems * sizeof(F);
+    HCHK(hipMalloc(&H->factors, std::max<size_t>(H->bytes, 16)));
+    F *store = static_cast<F *>(H->factors);
+    std::vector<LeafJob> lj;
+    for (const HBlock &b : H->blocks)
+      if (b.rank < 0) lj.push_back({Sptr(b.smat), b.r0, b.r1 - b.r0, (long long)b.off_u});
+    if (!lj.empty()) {
+      const LeafJob *d = static_cast<const LeafJob *>(upload(lj, st, keep));
+      hipLaunchKernelGGL((k_pack_leaf<T, F>), dim3(64, (unsigned)lj.size()), dim3(256), 0, st,
+                         d, d_perm, op->ld, store);
+    }
+    for (LevelData &D : levels) {
+      const int nbk = (int)D.blocks.size();
+      std::vector<PackJob> pj;
+      for (int b = 0; b < nbk; ++b) {
+        const HBlock &hb = D.blocks[b];
+        pj.push_back({static_cast<double *>(D.Y->p) + D.offY[b], static_cast<double *>(D.X->p) + D.offX[b],
+                      static_cast<double *>(D.V->p) + (size_t)b * D.s * D.s, static_cast<int *>(D.sel->p) + D.selofs[b],
+                      hb.r1 - hb.r0, hb.c1 - hb.c0, hb.rank, (long long)hb.off_u,
+                      (long long)hb.off_v});
+        H->blocks.push_back(hb);
+      }
+      const PackJob *d = static_cast<const PackJob *>(upload(pj, st, keep));
+      hipLaunchKernelGGL(k_pack<F>, dim3(32, nbk), dim3(256), 0, st, d, D.s, store);
+    }
+    HCHK(hipGetLastError());
+    HCHK(hipStreamSynchronize(st));
+    // ---- apply tables.  Transfer matrix sm = 2j (S_{j+1,j}, 0-based j here
+    // means output interface sm/2 reading interface sm/2 - 1) or 2j+1
+    // (reading sm/2 + 1).  For S^T, (S^T)_{a,b} = S_{b,a}^T: the block of
+    // matrix sm is applied transposed from its output interface to its input.
+    std::vector<LrJob> jobs;
+    std::vector<Contrib> con;
+    auto in_iface = [](int sm) { return (sm & 1) ? (sm >> 1) + 1 : (sm >> 1) - 1; };
+    auto out_iface = [](int sm) { return sm >> 1; };
+    for (int dir = 0; dir < 2; ++dir) {
+      H->off_lr[dir].assign(H->nlev, 0);
+      H->n_lr[dir].assign(H->nlev, 0);
+      for (int L = -1; L < H->nlev; ++L) {
+        std::vector<std::tuple<int, int, int, int>> keys;  // out iface, r0, r1, block
+        for (size_t bi = 0; bi < H->blocks.size(); ++bi) {
+          const HBlock &b = H->blocks[bi];
+          if (b.level != L) continue;
+          const int oi = dir ? in_iface(b.smat) : out_iface(b.smat);
+          keys.push_back({oi, dir ? b.c0 : b.r0, dir ? b.c1 : b.r1, (int)bi});
+        }
+        std::sort(keys.begin(), keys.end());
+        const size_t first_job = jobs.size();
+        for (size_t k = 0; k < keys.size();) {
+          size_t e = k;
+          while (e < keys.size() && std::get<0>(keys[e]) == std::get<0>(keys[k]) &&
+                 std::get<1>(keys[e]) == std::get<1>(keys[k]))
+            ++e;
+          LrJob jb{std::get<0>(keys[k]), std::get<1>(keys[k]), std::get<2>(keys[k]),
+                   (int)con.size(), (int)(e - k)};
+          for (size_t q = k; q < e; ++q) {
+            const HBlock &b = H->blocks[std::get<3>(keys[q])];
+            Contrib c{};
+            c.in_iface = dir ? out_iface(b.smat) : in_iface(b.smat);
+            c.c0 = dir ? b.r0 : b.c0;
+            c.c1 = dir ? b.r1 : b.c1;
+            c.rank = b.rank;
+            c.off_u = (long long)b.off_u;
+            c.off_v = (long long)b.off_v;
+            c.trans = dir;
+            con.push_back(c);
+          }
+          jobs.push_back(jb);
+          k = e;
+        }
+        if (L < 0) {
+          H->off_leaf[dir] = first_job;
+          H->n_leaf[dir] = (int)(jobs.size() - first_job);
+        } else {
+          H->off_lr[dir][L] = first_job;
+          H->n_lr[dir][L] = (int)(jobs.size() - first_job);
+        }
+      }
+    }
+    const size_t bytes_jobs = jobs.size() * sizeof(LrJob);
+    H->off_con = (bytes_jobs + 255) & ~size_t(255);
+    HCHK(hipMalloc(&H->jobs, H->off_con + std::max<size_t>(con.size(), 1) * sizeof(Contrib)));
+    if (!jobs.empty())
+      HCHK(hipMemcpyAsync(H->jobs, jobs.data(), bytes_jobs, hipMemcpyHostToDevice, st));
+    if (!con.empty())
+      HCHK(hipMemcpyAsync(static_cast<unsigned char *>(H->jobs) + H->off_con, con.data(),
+                          con.size() * sizeof(Contrib), hipMemcpyHostToDevice, st));
+    HCHK(hipStreamSynchronize(st));
+    cleanup();
+    if (H->min_rank > H->max_rank) H->min_rank = 0;
+    hodlr_free(op);
+    op->hodlr = H;
+    return DDST_OK;
+  } catch (...) {
+    cleanup();
+    drop();
+    throw;
+  }
+}
+
+}  // namespace
+
+void hodlr_free(ddst_op *op) {
+  if (!op || !op->hodlr) return;
+  Hodlr *H = op->hodlr;
+  if (H->d_perm) (void)hipFree(H->d_perm);
+  if (H->factors) (void)hipFree(H->factors);
+  if (H->jobs) (void)hipFree(H->jobs);
+  if (H->pbuf) (void)hipFree(H->pbuf);
+  delete H;
+  op->hodlr = nullptr;
+}
+
+bool hodlr_ready(const ddst_op *op) { return op && op->hodlr != nullptr; }
+
+void hodlr_info(const ddst_op *op, double *bytes, int *max_rank, int *min_rank) {
+  const Hodlr *H = op ? op->hodlr : nullptr;
+  if (bytes) *bytes = H ? (double)H->bytes : 0.0;
+  if (max_rank) *max_rank = H ? H->max_rank : 0;
+  if (min_rank) *min_rank = H ? H->min_rank : 0;
+}
+
+int hodlr_compress(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t s, int *overflow) {
+  if (op->prec == DDST_FP32) {
+    switch (o.factor_dtype) {
+      case DDST_FACTOR_BF16: return compress_impl<float, unsigned short>(op, o, s, overflow);
+      case DDST_FACTOR_FP32: return compress_impl<float, float>(op, o, s, overflow);
+      default: return compress_impl<float, double>(op, o, s, overflow);
+    }
+  }
+  switch (o.factor_dtype) {
+    case DDST_FACTOR_BF16: return compress_impl<double, unsigned short>(op, o, s, overflow);
+    case DDST_FACTOR_FP32: return compress_impl<double, float>(op, o, s, overflow);
+    default: return compress_impl<double, double>(op, o, s, overflow);
+  }
+}
+
+// y = S x (transpose 0) or S^T x (1) for padded interface vectors x, y
+// (distinct buffers), through the compressed blocks.
+int hodlr_apply_jobs(const ddst_op *op, const double *x, double *y, int transpose,
+                     hipStream_t s) {
+  Hodlr *H = op->hodlr;
+  if (!H) return DDST_ESTATE;
+  const int dir = transpose ? 1 : 0;
+  const LrJob *jobs = static_cast<const LrJob *>(H->jobs);
+  const Contrib *con = reinterpret_cast<const Contrib *>(
+      static_cast<const unsigned char *>(H->jobs) + H->off_con);
+  const size_t len = (size_t)op->n_ds * op->ld;
+  const bool perm = H->d_perm != nullptr;
+  double *xp = perm ? H->pbuf : nullptr;
+  double *yp = perm ? H->pbuf + len : y;
+  if (perm)
+    hipLaunchKernelGGL(k_permute, dim3(nb(op->ld), op->n_ds), dim3(256), 0, s, x, xp, H->d_perm,
+                       op->M, op->ld, 0);
+  const double *xi = perm ? xp : x;
+  hipLaunchKernelGGL(k_copy_d, dim3(nb(len)), dim3(256), 0, s, xi, yp, len);
+  auto launch = [&](size_t first, int count) {
+    if (count <= 0) return;
+    switch (H->dtype) {
+      case DDST_FACTOR_BF16:
+        hipLaunchKernelGGL(k_hodlr_apply<unsigned short>, dim3(count), dim3(256), 0, s,
+                           jobs + first, con, static_cast<const unsigned short *>(H->factors), xi,
+                           yp, op->ld);
+        break;
+      case DDST_FACTOR_FP32:
+        hipLaunchKernelGGL(k_hodlr_apply<float>, dim3(count), dim3(256), 0, s, jobs + first, con,
+                           static_cast<const float *>(H->factors), xi, yp, op->ld);
+        break;
+      default:
+        hipLaunchKernelGGL(k_hodlr_apply<double>, dim3(count), dim3(256), 0, s, jobs + first,
+                           con, static_cast<const double *>(H->factors), xi, yp, op->ld);
+    }
+  };
+  prof_begin(KK_GEMV, s);
+  launch(H->off_leaf[dir], H->n_leaf[dir]);
+  for (int L = 0; L < H->nlev; ++L) launch(H->off_lr[dir][L], H->n_lr[dir][L]);
+  prof_end(KK_GEMV, s, (double)H->bytes);
+  if (perm)
+    hipLaunchKernelGGL(k_permute, dim3(nb(op->ld), op->n_ds), dim3(256), 0, s, yp, y, H->d_perm,
+                       op->M, op->ld, 1);
+  return hipGetLastError() == hipSuccess ? DDST_OK : DDST_EHIP;
+}
+
+}  // namespace ddst

@@ -21,6 +21,7 @@
 struct ddst_op;
 
 namespace ddst {
+struct Hodlr;
 
 constexpr int kTile = 128;   // GEMM / update output tile (rows and cols)
 constexpr int kNB = 64;      // Gauss-Jordan block width
@@ -148,7 +149,9 @@ void launch_extract_block(const void *src, int prec, int M, int ld, double *dst,
 // ---- compressed form (hodlr.hip) -----------------------------------------
 void hodlr_free(ddst_op *op);
 bool hodlr_ready(const ddst_op *op);
-int hodlr_compress(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t s);
+// returns DDST_OK or DDST_ERANK (then *overflow = the largest rank found)
+int hodlr_compress(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t s, int *overflow);
+void hodlr_info(const ddst_op *op, double *bytes, int *max_rank, int *min_rank);
 // y = S x or S^T x through the compressed blocks (padded interface vectors)
 int hodlr_apply_jobs(const ddst_op *op, const double *x, double *y, int transpose,
                      hipStream_t s);
@@ -174,7 +177,7 @@ struct ddst_op {
   void *G = nullptr;          // n_slabs*(m-1) factor matrices (own allocation)
   int *flag = nullptr;        // device breakdown flag
   // compressed form (hodlr.hip)
-  struct Hodlr *hodlr = nullptr;
+  ddst::Hodlr *hodlr = nullptr;
   // reusable solve workspace (grown on demand)
   void *ws = nullptr;
   size_t ws_bytes = 0;

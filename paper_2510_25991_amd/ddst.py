@@ -73,7 +73,7 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_adjoint",
            "ddst_release_factors", "ddst_destroy", "ddst_last_error", "ddst_op_info",
            "ddst_get_transfer", "ddst_apply", "ddst_loads", "ddst_get_factor",
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
-           "ddst_profile_enable", "ddst_profile_read"]
+           "ddst_profile_enable", "ddst_profile_read", "ddst_compress_info"]
 KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv"}
 
 _lib = None
@@ -106,6 +106,8 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_test_gemm.argtypes = [i32, i32, i32, vp, vp, vp, vp, ctypes.c_double,
                                  ctypes.c_double, vp]
     L.ddst_test_invert.argtypes = [i32, i32, i32, vp, vp]
+    L.ddst_compress_info.argtypes = [vp, P(ctypes.c_double), P(i32), P(i32),
+                                     P(ctypes.c_double)]
     L.ddst_profile_enable.argtypes = [i32]
     L.ddst_profile_read.argtypes = [i32, P(ctypes.c_int64), P(ctypes.c_double),
                                     P(ctypes.c_double)]
@@ -276,6 +278,13 @@ class Operator:
         fd = {"bf16": FACTOR_BF16, "fp32": FACTOR_FP32, "fp64": FACTOR_FP64}[factor_dtype]
         o = CompressOptsC(tree, leaf, oversample, max_rank, fd, 0, tol, seed)
         _check(load_library().ddst_compress(self._h, ctypes.byref(o), _stream()))
+        return self.compress_info()
+
+    def compress_info(self):
+        b, mx, mn, ms = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(load_library().ddst_compress_info(self._h, ctypes.byref(b), ctypes.byref(mx),
+                                                 ctypes.byref(mn), ctypes.byref(ms)))
+        return {"bytes": b.value, "max_rank": mx.value, "min_rank": mn.value, "ms": ms.value}
 
 
 def _raw_ptr(t):

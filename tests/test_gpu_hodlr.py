@@ -1,0 +1,139 @@
+"""Parity of the randomized HODLR compression (through the C-ABI).
+
+The oracle's reference is the optimal-rank HODLR of the same partition
+(truncated SVD of every admissible block).  The randomized compression sees
+Q Q^T B instead of B, so its truncation keeps at most the optimal number of
+singular values above the threshold: ranks <= oracle rank, and the
+operator error is bounded by the discarded tail plus the range-finder
+error, a small multiple of tol per level:
+    ||S - S_H||_2 / ||S||_2 <= 4 * levels * tol   (FP64 factors).
+BF16 factors store each entry to about 4e-3 relative; their operator error
+is checked at 2e-2 and the solve through them is refined to 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+from problems import make_config
+from oracle import dd as odd
+from oracle import fd as ofd
+from oracle import hodlr as ohodlr
+
+pytestmark = pytest.mark.gpu
+
+
+def ddst():
+    from paper_2510_25991_amd import ddst as mod
+    return mod
+
+
+def banner(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+def op_error(op, n_iter=12, seed=0, transpose=False):
+    """||S - S_H||_2 / ||S||_2 by power iteration on the difference."""
+    rng = np.random.default_rng(seed)
+    N = op.n_ds * op.M
+    v = torch.tensor(rng.standard_normal(N), device="cuda")
+    v /= v.norm()
+    num = 0.0
+    for _ in range(n_iter):
+        d = op.apply(v, transpose=transpose, which="dense") - op.apply(v, transpose=transpose, which="hodlr")
+        dt = (op.apply(d.reshape(-1), transpose=not transpose, which="dense")
+              - op.apply(d.reshape(-1), transpose=not transpose, which="hodlr"))
+        num = float(dt.norm()) ** 0.5
+        v = dt.reshape(-1) / max(float(dt.norm()), 1e-300)
+    w = torch.tensor(rng.standard_normal(N), device="cuda")
+    for _ in range(n_iter):
+        y = op.apply(w, transpose=transpose) - w.view(op.n_ds, op.M)   # -K w
+        z = op.apply(y.reshape(-1), transpose=not transpose) - y       # K^T K w
+        den = float(z.norm()) ** 0.5
+        w = z.reshape(-1) / max(float(z.norm()), 1e-300)
+    return num / den
+
+
+def helmholtz_case():
+    # 2D oscillatory workload shape: k = 60, thin slabs (locally definite)
+    return make_config("cfg3", n=511, n_slabs=128)
+
+
+def test_binary_tree_fp64_error_and_ranks():
+    p = helmholtz_case()
+    banner(f"HODLR binary n={p.n} slabs={p.n_slabs} fp64 tol 1e-8")
+    op = ddst().Operator.from_problem(p, precision="fp64")
+    info = op.compress(tol=1e-8, leaf=128, oversample=10, max_rank=64, factor_dtype="fp64")
+    err = op_error(op)
+    errT = op_error(op, transpose=True)
+    levels = 2  # 511 -> 256/255 -> leaves of <= 128
+    print(f"  ranks {info['min_rank']}..{info['max_rank']} bytes {info['bytes']:.3e} "
+          f"err {err:.3e} errT {errT:.3e}")
+    assert err <= 4 * levels * 1e-8 and errT <= 4 * levels * 1e-8
+    # optimal ranks from the oracle, on two interior transfer blocks
+    o = odd.DDOracle(p)
+    tree = ohodlr.binary_tree(p.M, 128)
+    orank = 0
+    for j in (p.n_ds // 2, p.n_ds // 2 + 1):
+        for jp in (j - 1, j + 1):
+            H = ohodlr.compress(o.transfer_block(j, jp), tree, 1e-8)
+            orank = max(orank, max(ohodlr.ranks(H)))
+    print(f"  oracle optimal max rank {orank}")
+    assert info["max_rank"] <= orank + 2
+    assert info["max_rank"] >= max(1, orank - 4)
+    op.close()
+
+
+def test_quadtree_3d_fp64():
+    p = make_config("cfg4", n=31, n_slabs=8)
+    banner(f"HODLR quadtree 3D n={p.n} slabs={p.n_slabs} fp64 tol 1e-7")
+    op = ddst().Operator.from_problem(p, precision="fp64")
+    info = op.compress(tol=1e-7, leaf=128, oversample=10, max_rank=100, factor_dtype="fp64",
+                       tree=ddst().TREE_QUAD)
+    err = op_error(op)
+    errT = op_error(op, transpose=True)
+    print(f"  ranks {info['min_rank']}..{info['max_rank']} err {err:.3e} errT {errT:.3e}")
+    assert err <= 4 * 2 * 1e-7 and errT <= 4 * 2 * 1e-7
+    op.close()
+
+
+@pytest.mark.parametrize("name", ["helmholtz", "convdiff"])
+def test_bf16_operator_error(name):
+    p = helmholtz_case() if name == "helmholtz" else make_config("cfg2", n=511, n_slabs=16)
+    banner(f"HODLR BF16 factors on the FP32 build, {name}")
+    dd = ddst()
+    op = dd.Operator.from_problem(p, precision="fp32")
+    info = op.compress(tol=1e-8, leaf=128, oversample=10, max_rank=100, factor_dtype="bf16")
+    err = op_error(op)
+    print(f"  ranks {info['min_rank']}..{info['max_rank']} bytes {info['bytes']:.3e} "
+          f"bf16 operator err {err:.3e}")
+    assert err <= 2e-2
+    op.close()
+
+
+def test_bf16_solve_refined():
+    """Equilibrium GMRES through BF16 factors inside FP64 refinement reaches
+    the oracle's FD solution (2D convection-diffusion, 15 interfaces)."""
+    p = make_config("cfg2", n=511, n_slabs=16)
+    banner("HODLR BF16 factors, FP32 build, refined solve")
+    dd = ddst()
+    op = dd.Operator.from_problem(p, precision="fp32")
+    op.compress(tol=1e-8, leaf=128, oversample=10, max_rank=100, factor_dtype="bf16")
+    u, ug, st = op.solve(p.f, opts=dd.SolveOptions(use_hodlr=True, max_iter=300, max_outer=10,
+                                                   inner_tol=1e-5), allow_notconv=True)
+    ref = ofd.solve_global(p)
+    rel = float(np.abs(u.cpu().numpy().ravel() - ref).max() / np.abs(ref).max())
+    print(f"  solve rel err {rel:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']} "
+          f"status {st['status']}")
+    assert st["status"] == 0 and rel <= 1e-8
+    op.close()
+
+
+def test_rank_cap_reported():
+    p = helmholtz_case()
+    banner("HODLR rank cap")
+    dd = ddst()
+    op = dd.Operator.from_problem(p, precision="fp64")
+    with pytest.raises(dd.DDSTError) as e:
+        op.compress(tol=1e-12, leaf=128, oversample=4, max_rank=2, factor_dtype="fp64")
+    assert e.value.code == dd.DDST_ERANK
+    op.close()
