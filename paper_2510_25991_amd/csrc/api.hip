@@ -441,6 +441,7 @@ struct SolveWs {
   double *V;                 // Krylov basis (max_iter+1) * n_ds*ld
   double *hd;                // small scalars
   double *part;              // transposed-GEMV partial sums
+  double *dpart;             // dot-product partial sums
   double *nrm;               // norms
   size_t vol, ifc;
 };
@@ -463,7 +464,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   const int nchunk = std::min(op->ld / kGemvChunk, 64);
   const size_t part = (size_t)std::max(op->n_slabs, op->n_ds) * nchunk * op->ld;
   Carve cv;
-  size_t o[12];
+  size_t o[13];
   o[0] = cv.take(vol * 8); o[1] = cv.take(vol * 8); o[2] = cv.take(vol * 8);
   o[3] = cv.take(vol * 8);
   o[4] = cv.take(ifc * 8); o[5] = cv.take(ifc * 8); o[6] = cv.take(ifc * 8);
@@ -472,6 +473,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   o[9] = cv.take((size_t)(4 * max_iter + 16) * 8);
   o[10] = cv.take(part * 8);
   o[11] = cv.take(16 * 8);
+  o[12] = cv.take(dots_part_len(std::max(vol, ifc), max_iter + 2) * 8);
   ensure_ws(op, cv.off);
   auto at = [&](size_t x) {
     return reinterpret_cast<double *>(static_cast<unsigned char *>(op->ws) + x);
@@ -479,7 +481,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   SolveWs w;
   w.X = at(o[0]); w.R = at(o[1]); w.Z = at(o[2]); w.D = at(o[3]);
   w.fJ = at(o[4]); w.hh = at(o[5]); w.W = at(o[6]); w.xg = at(o[7]);
-  w.V = at(o[8]); w.hd = at(o[9]); w.part = at(o[10]); w.nrm = at(o[11]);
+  w.V = at(o[8]); w.hd = at(o[9]); w.part = at(o[10]); w.nrm = at(o[11]); w.dpart = at(o[12]);
   w.vol = vol;
   w.ifc = ifc;
   return w;
@@ -592,7 +594,7 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
           bool trans, bool hodlr, double *relres, hipStream_t s) {
   const size_t len = w.ifc;
   double *hh = op->hbuf_host;
-  launch_norm(rhs, len, w.nrm, s);
+  launch_norm(rhs, len, w.nrm, w.dpart, s);
   HIPCHK(hipMemcpyAsync(hh, w.nrm, 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const double beta = hh[0];
@@ -621,11 +623,11 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
       launch_gemv<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, trans ? 1 : 0, -1.0,
                      w.part, s);
     }
-    launch_dots(w.V, len, k + 1, w.W, len, w.hd, s);
+    launch_dots(w.V, len, k + 1, w.W, len, w.hd, w.dpart, s);
     launch_mgs_update(w.W, w.V, len, k + 1, w.hd, -1.0, len, s);
-    launch_dots(w.V, len, k + 1, w.W, len, w.hd + (k + 1), s);
+    launch_dots(w.V, len, k + 1, w.W, len, w.hd + (k + 1), w.dpart, s);
     launch_mgs_update(w.W, w.V, len, k + 1, w.hd + (k + 1), -1.0, len, s);
-    launch_norm(w.W, len, w.hd + 2 * (k + 1), s);
+    launch_norm(w.W, len, w.hd + 2 * (k + 1), w.dpart, s);
     launch_scale_by_inv(w.V + (size_t)(k + 1) * len, w.W, w.hd + 2 * (k + 1), len, s);
     HIPCHK(hipMemcpyAsync(hh, w.hd, (2 * (k + 1) + 1) * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -667,8 +669,9 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
   return k;
 }
 
-double dev_norm(ddst_op *op, const double *v, size_t len, double *scratch, hipStream_t s) {
-  launch_norm(v, len, scratch, s);
+double dev_norm(ddst_op *op, const double *v, size_t len, double *scratch, double *part,
+                hipStream_t s) {
+  launch_norm(v, len, scratch, part, s);
   HIPCHK(hipMemcpyAsync(op->hbuf_host, scratch, 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   return op->hbuf_host[0];
@@ -741,7 +744,7 @@ int refine(ddst_op *op, const void *G, const double *f, const double *g, bool tr
   for (int outer = 0; outer < o.max_outer; ++outer) {
     launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f, trans ? nullptr : g, w.X, w.R,
                     trans ? 1 : 0, s);
-    if (outer == 0) r0 = dev_norm(op, w.R, w.vol, w.nrm, s);
+    if (outer == 0) r0 = dev_norm(op, w.R, w.vol, w.nrm, w.dpart, s);
     launch_fill(w.D, 0.0, w.vol, s);
     double rr = 0;
     const int it = dd_correction<T>(op, w, G, trans, &o.inner_tol, o.max_iter,
@@ -751,8 +754,8 @@ int refine(ddst_op *op, const void *G, const double *f, const double *g, bool tr
     ro.relres = rr;
     if (rr > o.inner_tol) status = DDST_ENOTCONV;
     launch_axpy(w.X, w.D, 1.0, w.vol, s);
-    const double dn = dev_norm(op, w.D, w.vol, w.nrm, s);
-    const double xn = dev_norm(op, w.X, w.vol, w.nrm + 1, s);
+    const double dn = dev_norm(op, w.D, w.vol, w.nrm, w.dpart, s);
+    const double xn = dev_norm(op, w.X, w.vol, w.nrm + 1, w.dpart, s);
     ro.outer = outer + 1;
     ro.corr = (xn > 0) ? dn / xn : 0.0;
     bool done = ro.corr <= o.tol;
@@ -769,7 +772,7 @@ int refine(ddst_op *op, const void *G, const double *f, const double *g, bool tr
   }
   launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f, trans ? nullptr : g, w.X, w.R,
                   trans ? 1 : 0, s);
-  const double rf = dev_norm(op, w.R, w.vol, w.nrm, s);
+  const double rf = dev_norm(op, w.R, w.vol, w.nrm, w.dpart, s);
   ro.resrel = (r0 > 0) ? rf / r0 : 0.0;
   if (!ro.converged) status = DDST_ENOTCONV;
   return status;

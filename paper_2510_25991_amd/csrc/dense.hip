@@ -174,66 +174,73 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Elimination step K of the in-register pivot inverse, then K+1, ...: a
-// compile-time recursion so that every register index is a constant.
+// One Gauss-Jordan step, pivot part: one work-group (4 wavefronts) per
+// matrix inverts the kNB x kNB pivot block P = D[p, p] without pivoting, in
+// FP64.  Lane c of wave w holds column c, rows 16w..16w+15, in registers.
+// Step K: the wave owning row K publishes it through LDS (double-buffered,
+// one barrier per step); every wave reads the pivot-column entries of its
+// own rows from lane K with readlane.  The steps are a compile-time
+// recursion so every register index is a constant.  FP64 throughout: the
+// transfer blocks inherit the error of these small inverses amplified by
+// the conditioning of the interface Schur block.  Writes P^{-1} (row-major,
+// FP64) to Pinv[b].
+constexpr int kPivRows = kNB / 4;  // rows per wavefront
+
 template <int K>
-__device__ __forceinline__ void gj_pivot_steps(double (&col)[kNB], int c, bool &bad) {
+__device__ __forceinline__ void gj_pivot_steps(double (&col)[kPivRows], double (*rowbuf)[kNB],
+                                               int c, int w, bool &bad) {
   if constexpr (K < kNB) {
-    const double piv = readlane_f64(col[K], K);
+    constexpr int OW = K / kPivRows, OI = K % kPivRows;
+    double *rb = rowbuf[K & 1];
+    if (w == OW) rb[c] = col[OI];
+    __syncthreads();
+    const double piv = rb[K];
     if (!(piv > 0.0) || !isfinite(piv)) bad = true;
     const double inv = 1.0 / piv;
-    const double rk = col[K] * inv;  // this lane's entry of the scaled pivot row
+    const double rk = rb[c] * inv;  // scaled pivot row, this lane's column
     const bool own = (c == K);
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) {
-      if (i == K) {
-        col[i] = own ? inv : rk;
-      } else {
-        const double ci = readlane_f64(col[i], K);  // pivot column entry, broadcast
-        col[i] = own ? -ci * inv : col[i] - ci * rk;
-      }
+    for (int i = 0; i < kPivRows; ++i) {
+      const double ci = readlane_f64(col[i], K);  // P[row i of this wave][K]
+      if (w == OW && i == OI) col[i] = own ? inv : rk;
+      else col[i] = own ? -ci * inv : col[i] - ci * rk;
     }
-    gj_pivot_steps<K + 1>(col, c, bad);
+    gj_pivot_steps<K + 1>(col, rowbuf, c, w, bad);
   }
 }
 
-// One Gauss-Jordan step, pivot part: one wavefront per matrix inverts the
-// kNB x kNB pivot block P = D[p, p] without pivoting, in FP64, with lane c
-// holding column c of P in registers (the loops are fully unrolled so every
-// register index is static); the pivot column is broadcast with readlane.
-// FP64 throughout: the transfer blocks inherit the error of these small
-// inverses amplified by the conditioning of the interface Schur block.
-// Writes P^{-1} (row-major, FP64) to Pinv[b].
 template <typename T>
-__global__ __launch_bounds__(64) void k_gj_pivot(void *const *__restrict__ mats,
-                                                 double *__restrict__ Pinv, int ld, int p,
-                                                 int *__restrict__ flag) {
-  const int b = blockIdx.x, c = threadIdx.x;
+__global__ __launch_bounds__(256) void k_gj_pivot(void *const *__restrict__ mats,
+                                                  double *__restrict__ Pinv, int ld, int p,
+                                                  int *__restrict__ flag) {
+  __shared__ double rowbuf[2][kNB];
+  const int b = blockIdx.x, c = threadIdx.x & 63, w = threadIdx.x >> 6;
   const T *D = static_cast<const T *>(mats[b]);
   const int p0 = p * kNB;
-  double col[kNB];
+  double col[kPivRows];
 #pragma unroll
-  for (int i = 0; i < kNB; ++i) col[i] = (double)D[(size_t)(p0 + i) * ld + p0 + c];
+  for (int i = 0; i < kPivRows; ++i)
+    col[i] = (double)D[(size_t)(p0 + w * kPivRows + i) * ld + p0 + c];
   bool bad = false;
-  gj_pivot_steps<0>(col, c, bad);
-  if (bad && c == 0) atomicOr(flag, 1);
+  gj_pivot_steps<0>(col, rowbuf, c, w, bad);
+  if (bad && threadIdx.x == 0) atomicOr(flag, 1);
   double *out = Pinv + (size_t)b * kNB * kNB;
 #pragma unroll
-  for (int i = 0; i < kNB; ++i) out[i * kNB + c] = col[i];
+  for (int i = 0; i < kPivRows; ++i) out[(w * kPivRows + i) * kNB + c] = col[i];
 }
 
-// One Gauss-Jordan step, panel part.  Work-group (jt, b):
-//  * R[:, jt-block] = P^{-1} D[p, jt-block] (FP64 accumulation; P^{-1} itself
-//    when jt == p);
+// One Gauss-Jordan step, panel part.  Work-group (jt, b), 4 wavefronts:
+//  * R[:, jt-block] = P^{-1} D[p, jt-block] on the matrix cores (P^{-1}
+//    rounded to T; P^{-1} itself when jt == p);
 //  * Cbuf[jt-block rows, :] = D[jt-block rows, p] (copy of the old column).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats,
                                                   const double *__restrict__ Pinv,
                                                   T *__restrict__ Rbuf, T *__restrict__ Cbuf,
                                                   int ld, int p) {
-  __shared__ double Ps[kNB][kNB + 1];
-  __shared__ T X[kNB][kNB + 1];
+  __shared__ T Ps[kNB][kNB + 4];   // k-major copy of P^{-1}: Ps[k][i] = P^{-1}[i][k]
   const int b = blockIdx.y, jt = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const T *D = static_cast<const T *>(mats[b]);
   T *R = Rbuf + (size_t)b * kNB * ld;
   T *Cb = Cbuf + (size_t)b * ld * kNB;
@@ -241,27 +248,39 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
   const int p0 = p * kNB, j0 = jt * kNB;
   for (int e = tid; e < kNB * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
-    Ps[r][c] = Pi[e];
-    X[r][c] = D[(size_t)(p0 + r) * ld + j0 + c];
+    Ps[c][r] = (T)Pi[e];
     Cb[(size_t)(j0 + r) * kNB + c] = D[(size_t)(j0 + r) * ld + p0 + c];
   }
   __syncthreads();
-  const int r = tid >> 2, c0 = (tid & 3) * 16;
-  double out[16];
   if (jt == p) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) out[q] = Ps[r][c0 + q];
-  } else {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) out[q] = 0.0;
-    for (int k = 0; k < kNB; ++k) {
-      const double a = Ps[r][k];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) out[q] += a * (double)X[k][c0 + q];
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int r = e / kNB, c = e % kNB;
+      R[(size_t)r * ld + j0 + c] = Ps[c][r];
     }
+    return;
+  }
+  // wave w computes rows 16w..16w+15 of the 64 x 64 tile: 4 MFMA tiles;
+  // the B operand (pivot rows of D) is read straight from L2
+  const T *X = D + (size_t)p0 * ld + j0;
+  typename AccT<T>::type acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[j][r] = T(0);
+#pragma unroll
+  for (int k0 = 0; k0 < kNB; k0 += 4) {
+    const int kr = k0 + (lane >> 4);
+    const T a = Ps[kr][wave * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = mfma16(a, X[(size_t)kr * ld + j * 16 + (lane & 15)], acc[j]);
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) R[(size_t)r * ld + j0 + c0 + q] = (T)out[q];
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int in16 = sizeof(T) == 4 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
+      R[(size_t)(wave * 16 + in16) * ld + j0 + j * 16 + (lane & 15)] = acc[j][r];
+    }
 }
 
 // One Gauss-Jordan step, update part (Cbuf = old column p, R = P^{-1} D[p,:]):
@@ -417,7 +436,7 @@ void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, dou
   const int nreal = (M + kNB - 1) / kNB;
   for (int p = 0; p < nreal; ++p) {
     prof_begin(KK_GJ_PANEL, s);
-    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(64), 0, s, mats, Pinv, ld, p, flag);
+    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(256), 0, s, mats, Pinv, ld, p, flag);
     hipLaunchKernelGGL(k_gj_panel<T>, dim3(nblk, nmat), dim3(256), 0, s, mats, Pinv, Rbuf,
                        Cbuf, ld, p);
     prof_end(KK_GJ_PANEL, s, 2.0 * nmat * (double)kNB * kNB * M);

@@ -330,15 +330,41 @@ __global__ void k_fill(double *__restrict__ y, double v, size_t len) {
   if (e < len) y[e] = v;
 }
 
-__global__ __launch_bounds__(256) void k_dots(const double *__restrict__ V, size_t stride,
-                                              const double *__restrict__ w, size_t len,
-                                              double *__restrict__ out) {
+// Dot products of w with nvec vectors (stride apart), two passes:
+// part[chunk][i] = sum over a 256-element chunk (one wavefront per vector,
+// the chunk of w staged in LDS), then out[i] = sum over chunks (fixed order,
+// deterministic).  A null V means w itself (squared norm).
+constexpr int kDotChunk = 256;
+
+__global__ __launch_bounds__(256) void k_multidot_part(const double *__restrict__ V, size_t stride,
+                                                       int nvec, const double *__restrict__ w,
+                                                       size_t len, double *__restrict__ part) {
+  __shared__ double ws[kDotChunk];
+  const size_t base = (size_t)blockIdx.x * kDotChunk;
+  const int cn = (int)min((size_t)kDotChunk, len - base);
+  for (int e = threadIdx.x; e < kDotChunk; e += 256) ws[e] = (e < cn) ? w[base + e] : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nvec; i += 4) {
+    const double *v = V ? V + (size_t)i * stride + base : nullptr;
+    double s = 0.0;
+    for (int e = lane; e < cn; e += 64) s += (v ? v[e] : ws[e]) * ws[e];
+    s = wave_sum(s);
+    if (lane == 0) part[(size_t)blockIdx.x * nvec + i] = s;
+  }
+}
+
+// One work-group per vector sums its partials (strided, then a tree).
+__global__ __launch_bounds__(256) void k_multidot_reduce(const double *__restrict__ part,
+                                                         int nchunk, int nvec,
+                                                         double *__restrict__ out,
+                                                         int take_sqrt) {
   __shared__ double sh[4];
-  const double *v = V + (size_t)blockIdx.x * stride;
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (size_t e = threadIdx.x; e < len; e += 256) s += v[e] * w[e];
+  for (int c = threadIdx.x; c < nchunk; c += 256) s += part[(size_t)c * nvec + i];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[blockIdx.x] = s;
+  if (threadIdx.x == 0) out[i] = take_sqrt ? sqrt(s) : s;
 }
 
 __global__ void k_mgs_update(double *__restrict__ w, const double *__restrict__ V, size_t stride,
@@ -348,15 +374,6 @@ __global__ void k_mgs_update(double *__restrict__ w, const double *__restrict__ 
   double s = 0.0;
   for (int i = 0; i < nvec; ++i) s += V[(size_t)i * stride + e] * h[i];
   w[e] += sign * s;
-}
-
-__global__ __launch_bounds__(1024) void k_norm(const double *__restrict__ w, size_t len,
-                                               double *__restrict__ out) {
-  __shared__ double sh[16];
-  double s = 0.0;
-  for (size_t e = threadIdx.x; e < len; e += blockDim.x) s += w[e] * w[e];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[0] = sqrt(s);
 }
 
 __global__ void k_scale_by_inv(double *__restrict__ dst, const double *__restrict__ src,
@@ -505,8 +522,11 @@ void launch_fill(double *y, double v, size_t len, hipStream_t s) {
 }
 
 void launch_dots(const double *V, size_t stride, int nvec, const double *w, size_t len,
-                 double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(256), 0, s, V, stride, w, len, out);
+                 double *out, double *part, hipStream_t s) {
+  const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
+  hipLaunchKernelGGL(k_multidot_part, dim3(nchunk), dim3(256), 0, s, V, stride, nvec, w, len,
+                     part);
+  hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(256), 0, s, part, nchunk, nvec, out, 0);
 }
 
 void launch_mgs_update(double *w, const double *V, size_t stride, int nvec, const double *h,
@@ -515,8 +535,11 @@ void launch_mgs_update(double *w, const double *V, size_t stride, int nvec, cons
                      sign, len);
 }
 
-void launch_norm(const double *w, size_t len, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm, dim3(1), dim3(1024), 0, s, w, len, out);
+void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s) {
+  const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
+  hipLaunchKernelGGL(k_multidot_part, dim3(nchunk), dim3(256), 0, s, (const double *)nullptr,
+                     (size_t)0, 1, w, len, part);
+  hipLaunchKernelGGL(k_multidot_reduce, dim3(1), dim3(256), 0, s, part, nchunk, 1, out, 1);
 }
 
 void launch_scale_by_inv(double *dst, const double *src, const double *nrm, size_t len,
