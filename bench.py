@@ -28,6 +28,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
+# width of the pivot blocks of the library's Gauss-Jordan inversion (the rank
+# of each update step)
+GJ_RANK = 128
 
 
 def parse():
@@ -100,22 +103,37 @@ def roofline(prof, precision, M):
     """Dominant kernel class by total time; achieved = algorithmic work per
     launch / average launch duration (HIP events on the library's stream).
 
-    The Gauss-Jordan update is a rank-64 update: per matrix it reads and
-    writes the M x M block once and reads two M x 64 panels, 2 M^2 64 flops;
-    its intensity, 64 / (esize (1 + 64 / M)) flop/B, is below the FP32 and
-    FP64 ridges (157.3 / 8 and 78.6 / 8 flop/B), so it is bounded by HBM."""
+    The Gauss-Jordan update is a rank-GJ_RANK update: per matrix it reads
+    and writes the M x M block once and reads two M x GJ_RANK panels,
+    2 M^2 GJ_RANK flops.  Its bound is whichever floor is higher: HBM
+    (algorithmic bytes / 8 TB/s) or the matrix cores (flops / dense MFMA
+    peak of the precision).  At rank 128 the FP32 intensity,
+    128 / (4 (1 + 128 / M)) flop/B, is above the FP32 ridge (157.3 / 8), so
+    FP32 is MFMA-bound; FP64 (16 flop/B vs 78.6 / 8) stays HBM-bound."""
     name, (n, ms, work) = max(prof.items(), key=lambda kv: kv[1][1])
     avg_s = ms / 1e3 / max(n, 1)
     esz = 4 if precision == "fp32" else 8
+    mpeak = PEAK["fp32_mfma_tflops"] if precision == "fp32" else PEAK["fp64_mfma_tflops"]
     base = {"kernel": name, "launches": n, "avg_launch_us": round(avg_s * 1e6, 2)}
     if name == "gj_update":
-        bytes_per_launch = work / max(n, 1) * esz * (1.0 / 64 + 1.0 / M)
-        achieved = bytes_per_launch / avg_s / 1e9
+        flops_per_launch = work / max(n, 1)
+        bytes_per_launch = flops_per_launch * esz * (1.0 / GJ_RANK + 1.0 / M)
+        hbm_floor = bytes_per_launch / (PEAK["hbm_gbs"] * 1e9)
+        mfma_floor = flops_per_launch / (mpeak * 1e12)
         tr = _measured_traffic("gj_update") if precision == "fp32" else None
+        extra = {"traffic": tr, "bytes_per_launch": bytes_per_launch,
+                 "flops_per_launch": flops_per_launch,
+                 "hbm_gbs": round(bytes_per_launch / avg_s / 1e9, 1),
+                 "mfma_tflops": round(flops_per_launch / avg_s / 1e12, 3)}
+        if mfma_floor >= hbm_floor:
+            achieved = flops_per_launch / avg_s / 1e12
+            return name, {"bound": "mfma", "achieved": round(achieved, 3), "peak": mpeak,
+                          "unit": "TFLOP/s", "frac": round(achieved / mpeak, 4),
+                          **extra, **base}
+        achieved = bytes_per_launch / avg_s / 1e9
         return name, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK["hbm_gbs"],
                       "unit": "GB/s", "frac": round(achieved / PEAK["hbm_gbs"], 4),
-                      "traffic": tr, "bytes_per_launch": bytes_per_launch,
-                      "mfma_tflops": round(work / max(n, 1) / avg_s / 1e12, 3), **base}
+                      **extra, **base}
     if name in ("gemm", "gj_panel"):
         achieved = work / max(n, 1) / avg_s / 1e12
         peak = PEAK["fp32_mfma_tflops"] if precision == "fp32" else PEAK["fp64_mfma_tflops"]

@@ -262,7 +262,7 @@ int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipS
  */
 enum {
   DDST_K_GJ_PANEL = 0,  /* Gauss-Jordan pivot block inverse + panel   (flops) */
-  DDST_K_GJ_UPDATE = 1, /* Gauss-Jordan rank-64 update, MFMA          (flops) */
+  DDST_K_GJ_UPDATE = 1, /* Gauss-Jordan rank-128 update, MFMA         (flops) */
   DDST_K_GEMM = 2,      /* transfer chains / blocks, MFMA             (flops) */
   DDST_K_ASSEMBLE = 3,  /* plane-block (Schur recursion) assembly     (bytes) */
   DDST_K_GEMV = 4       /* slab sweeps and interface products         (bytes) */

@@ -167,138 +167,243 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmJob *__restrict__ jobs, 
       }
 }
 
-__device__ __forceinline__ double readlane_f64(double x, int lane) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+// Broadcast lane src (wave-uniform) of a double to the whole wavefront.
+__device__ __forceinline__ double bcast_lane(double x, int src) {
+  const long long u = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)u, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// In-place Gauss-Jordan inversion, without pivoting, of a 16 x 16 FP64 block
+// held by one wavefront: lane l holds row l % 16, columns l / 16 + 4c in
+// v[c].  That is the A-operand layout of four chained 16x16x4 FP64 MFMAs
+// (v[c] feeds k = 4c + l / 16), so the inverse multiplies without a
+// reshuffle.  Returns false if a pivot is not positive and finite.
+__device__ __forceinline__ bool leaf_invert16(double (&v)[4]) {
+  const int l = threadIdx.x & 63;
+  const int i = l & 15, g = l >> 4;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int kg = k & 3, kc = k >> 2;  // column k: lanes with g == kg, v[kc]
+    const double colk = __shfl(v[kc], kg * 16 + i);  // P[i][k]
+    double prow[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) prow[c] = __shfl(v[c], g * 16 + k);  // P[k][g + 4c]
+    const double piv = bcast_lane(v[kc], kg * 16 + k);
+    ok = ok && piv > 0.0 && isfinite(piv);
+    const double inv = 1.0 / piv;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bool isk = (g == kg) && (c == kc);
+      const double rk = isk ? inv : prow[c] * inv;  // new pivot row
+      // other rows: P[i][j] - P[i][k] rk[j]; column k itself -P[i][k] / piv
+      const double other = fma(-colk, rk, isk ? 0.0 : v[c]);
+      v[c] = (i == k) ? rk : other;
+    }
+  }
+  return ok;
 }
 
 // One Gauss-Jordan step, pivot part: one work-group (4 wavefronts) per
-// matrix inverts the kNB x kNB pivot block P = D[p, p] without pivoting, in
-// FP64.  Lane c of wave w holds column c, rows 16w..16w+15, in registers.
-// Step K: the wave owning row K publishes it through LDS (double-buffered,
-// one barrier per step); every wave reads the pivot-column entries of its
-// own rows from lane K with readlane.  The steps are a compile-time
-// recursion so every register index is a constant.  FP64 throughout: the
-// transfer blocks inherit the error of these small inverses amplified by
-// the conditioning of the interface Schur block.  Writes P^{-1} (row-major,
-// FP64) to Pinv[b].
-constexpr int kPivRows = kNB / 4;  // rows per wavefront
-
-template <int K>
-__device__ __forceinline__ void gj_pivot_steps(double (&col)[kPivRows], double (*rowbuf)[kNB],
-                                               int c, int w, bool &bad) {
-  if constexpr (K < kNB) {
-    constexpr int OW = K / kPivRows, OI = K % kPivRows;
-    double *rb = rowbuf[K & 1];
-    if (w == OW) rb[c] = col[OI];
-    __syncthreads();
-    const double piv = rb[K];
-    if (!(piv > 0.0) || !isfinite(piv)) bad = true;
-    const double inv = 1.0 / piv;
-    const double rk = rb[c] * inv;  // scaled pivot row, this lane's column
-    const bool own = (c == K);
-#pragma unroll
-    for (int i = 0; i < kPivRows; ++i) {
-      const double ci = readlane_f64(col[i], K);  // P[row i of this wave][K]
-      if (w == OW && i == OI) col[i] = own ? inv : rk;
-      else col[i] = own ? -ci * inv : col[i] - ci * rk;
-    }
-    gj_pivot_steps<K + 1>(col, rowbuf, c, w, bad);
-  }
-}
+// matrix inverts the kNB x kNB (128 x 128) pivot block P = D[p, p] in FP64,
+// without pivoting, and writes P^{-1} (row-major, rounded to T) to Pinv[b],
+// the operand of the panel product.  FP64 throughout: the transfer blocks inherit the error of these inverses
+// amplified by the conditioning of the interface Schur block.
+//
+// The block stays in registers for the whole inversion, as 16 x 16 tiles in
+// the FP64 MFMA output layout: wave w owns column tiles 2w and 2w + 1 of all
+// eight row tiles.  It is inverted by blocked Gauss-Jordan with 16-wide
+// leaves.  Sub-step q: the row block q and the column block q go to LDS
+// (double-buffered, one barrier per sub-step); every wave inverts the leaf
+// P_qq itself (the same arithmetic in each wave, so no second barrier), forms
+// R_J = P_qq^{-1} P_qJ for its own column tiles and applies the rank-16
+// update to them on the matrix cores, with the tiles as accumulators:
+//   row tile q:        T_qJ = R_J                   (R_q = P_qq^{-1})
+//   column tile q:     T_Iq = -P_Iq P_qq^{-1}       (formed from zero)
+//   others:            T_IJ = T_IJ - P_Iq R_J
+// The MFMA output layout of R_J (row 4r + l / 16 in register r) is the
+// B-operand layout of the update's k-step r, and the leaf layout is the
+// A-operand layout, so no data moves between the two.
+constexpr int kLeaf = 16;
+constexpr int kCqS = 20;        // LDS row stride of the column block (doubles)
+constexpr int kRqS = kNB + 16;  // LDS row stride of the row block (doubles)
+static_assert(kNB == 128, "the register layout below assumes 128-wide pivots");
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_pivot(void *const *__restrict__ mats,
-                                                  double *__restrict__ Pinv, int ld, int p,
+                                                  T *__restrict__ Pinv, int ld, int p,
                                                   int *__restrict__ flag) {
-  __shared__ double rowbuf[2][kNB];
-  const int b = blockIdx.x, c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const T *D = static_cast<const T *>(mats[b]);
-  const int p0 = p * kNB;
-  double col[kPivRows];
+  __shared__ double Cq[2][kNB][kCqS];
+  __shared__ double Rq[2][kLeaf][kRqS];
+  const int b = blockIdx.x, l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = l >> 4, lc = l & 15;
+  const T *D = static_cast<const T *>(mats[b]) + (size_t)p * kNB * ld + p * kNB;
+  f64x4 t[8][2];  // t[I][jj][r] = P[16 I + 4 r + lr][16 (2 w + jj) + lc]
 #pragma unroll
-  for (int i = 0; i < kPivRows; ++i)
-    col[i] = (double)D[(size_t)(p0 + w * kPivRows + i) * ld + p0 + c];
-  bool bad = false;
-  gj_pivot_steps<0>(col, rowbuf, c, w, bad);
-  if (bad && threadIdx.x == 0) atomicOr(flag, 1);
-  double *out = Pinv + (size_t)b * kNB * kNB;
+  for (int I = 0; I < 8; ++I)
 #pragma unroll
-  for (int i = 0; i < kPivRows; ++i) out[(w * kPivRows + i) * kNB + c] = col[i];
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        t[I][jj][r] = (double)D[(size_t)(16 * I + 4 * r + lr) * ld + 16 * (2 * w + jj) + lc];
+  bool ok = true;
+  for (int q = 0; q < kNB / kLeaf; ++q) {
+    const int buf = q & 1;
+#pragma unroll
+    for (int I = 0; I < 8; ++I)
+      if (I == q) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Rq[buf][4 * r + lr][16 * (2 * w + jj) + lc] = t[I][jj][r];
+      }
+    if (w == (q >> 1)) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+        if (jj == (q & 1)) {
+#pragma unroll
+          for (int I = 0; I < 8; ++I)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Cq[buf][16 * I + 4 * r + lr][lc] = t[I][jj][r];
+        }
+    }
+    __syncthreads();
+    double v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = Rq[buf][lc][16 * q + lr + 4 * c];
+    ok = leaf_invert16(v) && ok;
+    f64x4 R[2];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const int J = 2 * w + jj;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) R[jj][r] = 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double bs = J == q ? (4 * s + lr == lc ? 1.0 : 0.0) : Rq[buf][4 * s + lr][16 * J + lc];
+        R[jj] = mfma16(v[s], bs, R[jj]);
+      }
+    }
+#pragma unroll
+    for (int I = 0; I < 8; ++I) {
+      if (I == q) {
+        t[I][0] = R[0];
+        t[I][1] = R[1];
+        continue;
+      }
+      double a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[s] = -Cq[buf][16 * I + lc][4 * s + lr];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        f64x4 acc = t[I][jj];
+        if (2 * w + jj == q) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r] = 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = mfma16(a[s], R[jj][s], acc);
+        t[I][jj] = acc;
+      }
+    }
+  }
+  if (!ok && threadIdx.x == 0) atomicOr(flag, 1);
+  T *out = Pinv + (size_t)b * kNB * kNB;
+#pragma unroll
+  for (int I = 0; I < 8; ++I)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(16 * I + 4 * r + lr) * kNB + 16 * (2 * w + jj) + lc] = (T)t[I][jj][r];
 }
 
-// One Gauss-Jordan step, panel part.  Work-group (jt, b), 4 wavefronts:
-//  * R[:, jt-block] = P^{-1} D[p, jt-block] on the matrix cores (P^{-1}
-//    rounded to T; P^{-1} itself when jt == p);
-//  * Cbuf[jt-block rows, :] = D[jt-block rows, p] (copy of the old column).
+// One Gauss-Jordan step, panel part.  Work-group (jt, b), 4 wavefronts,
+// for the 128 columns j0 = 128 jt:
+//  * R[:, j0..j0+127] = P^{-1} D[p, j0..j0+127], a 128 x 128 x 128 product
+//    on the matrix cores through the LDS-staged tile routine (R = P^{-1}
+//    itself on the pivot block);
+//  * Cbuf[j0..j0+127, :] = D[j0..j0+127, p] (copy of the old pivot columns).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats,
-                                                  const double *__restrict__ Pinv,
+                                                  const T *__restrict__ Pinv,
                                                   T *__restrict__ Rbuf, T *__restrict__ Cbuf,
                                                   int ld, int p) {
-  __shared__ T Ps[kNB][kNB + 4];   // k-major copy of P^{-1}: Ps[k][i] = P^{-1}[i][k]
+  __shared__ T As[BK][LW];
+  __shared__ T Bs[BK][LW];
   const int b = blockIdx.y, jt = blockIdx.x, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
   const T *D = static_cast<const T *>(mats[b]);
   T *R = Rbuf + (size_t)b * kNB * ld;
   T *Cb = Cbuf + (size_t)b * ld * kNB;
-  const double *Pi = Pinv + (size_t)b * kNB * kNB;
-  const int p0 = p * kNB, j0 = jt * kNB;
-  for (int e = tid; e < kNB * kNB; e += 256) {
+  const T *Pi = Pinv + (size_t)b * kNB * kNB;
+  const int p0 = p * kNB, j0 = jt * kTile;
+  constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
+  for (int e = tid * V; e < kTile * kNB; e += 256 * V) {
     const int r = e / kNB, c = e % kNB;
-    Ps[c][r] = (T)Pi[e];
-    Cb[(size_t)(j0 + r) * kNB + c] = D[(size_t)(j0 + r) * ld + p0 + c];
+    *reinterpret_cast<float4 *>(Cb + (size_t)(j0 + r) * kNB + c) =
+        *reinterpret_cast<const float4 *>(D + (size_t)(j0 + r) * ld + p0 + c);
   }
-  __syncthreads();
   if (jt == p) {
-    for (int e = tid; e < kNB * kNB; e += 256) {
-      const int r = e / kNB, c = e % kNB;
-      R[(size_t)r * ld + j0 + c] = Ps[c][r];
+    for (int e = tid * V; e < kNB * kTile; e += 256 * V) {
+      const int r = e / kTile, c = e % kTile;
+      *reinterpret_cast<float4 *>(R + (size_t)r * ld + j0 + c) =
+          *reinterpret_cast<const float4 *>(Pi + r * kNB + c);
     }
     return;
   }
-  // wave w computes rows 16w..16w+15 of the 64 x 64 tile: 4 MFMA tiles;
-  // the B operand (pivot rows of D) is read straight from L2
-  const T *X = D + (size_t)p0 * ld + j0;
-  typename AccT<T>::type acc[4];
+  Tile<T> acc;
+  acc.zero();
+  mma_tile<T>(Pi, kNB, D + (size_t)p0 * ld + j0, ld, nullptr, kNB, As, Bs, acc);
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[j][r] = T(0);
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-  for (int k0 = 0; k0 < kNB; k0 += 4) {
-    const int kr = k0 + (lane >> 4);
-    const T a = Ps[kr][wave * 16 + (lane & 15)];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = mfma16(a, X[(size_t)kr * ld + j * 16 + (lane & 15)], acc[j]);
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int in16 = sizeof(T) == 4 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
-      R[(size_t)(wave * 16 + in16) * ld + j0 + j * 16 + (lane & 15)] = acc[j][r];
-    }
+      for (int r = 0; r < 4; ++r)
+        R[(size_t)acc_row<T>(i, r) * ld + j0 + acc_col(j)] = acc.v[i][j][r];
 }
 
 // One Gauss-Jordan step, update part (Cbuf = old column p, R = P^{-1} D[p,:]):
 //   pivot rows               D[p, :] = R             (P^{-1} on the block p)
 //   other rows, column p     D[i, p] = -D[i, p] P^{-1}
 //   other rows, other cols   D[i, j] -= D[i, p] P^{-1} D[p, j]
-// The D tile is loaded into registers before the MFMA loop (its latency
-// overlaps the panel product); the product is formed from zero and
-// subtracted once, which keeps the rounding at the scale of the update
-// rather than of D.  The pivot column is written as -acc rather than
-// D - (D + D P^{-1}), which would add O(1) to O(|P^{-1}|) entries.
+// The kernel is bound by streaming D through HBM, so the 128 x 128 tile is
+// read and written with 16-byte accesses, each wavefront covering whole
+// rows (VEC elements per lane), and loaded before the MFMA loop so its
+// latency overlaps the panel product.  The MFMA accumulators are exchanged
+// into that row layout through LDS, CR rows at a time, reusing the staging
+// buffers.  The product is formed from zero and subtracted once, keeping
+// the rounding at the scale of the update rather than of D; the pivot
+// column is written as -acc rather than D - (D + D P^{-1}), which would add
+// O(1) to O(|P^{-1}|) entries.
+template <typename T> struct UpdGeom;
+template <> struct UpdGeom<float> {
+  static constexpr int VEC = 4;     // floats per 16-byte access
+  static constexpr int RPI = 8;     // rows covered by one pass of 256 threads
+  static constexpr int NQ = 16;     // passes per tile (128 / RPI)
+  static constexpr int CR = 32;     // rows per LDS exchange chunk
+};
+template <> struct UpdGeom<double> {
+  static constexpr int VEC = 2;
+  static constexpr int RPI = 4;
+  static constexpr int NQ = 32;
+  static constexpr int CR = 16;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
                                                    const T *__restrict__ Cbuf, int ld,
                                                    int p, int tiles_per_mat) {
-  __shared__ T As[BK][LW];
-  __shared__ T Bs[BK][LW];
+  using G = UpdGeom<T>;
+  constexpr int XW = kTile + 4;  // exchange row width
+  static_assert(2 * BK * LW >= G::CR * XW, "exchange chunk must fit the staging LDS");
+  __shared__ T lds[2 * BK * LW];
+  T (*As)[LW] = reinterpret_cast<T (*)[LW]>(lds);
+  T (*Bs)[LW] = reinterpret_cast<T (*)[LW]>(lds + BK * LW);
+  T (*Xs)[XW] = reinterpret_cast<T (*)[XW]>(lds);
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int b = lin / tiles_per_mat;
   const int t = lin % tiles_per_mat;
@@ -308,33 +413,65 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   const T *R = Rbuf + (size_t)b * kNB * ld;
   const T *Cb = Cbuf + (size_t)b * ld * kNB;
   const int p0 = p * kNB;
-  T dold[4][4][4];
+  const int tid = threadIdx.x;
+  constexpr int LPR = kTile / G::VEC;           // lanes per row
+  const int trow = tid / LPR, tcol = (tid % LPR) * G::VEC;
+  // coalesced prefetch of the D tile (zero in the pivot columns)
+  T dold[G::NQ][G::VEC];
+  const bool pivcols = (bn + tcol >= p0) && (bn + tcol < p0 + kNB);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int q = 0; q < G::NQ; ++q) {
+    const T *src = D + (size_t)(bm + q * G::RPI + trow) * ld + bn + tcol;
+    if (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4 *>(src);
+      dold[q][0] = v.x; dold[q][1] = v.y; dold[q][2] = v.z; dold[q][G::VEC - 1] = v.w;
+    } else {
+      const double2 v = *reinterpret_cast<const double2 *>(src);
+      dold[q][0] = v.x; dold[q][G::VEC - 1] = v.y;
+    }
+    if (pivcols)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = bm + acc_row<T>(i, r), col = bn + acc_col(j);
-        const bool pivcol = col >= p0 && col < p0 + kNB;
-        dold[i][j][r] = pivcol ? T(0) : D[(size_t)row * ld + col];
-      }
+      for (int e = 0; e < G::VEC; ++e) dold[q][e] = T(0);
+  }
   Tile<T> acc;
   acc.zero();
   mma_tile<T>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, nullptr, kNB, As, Bs, acc);
+  // exchange and store, CR rows at a time
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int c = 0; c < kTile / G::CR; ++c) {
+    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = bm + acc_row<T>(i, r), col = bn + acc_col(j);
-        const size_t idx = (size_t)row * ld + col;
-        if (row >= p0 && row < p0 + kNB)
-          D[idx] = R[(size_t)(row - p0) * ld + col];
-        else
-          D[idx] = dold[i][j][r] - acc.v[i][j][r];
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = acc_row<T>(i, r);
+          if (row >= c * G::CR && row < (c + 1) * G::CR)
+            Xs[row - c * G::CR][acc_col(j)] = acc.v[i][j][r];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < G::NQ; ++q) {
+      const int lrow = q * G::RPI + trow;
+      if (lrow < c * G::CR || lrow >= (c + 1) * G::CR) continue;
+      const int row = bm + lrow;
+      T out[G::VEC];
+      if (row >= p0 && row < p0 + kNB) {
+#pragma unroll
+        for (int e = 0; e < G::VEC; ++e) out[e] = R[(size_t)(row - p0) * ld + bn + tcol + e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < G::VEC; ++e) out[e] = dold[q][e] - Xs[lrow - c * G::CR][tcol + e];
       }
+      T *dst = D + (size_t)row * ld + bn + tcol;
+      if (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[G::VEC - 1]);
+      } else {
+        *reinterpret_cast<double2 *>(dst) = make_double2(out[0], out[G::VEC - 1]);
+      }
+    }
+  }
 }
 
 // D = A_plane - diag(r1) G1 diag(c1) - diag(r2) G2 diag(c2); one block per row.
@@ -430,14 +567,16 @@ template <typename T>
 void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, double *Pinv,
                int *flag, hipStream_t s) {
   if (nmat <= 0) return;
-  const int nblk = ld / kNB;
-  const int tpm = (ld / kTile) * (ld / kTile);
+  static_assert(kNB == kTile, "one pivot block per tile row");
+  const int nt = ld / kTile;
+  const int tpm = nt * nt;
+  T *PinvT = reinterpret_cast<T *>(Pinv);  // nmat kNB x kNB inverses, rounded to T
   // blocks that hold only identity padding need no elimination step
   const int nreal = (M + kNB - 1) / kNB;
   for (int p = 0; p < nreal; ++p) {
     prof_begin(KK_GJ_PANEL, s);
-    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(256), 0, s, mats, Pinv, ld, p, flag);
-    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nblk, nmat), dim3(256), 0, s, mats, Pinv, Rbuf,
+    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(256), 0, s, mats, PinvT, ld, p, flag);
+    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nt, nmat), dim3(256), 0, s, mats, PinvT, Rbuf,
                        Cbuf, ld, p);
     prof_end(KK_GJ_PANEL, s, 2.0 * nmat * (double)kNB * kNB * M);
     prof_begin(KK_GJ_UPDATE, s);

@@ -24,7 +24,7 @@ namespace ddst {
 struct Hodlr;
 
 constexpr int kTile = 128;   // GEMM / update output tile (rows and cols)
-constexpr int kNB = 64;      // Gauss-Jordan block width
+constexpr int kNB = 128;     // Gauss-Jordan block width (= kTile)
 constexpr int kGemvChunk = 32;  // rows per partial sum in the transposed GEMV
 
 // Stencil coefficient slots: coef[slot * N + node], node = interior C-order.
@@ -95,9 +95,9 @@ template <typename T>
 void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, double beta,
                  hipStream_t s);
 // In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices.
-// Rbuf: nmat*kNB*ld, Cbuf: nmat*ld*kNB workspace of T; Pinv: nmat*kNB*kNB
-// doubles; flag: device int set to 1 when a pivot is non-positive or
-// non-finite.
+// Rbuf: nmat*kNB*ld, Cbuf: nmat*ld*kNB workspace of T; Pinv: room for
+// nmat*kNB*kNB doubles (holds the pivot-block inverses, rounded to T);
+// flag: device int set to 1 when a pivot is non-positive or non-finite.
 template <typename T>
 void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, double *Pinv,
                int *flag, hipStream_t s);
