@@ -103,13 +103,16 @@ def roofline(prof, precision, M):
     """Dominant kernel class by total time; achieved = algorithmic work per
     launch / average launch duration (HIP events on the library's stream).
 
-    The Gauss-Jordan update is a rank-GJ_RANK update: per matrix it reads
-    and writes the M x M block once and reads two M x GJ_RANK panels,
-    2 M^2 GJ_RANK flops.  Its bound is whichever floor is higher: HBM
-    (algorithmic bytes / 8 TB/s) or the matrix cores (flops / dense MFMA
-    peak of the precision).  At rank 128 the FP32 intensity,
-    128 / (4 (1 + 128 / M)) flop/B, is above the FP32 ridge (157.3 / 8), so
-    FP32 is MFMA-bound; FP64 (16 flop/B vs 78.6 / 8) stays HBM-bound."""
+    The Gauss-Jordan update of one step is a rank-r update (r = GJ_RANK) of
+    the M - r rows outside the pivot block: per matrix 2 r M (M - r) flops;
+    it reads and writes those rows once, writes the r pivot rows and reads
+    the two panels, esize (2 M^2 + r M - r^2) bytes.  Its bound is whichever
+    floor is higher: HBM (algorithmic bytes / 8 TB/s) or the matrix cores
+    (flops / dense MFMA peak of the precision).  At r = 128 and M = 1023 the
+    intensity is about 26.5 flop/B in FP32 and 13.3 in FP64, above both
+    ridges (157.3 / 8 and 78.6 / 8), so the update is MFMA-bound.  Launches of the look-ahead schedule cover
+    subsets of the tiles; their work is summed, so the figures are averages
+    over all update launches."""
     name, (n, ms, work) = max(prof.items(), key=lambda kv: kv[1][1])
     avg_s = ms / 1e3 / max(n, 1)
     esz = 4 if precision == "fp32" else 8
@@ -117,7 +120,9 @@ def roofline(prof, precision, M):
     base = {"kernel": name, "launches": n, "avg_launch_us": round(avg_s * 1e6, 2)}
     if name == "gj_update":
         flops_per_launch = work / max(n, 1)
-        bytes_per_launch = flops_per_launch * esz * (1.0 / GJ_RANK + 1.0 / M)
+        r = GJ_RANK
+        bytes_per_flop = esz * (2.0 * M * M + r * M - r * r) / (2.0 * r * M * (M - r))
+        bytes_per_launch = flops_per_launch * bytes_per_flop
         hbm_floor = bytes_per_launch / (PEAK["hbm_gbs"] * 1e9)
         mfma_floor = flops_per_launch / (mpeak * 1e12)
         tr = _measured_traffic("gj_update") if precision == "fp32" else None

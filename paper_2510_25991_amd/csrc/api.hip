@@ -192,9 +192,8 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
   }
   tab.upload(s);
   DeviceMem gjw(gj_workspace_bytes(nsw, ld, sizeof(T)));
-  T *Rb = static_cast<T *>(gjw.p);
-  T *Cb = Rb + (size_t)nsw * kNB * ld;
-  double *Pi = reinterpret_cast<double *>(Cb + (size_t)nsw * kNB * ld);
+  GjStreams gs;
+  HIPCHK(gs.create());
   // The transfer chain of plane k needs only G_k: it runs on a second
   // stream, overlapping the (memory-bound) assembly and inversion of plane
   // k+1 with its (matrix-core-bound) GEMM.  Before plane k+2 is assembled
@@ -220,7 +219,8 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
       if (chains && k >= 3) HIPCHK(hipStreamWaitEvent(s, ev_y[k - 2], 0));
       launch_assemble<T>(tab.at<AsmJob>(off_asm[k - 1]), nsw, op->coef, op->n, op->dim, op->M,
                          ld, s);
-      gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, Rb, Cb, Pi, op->flag, s);
+      HIPCHK(gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, gjw.p, op->flag, gs,
+                          s));
       if (ny_at[k - 1] > 0) {
         HIPCHK(hipEventRecord(ev_gj[k], s));
         HIPCHK(hipStreamWaitEvent(s2, ev_gj[k], 0));
@@ -334,9 +334,9 @@ int build_impl(ddst_op *op, int keep, hipStream_t s) {
   tab.upload(s);
   launch_assemble<T>(tab.at<AsmJob>(oc), nds, op->coef, op->n, op->dim, op->M, op->ld, s);
   DeviceMem gjw(gj_workspace_bytes(nds, op->ld, sizeof(T)));
-  T *Rb = static_cast<T *>(gjw.p);
-  gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, Rb, Rb + (size_t)nds * kNB * op->ld,
-               reinterpret_cast<double *>(Rb + (size_t)2 * nds * kNB * op->ld), op->flag, s);
+  GjStreams gs;
+  HIPCHK(gs.create());
+  HIPCHK(gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, gjw.p, op->flag, gs, s));
   launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, op->M, -1.0, 0.0, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -1219,17 +1219,13 @@ int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipS
     DeviceMem fl(sizeof(int));
     HIPCHK(hipMemsetAsync(fl.p, 0, sizeof(int), stream));
     DeviceMem w(gj_workspace_bytes(batch, ld, esize(precision)));
-    if (precision == DDST_FP32) {
-      float *R = static_cast<float *>(w.p);
-      gj_invert<float>(t.at<void *>(o), batch, ld, ld, R, R + (size_t)batch * kNB * ld,
-                       reinterpret_cast<double *>(R + (size_t)2 * batch * kNB * ld),
-                       static_cast<int *>(fl.p), stream);
-    } else {
-      double *R = static_cast<double *>(w.p);
-      gj_invert<double>(t.at<void *>(o), batch, ld, ld, R, R + (size_t)batch * kNB * ld,
-                        reinterpret_cast<double *>(R + (size_t)2 * batch * kNB * ld),
-                        static_cast<int *>(fl.p), stream);
-    }
+    GjStreams gs;
+    HIPCHK(gs.create());
+    int *flag = static_cast<int *>(fl.p);
+    if (precision == DDST_FP32)
+      HIPCHK(gj_invert<float>(t.at<void *>(o), batch, ld, ld, w.p, flag, gs, stream));
+    else
+      HIPCHK(gj_invert<double>(t.at<void *>(o), batch, ld, ld, w.p, flag, gs, stream));
     HIPCHK(hipGetLastError());
     int h = 0;
     HIPCHK(hipMemcpyAsync(&h, fl.p, sizeof(int), hipMemcpyDeviceToHost, stream));

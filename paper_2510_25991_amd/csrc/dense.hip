@@ -13,6 +13,9 @@
 // All matrices are ld x ld row-major, ld a multiple of 128, padded with the
 // identity, so no kernel tests edges.  Work-group tiles are 128 x 128 with 4
 // wavefronts of 64 lanes, each owning a 64 x 64 sub-tile (4 x 4 MFMA tiles).
+#include <algorithm>
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ddst {
@@ -175,6 +178,26 @@ __device__ __forceinline__ double bcast_lane(double x, int src) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Broadcast lane k (a compile-time constant after unrolling) of each
+// 16-lane row to the whole row: DPP row_newbcast (gfx90a and later).
+__device__ __forceinline__ int dpp_row_bcast(int x, int k) {
+  switch (k) {
+#define DDST_BC(K) \
+  case K: return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xF, 0xF, false);
+    DDST_BC(0) DDST_BC(1) DDST_BC(2) DDST_BC(3) DDST_BC(4) DDST_BC(5) DDST_BC(6) DDST_BC(7)
+    DDST_BC(8) DDST_BC(9) DDST_BC(10) DDST_BC(11) DDST_BC(12) DDST_BC(13) DDST_BC(14)
+    DDST_BC(15)
+#undef DDST_BC
+  }
+  return 0;
+}
+__device__ __forceinline__ double row_bcast(double x, int k) {
+  const long long u = __double_as_longlong(x);
+  const unsigned lo = (unsigned)dpp_row_bcast((int)u, k);
+  const unsigned hi = (unsigned)dpp_row_bcast((int)(u >> 32), k);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // In-place Gauss-Jordan inversion, without pivoting, of a 16 x 16 FP64 block
 // held by one wavefront: lane l holds row l % 16, columns l / 16 + 4c in
 // v[c].  That is the A-operand layout of four chained 16x16x4 FP64 MFMAs
@@ -190,7 +213,7 @@ __device__ __forceinline__ bool leaf_invert16(double (&v)[4]) {
     const double colk = __shfl(v[kc], kg * 16 + i);  // P[i][k]
     double prow[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) prow[c] = __shfl(v[c], g * 16 + k);  // P[k][g + 4c]
+    for (int c = 0; c < 4; ++c) prow[c] = row_bcast(v[c], k);  // P[k][g + 4c]
     const double piv = bcast_lane(v[kc], kg * 16 + k);
     ok = ok && piv > 0.0 && isfinite(piv);
     const double inv = 1.0 / piv;
@@ -209,8 +232,9 @@ __device__ __forceinline__ bool leaf_invert16(double (&v)[4]) {
 // One Gauss-Jordan step, pivot part: one work-group (4 wavefronts) per
 // matrix inverts the kNB x kNB (128 x 128) pivot block P = D[p, p] in FP64,
 // without pivoting, and writes P^{-1} (row-major, rounded to T) to Pinv[b],
-// the operand of the panel product.  FP64 throughout: the transfer blocks inherit the error of these inverses
-// amplified by the conditioning of the interface Schur block.
+// the operand of the panel product.  FP64 throughout: the transfer blocks
+// inherit the error of these inverses amplified by the conditioning of the
+// interface Schur block.
 //
 // The block stays in registers for the whole inversion, as 16 x 16 tiles in
 // the FP64 MFMA output layout: wave w owns column tiles 2w and 2w + 1 of all
@@ -218,21 +242,26 @@ __device__ __forceinline__ bool leaf_invert16(double (&v)[4]) {
 // leaves.  Sub-step q: the row block q and the column block q go to LDS
 // (double-buffered, one barrier per sub-step); every wave inverts the leaf
 // P_qq itself (the same arithmetic in each wave, so no second barrier), forms
-// R_J = P_qq^{-1} P_qJ for its own column tiles and applies the rank-16
-// update to them on the matrix cores, with the tiles as accumulators:
+// R_J = P_qq^{-1} P_qJ for its column tiles and applies the rank-16 update
+// to them on the matrix cores, with the tiles as accumulators:
 //   row tile q:        T_qJ = R_J                   (R_q = P_qq^{-1})
 //   column tile q:     T_Iq = -P_Iq P_qq^{-1}       (formed from zero)
 //   others:            T_IJ = T_IJ - P_Iq R_J
 // The MFMA output layout of R_J (row 4r + l / 16 in register r) is the
 // B-operand layout of the update's k-step r, and the leaf layout is the
-// A-operand layout, so no data moves between the two.
+// A-operand layout, so no data moves between the two.  The sub-step loop is
+// unrolled so that every tile index is static, and no vector ALU operation
+// touches a tile.  The register cap keeps the whole work-group within about
+// 190 registers per SIMD lane, so it can be placed on a CU next to the
+// update and GEMM work-groups that run concurrently on other streams (a
+// larger footprint waits for a CU to drain).
 constexpr int kLeaf = 16;
 constexpr int kCqS = 20;        // LDS row stride of the column block (doubles)
 constexpr int kRqS = kNB + 16;  // LDS row stride of the row block (doubles)
 static_assert(kNB == 128, "the register layout below assumes 128-wide pivots");
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gj_pivot(void *const *__restrict__ mats,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj_pivot(void *const *__restrict__ mats,
                                                   T *__restrict__ Pinv, int ld, int p,
                                                   int *__restrict__ flag) {
   __shared__ double Cq[2][kNB][kCqS];
@@ -249,25 +278,19 @@ __global__ __launch_bounds__(256) void k_gj_pivot(void *const *__restrict__ mats
       for (int r = 0; r < 4; ++r)
         t[I][jj][r] = (double)D[(size_t)(16 * I + 4 * r + lr) * ld + 16 * (2 * w + jj) + lc];
   bool ok = true;
+#pragma unroll
   for (int q = 0; q < kNB / kLeaf; ++q) {
-    const int buf = q & 1;
+    const int buf = q & 1, qj = q & 1;
+    const bool owner = w == (q >> 1);  // this wave holds column tile q (as jj = qj)
 #pragma unroll
-    for (int I = 0; I < 8; ++I)
-      if (I == q) {
+    for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj)
+      for (int r = 0; r < 4; ++r) Rq[buf][4 * r + lr][16 * (2 * w + jj) + lc] = t[q][jj][r];
+    if (owner) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Rq[buf][4 * r + lr][16 * (2 * w + jj) + lc] = t[I][jj][r];
-      }
-    if (w == (q >> 1)) {
+      for (int I = 0; I < 8; ++I)
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-        if (jj == (q & 1)) {
-#pragma unroll
-          for (int I = 0; I < 8; ++I)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Cq[buf][16 * I + 4 * r + lr][lc] = t[I][jj][r];
-        }
+        for (int r = 0; r < 4; ++r) Cq[buf][16 * I + 4 * r + lr][lc] = t[I][qj][r];
     }
     __syncthreads();
     double v[4];
@@ -277,37 +300,36 @@ __global__ __launch_bounds__(256) void k_gj_pivot(void *const *__restrict__ mats
     f64x4 R[2];
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) {
-      const int J = 2 * w + jj;
+      const bool pc = owner && jj == qj;
 #pragma unroll
       for (int r = 0; r < 4; ++r) R[jj][r] = 0.0;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const double bs = J == q ? (4 * s + lr == lc ? 1.0 : 0.0) : Rq[buf][4 * s + lr][16 * J + lc];
+        const double id = 4 * s + lr == lc ? 1.0 : 0.0;
+        const double bs = pc ? id : Rq[buf][4 * s + lr][16 * (2 * w + jj) + lc];
         R[jj] = mfma16(v[s], bs, R[jj]);
       }
     }
 #pragma unroll
     for (int I = 0; I < 8; ++I) {
-      if (I == q) {
-        t[I][0] = R[0];
-        t[I][1] = R[1];
-        continue;
-      }
+      if (I == q) continue;
       double a[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) a[s] = -Cq[buf][16 * I + lc][4 * s + lr];
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        f64x4 acc = t[I][jj];
-        if (2 * w + jj == q) {
+      for (int s = 0; s < 4; ++s) t[I][1 - qj] = mfma16(a[s], R[1 - qj][s], t[I][1 - qj]);
+      if (owner) {  // pivot-column tile, formed from zero
+        f64x4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[r] = 0.0;
-        }
+        for (int s = 0; s < 4; ++s) z = mfma16(a[s], R[qj][s], z);
+        t[I][qj] = z;
+      } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = mfma16(a[s], R[jj][s], acc);
-        t[I][jj] = acc;
+        for (int s = 0; s < 4; ++s) t[I][qj] = mfma16(a[s], R[qj][s], t[I][qj]);
       }
     }
+    t[q][0] = R[0];
+    t[q][1] = R[1];
   }
   if (!ok && threadIdx.x == 0) atomicOr(flag, 1);
   T *out = Pinv + (size_t)b * kNB * kNB;
@@ -392,11 +414,36 @@ template <> struct UpdGeom<double> {
   static constexpr int CR = 16;
 };
 
+// Tile subsets of one update (q = p + 1, the next pivot block).
+enum { kSelAll = 0, kSelNext = 1, kSelRest = 2 };
+__host__ __device__ inline int sel_tiles(int sel, int nt) {
+  return sel == kSelAll ? nt * nt : sel == kSelNext ? 2 * nt - 1 : (nt - 1) * (nt - 1);
+}
+__device__ __forceinline__ void sel_tile(int sel, int nt, int q, int t, int &tr, int &tc) {
+  if (sel == kSelAll) {
+    tr = t / nt;
+    tc = t % nt;
+  } else if (sel == kSelNext) {  // row block q, then column block q without (q, q)
+    if (t < nt) {
+      tr = q;
+      tc = t;
+    } else {
+      tr = t - nt + (t - nt >= q);
+      tc = q;
+    }
+  } else {  // everything outside row and column block q
+    tr = t / (nt - 1);
+    tc = t % (nt - 1);
+    tr += tr >= q;
+    tc += tc >= q;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
                                                    const T *__restrict__ Cbuf, int ld,
-                                                   int p, int tiles_per_mat) {
+                                                   int p, int sel) {
   using G = UpdGeom<T>;
   constexpr int XW = kTile + 4;  // exchange row width
   static_assert(2 * BK * LW >= G::CR * XW, "exchange chunk must fit the staging LDS");
@@ -404,11 +451,13 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   T (*As)[LW] = reinterpret_cast<T (*)[LW]>(lds);
   T (*Bs)[LW] = reinterpret_cast<T (*)[LW]>(lds + BK * LW);
   T (*Xs)[XW] = reinterpret_cast<T (*)[XW]>(lds);
+  const int nt = ld / kTile;
+  const int tiles_per_mat = sel_tiles(sel, nt);
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int b = lin / tiles_per_mat;
-  const int t = lin % tiles_per_mat;
-  const int nt = ld / kTile;
-  const int bm = (t / nt) * kTile, bn = (t % nt) * kTile;
+  int tr, tc;
+  sel_tile(sel, nt, p + 1, lin % tiles_per_mat, tr, tc);
+  const int bm = tr * kTile, bn = tc * kTile;
   T *D = static_cast<T *>(mats[b]);
   const T *R = Rbuf + (size_t)b * kNB * ld;
   const T *Cb = Cbuf + (size_t)b * ld * kNB;
@@ -432,6 +481,15 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
     if (pivcols)
 #pragma unroll
       for (int e = 0; e < G::VEC; ++e) dold[q][e] = T(0);
+  }
+  if (bm == p0) {  // pivot rows: D[p, :] = R, no product needed
+#pragma unroll
+    for (int q = 0; q < G::NQ; ++q) {
+      const int row = bm + q * G::RPI + trow;
+      *reinterpret_cast<float4 *>(D + (size_t)row * ld + bn + tcol) =
+          *reinterpret_cast<const float4 *>(R + (size_t)(row - p0) * ld + bn + tcol);
+    }
+    return;
   }
   Tile<T> acc;
   acc.zero();
@@ -474,50 +532,77 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   }
 }
 
-// D = A_plane - diag(r1) G1 diag(c1) - diag(r2) G2 diag(c2); one block per row.
+// D = A_plane - diag(r1) G1 diag(c1) - diag(r2) G2 diag(c2).  Streams G
+// and D once (HBM-bound): work-group (x, b) covers kAsmRows rows of job b,
+// each thread V consecutive columns with 16-byte loads and stores; the
+// column scales are read once per thread and reused over the rows.
+constexpr int kAsmRows = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ jobs,
                                                   const double *__restrict__ coef, int n,
                                                   int dim, int M, int ld) {
+  constexpr int V = 16 / sizeof(T);
+  using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   const AsmJob J = jobs[blockIdx.y];
-  const int r = blockIdx.x;
-  T *D = static_cast<T *>(J.D) + (size_t)r * ld;
-  if (r >= M) {
-    for (int c = threadIdx.x; c < ld; c += blockDim.x) D[c] = (c == r) ? T(1) : T(0);
-    return;
-  }
   const size_t N = (size_t)M * n;
-  const size_t node = (size_t)(J.plane - 1) * M + r;
-  // in-plane stencil entries of row r (boundary neighbours are not in A_plane)
-  int nb_col[4];
-  double nb_val[4];
-  int nnb = 0;
-  if (dim == 2) {
-    if (r >= 1) { nb_col[nnb] = r - 1; nb_val[nnb++] = coef[3 * N + node]; }
-    if (r <= n - 2) { nb_col[nnb] = r + 1; nb_val[nnb++] = coef[4 * N + node]; }
-  } else {
-    const int y = r / n, z = r % n;
-    if (y >= 1) { nb_col[nnb] = r - n; nb_val[nnb++] = coef[3 * N + node]; }
-    if (y <= n - 2) { nb_col[nnb] = r + n; nb_val[nnb++] = coef[4 * N + node]; }
-    if (z >= 1) { nb_col[nnb] = r - 1; nb_val[nnb++] = coef[5 * N + node]; }
-    if (z <= n - 2) { nb_col[nnb] = r + 1; nb_val[nnb++] = coef[6 * N + node]; }
-  }
-  const double diag = coef[node];
-  const T *G1 = J.G1 ? static_cast<const T *>(J.G1) + (size_t)r * ld : nullptr;
-  const T *G2 = J.G2 ? static_cast<const T *>(J.G2) + (size_t)r * ld : nullptr;
-  const double s1 = G1 ? J.r1[r] : 0.0;
-  const double s2 = G2 ? J.r2[r] : 0.0;
-  for (int c = threadIdx.x; c < ld; c += blockDim.x) {
-    double v = 0.0;
-    if (c < M) {
-      if (G1) v -= s1 * (double)G1[c] * J.c1[c];
-      if (G2) v -= s2 * (double)G2[c] * J.c2[c];
-      if (c == r) v += diag;
+  const T *G1 = static_cast<const T *>(J.G1);
+  const T *G2 = static_cast<const T *>(J.G2);
+  for (int c0 = threadIdx.x * V; c0 < ld; c0 += 256 * V) {
+    double sc1[V], sc2[V];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q < nnb && nb_col[q] == c) v += nb_val[q];
+    for (int e = 0; e < V; ++e) {
+      const bool in = c0 + e < M;
+      sc1[e] = (G1 && in) ? J.c1[c0 + e] : 0.0;
+      sc2[e] = (G2 && in) ? J.c2[c0 + e] : 0.0;
     }
-    D[c] = (T)v;
+#pragma unroll
+    for (int rr = 0; rr < kAsmRows; ++rr) {
+      const int r = blockIdx.x * kAsmRows + rr;
+      T out[V];
+      if (r >= M) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) out[e] = (c0 + e == r) ? T(1) : T(0);
+      } else {
+        T g1[V], g2[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) g1[e] = g2[e] = T(0);
+        if (G1)
+          *reinterpret_cast<VT *>(g1) = *reinterpret_cast<const VT *>(G1 + (size_t)r * ld + c0);
+        if (G2)
+          *reinterpret_cast<VT *>(g2) = *reinterpret_cast<const VT *>(G2 + (size_t)r * ld + c0);
+        const double s1 = G1 ? J.r1[r] : 0.0;
+        const double s2 = G2 ? J.r2[r] : 0.0;
+        double v[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          v[e] = c0 + e < M ? -s1 * (double)g1[e] * sc1[e] - s2 * (double)g2[e] * sc2[e] : 0.0;
+        // in-plane stencil entries of row r (boundary neighbours are not in A_plane)
+        const size_t node = (size_t)(J.plane - 1) * M + r;
+        auto add = [&](int col, double val) {
+          if (col >= c0 && col < c0 + V) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+              if (c0 + e == col) v[e] += val;
+          }
+        };
+        add(r, coef[node]);
+        if (dim == 2) {
+          if (r >= 1) add(r - 1, coef[3 * N + node]);
+          if (r <= n - 2) add(r + 1, coef[4 * N + node]);
+        } else {
+          const int y = r / n, z = r % n;
+          if (y >= 1) add(r - n, coef[3 * N + node]);
+          if (y <= n - 2) add(r + n, coef[4 * N + node]);
+          if (z >= 1) add(r - 1, coef[5 * N + node]);
+          if (z <= n - 2) add(r + 1, coef[6 * N + node]);
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) out[e] = (T)v[e];
+      }
+      *reinterpret_cast<VT *>(static_cast<T *>(J.D) + (size_t)r * ld + c0) =
+          *reinterpret_cast<const VT *>(out);
+    }
   }
 }
 
@@ -540,8 +625,8 @@ void launch_assemble(const AsmJob *jobs, int njobs, const double *coef, int n, i
                      int M, int ld, hipStream_t s) {
   if (njobs <= 0) return;
   prof_begin(KK_ASSEMBLE, s);
-  hipLaunchKernelGGL(k_assemble<T>, dim3(ld, njobs), dim3(256), 0, s, jobs, coef, n, dim, M,
-                     ld);
+  hipLaunchKernelGGL(k_assemble<T>, dim3(ld / kAsmRows, njobs), dim3(256), 0, s, jobs, coef,
+                     n, dim, M, ld);
   // reads G (and up to one more) and writes D: 2 M^2 elements per job
   prof_end(KK_ASSEMBLE, s, 2.0 * njobs * (double)M * M * sizeof(T));
 }
@@ -563,27 +648,80 @@ void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, do
   prof_end(KK_GEMM, s, 2.0 * njobs * (double)M * M * M);
 }
 
+hipError_t GjStreams::create() {
+  hipError_t e = hipStreamCreateWithFlags(&h, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&panel, hipEventDisableTiming);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&rest[i], hipEventDisableTiming);
+  return e;
+}
+
+GjStreams::~GjStreams() {
+  if (h) (void)hipStreamSynchronize(h);
+  for (hipEvent_t ev : {panel, rest[0], rest[1]})
+    if (ev) (void)hipEventDestroy(ev);
+  if (h) (void)hipStreamDestroy(h);
+}
+
+// Schedule of one inversion (U1 = tiles of row/column block p+1, U2 = the
+// rest, buffers of step p: R, Cbuf index p & 1):
+//   s  : pivot(0) panel(0) | U1(0) pivot(1) panel(1) | U1(1) ... | all(last)
+//   gs.h:                    U2(0)                     U2(1) ...
+// U2(p) waits for panel(p); U1(p) waits for U2(p-1) (it rewrites tiles
+// U2(p-1) produced, and panel(p+1) reuses the buffers U2(p-1) read).
 template <typename T>
-void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, double *Pinv,
-               int *flag, hipStream_t s) {
-  if (nmat <= 0) return;
+hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
+                     GjStreams &gs, hipStream_t s) {
+  if (nmat <= 0) return hipSuccess;
   static_assert(kNB == kTile, "one pivot block per tile row");
   const int nt = ld / kTile;
-  const int tpm = nt * nt;
-  T *PinvT = reinterpret_cast<T *>(Pinv);  // nmat kNB x kNB inverses, rounded to T
+  const size_t pan = (size_t)nmat * kNB * ld;
+  T *w = static_cast<T *>(work);
+  T *Rb[2] = {w, w + 2 * pan}, *Cb[2] = {w + pan, w + 3 * pan};
+  T *PinvT = w + 4 * pan;  // nmat kNB x kNB inverses, rounded to T
   // blocks that hold only identity padding need no elimination step
   const int nreal = (M + kNB - 1) / kNB;
-  for (int p = 0; p < nreal; ++p) {
+  // algorithmic flops of one step: rank-kNB update of the M - kNB other rows
+  const double step_flops = 2.0 * nmat * (double)kNB * M * std::max(M - kNB, 0);
+  const double mfma_tiles = (double)nt * (nt - 1);  // tiles off the pivot rows
+  auto pivot_panel = [&](int p) {
     prof_begin(KK_GJ_PANEL, s);
     hipLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(256), 0, s, mats, PinvT, ld, p, flag);
-    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nt, nmat), dim3(256), 0, s, mats, PinvT, Rbuf,
-                       Cbuf, ld, p);
+    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nt, nmat), dim3(256), 0, s, mats, PinvT, Rb[p & 1],
+                       Cb[p & 1], ld, p);
     prof_end(KK_GJ_PANEL, s, 2.0 * nmat * (double)kNB * kNB * M);
-    prof_begin(KK_GJ_UPDATE, s);
-    hipLaunchKernelGGL(k_gj_update<T>, dim3(tpm * nmat), dim3(256), 0, s, mats, Rbuf, Cbuf,
-                       ld, p, tpm);
-    prof_end(KK_GJ_UPDATE, s, 2.0 * nmat * (double)M * M * kNB);
+  };
+  auto update = [&](int p, int sel, hipStream_t st) {
+    const int ntiles = sel_tiles(sel, nt);
+    const double tiles = sel == kSelAll ? mfma_tiles : sel == kSelNext ? 2.0 * (nt - 1)
+                                                                       : (nt - 1.0) * (nt - 2);
+    prof_begin(KK_GJ_UPDATE, st);
+    hipLaunchKernelGGL(k_gj_update<T>, dim3(ntiles * nmat), dim3(256), 0, st, mats, Rb[p & 1],
+                       Cb[p & 1], ld, p, sel);
+    prof_end(KK_GJ_UPDATE, st, mfma_tiles > 0 ? step_flops * tiles / mfma_tiles : 0.0);
+  };
+  hipError_t e = hipSuccess;
+#define GJCHK(x)                      \
+  do {                                \
+    if ((e = (x)) != hipSuccess) return e; \
+  } while (0)
+  pivot_panel(0);
+  for (int p = 0; p < nreal; ++p) {
+    if (p + 1 < nreal) {
+      GJCHK(hipEventRecord(gs.panel, s));
+      GJCHK(hipStreamWaitEvent(gs.h, gs.panel, 0));
+      update(p, kSelRest, gs.h);
+      GJCHK(hipEventRecord(gs.rest[p & 1], gs.h));
+      if (p >= 1) GJCHK(hipStreamWaitEvent(s, gs.rest[(p - 1) & 1], 0));
+      update(p, kSelNext, s);
+      pivot_panel(p + 1);
+    } else {
+      if (p >= 1) GJCHK(hipStreamWaitEvent(s, gs.rest[(p - 1) & 1], 0));
+      update(p, kSelAll, s);
+    }
   }
+#undef GJCHK
+  return hipGetLastError();
 }
 
 #define DDST_INST(T)                                                                      \
@@ -591,8 +729,8 @@ void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, dou
                                    hipStream_t);                                           \
   template void launch_scale_cols<T>(const GemmJob *, int, int, double, hipStream_t);       \
   template void launch_gemm<T>(const GemmJob *, int, int, int, double, double, hipStream_t); \
-  template void gj_invert<T>(void *const *, int, int, int, T *, T *, double *, int *,       \
-                             hipStream_t);
+  template hipError_t gj_invert<T>(void *const *, int, int, int, void *, int *, GjStreams &, \
+                                   hipStream_t);
 DDST_INST(float)
 DDST_INST(double)
 #undef DDST_INST

@@ -94,16 +94,31 @@ void launch_scale_cols(const GemmJob *jobs, int njobs, int ld, double alpha, hip
 template <typename T>
 void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, double beta,
                  hipStream_t s);
-// In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices.
-// Rbuf: nmat*kNB*ld, Cbuf: nmat*ld*kNB workspace of T; Pinv: room for
-// nmat*kNB*kNB doubles (holds the pivot-block inverses, rounded to T);
-// flag: device int set to 1 when a pivot is non-positive or non-finite.
+// Helper stream and events of the look-ahead Gauss-Jordan schedule, created
+// once and reused by every inversion of a build (destroyed with the object).
+struct GjStreams {
+  hipStream_t h = nullptr;
+  hipEvent_t panel = nullptr;
+  hipEvent_t rest[2] = {nullptr, nullptr};
+  GjStreams() = default;
+  GjStreams(const GjStreams &) = delete;
+  GjStreams &operator=(const GjStreams &) = delete;
+  hipError_t create();
+  ~GjStreams();
+};
+// In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices
+// with look-ahead: the update of step p is split into the tiles of the next
+// pivot's row and column blocks (on s, followed by the next pivot and panel)
+// and all other tiles (on gs.h, concurrently).  work: gj_workspace_bytes
+// bytes (two R and two column panels, the pivot inverses); flag: device int
+// set to 1 when a pivot is non-positive or non-finite.  Everything is
+// ordered before later work on s when the call returns.
 template <typename T>
-void gj_invert(void *const *mats, int nmat, int ld, int M, T *Rbuf, T *Cbuf, double *Pinv,
-               int *flag, hipStream_t s);
+hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
+                     GjStreams &gs, hipStream_t s);
 // Bytes of Gauss-Jordan workspace for nmat matrices.
 inline size_t gj_workspace_bytes(int nmat, int ld, size_t esz) {
-  return (size_t)nmat * kNB * ld * esz * 2 + (size_t)nmat * kNB * kNB * sizeof(double);
+  return (size_t)nmat * kNB * ld * esz * 4 + (size_t)nmat * kNB * kNB * esz;
 }
 
 // ---- vector kernels (vec.hip) --------------------------------------------
