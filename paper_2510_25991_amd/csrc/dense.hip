@@ -56,10 +56,12 @@ __device__ __forceinline__ void ld8(const double *p, double *r) {
 
 // Map the linear work-group id so that consecutive logical tiles land on
 // the same XCD (work-groups are dispatched round-robin over the 8 XCDs):
-// tiles of one batch entry then share one L2.
+// tiles of one batch entry then share one L2.  XCD x receives ids x, x + 8,
+// ...; it is given the contiguous logical range starting at
+// x q + min(x, rem) (total = 8 q + rem), a bijection for any total.
 __device__ __forceinline__ int xcd_remap(int lin, int total) {
-  if ((total & 7) != 0) return lin;
-  return (lin & 7) * (total >> 3) + (lin >> 3);
+  const int x = lin & 7, k = lin >> 3, q = total >> 3, rem = total & 7;
+  return x * q + (x < rem ? x : rem) + k;
 }
 
 template <typename T>
@@ -465,23 +467,6 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   const int tid = threadIdx.x;
   constexpr int LPR = kTile / G::VEC;           // lanes per row
   const int trow = tid / LPR, tcol = (tid % LPR) * G::VEC;
-  // coalesced prefetch of the D tile (zero in the pivot columns)
-  T dold[G::NQ][G::VEC];
-  const bool pivcols = (bn + tcol >= p0) && (bn + tcol < p0 + kNB);
-#pragma unroll
-  for (int q = 0; q < G::NQ; ++q) {
-    const T *src = D + (size_t)(bm + q * G::RPI + trow) * ld + bn + tcol;
-    if (sizeof(T) == 4) {
-      const float4 v = *reinterpret_cast<const float4 *>(src);
-      dold[q][0] = v.x; dold[q][1] = v.y; dold[q][2] = v.z; dold[q][G::VEC - 1] = v.w;
-    } else {
-      const double2 v = *reinterpret_cast<const double2 *>(src);
-      dold[q][0] = v.x; dold[q][G::VEC - 1] = v.y;
-    }
-    if (pivcols)
-#pragma unroll
-      for (int e = 0; e < G::VEC; ++e) dold[q][e] = T(0);
-  }
   if (bm == p0) {  // pivot rows: D[p, :] = R, no product needed
 #pragma unroll
     for (int q = 0; q < G::NQ; ++q) {
@@ -491,6 +476,27 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
     }
     return;
   }
+  // coalesced prefetch of the D tile (zero in the pivot columns), issued
+  // before the product so its latency overlaps the matrix-core work
+  T dold[G::NQ][G::VEC];
+  const bool pivcols = (bn + tcol >= p0) && (bn + tcol < p0 + kNB);
+  auto read_d = [&]() {
+#pragma unroll
+    for (int q = 0; q < G::NQ; ++q) {
+      const T *src = D + (size_t)(bm + q * G::RPI + trow) * ld + bn + tcol;
+      if (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(src);
+        dold[q][0] = v.x; dold[q][1] = v.y; dold[q][2] = v.z; dold[q][G::VEC - 1] = v.w;
+      } else {
+        const double2 v = *reinterpret_cast<const double2 *>(src);
+        dold[q][0] = v.x; dold[q][G::VEC - 1] = v.y;
+      }
+      if (pivcols)
+#pragma unroll
+        for (int e = 0; e < G::VEC; ++e) dold[q][e] = T(0);
+    }
+  };
+  read_d();
   Tile<T> acc;
   acc.zero();
   mma_tile<T>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, nullptr, kNB, As, Bs, acc);
