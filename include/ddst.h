@@ -98,7 +98,8 @@ typedef struct {
 typedef struct {
   double tol;               /* target relative error of the refined solution   */
   double inner_tol;         /* relative residual of the interface GMRES        */
-  int32_t max_iter;         /* GMRES iteration cap (unrestarted; <= 1000)      */
+  int32_t max_iter;         /* GMRES iteration cap (unrestarted; <= 20000; the */
+                            /* basis takes (max_iter+1)*N_ds*ld*8 device bytes) */
   int32_t max_outer;        /* FP64 refinement passes (>= 1)                   */
   int32_t use_hodlr;        /* 1: apply S through the compressed form          */
   int32_t reserved;

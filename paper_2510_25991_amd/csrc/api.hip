@@ -505,7 +505,8 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   o[9] = cv.take((size_t)(4 * max_iter + 16) * 8);
   o[10] = cv.take(part * 8);
   o[11] = cv.take(16 * 8);
-  o[12] = cv.take(dots_part_len(std::max(vol, ifc), max_iter + 2) * 8);
+  // partial sums: up to max_iter + 2 interface-length dots, or one volume norm
+  o[12] = cv.take(std::max(dots_part_len(ifc, max_iter + 2), dots_part_len(vol, 1)) * 8);
   ensure_ws(op, cv.off);
   auto at = [&](size_t x) {
     return reinterpret_cast<double *>(static_cast<unsigned char *>(op->ws) + x);
@@ -641,8 +642,10 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
     for (int k = 0; k < max_iter; ++k)
       offs[k] = tab.add(interface_jobs(op, w.V + (size_t)k * len, w.W, trans));
   tab.upload(s);
-  std::vector<double> H((size_t)(max_iter + 1) * max_iter, 0.0), cs(max_iter), sn(max_iter),
-      gv(max_iter + 1, 0.0);
+  // Hessenberg columns, packed: column k holds k + 2 entries from offset
+  // k (k + 3) / 2 (only the iterations taken are stored)
+  std::vector<double> H, cs, sn, gv(1, 0.0);
+  auto hoff = [](int k) { return (size_t)k * (k + 3) / 2; };
   gv[0] = beta;
   int k = 0;
   double res = 1.0;
@@ -663,7 +666,11 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
     launch_scale_by_inv(w.V + (size_t)(k + 1) * len, w.W, w.hd + 2 * (k + 1), len, s);
     HIPCHK(hipMemcpyAsync(hh, w.hd, (2 * (k + 1) + 1) * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    double *col = &H[(size_t)k * (max_iter + 1)];
+    H.resize(hoff(k + 1), 0.0);
+    cs.push_back(1.0);
+    sn.push_back(0.0);
+    gv.push_back(0.0);
+    double *col = &H[hoff(k)];
     for (int i = 0; i <= k; ++i) col[i] = hh[i] + hh[k + 1 + i];
     col[k + 1] = hh[2 * (k + 1)];
     for (int i = 0; i < k; ++i) {
@@ -689,8 +696,8 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
   std::vector<double> y(k, 0.0);
   for (int i = k - 1; i >= 0; --i) {
     double t = gv[i];
-    for (int j = i + 1; j < k; ++j) t -= H[(size_t)j * (max_iter + 1) + i] * y[j];
-    const double d = H[(size_t)i * (max_iter + 1) + i];
+    for (int j = i + 1; j < k; ++j) t -= H[hoff(j) + i] * y[j];
+    const double d = H[hoff(i) + i];
     y[i] = (d != 0.0) ? t / d : 0.0;
   }
   std::memcpy(hh, y.data(), k * 8);
@@ -709,12 +716,18 @@ double dev_norm(ddst_op *op, const double *v, size_t len, double *scratch, doubl
   return op->hbuf_host[0];
 }
 
-void ensure_host(ddst_op *op) {
-  if (!op->hbuf_host) {
-    void *p = nullptr;
-    HIPCHK(hipHostMalloc(&p, 1 << 16, hipHostMallocDefault));
-    op->hbuf_host = static_cast<double *>(p);
-  }
+// Pinned host staging for GMRES scalars: 2 (max_iter + 1) + 1 doubles per
+// Arnoldi step and max_iter coefficients at the end.
+void ensure_host(ddst_op *op, int max_iter) {
+  const size_t need = std::max<size_t>((size_t)(2 * max_iter + 16) * 8, 1 << 16);
+  if (op->hbuf_host && op->hbuf_bytes >= need) return;
+  if (op->hbuf_host) (void)hipHostFree(op->hbuf_host);
+  op->hbuf_host = nullptr;
+  op->hbuf_bytes = 0;
+  void *p = nullptr;
+  HIPCHK(hipHostMalloc(&p, need, hipHostMallocDefault));
+  op->hbuf_host = static_cast<double *>(p);
+  op->hbuf_bytes = need;
 }
 
 // One DD solve of A d = r (transpose: A^T d = r) with zero boundary data,
@@ -822,7 +835,8 @@ ddst_solve_opts_t solve_defaults(const ddst_op *op) {
 
 int check_solve_opts(const ddst_solve_opts_t &o) {
   if (!(o.tol > 0) || !(o.inner_tol > 0)) return fail(DDST_EINVAL, "tolerances must be > 0");
-  if (o.max_iter < 1 || o.max_iter > 1000) return fail(DDST_EINVAL, "max_iter in [1, 1000]");
+  if (o.max_iter < 1 || o.max_iter > kMaxGmresIter)
+    return fail(DDST_EINVAL, "max_iter in [1, " + std::to_string(kMaxGmresIter) + "]");
   if (o.max_outer < 1 || o.max_outer > 100) return fail(DDST_EINVAL, "max_outer in [1, 100]");
   return DDST_OK;
 }
@@ -832,7 +846,7 @@ int solve_impl(ddst_op *op, const double *f, const double *g, const ddst_solve_o
                double *u_gamma, double *u_vol, ddst_stats_t *st, hipStream_t s) {
   if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
   if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
-  ensure_host(op);
+  ensure_host(op, o.max_iter);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -870,7 +884,7 @@ int adjoint_impl(ddst_op *op, const double *u_vol, const double *g, const double
                  const ddst_solve_opts_t &o, double *dkappa, double *lambda, ddst_stats_t *st,
                  hipStream_t s) {
   if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
-  ensure_host(op);
+  ensure_host(op, o.max_iter);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -25,6 +25,7 @@ struct Hodlr;
 
 constexpr int kTile = 128;   // GEMM / update output tile (rows and cols)
 constexpr int kNB = 128;     // Gauss-Jordan block width (= kTile)
+constexpr int kMaxGmresIter = 20000;  // unrestarted GMRES: basis kept in HBM
 constexpr int kGemvChunk = 32;  // rows per partial sum in the transposed GEMV
 
 // Stencil coefficient slots: coef[slot * N + node], node = interior C-order.
@@ -199,5 +200,6 @@ struct ddst_op {
   void *ws = nullptr;
   size_t ws_bytes = 0;
   double *hbuf_host = nullptr;  // pinned host staging for GMRES scalars
+  size_t hbuf_bytes = 0;
   ddst_stats_t last_build{};
 };

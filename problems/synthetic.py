@@ -127,6 +127,17 @@ def sensor_nodes(dim: int, n: int, count: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(n ** dim, size=count, replace=False)).astype(np.int64)
 
 
+def perturbed_kappa(prob, seed: int = 1009, amplitude: float = 0.1) -> np.ndarray:
+    """The "true" coefficient behind synthetic sensor data of the adjoint
+    workload: kappa * exp(amplitude * G') with G' an independent Fourier field
+    of the same spectrum as the workload's (16 modes, |k| <= 8 in 2D; 32
+    modes, |k| <= 6 in 3D).  Seed: 1005 + 4 for the adjoint configuration."""
+    n_modes, kmax = (16, 8) if prob.dim == 2 else (32, 6)
+    G = fourier_field(prob.dim, prob.n + 1, n_modes, kmax, seed=seed)
+    base = np.ones((prob.n + 1,) * prob.dim) if prob.kappa is None else prob.kappa
+    return np.asarray(base, dtype=np.float64) * np.exp(amplitude * G)
+
+
 def fd_directions(shape, count: int, seed: int) -> np.ndarray:
     """Random cellwise directions ``v ~ N(0,1)``, normalised to max|v| = 1."""
     rng = np.random.default_rng(seed)

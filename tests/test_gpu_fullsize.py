@@ -1,0 +1,169 @@
+"""Parity at the full sizes of the adjoint (1023^2, 32 slabs) and oscillatory
+(2047^2, 64 slabs, HODLR) workloads, through the C-ABI, in the launch
+configuration the benchmark uses (FP32 build, FP64 refinement).
+
+Outputs the oracle can produce in seconds are compared element by element
+(the adjoint gradient; one sampled transfer block); the rest is checked by
+properties that hold at any size (operator error of the compressed form,
+backward error of the refined solution).  The global direct solve of the
+oscillatory workload (about 2.5 minutes of CPU) runs only when
+DDST_SLOW_TESTS=1.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from problems import make_config, sensor_nodes, fd_directions, perturbed_kappa
+from oracle import adjoint as oadj
+from oracle import dd as odd
+from oracle import fd as ofd
+
+pytestmark = pytest.mark.gpu
+
+
+def ddst():
+    from paper_2510_25991_amd import ddst as mod
+    return mod
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def banner(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+_CFG5 = {}
+
+
+def cfg5_case():
+    """The adjoint workload: 256 seeded sensor nodes, data from a forward solve
+    with the perturbed coefficient (oracle), and the oracle's state."""
+    if not _CFG5:
+        p = make_config("cfg5")
+        sens = sensor_nodes(2, p.n, 256, seed=1008)
+        d = ofd.solve_global(p.replace(kappa=perturbed_kappa(p))).ravel()[sens]
+        u_ref = ofd.solve_global(p)
+        _CFG5.update(p=p, sens=sens, d=d, u_ref=u_ref)
+    return _CFG5
+
+
+def test_full_size_cfg5_adjoint_vs_oracle():
+    c = cfg5_case()
+    p = c["p"]
+    banner("full-size cfg5 adjoint 1023^2 32 slabs (fp32 build, fp64 refinement)")
+    gbar = oadj.sensor_loss_grad(c["u_ref"], c["sens"], c["d"], p.N)
+    gref, lref = oadj.gradient(p, c["u_ref"], gbar)
+    op = ddst().Operator.from_problem(p, precision="fp32")
+    u, _, st = op.solve(p.f)
+    assert st["status"] == 0
+    uerr = rel(u.cpu().numpy().ravel(), c["u_ref"])
+    dk, lam, sa = op.adjoint(u.reshape(-1), torch.tensor(gbar, device="cuda"), want_lambda=True)
+    lerr = rel(lam.cpu().numpy().ravel(), lref)
+    gerr = rel(dk.cpu().numpy(), gref)
+    print(f"  state {uerr:.3e} adjoint state {lerr:.3e} gradient {gerr:.3e} "
+          f"(adjoint outer {sa['outer_iters']} gmres {sa['gmres_iters']})")
+    assert uerr <= 1e-8 and lerr <= 1e-8 and gerr <= 1e-8
+    op.close()
+
+
+def test_full_size_cfg5_central_differences():
+    """Central differences of the sensor loss along 20 seeded directions, every
+    solve on the GPU in the mixed form (FP32 build, FP64 refinement to 1e-13),
+    against the hand-written backward through torch.autograd.
+
+    The loss of this workload is small (about 1.6e-12: the state is O(1e-6)
+    and the data differ from it by ~10%), and an FP64 solve of the FD system
+    carries ~3e-11 relative error (condition number ~4e5), so with the usual
+    step 1e-5 |kappa| the quotient is rounding-limited at ~1e-4.  The step is
+    1e-3 |kappa|, and Richardson extrapolation over the steps eps and 2 eps,
+    (4 D(eps) - D(2 eps)) / 3, removes the eps^2 truncation term."""
+    c = cfg5_case()
+    p = c["p"]
+    banner("full-size cfg5 central differences, 20 directions")
+    dd = ddst()
+    sens = torch.tensor(c["sens"], device="cuda")
+    data = torch.tensor(c["d"], device="cuda")
+    kap = torch.tensor(p.kappa, device="cuda", requires_grad=True)
+    f = torch.tensor(p.f, device="cuda")
+    opts = dd.SolveOptions(tol=1e-13, max_outer=10)
+
+    def loss(k):
+        u = dd.ddst_solve(k, f, p.n_slabs, bvec=p.bvec, precision="fp32", opts=opts)
+        return 0.5 * ((u.reshape(-1)[sens] - data) ** 2).sum()
+
+    L = loss(kap)
+    L.backward()
+    grad = kap.grad.detach().cpu().numpy()
+    dirs = fd_directions(p.kappa.shape, 20, seed=1007)
+    eps = 1e-3 * float(np.abs(p.kappa).max())
+    worst = 0.0
+    with torch.no_grad():
+        k0 = kap.detach()
+
+        def central(vt, e):
+            return (float(loss(k0 + e * vt)) - float(loss(k0 - e * vt))) / (2 * e)
+
+        for v in dirs:
+            vt = torch.tensor(v, device="cuda")
+            fdv = (4.0 * central(vt, eps) - central(vt, 2 * eps)) / 3.0
+            ad = float(np.sum(grad * v))
+            worst = max(worst, abs(fdv - ad) / abs(ad))
+    print(f"  loss {float(L.detach()):.6e} worst relative FD mismatch {worst:.2e}")
+    assert worst <= 1e-5
+
+
+def test_full_size_cfg3_hodlr():
+    p = make_config("cfg3")
+    banner("full-size cfg3 2047^2 64 slabs: fp32 build, bf16 HODLR, fp64 refinement")
+    dd = ddst()
+    op = dd.Operator.from_problem(p, precision="fp32")
+    # one sampled transfer block against the oracle's sparse-LU route
+    j = 32
+    SL, SR = (t.cpu().numpy() for t in op.transfer(j))
+    S = odd.DDOracle(p).transfer_block(j, j + 1)
+    berr = rel(SR, S)
+    print(f"  S_{j},{j+1} rel err {berr:.3e}")
+    assert berr <= max(1e-5, 4e-7 * p.m * p.m)
+    # compression (leaf 128, tol 1e-8 with the FP32 floor 1e-6, oversampling 10)
+    info = op.compress(tol=1e-8, leaf=128, oversample=10, max_rank=118, factor_dtype="bf16")
+    nS = np.linalg.norm(S, 2)
+    h = p.M // 2
+    exact = max(int((np.linalg.svd(S[a:b, c:d], compute_uv=False) > 1e-6 * nS).sum())
+                for (a, b, c, d) in ((0, h, h, p.M), (h, p.M, 0, h)))
+    print(f"  ranks {info['min_rank']}..{info['max_rank']} (exact 1e-6 rank of the sampled "
+          f"block's level-1 blocks: {exact}), {info['bytes'] / 2**20:.1f} MiB")
+    assert 1 <= info["min_rank"] and info["max_rank"] <= exact + 10
+    # compressed operator against the dense one on seeded vectors (BF16 factors)
+    rng = np.random.default_rng(1003 + 1)
+    for _ in range(3):
+        x = torch.tensor(rng.standard_normal(p.n_ds * p.M), device="cuda")
+        yd = op.apply(x, which="dense")
+        yh = op.apply(x, which="hodlr")
+        e = float((yd - yh).norm() / yd.norm())
+        assert e <= 2e-2, e
+    # refined solve through the compressed operator
+    u, _, st = op.solve(p.f, opts=dd.SolveOptions(tol=1e-9, max_iter=3000, max_outer=10,
+                                                   use_hodlr=True))
+    print(f"  solve status {st['status']} outer {st['outer_iters']} gmres {st['gmres_iters']} "
+          f"(last pass {st['last_gmres_iters']}) correction {st['correction_rel']:.2e}")
+    assert st["status"] == 0
+    x = u.cpu().numpy().ravel()
+    Ab = ofd.assemble(p)
+    A = Ab[0]
+    r = ofd.rhs(p, Ab) - A @ x
+    nA = float(abs(A).sum(axis=1).max())
+    bw = float(np.abs(r).max() / (nA * np.abs(x).max()))
+    print(f"  scaled FD residual {bw:.3e}")
+    assert bw <= 1e-10
+    if os.environ.get("DDST_SLOW_TESTS") == "1":
+        print("  global direct solve (slow)", flush=True)
+        err = rel(x, ofd.solve_global(p))
+        print(f"  rel err vs global direct {err:.3e}")
+        assert err <= 1e-8
+    op.close()
