@@ -75,6 +75,29 @@ class DDOracle:
         X = self._local_lu(j).solve(AIJ)
         return -X[centre, :]
 
+    def transfer_columns(self, j, jp, cols, rtol=1e-14):
+        """Columns ``cols`` of S_{j,jp} (eq. defS) for symmetric positive
+        definite operators, each by conjugate gradients (diagonal
+        preconditioner) on the double slab instead of a sparse LU: the route
+        for the 3D workload, whose double-slab LU takes minutes."""
+        p = self.prob
+        if abs(jp - j) != 1 or not (1 <= jp <= p.n_ds):
+            raise ValueError("jp must be an interior neighbour interface")
+        I, centre = self.double_slab(j)
+        J = plane_nodes(p, jp * p.m)
+        AII = self.A[I][:, I].tocsr()
+        AIJ = self.A[I][:, J].tocsc()
+        d = AII.diagonal()
+        precond = spla.LinearOperator(AII.shape, matvec=lambda x: x / d)
+        out = np.zeros((p.M, len(cols)))
+        for k, c in enumerate(cols):
+            rhs = AIJ[:, int(c)].toarray().ravel()
+            x, info = spla.cg(AII, rhs, rtol=rtol, atol=0.0, maxiter=20000, M=precond)
+            if info != 0:
+                raise RuntimeError("CG did not converge on the double slab")
+            out[:, k] = -x[centre]
+        return out
+
     def all_blocks(self):
         """Dict {(j, jp): S_{j,jp}} over all interior neighbour pairs."""
         out = {}

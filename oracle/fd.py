@@ -126,3 +126,21 @@ def solve_global(prob):
     Ab = assemble(prob)
     b = rhs(prob, Ab)
     return spla.splu(Ab[0].tocsc()).solve(b)
+
+
+def solve_global_cg(prob, rtol=1e-14, maxiter=50000):
+    """Global reference by conjugate gradients with the diagonal as
+    preconditioner, for symmetric positive definite FD operators (no
+    convection, c >= 0): the 3D workload, whose sparse LU is impractical at
+    full size.  Stops at ||b - A u||_2 <= rtol ||b||_2."""
+    import scipy.sparse.linalg as spla
+    Ab = assemble(prob)
+    A = Ab[0].tocsr()
+    b = rhs(prob, Ab)
+    d = A.diagonal()
+    precond = spla.LinearOperator(A.shape, matvec=lambda x: x / d)
+    u, info = spla.cg(A, b, rtol=rtol, atol=0.0, maxiter=maxiter, M=precond)
+    if info != 0:
+        raise RuntimeError(f"CG did not reach rtol={rtol} in {maxiter} iterations")
+    return u
+

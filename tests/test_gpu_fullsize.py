@@ -1,9 +1,11 @@
-"""Parity at the full sizes of the adjoint (1023^2, 32 slabs) and oscillatory
-(2047^2, 64 slabs, HODLR) workloads, through the C-ABI, in the launch
-configuration the benchmark uses (FP32 build, FP64 refinement).
+"""Parity at the full sizes of the adjoint (1023^2, 32 slabs), oscillatory
+(2047^2, 64 slabs, HODLR) and 3D (127^3, 16 slabs, quadtree HODLR)
+workloads, through the C-ABI, in the launch configuration the benchmark uses
+(FP32 build, FP64 refinement).
 
 Outputs the oracle can produce in seconds are compared element by element
-(the adjoint gradient; one sampled transfer block); the rest is checked by
+(the adjoint gradient; sampled transfer blocks or columns; the 3D solution
+against a conjugate-gradient reference); the rest is checked by
 properties that hold at any size (operator error of the compressed form,
 backward error of the refined solution).  The global direct solve of the
 oscillatory workload (about 2.5 minutes of CPU) runs only when
@@ -167,3 +169,45 @@ def test_full_size_cfg3_hodlr():
         print(f"  rel err vs global direct {err:.3e}")
         assert err <= 1e-8
     op.close()
+
+
+def test_full_size_cfg4_3d_quadtree():
+    """3D variable coefficient, 127^3 interior nodes, 16 slabs: 15 interfaces
+    of 16129 nodes, dense FP32 blocks of 16129 x 16129 (about 250 GB of HBM
+    during the build), quadtree HODLR at tol 1e-7 (FP32 floor 1e-6)."""
+    p = make_config("cfg4")
+    banner("full-size cfg4 127^3 16 slabs: fp32 build (~40 s), quadtree HODLR, refinement")
+    dd = ddst()
+    op = dd.Operator.from_problem(p, precision="fp32")
+    j = 8
+    cols = np.sort(np.random.default_rng(1004 + 1).choice(p.M, 16, replace=False))
+    SR = op.transfer(j)[1][:, torch.tensor(cols, device="cuda")].cpu().numpy()
+    torch.cuda.empty_cache()
+    print("  oracle columns by CG", flush=True)
+    ref = odd.DDOracle(p).transfer_columns(j, j + 1, cols)
+    berr = rel(SR, ref)
+    print(f"  S_{j},{j+1}[:, 16 seeded columns] rel err {berr:.3e}")
+    assert berr <= max(1e-5, 4e-7 * p.m * p.m)
+    info = op.compress(tol=1e-7, leaf=128, oversample=10, max_rank=118, factor_dtype="bf16")
+    print(f"  ranks {info['min_rank']}..{info['max_rank']}, {info['bytes'] / 2**20:.1f} MiB, "
+          f"{info['ms']:.0f} ms")
+    assert 1 <= info["min_rank"] <= info["max_rank"] <= 118
+    rng = np.random.default_rng(1004 + 2)
+    for _ in range(2):
+        x = torch.tensor(rng.standard_normal(p.n_ds * p.M), device="cuda")
+        yd = op.apply(x, which="dense")
+        yh = op.apply(x, which="hodlr")
+        e = float((yd - yh).norm() / yd.norm())
+        assert e <= 2e-2, e
+    u, _, st = op.solve(p.f, opts=dd.SolveOptions(tol=1e-9, max_iter=1000, max_outer=10,
+                                                   use_hodlr=True))
+    print(f"  solve status {st['status']} outer {st['outer_iters']} gmres {st['gmres_iters']} "
+          f"correction {st['correction_rel']:.2e}")
+    assert st["status"] == 0
+    x = u.cpu().numpy().ravel()
+    op.close()
+    print("  global reference by conjugate gradients", flush=True)
+    err = rel(x, ofd.solve_global_cg(p))
+    print(f"  rel err vs CG reference {err:.3e}")
+    assert err <= 1e-8
+
