@@ -126,6 +126,57 @@ __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
   }
 }
 
+// As mma_tile (NEG_A = false, no column scaling) for a compile-time depth
+// K, with the operands of two stages in flight: `hook()` runs after the
+// loads of stages 0 and 1 are issued.  Global loads retire in issue order,
+// so loads the hook issues (the caller's own data) delay only the operands
+// of stage 2 onwards, which wait behind two stages of matrix-core work.
+template <typename T, int K, typename Hook>
+__device__ __forceinline__ void mma_tile_pf2(const T *__restrict__ A, int lda,
+                                             const T *__restrict__ B, int ldb,
+                                             T (*As)[LW], T (*Bs)[LW], Tile<T> &acc,
+                                             Hook hook) {
+  static_assert(K % BK == 0 && K >= 2 * BK, "two stages in flight");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int ar = tid >> 1, ak = (tid & 1) * 8;    // A tile: 128 rows x 16
+  const int br = tid >> 4, bc = (tid & 15) * 8;   // B tile: 16 rows x 128
+  T ra[2][8], rb[2][8];
+  auto load = [&](int buf, int k0) {
+    ld8(A + (size_t)ar * lda + k0 + ak, ra[buf]);
+    ld8(B + (size_t)(k0 + br) * ldb + bc, rb[buf]);
+  };
+  load(0, 0);
+  load(1, BK);
+  hook();
+#pragma unroll
+  for (int st = 0; st < K / BK; ++st) {
+    const int buf = st & 1;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[ak + q][ar] = ra[buf][q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Bs[br][bc + q] = rb[buf][q];
+    __syncthreads();
+    if ((st + 2) * BK < K) load(buf, (st + 2) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T a[4], b[4];
+      const int kr = kk + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc.v[i][j] = mfma16(a[i], b[j], acc.v[i][j]);
+    }
+  }
+}
+
 // Row / column of accumulator element (i, j, r) inside the 128 x 128 tile.
 // Lane l holds column l % 16 of each 16 x 16 MFMA output; the row of
 // register r is 4*(l/16) + r for the FP32 instruction and 4*r + l/16 for
@@ -393,12 +444,12 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
 //   pivot rows               D[p, :] = R             (P^{-1} on the block p)
 //   other rows, column p     D[i, p] = -D[i, p] P^{-1}
 //   other rows, other cols   D[i, j] -= D[i, p] P^{-1} D[p, j]
-// The kernel is bound by streaming D through HBM, so the 128 x 128 tile is
-// read and written with 16-byte accesses, each wavefront covering whole
-// rows (VEC elements per lane), and loaded before the MFMA loop so its
-// latency overlaps the panel product.  The MFMA accumulators are exchanged
-// into that row layout through LDS, CR rows at a time, reusing the staging
-// buffers.  The product is formed from zero and subtracted once, keeping
+// The 128 x 128 tile of D is read and written with 16-byte accesses, each
+// wavefront covering whole rows (VEC elements per lane); its loads are
+// issued behind the first two operand stages so their latency overlaps the
+// product.  The MFMA accumulators are exchanged into that row layout through
+// one LDS tile (one barrier; the operand stages live in the same buffer).
+// The product is formed from zero and subtracted once, keeping
 // the rounding at the scale of the update rather than of D; the pivot
 // column is written as -acc rather than D - (D + D P^{-1}), which would add
 // O(1) to O(|P^{-1}|) entries.
@@ -407,13 +458,11 @@ template <> struct UpdGeom<float> {
   static constexpr int VEC = 4;     // floats per 16-byte access
   static constexpr int RPI = 8;     // rows covered by one pass of 256 threads
   static constexpr int NQ = 16;     // passes per tile (128 / RPI)
-  static constexpr int CR = 32;     // rows per LDS exchange chunk
 };
 template <> struct UpdGeom<double> {
   static constexpr int VEC = 2;
   static constexpr int RPI = 4;
   static constexpr int NQ = 32;
-  static constexpr int CR = 16;
 };
 
 // Tile subsets of one update (q = p + 1, the next pivot block).
@@ -448,8 +497,11 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
                                                    int p, int sel) {
   using G = UpdGeom<T>;
   constexpr int XW = kTile + 4;  // exchange row width
-  static_assert(2 * BK * LW >= G::CR * XW, "exchange chunk must fit the staging LDS");
-  __shared__ T lds[2 * BK * LW];
+  static_assert(kTile * XW >= 2 * BK * LW, "the staging buffers live inside the exchange tile");
+  // one LDS buffer: the operand stages during the product, then the whole
+  // product tile for the exchange (68 KB in FP32: the register footprint
+  // already limits the kernel to two work-groups per CU)
+  __shared__ T lds[kTile * XW];
   T (*As)[LW] = reinterpret_cast<T (*)[LW]>(lds);
   T (*Bs)[LW] = reinterpret_cast<T (*)[LW]>(lds + BK * LW);
   T (*Xs)[XW] = reinterpret_cast<T (*)[XW]>(lds);
@@ -477,7 +529,8 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
     return;
   }
   // coalesced prefetch of the D tile (zero in the pivot columns), issued
-  // before the product so its latency overlaps the matrix-core work
+  // behind the first two operand stages so its latency overlaps the
+  // matrix-core work without delaying them
   T dold[G::NQ][G::VEC];
   const bool pivcols = (bn + tcol >= p0) && (bn + tcol < p0 + kNB);
   auto read_d = [&]() {
@@ -496,44 +549,31 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
         for (int e = 0; e < G::VEC; ++e) dold[q][e] = T(0);
     }
   };
-  read_d();
   Tile<T> acc;
   acc.zero();
-  mma_tile<T>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, nullptr, kNB, As, Bs, acc);
-  // exchange and store, CR rows at a time
+  mma_tile_pf2<T, kNB>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, As, Bs, acc, read_d);
+  // exchange the whole tile through LDS (conflict-free: the 4 row groups
+  // of a store land 16 banks apart), then read it back in the row layout
+  // of the prefetched D and store with 16-byte accesses
+  __syncthreads();
 #pragma unroll
-  for (int c = 0; c < kTile / G::CR; ++c) {
-    __syncthreads();
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) Xs[acc_row<T>(i, r)][acc_col(j)] = acc.v[i][j][r];
+  __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = acc_row<T>(i, r);
-          if (row >= c * G::CR && row < (c + 1) * G::CR)
-            Xs[row - c * G::CR][acc_col(j)] = acc.v[i][j][r];
-        }
-    __syncthreads();
+  for (int q = 0; q < G::NQ; ++q) {
+    const int lrow = q * G::RPI + trow;
+    T out[G::VEC];
 #pragma unroll
-    for (int q = 0; q < G::NQ; ++q) {
-      const int lrow = q * G::RPI + trow;
-      if (lrow < c * G::CR || lrow >= (c + 1) * G::CR) continue;
-      const int row = bm + lrow;
-      T out[G::VEC];
-      if (row >= p0 && row < p0 + kNB) {
-#pragma unroll
-        for (int e = 0; e < G::VEC; ++e) out[e] = R[(size_t)(row - p0) * ld + bn + tcol + e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < G::VEC; ++e) out[e] = dold[q][e] - Xs[lrow - c * G::CR][tcol + e];
-      }
-      T *dst = D + (size_t)row * ld + bn + tcol;
-      if (sizeof(T) == 4) {
-        *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[G::VEC - 1]);
-      } else {
-        *reinterpret_cast<double2 *>(dst) = make_double2(out[0], out[G::VEC - 1]);
-      }
+    for (int e = 0; e < G::VEC; ++e) out[e] = dold[q][e] - Xs[lrow][tcol + e];
+    T *dst = D + (size_t)(bm + lrow) * ld + bn + tcol;
+    if (sizeof(T) == 4) {
+      *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[G::VEC - 1]);
+    } else {
+      *reinterpret_cast<double2 *>(dst) = make_double2(out[0], out[G::VEC - 1]);
     }
   }
 }
