@@ -126,57 +126,6 @@ __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
   }
 }
 
-// As mma_tile (NEG_A = false, no column scaling) for a compile-time depth
-// K, with the operands of two stages in flight: `hook()` runs after the
-// loads of stages 0 and 1 are issued.  Global loads retire in issue order,
-// so loads the hook issues (the caller's own data) delay only the operands
-// of stage 2 onwards, which wait behind two stages of matrix-core work.
-template <typename T, int K, typename Hook>
-__device__ __forceinline__ void mma_tile_pf2(const T *__restrict__ A, int lda,
-                                             const T *__restrict__ B, int ldb,
-                                             T (*As)[LW], T (*Bs)[LW], Tile<T> &acc,
-                                             Hook hook) {
-  static_assert(K % BK == 0 && K >= 2 * BK, "two stages in flight");
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int ar = tid >> 1, ak = (tid & 1) * 8;    // A tile: 128 rows x 16
-  const int br = tid >> 4, bc = (tid & 15) * 8;   // B tile: 16 rows x 128
-  T ra[2][8], rb[2][8];
-  auto load = [&](int buf, int k0) {
-    ld8(A + (size_t)ar * lda + k0 + ak, ra[buf]);
-    ld8(B + (size_t)(k0 + br) * ldb + bc, rb[buf]);
-  };
-  load(0, 0);
-  load(1, BK);
-  hook();
-#pragma unroll
-  for (int st = 0; st < K / BK; ++st) {
-    const int buf = st & 1;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) As[ak + q][ar] = ra[buf][q];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) Bs[br][bc + q] = rb[buf][q];
-    __syncthreads();
-    if ((st + 2) * BK < K) load(buf, (st + 2) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T a[4], b[4];
-      const int kr = kk + (lane >> 4);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc.v[i][j] = mfma16(a[i], b[j], acc.v[i][j]);
-    }
-  }
-}
-
 // Row / column of accumulator element (i, j, r) inside the 128 x 128 tile.
 // Lane l holds column l % 16 of each 16 x 16 MFMA output; the row of
 // register r is 4*(l/16) + r for the FP32 instruction and 4*r + l/16 for
@@ -445,11 +394,14 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
 //   other rows, column p     D[i, p] = -D[i, p] P^{-1}
 //   other rows, other cols   D[i, j] -= D[i, p] P^{-1} D[p, j]
 // The 128 x 128 tile of D is read and written with 16-byte accesses, each
-// wavefront covering whole rows (VEC elements per lane); its loads are
-// issued behind the first two operand stages so their latency overlaps the
-// product.  The MFMA accumulators are exchanged into that row layout through
-// one LDS tile (one barrier; the operand stages live in the same buffer).
-// The product is formed from zero and subtracted once, keeping
+// wavefront covering whole rows (VEC elements per lane).  It is read after
+// the product, half a tile at a time, and the MFMA accumulators are
+// exchanged into its row layout through LDS (64 rows, the two wavefronts
+// holding them write, all four read; the operand stages live in the same
+// buffer).  Keeping D out of registers during the product and the LDS
+// buffer at 34 KB lets three work-groups share a CU (FP32), whose products
+// hide each other's D latency.  The product is formed from zero and
+// subtracted once, keeping
 // the rounding at the scale of the update rather than of D; the pivot
 // column is written as -acc rather than D - (D + D P^{-1}), which would add
 // O(1) to O(|P^{-1}|) entries.
@@ -497,11 +449,9 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
                                                    int p, int sel) {
   using G = UpdGeom<T>;
   constexpr int XW = kTile + 4;  // exchange row width
-  static_assert(kTile * XW >= 2 * BK * LW, "the staging buffers live inside the exchange tile");
-  // one LDS buffer: the operand stages during the product, then the whole
-  // product tile for the exchange (68 KB in FP32: the register footprint
-  // already limits the kernel to two work-groups per CU)
-  __shared__ T lds[kTile * XW];
+  constexpr int HR = kTile / 2;  // rows per exchange half
+  static_assert(HR * XW >= 2 * BK * LW, "the staging buffers live inside the exchange buffer");
+  __shared__ T lds[HR * XW];
   T (*As)[LW] = reinterpret_cast<T (*)[LW]>(lds);
   T (*Bs)[LW] = reinterpret_cast<T (*)[LW]>(lds + BK * LW);
   T (*Xs)[XW] = reinterpret_cast<T (*)[XW]>(lds);
@@ -519,61 +469,49 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   const int tid = threadIdx.x;
   constexpr int LPR = kTile / G::VEC;           // lanes per row
   const int trow = tid / LPR, tcol = (tid % LPR) * G::VEC;
+  using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   if (bm == p0) {  // pivot rows: D[p, :] = R, no product needed
 #pragma unroll
     for (int q = 0; q < G::NQ; ++q) {
       const int row = bm + q * G::RPI + trow;
-      *reinterpret_cast<float4 *>(D + (size_t)row * ld + bn + tcol) =
-          *reinterpret_cast<const float4 *>(R + (size_t)(row - p0) * ld + bn + tcol);
+      *reinterpret_cast<VT *>(D + (size_t)row * ld + bn + tcol) =
+          *reinterpret_cast<const VT *>(R + (size_t)(row - p0) * ld + bn + tcol);
     }
     return;
   }
-  // coalesced prefetch of the D tile (zero in the pivot columns), issued
-  // behind the first two operand stages so its latency overlaps the
-  // matrix-core work without delaying them
-  T dold[G::NQ][G::VEC];
-  const bool pivcols = (bn + tcol >= p0) && (bn + tcol < p0 + kNB);
-  auto read_d = [&]() {
-#pragma unroll
-    for (int q = 0; q < G::NQ; ++q) {
-      const T *src = D + (size_t)(bm + q * G::RPI + trow) * ld + bn + tcol;
-      if (sizeof(T) == 4) {
-        const float4 v = *reinterpret_cast<const float4 *>(src);
-        dold[q][0] = v.x; dold[q][1] = v.y; dold[q][2] = v.z; dold[q][G::VEC - 1] = v.w;
-      } else {
-        const double2 v = *reinterpret_cast<const double2 *>(src);
-        dold[q][0] = v.x; dold[q][G::VEC - 1] = v.y;
-      }
-      if (pivcols)
-#pragma unroll
-        for (int e = 0; e < G::VEC; ++e) dold[q][e] = T(0);
-    }
-  };
   Tile<T> acc;
   acc.zero();
-  mma_tile_pf2<T, kNB>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, As, Bs, acc, read_d);
-  // exchange the whole tile through LDS (conflict-free: the 4 row groups
-  // of a store land 16 banks apart), then read it back in the row layout
-  // of the prefetched D and store with 16-byte accesses
-  __syncthreads();
+  mma_tile<T>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, nullptr, kNB, As, Bs, acc);
+  const bool pivcols = (bn + tcol >= p0) && (bn + tcol < p0 + kNB);
+  const int wave = tid >> 6;
+  constexpr int NH = G::NQ / 2;  // row passes per half
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int h = 0; h < 2; ++h) {
+    VT dv[NH];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int q = 0; q < NH; ++q)
+      dv[q] = *reinterpret_cast<const VT *>(D + (size_t)(bm + h * HR + q * G::RPI + trow) * ld +
+                                            bn + tcol);
+    __syncthreads();
+    if ((wave >> 1) == h) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Xs[acc_row<T>(i, r)][acc_col(j)] = acc.v[i][j][r];
-  __syncthreads();
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-  for (int q = 0; q < G::NQ; ++q) {
-    const int lrow = q * G::RPI + trow;
-    T out[G::VEC];
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int e = 0; e < G::VEC; ++e) out[e] = dold[q][e] - Xs[lrow][tcol + e];
-    T *dst = D + (size_t)(bm + lrow) * ld + bn + tcol;
-    if (sizeof(T) == 4) {
-      *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[G::VEC - 1]);
-    } else {
-      *reinterpret_cast<double2 *>(dst) = make_double2(out[0], out[G::VEC - 1]);
+          for (int r = 0; r < 4; ++r)
+            Xs[acc_row<T>(i, r) - h * HR][acc_col(j)] = acc.v[i][j][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      const int lrow = q * G::RPI + trow;
+      const T *dq = reinterpret_cast<const T *>(&dv[q]);
+      T out[G::VEC];
+#pragma unroll
+      for (int e = 0; e < G::VEC; ++e) out[e] = (pivcols ? T(0) : dq[e]) - Xs[lrow][tcol + e];
+      *reinterpret_cast<VT *>(D + (size_t)(bm + h * HR + lrow) * ld + bn + tcol) =
+          *reinterpret_cast<const VT *>(out);
     }
   }
 }
