@@ -195,10 +195,9 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
   GjStreams gs;
   HIPCHK(gs.create());
   // The transfer chain of plane k needs only G_k: it runs on a second
-  // stream, overlapping the (memory-bound) assembly and inversion of plane
-  // k+1 with its (matrix-core-bound) GEMM.  Before plane k+2 is assembled
-  // into the ping-pong slot that held G_k, the main stream waits for that
-  // GEMM.
+  // stream, overlapping the inversion of plane k+1 with its
+  // (matrix-core-bound) GEMM.  Before plane k+2 is assembled into the
+  // ping-pong slot that held G_k, the main stream waits for that GEMM.
   const bool chains = plan.n_y > 0;
   hipStream_t s2 = nullptr;
   std::vector<hipEvent_t> ev_gj(m, nullptr), ev_y(m, nullptr);
@@ -215,22 +214,28 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
         HIPCHK(hipEventCreateWithFlags(&ev_y[k], hipEventDisableTiming));
       }
     }
+    // the chain GEMM of plane k is released after the assembly of plane
+    // k + 1 has been enqueued: the (HBM-bound, critical-path) assembly then
+    // runs alone and the GEMM overlaps the elimination steps of plane k + 1
+    auto chain = [&](int k) {
+      if (ny_at[k - 1] <= 0) return;
+      HIPCHK(hipEventRecord(ev_gj[k], s));
+      HIPCHK(hipStreamWaitEvent(s2, ev_gj[k], 0));
+      if (k == 1)
+        launch_scale_cols<T>(tab.at<GemmJob>(off_y[0]), ny_at[0], ld, -1.0, s2);
+      else
+        launch_gemm<T>(tab.at<GemmJob>(off_y[k - 1]), ny_at[k - 1], ld, op->M, -1.0, 0.0, s2);
+      HIPCHK(hipEventRecord(ev_y[k], s2));
+    };
     for (int k = 1; k <= m - 1; ++k) {
       if (chains && k >= 3) HIPCHK(hipStreamWaitEvent(s, ev_y[k - 2], 0));
       launch_assemble<T>(tab.at<AsmJob>(off_asm[k - 1]), nsw, op->coef, op->n, op->dim, op->M,
                          ld, s);
+      if (k >= 2) chain(k - 1);
       HIPCHK(gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, gjw.p, op->flag, gs,
                           s));
-      if (ny_at[k - 1] > 0) {
-        HIPCHK(hipEventRecord(ev_gj[k], s));
-        HIPCHK(hipStreamWaitEvent(s2, ev_gj[k], 0));
-        if (k == 1)
-          launch_scale_cols<T>(tab.at<GemmJob>(off_y[0]), ny_at[0], ld, -1.0, s2);
-        else
-          launch_gemm<T>(tab.at<GemmJob>(off_y[k - 1]), ny_at[k - 1], ld, op->M, -1.0, 0.0, s2);
-        HIPCHK(hipEventRecord(ev_y[k], s2));
-      }
     }
+    chain(m - 1);
     if (chains) HIPCHK(hipStreamWaitEvent(s, ev_y[m - 1], 0));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));  // keeps the job tables alive until done
@@ -475,6 +480,7 @@ struct SolveWs {
   double *part;              // transposed-GEMV partial sums
   double *dpart;             // dot-product partial sums
   double *nrm;               // norms
+  GmresDev gm;               // device GMRES state
   size_t vol, ifc;
 };
 
@@ -507,6 +513,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   o[11] = cv.take(16 * 8);
   // partial sums: up to max_iter + 2 interface-length dots, or one volume norm
   o[12] = cv.take(std::max(dots_part_len(ifc, max_iter + 2), dots_part_len(vol, 1)) * 8);
+  const size_t o_gm = cv.take(GmresDev::doubles(max_iter) * 8);
   ensure_ws(op, cv.off);
   auto at = [&](size_t x) {
     return reinterpret_cast<double *>(static_cast<unsigned char *>(op->ws) + x);
@@ -515,6 +522,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   w.X = at(o[0]); w.R = at(o[1]); w.Z = at(o[2]); w.D = at(o[3]);
   w.fJ = at(o[4]); w.hh = at(o[5]); w.W = at(o[6]); w.xg = at(o[7]);
   w.V = at(o[8]); w.hd = at(o[9]); w.part = at(o[10]); w.nrm = at(o[11]); w.dpart = at(o[12]);
+  w.gm.carve(at(o_gm), max_iter);
   w.vol = vol;
   w.ifc = ifc;
   return w;
@@ -621,7 +629,15 @@ std::vector<GemvJob> sinv_jobs(const ddst_op *op, const double *x, double *y) {
 }
 
 // Unrestarted GMRES with classical Gram-Schmidt applied twice (FP64).
-// Basis vectors are padded interface vectors.  Returns iterations.
+// Basis vectors are padded interface vectors.  The Givens rotations run on
+// the device (one tiny kernel per iteration) and the host reads the
+// residual estimates back at most every kGmresCheck iterations (sooner when
+// the observed reduction rate predicts the tolerance), so the GPU is fed
+// several iterations ahead; iterations past the stopping point are computed
+// and discarded (they touch only later columns).
+// Returns the iterations used.
+constexpr int kGmresCheck = 8;
+
 template <typename T>
 int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int max_iter,
           bool trans, bool hodlr, double *relres, hipStream_t s) {
@@ -642,14 +658,13 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
     for (int k = 0; k < max_iter; ++k)
       offs[k] = tab.add(interface_jobs(op, w.V + (size_t)k * len, w.W, trans));
   tab.upload(s);
-  // Hessenberg columns, packed: column k holds k + 2 entries from offset
-  // k (k + 3) / 2 (only the iterations taken are stored)
-  std::vector<double> H, cs, sn, gv(1, 0.0);
-  auto hoff = [](int k) { return (size_t)k * (k + 3) / 2; };
-  gv[0] = beta;
-  int k = 0;
+  GmresDev d = w.gm;
+  int used = 0;
   double res = 1.0;
-  for (k = 0; k < max_iter; ++k) {
+  int checked = 0;  // iterations whose estimates were read back
+  int next_check = std::min(kGmresCheck, max_iter);
+  double prev_res = 1.0;
+  for (int k = 0; k < max_iter && used == 0; ++k) {
     const double *vk = w.V + (size_t)k * len;
     if (hodlr) {
       int st = hodlr_apply_jobs(op, vk, w.W, trans ? 1 : 0, s);
@@ -664,48 +679,41 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
     launch_mgs_update(w.W, w.V, len, k + 1, w.hd + (k + 1), -1.0, len, s);
     launch_norm(w.W, len, w.hd + 2 * (k + 1), w.dpart, s);
     launch_scale_by_inv(w.V + (size_t)(k + 1) * len, w.W, w.hd + 2 * (k + 1), len, s);
-    HIPCHK(hipMemcpyAsync(hh, w.hd, (2 * (k + 1) + 1) * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    H.resize(hoff(k + 1), 0.0);
-    cs.push_back(1.0);
-    sn.push_back(0.0);
-    gv.push_back(0.0);
-    double *col = &H[hoff(k)];
-    for (int i = 0; i <= k; ++i) col[i] = hh[i] + hh[k + 1 + i];
-    col[k + 1] = hh[2 * (k + 1)];
-    for (int i = 0; i < k; ++i) {
-      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-      col[i] = t;
-    }
-    const double r = std::hypot(col[k], col[k + 1]);
-    cs[k] = (r > 0) ? col[k] / r : 1.0;
-    sn[k] = (r > 0) ? col[k + 1] / r : 0.0;
-    col[k] = r;
-    col[k + 1] = 0.0;
-    gv[k + 1] = -sn[k] * gv[k];
-    gv[k] = cs[k] * gv[k];
-    res = std::fabs(gv[k + 1]) / beta;
-    if (res <= tol || !(hh[2 * (k + 1)] > 0.0)) {
-      ++k;
-      break;
+    launch_gmres_givens(w.hd, d, k, beta, s);
+    if (k + 1 == next_check) {
+      const int n = k + 1 - checked;
+      HIPCHK(hipMemcpyAsync(hh, d.res + 2 * (size_t)checked, (size_t)n * 16,
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < n; ++i) {
+        res = hh[2 * i];
+        // stop at the tolerance or at a breakdown (the new direction
+        // vanished: the Krylov space is exhausted)
+        if (res <= tol || hh[2 * i + 1] != 0.0) {
+          used = checked + i + 1;
+          break;
+        }
+      }
+      if (used == 0) {
+        // next read-back: when the reduction rate seen over this window
+        // predicts the tolerance, at most kGmresCheck iterations ahead
+        int step = kGmresCheck;
+        if (res > 0.0 && res < prev_res) {
+          const double rate = std::log(res / prev_res) / n;  // per iteration, < 0
+          const double need = std::ceil(std::log(tol / res) / rate);
+          if (need < step) step = std::max(1, (int)need);
+        }
+        prev_res = res;
+        next_check = std::min(k + 1 + step, max_iter);
+      }
+      checked = k + 1;
     }
   }
-  if (k > max_iter) k = max_iter;
-  // back substitution R y = g, then x = V y
-  std::vector<double> y(k, 0.0);
-  for (int i = k - 1; i >= 0; --i) {
-    double t = gv[i];
-    for (int j = i + 1; j < k; ++j) t -= H[hoff(j) + i] * y[j];
-    const double d = H[hoff(i) + i];
-    y[i] = (d != 0.0) ? t / d : 0.0;
-  }
-  std::memcpy(hh, y.data(), k * 8);
-  HIPCHK(hipMemcpyAsync(w.hd, hh, k * 8, hipMemcpyHostToDevice, s));
-  launch_mgs_update(x, w.V, len, k, w.hd, 1.0, len, s);
+  if (used == 0) used = checked;
+  launch_gmres_solution(d, used, x, w.V, len, s);
   HIPCHK(hipStreamSynchronize(s));
   *relres = res;
-  return k;
+  return used;
 }
 
 double dev_norm(ddst_op *op, const double *v, size_t len, double *scratch, double *part,

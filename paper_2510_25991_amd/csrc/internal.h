@@ -154,6 +154,33 @@ void launch_dots(const double *V, size_t stride, int nvec, const double *w, size
 void launch_mgs_update(double *w, const double *V, size_t stride, int nvec,
                        const double *h, double sign, size_t len, hipStream_t s);
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s);
+// GMRES state on the device: packed Hessenberg columns (column k, k + 2
+// entries, from offset k (k + 3) / 2), Givens pairs, the rotated right-hand
+// side g and per-iteration residual estimates.
+__host__ __device__ inline size_t gmres_hoff(int k) { return (size_t)k * (k + 3) / 2; }
+struct GmresDev {
+  double *H, *cs, *sn, *g, *res, *y;
+  static size_t doubles(int max_iter) {
+    return gmres_hoff(max_iter) + 6 * (size_t)max_iter + 8;
+  }
+  void carve(double *base, int max_iter) {
+    H = base;
+    cs = H + gmres_hoff(max_iter);
+    sn = cs + max_iter;
+    g = sn + max_iter;
+    res = g + max_iter + 1;  // pairs (estimate, breakdown flag) per iteration
+    y = res + 2 * (size_t)max_iter;
+  }
+};
+// Iteration k: column k of H from the two Gram-Schmidt passes (hd[0..k],
+// hd[k+1..2k+1]) and the new norm hd[2k+2]; previous rotations applied, the
+// new one formed, g updated; res[2k] = |g[k+1]| / beta, res[2k+1] = 1 when
+// the new norm is not positive and finite (breakdown: the Krylov space is
+// exhausted; a zero norm makes the estimate exactly 0), else 0.
+void launch_gmres_givens(const double *hd, GmresDev d, int k, double beta, hipStream_t s);
+// y = R^{-1} g over the first k columns (one work-group), then x = V y.
+void launch_gmres_solution(GmresDev d, int k, double *x, const double *V, size_t len,
+                           hipStream_t s);
 void launch_scale_by_inv(double *dst, const double *src, const double *nrm, size_t len,
                          hipStream_t s);
 void launch_cell_gradient(const double *u, const double *lam, const double *g, int dim,

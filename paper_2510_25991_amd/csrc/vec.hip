@@ -542,6 +542,57 @@ void launch_norm(const double *w, size_t len, double *out, double *part, hipStre
   hipLaunchKernelGGL(k_multidot_reduce, dim3(1), dim3(256), 0, s, part, nchunk, 1, out, 1);
 }
 
+namespace {
+__global__ void k_gmres_givens(const double *__restrict__ hd, GmresDev d, int k, double beta) {
+  if (threadIdx.x != 0) return;
+  double *col = d.H + gmres_hoff(k);
+  for (int i = 0; i <= k; ++i) col[i] = hd[i] + hd[k + 1 + i];
+  const double hn = hd[2 * (k + 1)];
+  col[k + 1] = hn;
+  for (int i = 0; i < k; ++i) {
+    const double t = d.cs[i] * col[i] + d.sn[i] * col[i + 1];
+    col[i + 1] = -d.sn[i] * col[i] + d.cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double r = hypot(col[k], col[k + 1]);
+  d.cs[k] = r > 0.0 ? col[k] / r : 1.0;
+  d.sn[k] = r > 0.0 ? col[k + 1] / r : 0.0;
+  col[k] = r;
+  col[k + 1] = 0.0;
+  if (k == 0) d.g[0] = beta;
+  d.g[k + 1] = -d.sn[k] * d.g[k];
+  d.g[k] = d.cs[k] * d.g[k];
+  d.res[2 * k] = fabs(d.g[k + 1]) / beta;
+  d.res[2 * k + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
+}
+
+// Back substitution R y = g, column by column: y_j is fixed, then every
+// thread removes its contribution from rows i < j.
+__global__ __launch_bounds__(256) void k_gmres_backsub(GmresDev d, int k) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) d.y[i] = d.g[i];
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const double *col = d.H + gmres_hoff(j);
+    const double yj = col[j] != 0.0 ? d.y[j] / col[j] : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) d.y[j] = yj;
+    for (int i = threadIdx.x; i < j; i += blockDim.x) d.y[i] -= col[i] * yj;
+    __syncthreads();
+  }
+}
+}  // namespace
+
+void launch_gmres_givens(const double *hd, GmresDev d, int k, double beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, s, hd, d, k, beta);
+}
+
+void launch_gmres_solution(GmresDev d, int k, double *x, const double *V, size_t len,
+                           hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_gmres_backsub, dim3(1), dim3(256), 0, s, d, k);
+  launch_mgs_update(x, V, len, k, d.y, 1.0, len, s);
+}
+
 void launch_scale_by_inv(double *dst, const double *src, const double *nrm, size_t len,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_scale_by_inv, dim3(nblk(len)), dim3(256), 0, s, dst, src, nrm, len);
