@@ -78,9 +78,10 @@ def timed(dd, torch, dev, precision, opts, steps, warmup, profile):
     return (t1 - t0) / steps, stats, u, prof
 
 
-def _measured_traffic(kernel):
-    """Calibrated HBM bytes per launch from the committed rocprofv3 PMC summary,
-    valid only while the library sources hash to the measured ones."""
+def _measured_traffic(kernel, key="traffic_bytes_per_launch"):
+    """A figure (by default the calibrated HBM bytes per launch) from the
+    committed rocprofv3 PMC summary of `kernel`, valid only while the library
+    sources hash to the measured ones."""
     import glob
     import hashlib
     import re
@@ -88,7 +89,7 @@ def _measured_traffic(kernel):
     if not summ:
         return None
     text = open(summ[0]).read()
-    m = re.search(r"traffic_bytes_per_launch: (\S+)", text)
+    m = re.search(key + r": (\S+)", text)
     hsh = re.search(r"source_sha256_csrc: (\S+)", text)
     if not (m and hsh):
         return None
@@ -126,9 +127,15 @@ def roofline(prof, precision, M):
         hbm_floor = bytes_per_launch / (PEAK["hbm_gbs"] * 1e9)
         mfma_floor = flops_per_launch / (mpeak * 1e12)
         tr = _measured_traffic("gj_update") if precision == "fp32" else None
+        busy = (_measured_traffic("gj_update", "mfma_busy_fraction_serialised")
+                if precision == "fp32" else None)
         extra = {"traffic": tr, "bytes_per_launch": bytes_per_launch,
                  "flops_per_launch": flops_per_launch,
                  "hbm_gbs": round(bytes_per_launch / avg_s / 1e9, 1),
+                 # matrix-core busy fraction of the same launches when rocprofv3
+                 # serialises them (the two look-ahead halves otherwise overlap,
+                 # which lengthens each launch's duration above)
+                 "mfma_busy_serialised": busy,
                  "mfma_tflops": round(flops_per_launch / avg_s / 1e12, 3)}
         if mfma_floor >= hbm_floor:
             achieved = flops_per_launch / avg_s / 1e12
