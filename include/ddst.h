@@ -254,12 +254,18 @@ int ddst_test_gemm(int32_t precision, int32_t ld, int32_t batch, const void *A, 
 int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipStream_t stream);
 
 /*
- * Per-kernel-class timing.  ddst_profile_enable(1) clears and starts the
- * counters, (0) stops them.  While on, every launch of the classes below is
- * bracketed by HIP events recorded on the stream it is launched on.
- * ddst_profile_read returns, for one class, the number of launches, their
- * summed duration in ms and their summed algorithmic work (flops for the
- * matrix-core classes, bytes for the others; padding excluded).
+ * Per-kernel-class timing.  ddst_profile_select(kinds) clears the counters
+ * and times the classes whose bit (1 << DDST_K_...) is set in `kinds`
+ * (0 stops timing and keeps the counters); ddst_profile_enable(1) selects
+ * every class, (0) stops.  Each timed launch carries a start and a stop HIP
+ * event on the stream it is launched on, attached to the dispatch itself
+ * where the launch is a single kernel (or to its first and last kernel), so
+ * timing adds no packets to the stream.  ddst_profile_read drains pending
+ * events and returns, for one class, the number of launches, their summed
+ * duration in ms and their summed algorithmic work (flops for the
+ * matrix-core classes, bytes for the others; padding excluded).  Returns
+ * DDST_EINVAL for a class index out of range.  Timing state is
+ * process-wide, shared by every operator.
  */
 enum {
   DDST_K_GJ_PANEL = 0,  /* Gauss-Jordan pivot block inverse + panel   (flops) */
@@ -268,8 +274,13 @@ enum {
   DDST_K_ASSEMBLE = 3,  /* plane-block (Schur recursion) assembly     (bytes) */
   DDST_K_GEMV = 4       /* slab sweeps and interface products         (bytes) */
 };
+int ddst_profile_select(uint32_t kinds);
 int ddst_profile_enable(int32_t on);
 int ddst_profile_read(int32_t kind, int64_t *launches, double *total_ms, double *work);
+/* Union of the time intervals of the timed launches of one class (ms): less
+ * than total_ms when launches of the class overlap on different streams.
+ * DDST_EINVAL for a class index out of range or a NULL pointer. */
+int ddst_profile_busy(int32_t kind, double *busy_ms);
 
 #ifdef __cplusplus
 }

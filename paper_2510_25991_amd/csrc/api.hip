@@ -209,9 +209,11 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
   try {
     if (chains) {
       HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+      // stream ordering only: no timing, device-scope release
+      const unsigned evf = hipEventDisableTiming | hipEventDisableSystemFence;
       for (int k = 1; k <= m - 1; ++k) {
-        HIPCHK(hipEventCreateWithFlags(&ev_gj[k], hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&ev_y[k], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev_gj[k], evf));
+        HIPCHK(hipEventCreateWithFlags(&ev_y[k], evf));
       }
     }
     // the chain GEMM of plane k is released after the assembly of plane

@@ -54,6 +54,24 @@ __device__ __forceinline__ void ld8(const double *p, double *r) {
   }
 }
 
+// N consecutive elements (N * sizeof(T) a multiple of 16, p 16-byte aligned)
+// with 16-byte loads.
+template <int N, typename T>
+__device__ __forceinline__ void ld16n(const T *p, T *r) {
+  constexpr int V = 16 / sizeof(T);
+  static_assert(N % V == 0, "whole 16-byte vectors");
+#pragma unroll
+  for (int i = 0; i < N / V; ++i) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = reinterpret_cast<const float4 *>(p)[i];
+      r[4 * i] = v.x; r[4 * i + 1] = v.y; r[4 * i + 2] = v.z; r[4 * i + 3] = v.w;
+    } else {
+      const double2 v = reinterpret_cast<const double2 *>(p)[i];
+      r[2 * i] = v.x; r[2 * i + 1] = v.y;
+    }
+  }
+}
+
 // Map the linear work-group id so that consecutive logical tiles land on
 // the same XCD (work-groups are dispatched round-robin over the 8 XCDs):
 // tiles of one batch entry then share one L2.  XCD x receives ids x, x + 8,
@@ -264,21 +282,99 @@ static_assert(kNB == 128, "the register layout below assumes 128-wide pivots");
 
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj_pivot(void *const *__restrict__ mats,
-                                                  T *__restrict__ Pinv, int ld, int p,
+                                                  T *__restrict__ Pinv,
+                                                  const T *__restrict__ Rprev,
+                                                  const T *__restrict__ Cprev, int ld, int p,
                                                   int *__restrict__ flag) {
-  __shared__ double Cq[2][kNB][kCqS];
-  __shared__ double Rq[2][kLeaf][kRqS];
+  constexpr int kCqN = 2 * kNB * kCqS, kRqN = 2 * kLeaf * kRqS;
+  __shared__ double lds[kCqN + kRqN];
+  double (*Cq)[kNB][kCqS] = reinterpret_cast<double (*)[kNB][kCqS]>(lds);
+  double (*Rq)[kLeaf][kRqS] = reinterpret_cast<double (*)[kLeaf][kRqS]>(lds + kCqN);
   const int b = blockIdx.x, l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = l >> 4, lc = l & 15;
   const T *D = static_cast<const T *>(mats[b]) + (size_t)p * kNB * ld + p * kNB;
   f64x4 t[8][2];  // t[I][jj][r] = P[16 I + 4 r + lr][16 (2 w + jj) + lc]
+  auto load_block = [&]() {
 #pragma unroll
-  for (int I = 0; I < 8; ++I)
+    for (int I = 0; I < 8; ++I)
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
+      for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        t[I][jj][r] = (double)D[(size_t)(16 * I + 4 * r + lr) * ld + 16 * (2 * w + jj) + lc];
+        for (int r = 0; r < 4; ++r)
+          t[I][jj][r] = (double)D[(size_t)(16 * I + 4 * r + lr) * ld + 16 * (2 * w + jj) + lc];
+  };
+  if (Rprev) {
+    // The previous step's update of this block, P = D - Cprev[p] Rprev[:, p].
+    // FP32: the arithmetic of the update kernel (products accumulated over k
+    // in order from zero, subtracted once in FP32), so the block equals what
+    // that kernel would have written; the A rows are fed permuted (row
+    // 4 (i % 4) + i / 4 at position i) so that the accumulators come out in
+    // the FP64 layout of t.  FP64: accumulated into the block itself (a
+    // second set of FP64 accumulators would not fit next to it).  Operands
+    // are staged through LDS in KS-deep slices.
+    constexpr int KS = sizeof(T) == 4 ? 32 : 16;
+    static_assert(2 * KS * LW * sizeof(T) <= sizeof(lds), "operand slices fit the LDS");
+    T (*As)[LW] = reinterpret_cast<T (*)[LW]>(lds);
+    T (*Bs)[LW] = reinterpret_cast<T (*)[LW]>(reinterpret_cast<T *>(lds) + KS * LW);
+    const T *A = Cprev + (size_t)b * ld * kNB + (size_t)p * kNB * kNB;  // rows p, kNB wide
+    const T *B = Rprev + (size_t)b * kNB * ld + p * kNB;               // kNB rows, cols p
+    const int tid = threadIdx.x;
+    constexpr int AE = kNB * KS / 256;  // A elements per thread (128 rows x KS)
+    constexpr int BE = KS * kNB / 256;  // B elements per thread (KS rows x 128)
+    const int ar = tid / (KS / AE), ak = (tid % (KS / AE)) * AE;
+    const int bk = tid / (kNB / BE), bc = (tid % (kNB / BE)) * BE;
+    const int arow = sizeof(T) == 4 ? 4 * (lc & 3) + (lc >> 2) : lc;
+    auto product = [&](auto &C, T sign) {
+      for (int k0 = 0; k0 < kNB; k0 += KS) {
+        T ra[AE], rb[BE];
+        ld16n<AE>(A + (size_t)ar * kNB + k0 + ak, ra);
+        ld16n<BE>(B + (size_t)(k0 + bk) * ld + bc, rb);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < AE; ++e) As[ak + e][ar] = sign * ra[e];
+#pragma unroll
+        for (int e = 0; e < BE; ++e) Bs[bk][bc + e] = rb[e];
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KS; kk += 4) {
+          T bv[2];
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) bv[jj] = Bs[kk + lr][16 * (2 * w + jj) + lc];
+#pragma unroll
+          for (int I = 0; I < 8; ++I) {
+            const T av = As[kk + lr][16 * I + arow];
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) C[I][jj] = mfma16(av, bv[jj], C[I][jj]);
+          }
+        }
+      }
+      __syncthreads();  // the slices alias the blocks used below
+    };
+    if constexpr (sizeof(T) == 4) {
+      f32x4 acc[8][2];
+#pragma unroll
+      for (int I = 0; I < 8; ++I)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[I][jj][r] = 0.f;
+      product(acc, 1.f);
+#pragma unroll
+      for (int I = 0; I < 8; ++I)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float d = D[(size_t)(16 * I + 4 * r + lr) * ld + 16 * (2 * w + jj) + lc];
+            t[I][jj][r] = (double)(d - acc[I][jj][r]);
+          }
+    } else {
+      load_block();
+      product(t, -1.0);
+    }
+  } else {
+    load_block();
+  }
   bool ok = true;
 #pragma unroll
   for (int q = 0; q < kNB / kLeaf; ++q) {
@@ -349,12 +445,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj
 //  * R[:, j0..j0+127] = P^{-1} D[p, j0..j0+127], a 128 x 128 x 128 product
 //    on the matrix cores through the LDS-staged tile routine (R = P^{-1}
 //    itself on the pivot block);
-//  * Cbuf[j0..j0+127, :] = D[j0..j0+127, p] (copy of the old pivot columns).
+//  * Cbuf[j0..j0+127, :] = D[j0..j0+127, p] (copy of the old pivot columns)
+//    when copy_c is set; after the first step the update that produced
+//    column block p writes this copy itself.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats,
                                                   const T *__restrict__ Pinv,
                                                   T *__restrict__ Rbuf, T *__restrict__ Cbuf,
-                                                  int ld, int p) {
+                                                  int ld, int p, int copy_c) {
   __shared__ T As[BK][LW];
   __shared__ T Bs[BK][LW];
   const int b = blockIdx.y, jt = blockIdx.x, tid = threadIdx.x;
@@ -364,7 +462,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
   const T *Pi = Pinv + (size_t)b * kNB * kNB;
   const int p0 = p * kNB, j0 = jt * kTile;
   constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
-  for (int e = tid * V; e < kTile * kNB; e += 256 * V) {
+  for (int e = tid * V; copy_c && e < kTile * kNB; e += 256 * V) {
     const int r = e / kNB, c = e % kNB;
     *reinterpret_cast<float4 *>(Cb + (size_t)(j0 + r) * kNB + c) =
         *reinterpret_cast<const float4 *>(D + (size_t)(j0 + r) * ld + p0 + c);
@@ -417,21 +515,25 @@ template <> struct UpdGeom<double> {
   static constexpr int NQ = 32;
 };
 
-// Tile subsets of one update (q = p + 1, the next pivot block).
-enum { kSelAll = 0, kSelNext = 1, kSelRest = 2 };
+// Tile subsets of one update (q = p + 1, the next pivot block): all tiles
+// (last step); the row and column blocks of q without the tile (q, q)
+// (whose update the next pivot kernel does itself); everything outside
+// them.
+enum { kSelAll = 0, kSelCross = 1, kSelRest = 2 };
 __host__ __device__ inline int sel_tiles(int sel, int nt) {
-  return sel == kSelAll ? nt * nt : sel == kSelNext ? 2 * nt - 1 : (nt - 1) * (nt - 1);
+  return sel == kSelAll ? nt * nt : sel == kSelCross ? 2 * nt - 2 : (nt - 1) * (nt - 1);
 }
 __device__ __forceinline__ void sel_tile(int sel, int nt, int q, int t, int &tr, int &tc) {
   if (sel == kSelAll) {
     tr = t / nt;
     tc = t % nt;
-  } else if (sel == kSelNext) {  // row block q, then column block q without (q, q)
-    if (t < nt) {
+  } else if (sel == kSelCross) {  // row block q, then column block q, both without (q, q)
+    if (t < nt - 1) {
       tr = q;
-      tc = t;
+      tc = t + (t >= q);
     } else {
-      tr = t - nt + (t - nt >= q);
+      const int u = t - (nt - 1);
+      tr = u + (u >= q);
       tc = q;
     }
   } else {  // everything outside row and column block q
@@ -445,8 +547,9 @@ __device__ __forceinline__ void sel_tile(int sel, int nt, int q, int t, int &tr,
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
-                                                   const T *__restrict__ Cbuf, int ld,
-                                                   int p, int sel) {
+                                                   const T *__restrict__ Cbuf,
+                                                   T *__restrict__ Cnext, int ld, int p,
+                                                   int sel) {
   using G = UpdGeom<T>;
   constexpr int XW = kTile + 4;  // exchange row width
   constexpr int HR = kTile / 2;  // rows per exchange half
@@ -470,12 +573,15 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   constexpr int LPR = kTile / G::VEC;           // lanes per row
   const int trow = tid / LPR, tcol = (tid % LPR) * G::VEC;
   using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  // tiles of column block p + 1 also go to the next step's column panel
+  T *Cn = (Cnext && bn == p0 + kNB) ? Cnext + (size_t)b * ld * kNB : nullptr;
   if (bm == p0) {  // pivot rows: D[p, :] = R, no product needed
 #pragma unroll
     for (int q = 0; q < G::NQ; ++q) {
       const int row = bm + q * G::RPI + trow;
-      *reinterpret_cast<VT *>(D + (size_t)row * ld + bn + tcol) =
-          *reinterpret_cast<const VT *>(R + (size_t)(row - p0) * ld + bn + tcol);
+      const VT v = *reinterpret_cast<const VT *>(R + (size_t)(row - p0) * ld + bn + tcol);
+      *reinterpret_cast<VT *>(D + (size_t)row * ld + bn + tcol) = v;
+      if (Cn) *reinterpret_cast<VT *>(Cn + (size_t)row * kNB + tcol) = v;
     }
     return;
   }
@@ -510,8 +616,9 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
       T out[G::VEC];
 #pragma unroll
       for (int e = 0; e < G::VEC; ++e) out[e] = (pivcols ? T(0) : dq[e]) - Xs[lrow][tcol + e];
-      *reinterpret_cast<VT *>(D + (size_t)(bm + h * HR + lrow) * ld + bn + tcol) =
-          *reinterpret_cast<const VT *>(out);
+      const VT v = *reinterpret_cast<const VT *>(out);
+      *reinterpret_cast<VT *>(D + (size_t)(bm + h * HR + lrow) * ld + bn + tcol) = v;
+      if (Cn) *reinterpret_cast<VT *>(Cn + (size_t)(bm + h * HR + lrow) * kNB + tcol) = v;
     }
   }
 }
@@ -608,11 +715,11 @@ template <typename T>
 void launch_assemble(const AsmJob *jobs, int njobs, const double *coef, int n, int dim,
                      int M, int ld, hipStream_t s) {
   if (njobs <= 0) return;
-  prof_begin(KK_ASSEMBLE, s);
-  hipLaunchKernelGGL(k_assemble<T>, dim3(ld / kAsmRows, njobs), dim3(256), 0, s, jobs, coef,
-                     n, dim, M, ld);
+  const ProfSpan ps = prof_open(KK_ASSEMBLE);
+  hipExtLaunchKernelGGL(k_assemble<T>, dim3(ld / kAsmRows, njobs), dim3(256), 0, s, ps.a, ps.b,
+                        0, jobs, coef, n, dim, M, ld);
   // reads G (and up to one more) and writes D: 2 M^2 elements per job
-  prof_end(KK_ASSEMBLE, s, 2.0 * njobs * (double)M * M * sizeof(T));
+  prof_close(ps, KK_ASSEMBLE, 2.0 * njobs * (double)M * M * sizeof(T));
 }
 
 template <typename T>
@@ -626,33 +733,44 @@ void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, do
                  hipStream_t s) {
   if (njobs <= 0) return;
   const int tpm = (ld / kTile) * (ld / kTile);
-  prof_begin(KK_GEMM, s);
-  hipLaunchKernelGGL(k_gemm<T>, dim3(tpm * njobs), dim3(256), 0, s, jobs, ld, tpm, (T)alpha,
-                     (T)beta);
-  prof_end(KK_GEMM, s, 2.0 * njobs * (double)M * M * M);
+  const ProfSpan ps = prof_open(KK_GEMM);
+  hipExtLaunchKernelGGL(k_gemm<T>, dim3(tpm * njobs), dim3(256), 0, s, ps.a, ps.b, 0, jobs, ld,
+                        tpm, (T)alpha, (T)beta);
+  prof_close(ps, KK_GEMM, 2.0 * njobs * (double)M * M * M);
 }
 
 hipError_t GjStreams::create() {
   hipError_t e = hipStreamCreateWithFlags(&h, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&panel, hipEventDisableTiming);
-  for (int i = 0; i < 2 && e == hipSuccess; ++i)
-    e = hipEventCreateWithFlags(&rest[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+  for (hipEvent_t *ev : {&panel, &rest[0], &rest[1], &cross[0], &cross[1]})
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventDisableSystemFence);
   return e;
 }
 
 GjStreams::~GjStreams() {
-  if (h) (void)hipStreamSynchronize(h);
-  for (hipEvent_t ev : {panel, rest[0], rest[1]})
+  for (hipStream_t st : {h, x})
+    if (st) (void)hipStreamSynchronize(st);
+  for (hipEvent_t ev : {panel, rest[0], rest[1], cross[0], cross[1]})
     if (ev) (void)hipEventDestroy(ev);
-  if (h) (void)hipStreamDestroy(h);
+  for (hipStream_t st : {h, x})
+    if (st) (void)hipStreamDestroy(st);
 }
 
-// Schedule of one inversion (U1 = tiles of row/column block p+1, U2 = the
-// rest, buffers of step p: R, Cbuf index p & 1):
-//   s  : pivot(0) panel(0) | U1(0) pivot(1) panel(1) | U1(1) ... | all(last)
-//   gs.h:                    U2(0)                     U2(1) ...
-// U2(p) waits for panel(p); U1(p) waits for U2(p-1) (it rewrites tiles
-// U2(p-1) produced, and panel(p+1) reuses the buffers U2(p-1) read).
+// Schedule of one inversion (q = p + 1; buffers of step p: R, Cbuf index
+// p & 1; Ux(p) = the tiles of row and column block q except (q, q), Ur(p) =
+// all tiles outside them):
+//   s   : pivot(0) panel(0) | pivot(1) . panel(1) | pivot(2) . panel(2) ...
+//   gs.x:                     Ux(0)                 Ux(1)
+//   gs.h:                     Ur(0)                 Ur(1) ...
+// pivot(q) first applies step p's update to the block (q, q) itself, so the
+// next pivot is inverted while the other tiles are updated; Ux(p), which
+// the panel of step q needs, runs beside the larger Ur(p) rather than before
+// it.  Ux(p) also writes column block q to the column panel of step q.
+// Dependencies: Ux(p) and Ur(p) wait for panel(p); Ux(p) and pivot(q) wait
+// for Ur(p - 1) (which last wrote their tiles and read the buffers that
+// Ux(p) and panel(q) overwrite); Ur(p) waits for Ux(p - 1) (same reason);
+// panel(q) waits for Ux(p).  The last step updates all tiles on s.
 template <typename T>
 hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
                      GjStreams &gs, hipStream_t s) {
@@ -668,40 +786,60 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
   // algorithmic flops of one step: rank-kNB update of the M - kNB other rows
   const double step_flops = 2.0 * nmat * (double)kNB * M * std::max(M - kNB, 0);
   const double mfma_tiles = (double)nt * (nt - 1);  // tiles off the pivot rows
-  auto pivot_panel = [&](int p) {
-    prof_begin(KK_GJ_PANEL, s);
-    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(256), 0, s, mats, PinvT, ld, p, flag);
-    hipLaunchKernelGGL(k_gj_panel<T>, dim3(nt, nmat), dim3(256), 0, s, mats, PinvT, Rb[p & 1],
-                       Cb[p & 1], ld, p);
-    prof_end(KK_GJ_PANEL, s, 2.0 * nmat * (double)kNB * kNB * M);
+  // Each launch signals its completion through the profiler's stop event
+  // when its class is timed, else through `done` (attached either way).
+  auto pivot = [&](int p) {
+    const ProfSpan ps = prof_open(KK_GJ_PANEL);
+    const T *Rp = p >= 1 ? Rb[(p - 1) & 1] : nullptr;
+    const T *Cp = p >= 1 ? Cb[(p - 1) & 1] : nullptr;
+    hipExtLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(256), 0, s, ps.a, ps.b, 0, mats,
+                          PinvT, Rp, Cp, ld, p, flag);
+    prof_close(ps, KK_GJ_PANEL, (p >= 1 ? 4.0 : 2.0) * nmat * (double)kNB * kNB * kNB);
   };
-  auto update = [&](int p, int sel, hipStream_t st) {
+  auto panel = [&](int p, hipEvent_t done) {
+    const ProfSpan ps = prof_open(KK_GJ_PANEL);
+    hipExtLaunchKernelGGL(k_gj_panel<T>, dim3(nt, nmat), dim3(256), 0, s, ps.a,
+                          ps.b ? ps.b : done, 0, mats, PinvT, Rb[p & 1], Cb[p & 1], ld, p,
+                          p == 0 ? 1 : 0);
+    prof_close(ps, KK_GJ_PANEL, 2.0 * nmat * (double)kNB * kNB * std::max(M - kNB, 0));
+    return ps.b ? ps.b : done;
+  };
+  auto update = [&](int p, int sel, hipStream_t st, hipEvent_t done) {
     const int ntiles = sel_tiles(sel, nt);
-    const double tiles = sel == kSelAll ? mfma_tiles : sel == kSelNext ? 2.0 * (nt - 1)
-                                                                       : (nt - 1.0) * (nt - 2);
-    prof_begin(KK_GJ_UPDATE, st);
-    hipLaunchKernelGGL(k_gj_update<T>, dim3(ntiles * nmat), dim3(256), 0, st, mats, Rb[p & 1],
-                       Cb[p & 1], ld, p, sel);
-    prof_end(KK_GJ_UPDATE, st, mfma_tiles > 0 ? step_flops * tiles / mfma_tiles : 0.0);
+    // tiles that take a product (the pivot-row tiles are copies)
+    const double tiles = sel == kSelAll     ? mfma_tiles
+                         : sel == kSelCross ? 2.0 * nt - 3
+                                            : (nt - 1.0) * (nt - 2);
+    T *Cn = sel == kSelCross ? Cb[(p + 1) & 1] : nullptr;
+    const ProfSpan ps = prof_open(KK_GJ_UPDATE);
+    hipExtLaunchKernelGGL(k_gj_update<T>, dim3(ntiles * nmat), dim3(256), 0, st, ps.a,
+                          ps.b ? ps.b : done, 0, mats, Rb[p & 1], Cb[p & 1], Cn, ld, p, sel);
+    prof_close(ps, KK_GJ_UPDATE, mfma_tiles > 0 ? step_flops * tiles / mfma_tiles : 0.0);
+    return ps.b ? ps.b : done;
   };
   hipError_t e = hipSuccess;
-#define GJCHK(x)                      \
-  do {                                \
-    if ((e = (x)) != hipSuccess) return e; \
+#define GJCHK(call)                           \
+  do {                                        \
+    if ((e = (call)) != hipSuccess) return e; \
   } while (0)
-  pivot_panel(0);
+  pivot(0);
+  hipEvent_t ev_panel = panel(0, gs.panel);
+  hipEvent_t ev_rest[2] = {nullptr, nullptr}, ev_cross[2] = {nullptr, nullptr};
   for (int p = 0; p < nreal; ++p) {
     if (p + 1 < nreal) {
-      GJCHK(hipEventRecord(gs.panel, s));
-      GJCHK(hipStreamWaitEvent(gs.h, gs.panel, 0));
-      update(p, kSelRest, gs.h);
-      GJCHK(hipEventRecord(gs.rest[p & 1], gs.h));
-      if (p >= 1) GJCHK(hipStreamWaitEvent(s, gs.rest[(p - 1) & 1], 0));
-      update(p, kSelNext, s);
-      pivot_panel(p + 1);
+      GJCHK(hipStreamWaitEvent(gs.x, ev_panel, 0));
+      if (p >= 1) GJCHK(hipStreamWaitEvent(gs.x, ev_rest[(p - 1) & 1], 0));
+      ev_cross[p & 1] = update(p, kSelCross, gs.x, gs.cross[p & 1]);
+      GJCHK(hipStreamWaitEvent(gs.h, ev_panel, 0));
+      if (p >= 1) GJCHK(hipStreamWaitEvent(gs.h, ev_cross[(p - 1) & 1], 0));
+      ev_rest[p & 1] = update(p, kSelRest, gs.h, gs.rest[p & 1]);
+      if (p >= 1) GJCHK(hipStreamWaitEvent(s, ev_rest[(p - 1) & 1], 0));
+      pivot(p + 1);
+      GJCHK(hipStreamWaitEvent(s, ev_cross[p & 1], 0));
+      ev_panel = panel(p + 1, gs.panel);
     } else {
-      if (p >= 1) GJCHK(hipStreamWaitEvent(s, gs.rest[(p - 1) & 1], 0));
-      update(p, kSelAll, s);
+      if (p >= 1) GJCHK(hipStreamWaitEvent(s, ev_rest[(p - 1) & 1], 0));
+      update(p, kSelAll, s, nullptr);
     }
   }
 #undef GJCHK

@@ -9,6 +9,7 @@
 //  * interface vectors: interface j (1..N_ds) occupies [(j-1)*ld, j*ld).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -80,7 +81,16 @@ enum KernelKind {
   KK_GEMV = 4,       // slab sweeps and interface products (work: bytes)
   KK_COUNT = 5
 };
-bool prof_on();
+// Start/stop events of one timed launch (both null when its class is off).
+// Single-kernel launches pass them to hipExtLaunchKernelGGL; a sequence of
+// kernels gives the start to its first and the stop to its last dispatch.
+struct ProfSpan {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+ProfSpan prof_open(int kind);
+void prof_close(const ProfSpan &sp, int kind, double work);
+// Marker form for sequences whose last kernel is chosen at run time: events
+// recorded on s before and after.
 void prof_begin(int kind, hipStream_t s);
 void prof_end(int kind, hipStream_t s, double work);
 
@@ -97,10 +107,16 @@ void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, do
                  hipStream_t s);
 // Helper stream and events of the look-ahead Gauss-Jordan schedule, created
 // once and reused by every inversion of a build (destroyed with the object).
+// Events are created without timing and with device-scope release only (a
+// system-scope release writes back the L2 caches, which after an update
+// launch holds megabytes of dirty lines); they are attached to the
+// dispatches they follow where possible.
 struct GjStreams {
-  hipStream_t h = nullptr;
+  hipStream_t h = nullptr;   // bulk of each update
+  hipStream_t x = nullptr;   // the next pivot's row and column blocks
   hipEvent_t panel = nullptr;
   hipEvent_t rest[2] = {nullptr, nullptr};
+  hipEvent_t cross[2] = {nullptr, nullptr};
   GjStreams() = default;
   GjStreams(const GjStreams &) = delete;
   GjStreams &operator=(const GjStreams &) = delete;
@@ -108,9 +124,9 @@ struct GjStreams {
   ~GjStreams();
 };
 // In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices
-// with look-ahead: the update of step p is split into the tiles of the next
-// pivot's row and column blocks (on s, followed by the next pivot and panel)
-// and all other tiles (on gs.h, concurrently).  work: gj_workspace_bytes
+// with look-ahead: the pivot and panel kernels of step p + 1 apply step p's
+// update to their own row block (on s), while the update of every other
+// tile of step p runs on gs.h.  work: gj_workspace_bytes
 // bytes (two R and two column panels, the pivot inverses); flag: device int
 // set to 1 when a pivot is non-positive or non-finite.  Everything is
 // ordered before later work on s when the call returns.

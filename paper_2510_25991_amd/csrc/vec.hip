@@ -478,20 +478,20 @@ void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, d
                  double *partial, hipStream_t s) {
   (void)M;
   if (njobs <= 0) return;
-  prof_begin(KK_GEMV, s);
+  const ProfSpan ps = prof_open(KK_GEMV);
   if (!transpose) {
-    hipLaunchKernelGGL(k_gemv_n<T>, dim3(ld / (4 * kGemvRowsPerWave), njobs), dim3(256), 0, s,
-                       jobs, ld, alpha);
+    hipExtLaunchKernelGGL(k_gemv_n<T>, dim3(ld / (4 * kGemvRowsPerWave), njobs), dim3(256), 0,
+                          s, ps.a, ps.b, 0, jobs, ld, alpha);
   } else {
     const int nchunk = (ld / kGemvChunk <= 64) ? ld / kGemvChunk : 64;
     const int rpc = ld / nchunk;
-    hipLaunchKernelGGL(k_gemv_t_part<T>, dim3(nchunk, njobs), dim3(256),
-                       2 * rpc * sizeof(double), s, jobs, ld, rpc, partial);
-    hipLaunchKernelGGL(k_gemv_t_reduce, dim3(nblk(ld), njobs), dim3(256), 0, s, jobs, ld,
-                       nchunk, partial, alpha);
+    hipExtLaunchKernelGGL(k_gemv_t_part<T>, dim3(nchunk, njobs), dim3(256),
+                          2 * rpc * sizeof(double), s, ps.a, nullptr, 0, jobs, ld, rpc, partial);
+    hipExtLaunchKernelGGL(k_gemv_t_reduce, dim3(nblk(ld), njobs), dim3(256), 0, s, nullptr, ps.b,
+                          0, jobs, ld, nchunk, partial, alpha);
   }
   // matrix bytes dominate: one or two M x M matrices per job (upper bound 1)
-  prof_end(KK_GEMV, s, (double)njobs * M * M * sizeof(T));
+  prof_close(ps, KK_GEMV, (double)njobs * M * M * sizeof(T));
 }
 template void launch_gemv<float>(const GemvJob *, int, int, int, int, double, double *,
                                  hipStream_t);

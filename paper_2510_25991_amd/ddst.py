@@ -73,7 +73,8 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_adjoint",
            "ddst_release_factors", "ddst_destroy", "ddst_last_error", "ddst_op_info",
            "ddst_get_transfer", "ddst_apply", "ddst_loads", "ddst_get_factor",
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
-           "ddst_profile_enable", "ddst_profile_read", "ddst_compress_info"]
+           "ddst_profile_enable", "ddst_profile_select", "ddst_profile_read",
+           "ddst_profile_busy", "ddst_compress_info"]
 KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv"}
 
 _lib = None
@@ -109,6 +110,8 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_compress_info.argtypes = [vp, P(ctypes.c_double), P(i32), P(i32),
                                      P(ctypes.c_double)]
     L.ddst_profile_enable.argtypes = [i32]
+    L.ddst_profile_select.argtypes = [ctypes.c_uint32]
+    L.ddst_profile_busy.argtypes = [i32, P(ctypes.c_double)]
     L.ddst_profile_read.argtypes = [i32, P(ctypes.c_int64), P(ctypes.c_double),
                                     P(ctypes.c_double)]
     for name in EXPORTS:
@@ -312,8 +315,17 @@ def kernel_invert(A):
     return A
 
 
-def profile_enable(on=True):
-    _check(load_library().ddst_profile_enable(1 if on else 0))
+def profile_enable(on=True, kinds=None):
+    """Start (clearing the counters) or stop per-launch timing; `kinds`
+    restricts it to the named classes (names of KERNEL_CLASSES)."""
+    if kinds is None or not on:
+        _check(load_library().ddst_profile_enable(1 if on else 0))
+        return
+    ids = {v: k for k, v in KERNEL_CLASSES.items()}
+    mask = 0
+    for name in kinds:
+        mask |= 1 << ids[name]
+    _check(load_library().ddst_profile_select(mask))
 
 
 def profile_read():
@@ -324,6 +336,17 @@ def profile_read():
         n, ms, w = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
         _check(L.ddst_profile_read(k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
         out[name] = (n.value, ms.value, w.value)
+    return out
+
+
+def profile_busy():
+    """{class name: union of its launch intervals in ms}."""
+    out = {}
+    L = load_library()
+    for k, name in KERNEL_CLASSES.items():
+        b = ctypes.c_double()
+        _check(L.ddst_profile_busy(k, ctypes.byref(b)))
+        out[name] = b.value
     return out
 
 

@@ -69,6 +69,24 @@ def test_gauss_jordan_inverse(dtype, ld, M):
     assert relerr(Ad.cpu().double(), ref) <= TOL[dtype] * 4
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("ld,M", [(256, 256), (512, 450), (640, 640)])
+def test_gauss_jordan_inverse_nonsymmetric(dtype, ld, M):
+    """Non-symmetric, well conditioned (eigenvalues within a unit disc around
+    3, and so are those of every leading block: positive pivots), several
+    look-ahead steps and a ragged last block."""
+    print(f"\n[gpu] kernel invert nonsymmetric {dtype} ld={ld} M={M}", flush=True)
+    g = torch.Generator().manual_seed(M + 1)
+    batch = 3
+    A = torch.eye(ld, dtype=torch.float64).repeat(batch, 1, 1)
+    A[:, :M, :M] = (3.0 * torch.eye(M, dtype=torch.float64)
+                    + torch.randn(batch, M, M, generator=g, dtype=torch.float64) / M ** 0.5)
+    Ad = A.to(dtype).cuda()
+    ddst().kernel_invert(Ad)
+    ref = torch.linalg.inv(A.to(dtype).double())
+    assert relerr(Ad.cpu().double(), ref) <= TOL[dtype] * 4
+
+
 def test_gauss_jordan_breakdown_flag():
     print("\n[gpu] kernel invert breakdown", flush=True)
     A = torch.eye(128, dtype=torch.float64).repeat(2, 1, 1)
