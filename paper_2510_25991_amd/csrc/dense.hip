@@ -38,19 +38,14 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 constexpr int BK = 16;           // k-depth of one LDS stage
 constexpr int LW = kTile + 16;   // LDS row width (padding spreads banks)
 
-__device__ __forceinline__ void ld8(const float *p, float *r) {
-  float4 a = *reinterpret_cast<const float4 *>(p);
-  float4 b = *reinterpret_cast<const float4 *>(p + 4);
-  r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
-  r[4] = b.x; r[5] = b.y; r[6] = b.z; r[7] = b.w;
-}
-__device__ __forceinline__ void ld8(const double *p, double *r) {
-  const double2 *q = reinterpret_cast<const double2 *>(p);
+template <typename T>
+__device__ __forceinline__ void ld8(const T *p, T *r) {
+  constexpr int V = 16 / sizeof(T);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double2 v = q[i];
-    r[2 * i] = v.x;
-    r[2 * i + 1] = v.y;
+  for (int i = 0; i < 8 / V; ++i) {
+    const typename V16<T>::type v = ld16(p + V * i);
+#pragma unroll
+    for (int e = 0; e < V; ++e) r[V * i + e] = v[e];
   }
 }
 
@@ -62,13 +57,9 @@ __device__ __forceinline__ void ld16n(const T *p, T *r) {
   static_assert(N % V == 0, "whole 16-byte vectors");
 #pragma unroll
   for (int i = 0; i < N / V; ++i) {
-    if constexpr (sizeof(T) == 4) {
-      const float4 v = reinterpret_cast<const float4 *>(p)[i];
-      r[4 * i] = v.x; r[4 * i + 1] = v.y; r[4 * i + 2] = v.z; r[4 * i + 3] = v.w;
-    } else {
-      const double2 v = reinterpret_cast<const double2 *>(p)[i];
-      r[2 * i] = v.x; r[2 * i + 1] = v.y;
-    }
+    const typename V16<T>::type v = ld16(p + V * i);
+#pragma unroll
+    for (int e = 0; e < V; ++e) r[V * i + e] = v[e];
   }
 }
 
@@ -114,7 +105,7 @@ __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
     ld8(A + (size_t)ar * lda + k0 + ak, ra);
     ld8(B + (size_t)(k0 + br) * ldb + bc, rb);
     if (bscale) {
-      const T s = (T)bscale[k0 + br];
+      const T s = (T)gp(bscale)[k0 + br];
 #pragma unroll
       for (int q = 0; q < 8; ++q) rb[q] *= s;
     }
@@ -173,7 +164,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmJob *__restrict__ jobs, 
   const GemmJob J = jobs[b];
   const T *A = static_cast<const T *>(J.A);
   const T *B = static_cast<const T *>(J.B);
-  T *C = static_cast<T *>(J.C);
+  auto *C = gp(static_cast<T *>(J.C));
   Tile<T> acc;
   acc.zero();
   mma_tile<T>(A + (size_t)bm * ld, ld, B + bn, ld, J.bscale, ld, As, Bs, acc);
@@ -292,7 +283,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj
   double (*Rq)[kLeaf][kRqS] = reinterpret_cast<double (*)[kLeaf][kRqS]>(lds + kCqN);
   const int b = blockIdx.x, l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = l >> 4, lc = l & 15;
-  const T *D = static_cast<const T *>(mats[b]) + (size_t)p * kNB * ld + p * kNB;
+  const auto *D = gp(static_cast<const T *>(mats[b]) + (size_t)p * kNB * ld + p * kNB);
   f64x4 t[8][2];  // t[I][jj][r] = P[16 I + 4 r + lr][16 (2 w + jj) + lc]
   auto load_block = [&]() {
 #pragma unroll
@@ -464,14 +455,12 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
   constexpr int V = 16 / sizeof(T);  // elements per 16-byte access
   for (int e = tid * V; copy_c && e < kTile * kNB; e += 256 * V) {
     const int r = e / kNB, c = e % kNB;
-    *reinterpret_cast<float4 *>(Cb + (size_t)(j0 + r) * kNB + c) =
-        *reinterpret_cast<const float4 *>(D + (size_t)(j0 + r) * ld + p0 + c);
+    st16(Cb + (size_t)(j0 + r) * kNB + c, ld16(D + (size_t)(j0 + r) * ld + p0 + c));
   }
   if (jt == p) {
     for (int e = tid * V; e < kNB * kTile; e += 256 * V) {
       const int r = e / kTile, c = e % kTile;
-      *reinterpret_cast<float4 *>(R + (size_t)r * ld + j0 + c) =
-          *reinterpret_cast<const float4 *>(Pi + r * kNB + c);
+      st16(R + (size_t)r * ld + j0 + c, ld16(Pi + r * kNB + c));
     }
     return;
   }
@@ -572,16 +561,16 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
   const int tid = threadIdx.x;
   constexpr int LPR = kTile / G::VEC;           // lanes per row
   const int trow = tid / LPR, tcol = (tid % LPR) * G::VEC;
-  using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  using VT = typename V16<T>::type;
   // tiles of column block p + 1 also go to the next step's column panel
   T *Cn = (Cnext && bn == p0 + kNB) ? Cnext + (size_t)b * ld * kNB : nullptr;
   if (bm == p0) {  // pivot rows: D[p, :] = R, no product needed
 #pragma unroll
     for (int q = 0; q < G::NQ; ++q) {
       const int row = bm + q * G::RPI + trow;
-      const VT v = *reinterpret_cast<const VT *>(R + (size_t)(row - p0) * ld + bn + tcol);
-      *reinterpret_cast<VT *>(D + (size_t)row * ld + bn + tcol) = v;
-      if (Cn) *reinterpret_cast<VT *>(Cn + (size_t)row * kNB + tcol) = v;
+      const VT v = ld16(R + (size_t)(row - p0) * ld + bn + tcol);
+      st16(D + (size_t)row * ld + bn + tcol, v);
+      if (Cn) st16(Cn + (size_t)row * kNB + tcol, v);
     }
     return;
   }
@@ -596,8 +585,7 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
     VT dv[NH];
 #pragma unroll
     for (int q = 0; q < NH; ++q)
-      dv[q] = *reinterpret_cast<const VT *>(D + (size_t)(bm + h * HR + q * G::RPI + trow) * ld +
-                                            bn + tcol);
+      dv[q] = ld16(D + (size_t)(bm + h * HR + q * G::RPI + trow) * ld + bn + tcol);
     __syncthreads();
     if ((wave >> 1) == h) {
 #pragma unroll
@@ -612,13 +600,11 @@ __global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mat
 #pragma unroll
     for (int q = 0; q < NH; ++q) {
       const int lrow = q * G::RPI + trow;
-      const T *dq = reinterpret_cast<const T *>(&dv[q]);
-      T out[G::VEC];
+      VT v;
 #pragma unroll
-      for (int e = 0; e < G::VEC; ++e) out[e] = (pivcols ? T(0) : dq[e]) - Xs[lrow][tcol + e];
-      const VT v = *reinterpret_cast<const VT *>(out);
-      *reinterpret_cast<VT *>(D + (size_t)(bm + h * HR + lrow) * ld + bn + tcol) = v;
-      if (Cn) *reinterpret_cast<VT *>(Cn + (size_t)(bm + h * HR + lrow) * kNB + tcol) = v;
+      for (int e = 0; e < G::VEC; ++e) v[e] = (pivcols ? T(0) : dv[q][e]) - Xs[lrow][tcol + e];
+      st16(D + (size_t)(bm + h * HR + lrow) * ld + bn + tcol, v);
+      if (Cn) st16(Cn + (size_t)(bm + h * HR + lrow) * kNB + tcol, v);
     }
   }
 }
@@ -634,7 +620,7 @@ __global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ job
                                                   const double *__restrict__ coef, int n,
                                                   int dim, int M, int ld) {
   constexpr int V = 16 / sizeof(T);
-  using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  using VT = typename V16<T>::type;
   const AsmJob J = jobs[blockIdx.y];
   const size_t N = (size_t)M * n;
   const T *G1 = static_cast<const T *>(J.G1);
@@ -644,8 +630,8 @@ __global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ job
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       const bool in = c0 + e < M;
-      sc1[e] = (G1 && in) ? J.c1[c0 + e] : 0.0;
-      sc2[e] = (G2 && in) ? J.c2[c0 + e] : 0.0;
+      sc1[e] = (G1 && in) ? gp(J.c1)[c0 + e] : 0.0;
+      sc2[e] = (G2 && in) ? gp(J.c2)[c0 + e] : 0.0;
     }
 #pragma unroll
     for (int rr = 0; rr < kAsmRows; ++rr) {
@@ -655,15 +641,11 @@ __global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ job
 #pragma unroll
         for (int e = 0; e < V; ++e) out[e] = (c0 + e == r) ? T(1) : T(0);
       } else {
-        T g1[V], g2[V];
-#pragma unroll
-        for (int e = 0; e < V; ++e) g1[e] = g2[e] = T(0);
-        if (G1)
-          *reinterpret_cast<VT *>(g1) = *reinterpret_cast<const VT *>(G1 + (size_t)r * ld + c0);
-        if (G2)
-          *reinterpret_cast<VT *>(g2) = *reinterpret_cast<const VT *>(G2 + (size_t)r * ld + c0);
-        const double s1 = G1 ? J.r1[r] : 0.0;
-        const double s2 = G2 ? J.r2[r] : 0.0;
+        VT g1 = {}, g2 = {};
+        if (G1) g1 = ld16(G1 + (size_t)r * ld + c0);
+        if (G2) g2 = ld16(G2 + (size_t)r * ld + c0);
+        const double s1 = G1 ? gp(J.r1)[r] : 0.0;
+        const double s2 = G2 ? gp(J.r2)[r] : 0.0;
         double v[V];
 #pragma unroll
         for (int e = 0; e < V; ++e)
@@ -691,8 +673,10 @@ __global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ job
 #pragma unroll
         for (int e = 0; e < V; ++e) out[e] = (T)v[e];
       }
-      *reinterpret_cast<VT *>(static_cast<T *>(J.D) + (size_t)r * ld + c0) =
-          *reinterpret_cast<const VT *>(out);
+      VT o;
+#pragma unroll
+      for (int e = 0; e < V; ++e) o[e] = out[e];
+      st16(static_cast<T *>(J.D) + (size_t)r * ld + c0, o);
     }
   }
 }
@@ -703,10 +687,10 @@ __global__ __launch_bounds__(256) void k_scale_cols(const GemmJob *__restrict__ 
                                                     T alpha) {
   const GemmJob J = jobs[blockIdx.y];
   const int r = blockIdx.x;
-  const T *A = static_cast<const T *>(J.A) + (size_t)r * ld;
-  T *C = static_cast<T *>(J.C) + (size_t)r * ld;
+  const auto *A = gp(static_cast<const T *>(J.A) + (size_t)r * ld);
+  auto *C = gp(static_cast<T *>(J.C) + (size_t)r * ld);
   for (int c = threadIdx.x; c < ld; c += blockDim.x)
-    C[c] = alpha * A[c] * (T)J.bscale[c];
+    C[c] = alpha * A[c] * (T)gp(J.bscale)[c];
 }
 
 }  // namespace

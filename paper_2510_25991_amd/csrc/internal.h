@@ -71,6 +71,29 @@ struct GemvJob {
   double *out;
 };
 
+// ---- global-memory access helpers (device code) ---------------------------
+// Pointers read from job tables are generic to the compiler, which then
+// emits flat loads and stores; those also count against the LDS counter, so
+// every wait for LDS data would also wait for outstanding matrix loads.  All
+// matrices and vectors live in device memory: these helpers access them
+// through global-address-space pointers (16-byte vectors of native vector
+// type, which keep the address space through the copy).
+template <typename T> struct V16;
+template <> struct V16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct V16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ typename V16<T>::type ld16(const T *p) {
+  return *(__attribute__((address_space(1))) const typename V16<T>::type *)p;
+}
+template <typename T>
+__device__ __forceinline__ void st16(T *p, typename V16<T>::type v) {
+  *(__attribute__((address_space(1))) typename V16<T>::type *)p = v;
+}
+
 // ---- per-kernel timing (prof.hip) ----------------------------------------
 // Kernel classes; the numbering is part of the C-ABI (ddst_profile_read).
 enum KernelKind {

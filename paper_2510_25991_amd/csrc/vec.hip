@@ -173,73 +173,134 @@ __global__ void k_unpad(const double *__restrict__ src, double *__restrict__ dst
   dst[e] = src[row * ld + c];
 }
 
-constexpr int kGemvRowsPerWave = 4;
+// rows per wavefront of the GEMV (8 FP32 rows would take all 256 registers:
+// the conversions to FP64 are scheduled early)
+template <typename T> constexpr int gemv_rpw() { return 4; }
 constexpr int kGemvCh = 1024;
 
+// four consecutive matrix entries as doubles (global-memory vector loads)
 template <typename T>
-__device__ __forceinline__ void ld4(const T *p, double *o);
-template <>
-__device__ __forceinline__ void ld4<float>(const float *p, double *o) {
-  float4 v = *reinterpret_cast<const float4 *>(p);
-  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-}
-template <>
-__device__ __forceinline__ void ld4<double>(const double *p, double *o) {
-  double2 a = reinterpret_cast<const double2 *>(p)[0];
-  double2 b = reinterpret_cast<const double2 *>(p)[1];
-  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+__device__ __forceinline__ void ld4(const T *p, double *o) {
+  constexpr int V = 16 / sizeof(T);
+#pragma unroll
+  for (int h = 0; h < 4 / V; ++h) {
+    const typename V16<T>::type v = ld16(p + V * h);
+#pragma unroll
+    for (int e = 0; e < V; ++e) o[V * h + e] = (double)v[e];
+  }
 }
 
-// out[r] = w[r] + alpha * (G[r,:] (x1 - e.*x2) + G2[r,:] x3); 16 rows per block.
+// out[r] = w[r] + alpha * (G[r,:] (x1 - e.*x2) + G2[r,:] x3); 4 R rows per block.
+// HBM-bound: each wavefront owns R rows and, per chunk of
+// kGemvCh columns, issues all its 16-byte loads of a matrix before using
+// any (4 R per matrix and chunk in flight per wavefront; no branches between
+// them: columns past the chunk re-read an in-bounds address and meet x = 0);
+// the first matrix's loads are issued before x is staged in LDS, which they
+// do not depend on.
+template <typename T, int R>
+__device__ __forceinline__ void gemv_rows_load(const T *M, size_t row0_off, int ld, int c0,
+                                               int cn, int lane, T (&g)[R][kGemvCh / 256][4]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int i = 0; i < kGemvCh / 256; ++i) {
+      const int c = lane * 4 + 256 * i;
+      const T *src = M + row0_off + (size_t)q * ld + c0 + (c < cn ? c : 0);
+      constexpr int V = 16 / sizeof(T);
+#pragma unroll
+      for (int h = 0; h < 4 / V; ++h) {
+        const typename V16<T>::type v = ld16(src + V * h);
+#pragma unroll
+        for (int e = 0; e < V; ++e) g[q][i][V * h + e] = v[e];
+      }
+    }
+}
+// x: kGemvCh doubles in LDS, zero past the chunk
+template <typename T, int R>
+__device__ __forceinline__ void gemv_rows_fma(const T (&g)[R][kGemvCh / 256][4],
+                                              const double *x, int lane, double (&acc)[R]) {
+#pragma unroll
+  for (int i = 0; i < kGemvCh / 256; ++i) {
+    const int c = lane * 4 + 256 * i;
+    const double x0 = x[c], x1 = x[c + 1], x2 = x[c + 2], x3 = x[c + 3];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      acc[q] += (double)g[q][i][0] * x0 + (double)g[q][i][1] * x1 +
+                (double)g[q][i][2] * x2 + (double)g[q][i][3] * x3;
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *__restrict__ jobs, int ld,
-                                                double alpha) {
+__device__ __forceinline__ void gemv_n_body(const GemvJob *__restrict__ jobs, int ld,
+                                            double alpha) {
+  constexpr int R = gemv_rpw<T>();
   __shared__ double xs[kGemvCh];
   __shared__ double x3s[kGemvCh];
   const GemvJob J = jobs[blockIdx.y];
   const T *G = static_cast<const T *>(J.G);
   const T *G2 = static_cast<const T *>(J.G2);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row0 = blockIdx.x * (4 * kGemvRowsPerWave) + wave * kGemvRowsPerWave;
-  double acc[kGemvRowsPerWave];
+  const int row0 = blockIdx.x * (4 * R) + wave * R;
+  const size_t ro = (size_t)row0 * ld;
+  if (!G && !G2) {  // no matrix term (an end of a sweep): out = w
+    if (lane < R) {
+      const int r = row0 + lane;
+      gp(J.out)[r] = J.w ? gp(J.w)[r] : 0.0;
+    }
+    return;
+  }
+  double acc[R];
 #pragma unroll
-  for (int q = 0; q < kGemvRowsPerWave; ++q) acc[q] = 0.0;
+  for (int q = 0; q < R; ++q) acc[q] = 0.0;
+  T g[R][kGemvCh / 256][4];
   for (int c0 = 0; c0 < ld; c0 += kGemvCh) {
     const int cn = min(kGemvCh, ld - c0);
-    __syncthreads();
-    for (int c = threadIdx.x; c < cn; c += 256) {
-      double v = J.x1 ? J.x1[c0 + c] : 0.0;
-      if (J.e) v -= J.e[c0 + c] * J.x2[c0 + c];
+    gemv_rows_load<T, R>(G ? G : G2, ro, ld, c0, cn, lane, g);
+    if (c0 > 0) __syncthreads();  // the previous chunk's x is no longer read
+    for (int c = threadIdx.x; c < kGemvCh; c += 256) {
+      double v = 0.0, v3 = 0.0;
+      if (c < cn) {
+        v = J.x1 ? gp(J.x1)[c0 + c] : 0.0;
+        if (J.e) v -= gp(J.e)[c0 + c] * gp(J.x2)[c0 + c];
+        v3 = (G2 && J.x3) ? gp(J.x3)[c0 + c] : 0.0;
+      }
       xs[c] = v;
-      x3s[c] = (G2 && J.x3) ? J.x3[c0 + c] : 0.0;
+      x3s[c] = v3;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kGemvRowsPerWave; ++q) {
-      const size_t ro = (size_t)(row0 + q) * ld + c0;
-      double s = 0.0;
-      for (int c = lane * 4; c < cn; c += 256) {
-        double gv[4];
-        if (G) {
-          ld4<T>(G + ro + c, gv);
-          s += gv[0] * xs[c] + gv[1] * xs[c + 1] + gv[2] * xs[c + 2] + gv[3] * xs[c + 3];
-        }
-        if (G2) {
-          ld4<T>(G2 + ro + c, gv);
-          s += gv[0] * x3s[c] + gv[1] * x3s[c + 1] + gv[2] * x3s[c + 2] + gv[3] * x3s[c + 3];
-        }
+    if (G) {
+      gemv_rows_fma<T, R>(g, xs, lane, acc);
+      if (G2) {
+        // keep the second matrix's loads after the first one's products
+        // (hoisting them doubles the live registers)
+        asm volatile("" ::: "memory");
+        gemv_rows_load<T, R>(G2, ro, ld, c0, cn, lane, g);
+        gemv_rows_fma<T, R>(g, x3s, lane, acc);
       }
-      acc[q] += s;
+    } else {
+      gemv_rows_fma<T, R>(g, x3s, lane, acc);
     }
   }
 #pragma unroll
-  for (int q = 0; q < kGemvRowsPerWave; ++q) {
+  for (int q = 0; q < R; ++q) {
     const double s = wave_sum(acc[q]);
     if (lane == 0) {
       const int r = row0 + q;
-      J.out[r] = (J.w ? J.w[r] : 0.0) + alpha * s;
+      gp(J.out)[r] = (J.w ? gp(J.w)[r] : 0.0) + alpha * s;
     }
   }
+}
+
+// FP32 matrices: capped at 3 wavefronts' registers per SIMD (138 VGPRs, no
+// spills) for more loads in flight per CU; FP64 keeps the compiler's choice
+// (a cap spills).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemv_n_f32(
+    const GemvJob *__restrict__ jobs, int ld, double alpha) {
+  gemv_n_body<float>(jobs, ld, alpha);
+}
+__global__ __launch_bounds__(256) void k_gemv_n_f64(const GemvJob *__restrict__ jobs, int ld,
+                                                    double alpha) {
+  gemv_n_body<double>(jobs, ld, alpha);
 }
 
 // Transposed product, partial sums over row chunks:
@@ -257,10 +318,10 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(const GemvJob *__restrict__
   const T *G2 = static_cast<const T *>(J.G2);
   const int r0 = chunk * rows_per_chunk;
   for (int r = threadIdx.x; r < rows_per_chunk; r += 256) {
-    double v = J.x1 ? J.x1[r0 + r] : 0.0;
-    if (J.e) v -= J.e[r0 + r] * J.x2[r0 + r];
+    double v = J.x1 ? gp(J.x1)[r0 + r] : 0.0;
+    if (J.e) v -= gp(J.e)[r0 + r] * gp(J.x2)[r0 + r];
     xs[r] = v;
-    x3s[r] = (G2 && J.x3) ? J.x3[r0 + r] : 0.0;
+    x3s[r] = (G2 && J.x3) ? gp(J.x3)[r0 + r] : 0.0;
   }
   __syncthreads();
   for (int c = threadIdx.x * 4; c < ld; c += 1024) {
@@ -292,7 +353,7 @@ __global__ void k_gemv_t_reduce(const GemvJob *__restrict__ jobs, int ld, int nc
   const GemvJob J = jobs[job];
   double s = 0.0;
   for (int k = 0; k < nchunk; ++k) s += part[((size_t)job * nchunk + k) * ld + c];
-  J.out[c] = (J.w ? J.w[c] : 0.0) + alpha * s;
+  gp(J.out)[c] = (J.w ? gp(J.w)[c] : 0.0) + alpha * s;
 }
 
 __global__ void k_interface_rhs(const double *__restrict__ vol, const double *__restrict__ Z,
@@ -346,9 +407,13 @@ __global__ __launch_bounds__(256) void k_multidot_part(const double *__restrict_
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = wave; i < nvec; i += 4) {
-    const double *v = V ? V + (size_t)i * stride + base : nullptr;
     double s = 0.0;
-    for (int e = lane; e < cn; e += 64) s += (v ? v[e] : ws[e]) * ws[e];
+    if (V) {
+      const double *v = V + (size_t)i * stride + base;
+      for (int e = lane; e < cn; e += 64) s += v[e] * ws[e];
+    } else {
+      for (int e = lane; e < cn; e += 64) s += ws[e] * ws[e];
+    }
     s = wave_sum(s);
     if (lane == 0) part[(size_t)blockIdx.x * nvec + i] = s;
   }
@@ -480,8 +545,9 @@ void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, d
   if (njobs <= 0) return;
   const ProfSpan ps = prof_open(KK_GEMV);
   if (!transpose) {
-    hipExtLaunchKernelGGL(k_gemv_n<T>, dim3(ld / (4 * kGemvRowsPerWave), njobs), dim3(256), 0,
-                          s, ps.a, ps.b, 0, jobs, ld, alpha);
+    auto kern = sizeof(T) == 4 ? k_gemv_n_f32 : k_gemv_n_f64;
+    hipExtLaunchKernelGGL(kern, dim3(ld / (4 * gemv_rpw<T>()), njobs), dim3(256), 0, s, ps.a,
+                          ps.b, 0, jobs, ld, alpha);
   } else {
     const int nchunk = (ld / kGemvChunk <= 64) ? ld / kGemvChunk : 64;
     const int rpc = ld / nchunk;
@@ -543,27 +609,57 @@ void launch_norm(const double *w, size_t len, double *out, double *part, hipStre
 }
 
 namespace {
-__global__ void k_gmres_givens(const double *__restrict__ hd, GmresDev d, int k, double beta) {
-  if (threadIdx.x != 0) return;
+// Column k of H (two Gram-Schmidt passes summed) is rotated by the k
+// previous Givens rotations, a new rotation zeroes its subdiagonal entry and
+// is applied to g.  The column and the rotations are staged in LDS by the
+// whole work-group (when they fit), so the serial rotation chain of thread
+// 0 reads no global memory.
+constexpr int kGivensLds = 2048;
+__global__ __launch_bounds__(64) void k_gmres_givens(const double *__restrict__ hd, GmresDev d,
+                                                     int k, double beta) {
+  __shared__ double cl[kGivensLds + 2], cs[kGivensLds], sn[kGivensLds];
   double *col = d.H + gmres_hoff(k);
-  for (int i = 0; i <= k; ++i) col[i] = hd[i] + hd[k + 1 + i];
   const double hn = hd[2 * (k + 1)];
-  col[k + 1] = hn;
-  for (int i = 0; i < k; ++i) {
-    const double t = d.cs[i] * col[i] + d.sn[i] * col[i + 1];
-    col[i + 1] = -d.sn[i] * col[i] + d.cs[i] * col[i + 1];
-    col[i] = t;
+  const bool staged = k + 2 <= kGivensLds;
+  if (staged) {
+    for (int i = threadIdx.x; i <= k; i += blockDim.x) {
+      cl[i] = hd[i] + hd[k + 1 + i];
+      if (i < k) {
+        cs[i] = d.cs[i];
+        sn[i] = d.sn[i];
+      }
+    }
+    __syncthreads();
   }
-  const double r = hypot(col[k], col[k + 1]);
-  d.cs[k] = r > 0.0 ? col[k] / r : 1.0;
-  d.sn[k] = r > 0.0 ? col[k + 1] / r : 0.0;
-  col[k] = r;
-  col[k + 1] = 0.0;
-  if (k == 0) d.g[0] = beta;
-  d.g[k + 1] = -d.sn[k] * d.g[k];
-  d.g[k] = d.cs[k] * d.g[k];
-  d.res[2 * k] = fabs(d.g[k + 1]) / beta;
-  d.res[2 * k + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
+  if (threadIdx.x == 0) {
+    double *c = staged ? cl : col;
+    const double *rc = staged ? cs : d.cs, *rs = staged ? sn : d.sn;
+    if (!staged)
+      for (int i = 0; i <= k; ++i) c[i] = hd[i] + hd[k + 1 + i];
+    c[k + 1] = hn;
+    double a = c[0];
+    for (int i = 0; i < k; ++i) {
+      const double bnext = c[i + 1];
+      c[i] = rc[i] * a + rs[i] * bnext;
+      a = -rs[i] * a + rc[i] * bnext;
+    }
+    const double r = hypot(a, c[k + 1]);
+    const double ck = r > 0.0 ? a / r : 1.0;
+    const double sk = r > 0.0 ? c[k + 1] / r : 0.0;
+    d.cs[k] = ck;
+    d.sn[k] = sk;
+    c[k] = r;
+    c[k + 1] = 0.0;
+    const double gk = k == 0 ? beta : d.g[k];
+    d.g[k + 1] = -sk * gk;
+    d.g[k] = ck * gk;
+    d.res[2 * k] = fabs(d.g[k + 1]) / beta;
+    d.res[2 * k + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
+  }
+  if (staged) {
+    __syncthreads();
+    for (int i = threadIdx.x; i <= k + 1; i += blockDim.x) col[i] = cl[i];
+  }
 }
 
 // Back substitution R y = g, column by column: y_j is fixed, then every
