@@ -675,12 +675,7 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
       launch_gemv<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, trans ? 1 : 0, -1.0,
                      w.part, s);
     }
-    launch_dots(w.V, len, k + 1, w.W, len, w.hd, w.dpart, s);
-    launch_mgs_update(w.W, w.V, len, k + 1, w.hd, -1.0, len, s);
-    launch_dots(w.V, len, k + 1, w.W, len, w.hd + (k + 1), w.dpart, s);
-    launch_mgs_update(w.W, w.V, len, k + 1, w.hd + (k + 1), -1.0, len, s);
-    launch_norm(w.W, len, w.hd + 2 * (k + 1), w.dpart, s);
-    launch_scale_by_inv(w.V + (size_t)(k + 1) * len, w.W, w.hd + 2 * (k + 1), len, s);
+    launch_cgs2_step(w.V, len, k + 1, w.W, len, w.hd, w.V + (size_t)(k + 1) * len, w.dpart, s);
     launch_gmres_givens(w.hd, d, k, beta, s);
     if (k + 1 == next_check) {
       const int n = k + 1 - checked;

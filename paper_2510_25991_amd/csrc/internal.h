@@ -193,6 +193,12 @@ void launch_dots(const double *V, size_t stride, int nvec, const double *w, size
 void launch_mgs_update(double *w, const double *V, size_t stride, int nvec,
                        const double *h, double sign, size_t len, hipStream_t s);
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s);
+// One Arnoldi step by classical Gram-Schmidt applied twice (FP64):
+//   h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; vnext = w / |w|
+// with V nvec vectors of stride `stride`; hd[0..nvec) = h1,
+// hd[nvec..2 nvec) = h2, hd[2 nvec] = |w|.  part: dots_part_len(len, nvec).
+void launch_cgs2_step(const double *V, size_t stride, int nvec, double *w, size_t len,
+                      double *hd, double *vnext, double *part, hipStream_t s);
 // GMRES state on the device: packed Hessenberg columns (column k, k + 2
 // entries, from offset k (k + 3) / 2), Givens pairs, the rotated right-hand
 // side g and per-iteration residual estimates.

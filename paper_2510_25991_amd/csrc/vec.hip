@@ -397,14 +397,12 @@ __global__ void k_fill(double *__restrict__ y, double v, size_t len) {
 // deterministic).  A null V means w itself (squared norm).
 constexpr int kDotChunk = 256;
 
-__global__ __launch_bounds__(256) void k_multidot_part(const double *__restrict__ V, size_t stride,
-                                                       int nvec, const double *__restrict__ w,
-                                                       size_t len, double *__restrict__ part) {
-  __shared__ double ws[kDotChunk];
-  const size_t base = (size_t)blockIdx.x * kDotChunk;
-  const int cn = (int)min((size_t)kDotChunk, len - base);
-  for (int e = threadIdx.x; e < kDotChunk; e += 256) ws[e] = (e < cn) ? w[base + e] : 0.0;
-  __syncthreads();
+// Partial dot products of one kDotChunk chunk (in LDS, zero past the end)
+// with V_0..V_{nvec-1} (V null: the chunk with itself), one wavefront per
+// vector: part[chunk * nvec + i].
+__device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t stride,
+                                           int nvec, const double *ws, size_t base, int cn,
+                                           double *__restrict__ part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = wave; i < nvec; i += 4) {
     double s = 0.0;
@@ -417,6 +415,68 @@ __global__ __launch_bounds__(256) void k_multidot_part(const double *__restrict_
     s = wave_sum(s);
     if (lane == 0) part[(size_t)blockIdx.x * nvec + i] = s;
   }
+}
+
+__global__ __launch_bounds__(256) void k_multidot_part(const double *__restrict__ V, size_t stride,
+                                                       int nvec, const double *__restrict__ w,
+                                                       size_t len, double *__restrict__ part) {
+  __shared__ double ws[kDotChunk];
+  const size_t base = (size_t)blockIdx.x * kDotChunk;
+  const int cn = (int)min((size_t)kDotChunk, len - base);
+  for (int e = threadIdx.x; e < kDotChunk; e += 256) ws[e] = (e < cn) ? w[base + e] : 0.0;
+  __syncthreads();
+  chunk_dots(V, stride, nvec, ws, base, cn, part);
+}
+
+// One Gram-Schmidt update of a chunk, w += sign * V h, followed by the
+// partial dot products of the updated chunk for the next pass (V2 = V,
+// nvec2 = nvec) or its partial squared norm (V2 null, nvec2 = 1): the two
+// kernels of the classical scheme that touch the same chunk, fused.
+__global__ __launch_bounds__(256) void k_mgs_update_dots(double *__restrict__ w,
+                                                         const double *__restrict__ V,
+                                                         size_t stride, int nvec,
+                                                         const double *__restrict__ h,
+                                                         double sign, size_t len,
+                                                         const double *__restrict__ V2,
+                                                         int nvec2, double *__restrict__ part) {
+  __shared__ double ws[kDotChunk];
+  const size_t base = (size_t)blockIdx.x * kDotChunk;
+  const int cn = (int)min((size_t)kDotChunk, len - base);
+  const int e = threadIdx.x;  // kDotChunk == blockDim.x
+  double we = 0.0;
+  if (e < cn) {
+    double s = 0.0;
+    for (int i = 0; i < nvec; ++i) s += V[(size_t)i * stride + base + e] * h[i];
+    we = w[base + e] + sign * s;
+    w[base + e] = we;
+  }
+  ws[e] = we;
+  __syncthreads();
+  chunk_dots(V2, stride, nvec2, ws, base, cn, part);
+}
+
+// dst = src / sqrt(sum of the nchunk partial squared norms); every
+// work-group sums the partials in the same order, the first one stores the
+// norm.
+__global__ __launch_bounds__(256) void k_norm_scale(const double *__restrict__ part, int nchunk,
+                                                    double *__restrict__ nrm_out,
+                                                    const double *__restrict__ src,
+                                                    double *__restrict__ dst, size_t len) {
+  __shared__ double sh[1];
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += 64) s += part[c];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+      const double d = sqrt(s);
+      sh[0] = d;
+      if (blockIdx.x == 0) nrm_out[0] = d;
+    }
+  }
+  __syncthreads();
+  const double d = sh[0];
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) dst[e] = (d > 0.0) ? src[e] / d : 0.0;
 }
 
 // One work-group per vector sums its partials (strided, then a tree).
@@ -599,6 +659,27 @@ void launch_mgs_update(double *w, const double *V, size_t stride, int nvec, cons
                        double sign, size_t len, hipStream_t s) {
   hipLaunchKernelGGL(k_mgs_update, dim3(nblk(len)), dim3(256), 0, s, w, V, stride, nvec, h,
                      sign, len);
+}
+
+void launch_cgs2_step(const double *V, size_t stride, int nvec, double *w, size_t len,
+                      double *hd, double *vnext, double *part, hipStream_t s) {
+  const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
+  static_assert(kDotChunk == 256, "one element per thread in the fused update");
+  // pass 1: h1 = V^T w
+  hipLaunchKernelGGL(k_multidot_part, dim3(nchunk), dim3(256), 0, s, V, stride, nvec,
+                     (const double *)w, len, part);
+  hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(256), 0, s, (const double *)part,
+                     nchunk, nvec, hd, 0);
+  // w -= V h1, then pass 2 partials
+  hipLaunchKernelGGL(k_mgs_update_dots, dim3(nchunk), dim3(256), 0, s, w, V, stride, nvec,
+                     (const double *)hd, -1.0, len, V, nvec, part);
+  hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(256), 0, s, (const double *)part,
+                     nchunk, nvec, hd + nvec, 0);
+  // w -= V h2, then partial squared norms; v_next = w / |w|
+  hipLaunchKernelGGL(k_mgs_update_dots, dim3(nchunk), dim3(256), 0, s, w, V, stride, nvec,
+                     (const double *)(hd + nvec), -1.0, len, (const double *)nullptr, 1, part);
+  hipLaunchKernelGGL(k_norm_scale, dim3(nblk(len)), dim3(256), 0, s, (const double *)part,
+                     nchunk, hd + 2 * nvec, (const double *)w, vnext, len);
 }
 
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s) {
