@@ -97,7 +97,8 @@ typedef struct {
 
 typedef struct {
   double tol;               /* target relative error of the refined solution   */
-  double inner_tol;         /* relative residual of the interface GMRES        */
+  double inner_tol;         /* relative residual of the interface GMRES per    */
+                            /* refinement pass (default 1e-4 FP32, 1e-12 FP64) */
   int32_t max_iter;         /* GMRES iteration cap (unrestarted; <= 20000; the */
                             /* basis takes (max_iter+1)*N_ds*ld*8 device bytes) */
   int32_t max_outer;        /* FP64 refinement passes (>= 1)                   */

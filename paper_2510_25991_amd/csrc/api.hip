@@ -831,7 +831,9 @@ int refine(ddst_op *op, const void *G, const double *f, const double *g, bool tr
 ddst_solve_opts_t solve_defaults(const ddst_op *op) {
   ddst_solve_opts_t o{};
   o.tol = 1e-10;
-  o.inner_tol = (op->prec == DDST_FP32) ? 1e-6 : 1e-12;
+  // FP32 operators: the inner solve need not beat the contraction one
+  // refinement pass gets from the FP32 build (about 1e-4 per pass)
+  o.inner_tol = (op->prec == DDST_FP32) ? 1e-4 : 1e-12;
   o.max_iter = 300;
   o.max_outer = 4;
   o.use_hodlr = 0;

@@ -55,8 +55,12 @@ hipEvent_t take(Prof &p) {
   return e;
 }
 
-void drain(Prof &p) {
-  for (Pending &q : p.pend) {
+// Collects the elapsed times of the first `count` pending pairs (all by
+// default) and returns their events to the pool.
+void drain(Prof &p, size_t count = (size_t)-1) {
+  count = std::min(count, p.pend.size());
+  for (size_t j = 0; j < count; ++j) {
+    Pending &q = p.pend[j];
     float ms = 0.f, t0 = 0.f, t1 = 0.f;
     if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
       p.ms[q.kind] += ms;
@@ -69,7 +73,7 @@ void drain(Prof &p) {
     p.pool.push_back(q.a);
     p.pool.push_back(q.b);
   }
-  p.pend.clear();
+  p.pend.erase(p.pend.begin(), p.pend.begin() + count);
 }
 
 }  // namespace
@@ -92,7 +96,9 @@ void prof_close(const ProfSpan &sp, int kind, double work) {
   Prof &p = prof();
   std::lock_guard<std::mutex> g(p.mu);
   p.pend.push_back({sp.a, sp.b, kind, work});
-  if (p.pend.size() > 4096) drain(p);
+  // Launch schedules wait on the stop events of recent launches; only the
+  // older half is recycled here, far older than any event still waited on.
+  if (p.pend.size() > 4096) drain(p, 2048);
 }
 
 void prof_begin(int kind, hipStream_t s) {

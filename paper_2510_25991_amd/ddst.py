@@ -151,7 +151,7 @@ def _dev(x, device="cuda"):
 @dataclasses.dataclass
 class SolveOptions:
     tol: float = 1e-10
-    inner_tol: Optional[float] = None      # default: 1e-6 (FP32), 1e-12 (FP64)
+    inner_tol: Optional[float] = None      # default: 1e-4 (FP32), 1e-12 (FP64)
     max_iter: int = 300
     max_outer: int = 4
     use_hodlr: bool = False
@@ -205,7 +205,7 @@ class Operator:
     # -- operations --------------------------------------------------------
     def _solve_opts(self, opts: Optional[SolveOptions]):
         o = opts or SolveOptions()
-        inner = o.inner_tol if o.inner_tol is not None else (1e-6 if self.precision == "fp32" else 1e-12)
+        inner = o.inner_tol if o.inner_tol is not None else (1e-4 if self.precision == "fp32" else 1e-12)
         return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0, 0)
 
     def solve(self, f=None, g=None, opts: Optional[SolveOptions] = None, want_gamma=True,
