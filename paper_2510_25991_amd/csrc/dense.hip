@@ -486,12 +486,12 @@ __global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats
 // exchanged into its row layout through LDS (64 rows, the two wavefronts
 // holding them write, all four read; the operand stages live in the same
 // buffer).  Keeping D out of registers during the product and the LDS
-// buffer at 34 KB lets three work-groups share a CU (FP32), whose products
-// hide each other's D latency.  The product is formed from zero and
-// subtracted once, keeping
-// the rounding at the scale of the update rather than of D; the pivot
-// column is written as -acc rather than D - (D + D P^{-1}), which would add
-// O(1) to O(|P^{-1}|) entries.
+// buffer at 34 KB lets four work-groups share a CU (FP32), whose products
+// hide each other's D latency.  With Cnext, tiles of column block p + 1 are
+// also written to the next step's column panel.  The product is formed from
+// zero and subtracted once, keeping the rounding at the scale of the update
+// rather than of D; the pivot column is written as -acc rather than
+// D - (D + D P^{-1}), which would add O(1) to O(|P^{-1}|) entries.
 template <typename T> struct UpdGeom;
 template <> struct UpdGeom<float> {
   static constexpr int VEC = 4;     // floats per 16-byte access
