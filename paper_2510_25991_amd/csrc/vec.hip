@@ -400,20 +400,47 @@ constexpr int kDotChunk = 256;
 // Partial dot products of one kDotChunk chunk (in LDS, zero past the end)
 // with V_0..V_{nvec-1} (V null: the chunk with itself), one wavefront per
 // vector: part[chunk * nvec + i].
+// Each wavefront takes four vectors at a time with independent sums, their
+// loads issued together (entries past the chunk re-read its last element
+// and meet a zero of ws).
 __device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t stride,
                                            int nvec, const double *ws, size_t base, int cn,
                                            double *__restrict__ part) {
+  constexpr int E = kDotChunk / 64;  // entries per lane
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < nvec; i += 4) {
-    double s = 0.0;
-    if (V) {
-      const double *v = V + (size_t)i * stride + base;
-      for (int e = lane; e < cn; e += 64) s += v[e] * ws[e];
-    } else {
-      for (int e = lane; e < cn; e += 64) s += ws[e] * ws[e];
+  double wv[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) wv[t] = ws[lane + 64 * t];
+  if (!V) {  // squared norm of the chunk (nvec == 1): the first wavefront
+    if (wave == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < E; ++t) s += wv[t] * wv[t];
+      s = wave_sum(s);
+      if (lane == 0) part[blockIdx.x] = s;
     }
-    s = wave_sum(s);
-    if (lane == 0) part[(size_t)blockIdx.x * nvec + i] = s;
+    return;
+  }
+  for (int i0 = wave; i0 < nvec; i0 += 16) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 4 * u;
+      if (i < nvec) {
+        const double *v = V + (size_t)i * stride + base;
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+          const int e = lane + 64 * t;
+          s[u] += v[e < cn ? e : cn - 1] * wv[t];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 4 * u;
+      const double r = wave_sum(s[u]);
+      if (lane == 0 && i < nvec) part[(size_t)blockIdx.x * nvec + i] = r;
+    }
   }
 }
 
