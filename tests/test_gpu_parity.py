@@ -265,6 +265,42 @@ def test_build_is_deterministic():
     b.close()
 
 
+def test_profiler_counts_and_union():
+    """Per-class timing: every class timed, then the update class alone.  The
+    launch counts follow the schedule (per matrix batch and elimination step:
+    pivot + panel, and the two update parts, one launch on the last step),
+    the union of a class's launch intervals never exceeds their sum, and a
+    class left out is not timed."""
+    p = prob("cfg2s")
+    banner("profiler: launch counts, union of intervals, class selection")
+    dd = ddst()
+    dd.profile_enable(True)
+    op = dd.Operator.from_problem(p, precision="fp32")
+    torch.cuda.synchronize()
+    pr = dd.profile_read()
+    busy = dd.profile_busy()
+    dd.profile_enable(False)
+    op.close()
+    steps = -(-p.M // 128)  # elimination steps per inversion
+    ninv = (p.m - 1) + 1    # plane steps of the sweeps + the interface centres
+    assert pr["gj_panel"][0] == ninv * 2 * steps
+    assert pr["gj_update"][0] == ninv * (2 * (steps - 1) + 1)
+    for k, (n, ms, work) in pr.items():
+        if n:
+            assert ms > 0 and work > 0
+            # the union is built from float ms offsets against a common
+            # origin: allow their rounding (well under 1 us per launch)
+            assert 0 < busy[k] <= ms + n * 1e-3, (k, busy[k], ms)
+    dd.profile_enable(True, kinds=["gj_update"])
+    op = dd.Operator.from_problem(p, precision="fp32")
+    torch.cuda.synchronize()
+    pr2 = dd.profile_read()
+    dd.profile_enable(False)
+    op.close()
+    assert pr2["gj_update"][0] == pr["gj_update"][0]
+    assert all(pr2[k][0] == 0 for k in pr2 if k != "gj_update")
+
+
 def test_full_size_cfg2_sampled():
     """The benchmarked workload at full size (1023^2, 32 slabs, FP32 build,
     FP64 refinement): two sampled transfer blocks and the full solution."""
