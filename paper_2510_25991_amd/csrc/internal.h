@@ -188,8 +188,6 @@ void launch_axpy(double *y, const double *x, double a, size_t len, hipStream_t s
 void launch_fill(double *y, double v, size_t len, hipStream_t s);
 // part: at least dots_part_len(len, nvec) doubles of workspace
 inline size_t dots_part_len(size_t len, int nvec) { return ((len + 255) / 256) * (size_t)nvec; }
-void launch_dots(const double *V, size_t stride, int nvec, const double *w, size_t len,
-                 double *out, double *part, hipStream_t s);
 void launch_mgs_update(double *w, const double *V, size_t stride, int nvec,
                        const double *h, double sign, size_t len, hipStream_t s);
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s);

@@ -674,14 +674,6 @@ void launch_fill(double *y, double v, size_t len, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(len)), dim3(256), 0, s, y, v, len);
 }
 
-void launch_dots(const double *V, size_t stride, int nvec, const double *w, size_t len,
-                 double *out, double *part, hipStream_t s) {
-  const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
-  hipLaunchKernelGGL(k_multidot_part, dim3(nchunk), dim3(256), 0, s, V, stride, nvec, w, len,
-                     part);
-  hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(256), 0, s, part, nchunk, nvec, out, 0);
-}
-
 void launch_mgs_update(double *w, const double *V, size_t stride, int nvec, const double *h,
                        double sign, size_t len, hipStream_t s) {
   hipLaunchKernelGGL(k_mgs_update, dim3(nblk(len)), dim3(256), 0, s, w, V, stride, nvec, h,
