@@ -675,8 +675,8 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
       launch_gemv<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, trans ? 1 : 0, -1.0,
                      w.part, s);
     }
-    launch_cgs2_step(w.V, len, k + 1, w.W, len, w.hd, w.V + (size_t)(k + 1) * len, w.dpart, s);
-    launch_gmres_givens(w.hd, d, k, beta, s);
+    launch_arnoldi_step(w.V, len, k, w.W, len, w.hd, w.V + (size_t)(k + 1) * len, w.dpart, d,
+                        beta, s);
     if (k + 1 == next_check) {
       const int n = k + 1 - checked;
       HIPCHK(hipMemcpyAsync(hh, d.res + 2 * (size_t)checked, (size_t)n * 16,

@@ -191,12 +191,6 @@ inline size_t dots_part_len(size_t len, int nvec) { return ((len + 255) / 256) *
 void launch_mgs_update(double *w, const double *V, size_t stride, int nvec,
                        const double *h, double sign, size_t len, hipStream_t s);
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s);
-// One Arnoldi step by classical Gram-Schmidt applied twice (FP64):
-//   h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; vnext = w / |w|
-// with V nvec vectors of stride `stride`; hd[0..nvec) = h1,
-// hd[nvec..2 nvec) = h2, hd[2 nvec] = |w|.  part: dots_part_len(len, nvec).
-void launch_cgs2_step(const double *V, size_t stride, int nvec, double *w, size_t len,
-                      double *hd, double *vnext, double *part, hipStream_t s);
 // GMRES state on the device: packed Hessenberg columns (column k, k + 2
 // entries, from offset k (k + 3) / 2), Givens pairs, the rotated right-hand
 // side g and per-iteration residual estimates.
@@ -215,12 +209,18 @@ struct GmresDev {
     y = res + 2 * (size_t)max_iter;
   }
 };
-// Iteration k: column k of H from the two Gram-Schmidt passes (hd[0..k],
-// hd[k+1..2k+1]) and the new norm hd[2k+2]; previous rotations applied, the
-// new one formed, g updated; res[2k] = |g[k+1]| / beta, res[2k+1] = 1 when
-// the new norm is not positive and finite (breakdown: the Krylov space is
-// exhausted; a zero norm makes the estimate exactly 0), else 0.
-void launch_gmres_givens(const double *hd, GmresDev d, int k, double beta, hipStream_t s);
+// GMRES iteration k after the matvec w = S v_k: one Arnoldi step by
+// classical Gram-Schmidt applied twice (FP64), V the k + 1 basis vectors of
+// stride `stride`,
+//   h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; vnext = w / |w|
+// (hd[0..k] = h1, hd[k+1 .. 2k+1] = h2, hd[2k+2] = |w|), then column k of H
+// from them: previous rotations applied, the new one formed, g updated;
+// res[2k] = |g[k+1]| / beta, res[2k+1] = 1 when the new norm is not
+// positive and finite (breakdown: the Krylov space is exhausted; a zero norm
+// makes the estimate exactly 0), else 0.  part: dots_part_len(len, k + 1).
+void launch_arnoldi_step(const double *V, size_t stride, int k, double *w, size_t len,
+                         double *hd, double *vnext, double *part, GmresDev gd, double beta,
+                         hipStream_t s);
 // y = R^{-1} g over the first k columns (one work-group), then x = V y.
 void launch_gmres_solution(GmresDev d, int k, double *x, const double *V, size_t len,
                            hipStream_t s);

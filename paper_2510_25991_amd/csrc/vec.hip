@@ -482,13 +482,67 @@ __global__ __launch_bounds__(256) void k_mgs_update_dots(double *__restrict__ w,
   chunk_dots(V2, stride, nvec2, ws, base, cn, part);
 }
 
-// dst = src / sqrt(sum of the nchunk partial squared norms); every
-// work-group sums the partials in the same order, the first one stores the
-// norm.
-__global__ __launch_bounds__(256) void k_norm_scale(const double *__restrict__ part, int nchunk,
-                                                    double *__restrict__ nrm_out,
-                                                    const double *__restrict__ src,
-                                                    double *__restrict__ dst, size_t len) {
+// Column k of H (two Gram-Schmidt passes summed, new norm hn) is rotated by
+// the k previous Givens rotations, a new rotation zeroes its subdiagonal
+// entry and is applied to g.  Called by every thread of one work-group: the
+// column and the rotations are staged in LDS (when they fit), so the serial
+// rotation chain of thread 0 reads no global memory.
+constexpr int kGivensLds = 2048;
+__device__ __forceinline__ void gmres_givens_block(const double *__restrict__ hd, GmresDev d,
+                                                   int k, double beta, double hn) {
+  __shared__ double cl[kGivensLds + 2], cs[kGivensLds], sn[kGivensLds];
+  double *col = d.H + gmres_hoff(k);
+  const bool staged = k + 2 <= kGivensLds;
+  if (staged) {
+    for (int i = threadIdx.x; i <= k; i += blockDim.x) {
+      cl[i] = hd[i] + hd[k + 1 + i];
+      if (i < k) {
+        cs[i] = d.cs[i];
+        sn[i] = d.sn[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *c = staged ? cl : col;
+    const double *rc = staged ? cs : d.cs, *rs = staged ? sn : d.sn;
+    if (!staged)
+      for (int i = 0; i <= k; ++i) c[i] = hd[i] + hd[k + 1 + i];
+    c[k + 1] = hn;
+    double a = c[0];
+    for (int i = 0; i < k; ++i) {
+      const double bnext = c[i + 1];
+      c[i] = rc[i] * a + rs[i] * bnext;
+      a = -rs[i] * a + rc[i] * bnext;
+    }
+    const double r = hypot(a, c[k + 1]);
+    const double ck = r > 0.0 ? a / r : 1.0;
+    const double sk = r > 0.0 ? c[k + 1] / r : 0.0;
+    d.cs[k] = ck;
+    d.sn[k] = sk;
+    c[k] = r;
+    c[k + 1] = 0.0;
+    const double gk = k == 0 ? beta : d.g[k];
+    d.g[k + 1] = -sk * gk;
+    d.g[k] = ck * gk;
+    d.res[2 * k] = fabs(d.g[k + 1]) / beta;
+    d.res[2 * k + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
+  }
+  if (staged) {
+    __syncthreads();
+    for (int i = threadIdx.x; i <= k + 1; i += blockDim.x) col[i] = cl[i];
+  }
+}
+
+// Last kernel of Arnoldi step k: dst = src / sqrt(sum of the nchunk partial
+// squared norms), every work-group summing the partials in the same order;
+// the first one stores the norm in hd and then applies the Givens rotations
+// (column k of H from hd), concurrently with the others' scaling.
+__global__ __launch_bounds__(256) void k_norm_scale_givens(const double *__restrict__ part,
+                                                           int nchunk, double *__restrict__ hd,
+                                                           const double *__restrict__ src,
+                                                           double *__restrict__ dst, size_t len,
+                                                           GmresDev gd, int k, double beta) {
   __shared__ double sh[1];
   if (threadIdx.x < 64) {
     double s = 0.0;
@@ -497,13 +551,14 @@ __global__ __launch_bounds__(256) void k_norm_scale(const double *__restrict__ p
     if (threadIdx.x == 0) {
       const double d = sqrt(s);
       sh[0] = d;
-      if (blockIdx.x == 0) nrm_out[0] = d;
+      if (blockIdx.x == 0) hd[2 * (k + 1)] = d;
     }
   }
   __syncthreads();
   const double d = sh[0];
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < len) dst[e] = (d > 0.0) ? src[e] / d : 0.0;
+  if (blockIdx.x == 0) gmres_givens_block(hd, gd, k, beta, d);
 }
 
 // One work-group per vector sums its partials (strided, then a tree).
@@ -680,8 +735,10 @@ void launch_mgs_update(double *w, const double *V, size_t stride, int nvec, cons
                      sign, len);
 }
 
-void launch_cgs2_step(const double *V, size_t stride, int nvec, double *w, size_t len,
-                      double *hd, double *vnext, double *part, hipStream_t s) {
+void launch_arnoldi_step(const double *V, size_t stride, int k, double *w, size_t len,
+                         double *hd, double *vnext, double *part, GmresDev gd, double beta,
+                         hipStream_t s) {
+  const int nvec = k + 1;
   const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
   static_assert(kDotChunk == 256, "one element per thread in the fused update");
   // pass 1: h1 = V^T w
@@ -694,11 +751,11 @@ void launch_cgs2_step(const double *V, size_t stride, int nvec, double *w, size_
                      (const double *)hd, -1.0, len, V, nvec, part);
   hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(256), 0, s, (const double *)part,
                      nchunk, nvec, hd + nvec, 0);
-  // w -= V h2, then partial squared norms; v_next = w / |w|
+  // w -= V h2, then partial squared norms; v_next = w / |w| and the rotations
   hipLaunchKernelGGL(k_mgs_update_dots, dim3(nchunk), dim3(256), 0, s, w, V, stride, nvec,
                      (const double *)(hd + nvec), -1.0, len, (const double *)nullptr, 1, part);
-  hipLaunchKernelGGL(k_norm_scale, dim3(nblk(len)), dim3(256), 0, s, (const double *)part,
-                     nchunk, hd + 2 * nvec, (const double *)w, vnext, len);
+  hipLaunchKernelGGL(k_norm_scale_givens, dim3(nblk(len)), dim3(256), 0, s,
+                     (const double *)part, nchunk, hd, (const double *)w, vnext, len, gd, k, beta);
 }
 
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s) {
@@ -709,59 +766,6 @@ void launch_norm(const double *w, size_t len, double *out, double *part, hipStre
 }
 
 namespace {
-// Column k of H (two Gram-Schmidt passes summed) is rotated by the k
-// previous Givens rotations, a new rotation zeroes its subdiagonal entry and
-// is applied to g.  The column and the rotations are staged in LDS by the
-// whole work-group (when they fit), so the serial rotation chain of thread
-// 0 reads no global memory.
-constexpr int kGivensLds = 2048;
-__global__ __launch_bounds__(64) void k_gmres_givens(const double *__restrict__ hd, GmresDev d,
-                                                     int k, double beta) {
-  __shared__ double cl[kGivensLds + 2], cs[kGivensLds], sn[kGivensLds];
-  double *col = d.H + gmres_hoff(k);
-  const double hn = hd[2 * (k + 1)];
-  const bool staged = k + 2 <= kGivensLds;
-  if (staged) {
-    for (int i = threadIdx.x; i <= k; i += blockDim.x) {
-      cl[i] = hd[i] + hd[k + 1 + i];
-      if (i < k) {
-        cs[i] = d.cs[i];
-        sn[i] = d.sn[i];
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double *c = staged ? cl : col;
-    const double *rc = staged ? cs : d.cs, *rs = staged ? sn : d.sn;
-    if (!staged)
-      for (int i = 0; i <= k; ++i) c[i] = hd[i] + hd[k + 1 + i];
-    c[k + 1] = hn;
-    double a = c[0];
-    for (int i = 0; i < k; ++i) {
-      const double bnext = c[i + 1];
-      c[i] = rc[i] * a + rs[i] * bnext;
-      a = -rs[i] * a + rc[i] * bnext;
-    }
-    const double r = hypot(a, c[k + 1]);
-    const double ck = r > 0.0 ? a / r : 1.0;
-    const double sk = r > 0.0 ? c[k + 1] / r : 0.0;
-    d.cs[k] = ck;
-    d.sn[k] = sk;
-    c[k] = r;
-    c[k + 1] = 0.0;
-    const double gk = k == 0 ? beta : d.g[k];
-    d.g[k + 1] = -sk * gk;
-    d.g[k] = ck * gk;
-    d.res[2 * k] = fabs(d.g[k + 1]) / beta;
-    d.res[2 * k + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
-  }
-  if (staged) {
-    __syncthreads();
-    for (int i = threadIdx.x; i <= k + 1; i += blockDim.x) col[i] = cl[i];
-  }
-}
-
 // Back substitution R y = g, column by column: y_j is fixed, then every
 // thread removes its contribution from rows i < j.
 __global__ __launch_bounds__(256) void k_gmres_backsub(GmresDev d, int k) {
@@ -778,9 +782,6 @@ __global__ __launch_bounds__(256) void k_gmres_backsub(GmresDev d, int k) {
 }
 }  // namespace
 
-void launch_gmres_givens(const double *hd, GmresDev d, int k, double beta, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, s, hd, d, k, beta);
-}
 
 void launch_gmres_solution(GmresDev d, int k, double *x, const double *V, size_t len,
                            hipStream_t s) {
