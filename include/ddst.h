@@ -60,8 +60,10 @@ enum { DDST_FP64 = 0, DDST_FP32 = 1 };
 enum { DDST_TREE_BINARY = 0, DDST_TREE_QUAD = 1 };
 /* Storage type of the compressed low-rank factors. */
 enum { DDST_FACTOR_BF16 = 0, DDST_FACTOR_FP32 = 1, DDST_FACTOR_FP64 = 2 };
-/* Which representation ddst_apply uses. */
-enum { DDST_APPLY_DENSE = 0, DDST_APPLY_HODLR = 1 };
+/* Which representation ddst_apply uses: the dense transfer blocks, their
+ * compressed form, or no blocks at all (matrix-free: sweeps with the stored
+ * single-slab factors and the interface blocks, Sections 2.2 and 5.1). */
+enum { DDST_APPLY_DENSE = 0, DDST_APPLY_HODLR = 1, DDST_APPLY_MATFREE = 2 };
 
 typedef struct ddst_op ddst_op_t; /* opaque, library-owned */
 
@@ -103,7 +105,8 @@ typedef struct {
                             /* basis takes (max_iter+1)*N_ds*ld*8 device bytes) */
   int32_t max_outer;        /* FP64 refinement passes (>= 1)                   */
   int32_t use_hodlr;        /* 1: apply S through the compressed form          */
-  int32_t reserved;
+  int32_t matrix_free;      /* 1: apply S by sweeps with the stored factors,
+                               without its blocks (exclusive with use_hodlr)   */
 } ddst_solve_opts_t;
 
 typedef struct {
@@ -215,7 +218,11 @@ int ddst_op_info(const ddst_op_t *op, int32_t *M, int32_t *n_ds, int32_t *ld,
  *   the physical boundary -- is written as zeros); either pointer may be NULL.
  * ddst_apply: y = S x (transpose 0) or S^T x (transpose 1) for the equilibrium
  *   matrix S = I - K, x and y device N_ds*M float64, through the dense blocks
- *   (which = DDST_APPLY_DENSE) or the compressed form (DDST_APPLY_HODLR).
+ *   (which = DDST_APPLY_DENSE), the compressed form (DDST_APPLY_HODLR) or
+ *   matrix-free (DDST_APPLY_MATFREE: for every single slab between two
+ *   interfaces, two chains of m-1 products with its stored factors, then
+ *   Sigma_j^{-1}; the paper's matrix-free alternative, Section 5.1).
+ *   ESTATE if the chosen form is not held (no compression; factors dropped).
  * ddst_loads: equivalent loads hhat (eq. equilib1) of the load f and boundary
  *   data g, device N_ds*M output.
  */

@@ -477,6 +477,8 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
 struct SolveWs {
   double *X, *R, *Z, *D;     // padded volumes (n*ld)
   double *fJ, *hh, *W, *xg;  // interface vectors (n_ds*ld)
+  double *Zf, *Zb;           // padded volumes of the matrix-free apply's chains
+  double *mfx, *mfv, *mff;   // interface vectors of the matrix-free apply
   double *V;                 // Krylov basis (max_iter+1) * n_ds*ld
   double *hd;                // small scalars
   double *part;              // transposed-GEMV partial sums
@@ -502,7 +504,8 @@ void ensure_ws(ddst_op *op, size_t bytes) {
 SolveWs carve_ws(ddst_op *op, int max_iter) {
   const size_t vol = (size_t)op->n * op->ld, ifc = (size_t)op->n_ds * op->ld;
   const int nchunk = std::min(op->ld / kGemvChunk, 64);
-  const size_t part = (size_t)std::max(op->n_slabs, op->n_ds) * nchunk * op->ld;
+  // transposed GEMVs: at most 2 n_slabs jobs (the matrix-free chains)
+  const size_t part = (size_t)2 * op->n_slabs * nchunk * op->ld;
   Carve cv;
   size_t o[13];
   o[0] = cv.take(vol * 8); o[1] = cv.take(vol * 8); o[2] = cv.take(vol * 8);
@@ -516,6 +519,8 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   // partial sums: up to max_iter + 2 interface-length dots, or one volume norm
   o[12] = cv.take(std::max(dots_part_len(ifc, max_iter + 2), dots_part_len(vol, 1)) * 8);
   const size_t o_gm = cv.take(GmresDev::doubles(max_iter) * 8);
+  const size_t o_zf = cv.take(vol * 8), o_zb = cv.take(vol * 8);
+  const size_t o_mx = cv.take(ifc * 8), o_mv = cv.take(ifc * 8), o_mf = cv.take(ifc * 8);
   ensure_ws(op, cv.off);
   auto at = [&](size_t x) {
     return reinterpret_cast<double *>(static_cast<unsigned char *>(op->ws) + x);
@@ -525,6 +530,8 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   w.fJ = at(o[4]); w.hh = at(o[5]); w.W = at(o[6]); w.xg = at(o[7]);
   w.V = at(o[8]); w.hd = at(o[9]); w.part = at(o[10]); w.nrm = at(o[11]); w.dpart = at(o[12]);
   w.gm.carve(at(o_gm), max_iter);
+  w.Zf = at(o_zf); w.Zb = at(o_zb);
+  w.mfx = at(o_mx); w.mfv = at(o_mv); w.mff = at(o_mf);
   w.vol = vol;
   w.ifc = ifc;
   return w;
@@ -630,6 +637,106 @@ std::vector<GemvJob> sinv_jobs(const ddst_op *op, const double *x, double *y) {
   return jobs;
 }
 
+// Matrix-free application of the equilibrium matrix (the alternative to
+// forming the transfer blocks, Sections 2.2 and 5.1): only the stored
+// left-to-right factors G_k of the single slabs and the interface blocks
+// Sigma_j^{-1} are read.  With O the couplings between different interfaces
+// of the interface Schur complement, S x = x + Sigma^{-1} O x and
+//   (O x)_j = Em(c) .* a_{j-1} + Ep(c) .* b_j        (c = j m),
+// where a_s is the plane next to the right interface of slab s for Dirichlet
+// data x on its left interface only and b_s the plane next to its left
+// interface for data on its right interface only:
+//   a: y_1 = G_1 (-Em(P(1)) .* x_s),  y_k = G_k (-Em(P(k)) .* y_{k-1}),  a_s = y_{m-1};
+//   b: z_{m-1} = G_{m-1} (-Ep(P(m-1)) .* x_{s+1}),  z_k = G_k (-Ep(P(k)) .* z_{k+1}),
+//      b_s = z_1.
+// The interface sum is -f with f = interface_rhs(0, a, b).  Transposed:
+// S^T x = x + O^T Sigma^{-T} x, and O^T is the same two chains with G_k^T
+// and the couplings of A^T (Ep(P-1) towards P-1, Em(P+1) towards P+1).
+// Slabs next to the physical boundary have one interface and no chain; the
+// planes they would fill stay zero.  Launch i = 1..m-1 takes step k = i of
+// every a-chain and step k = m-i of every b-chain (2 (n_slabs - 2) jobs).
+struct MatfreeTables {
+  JobTable tab;
+  std::vector<size_t> chain;  // per launch i = 1..m-1 (index i-1)
+  int nchain = 0;             // jobs per chain launch
+  size_t sinv = 0;            // n_ds jobs with Sigma_j^{-1}
+};
+
+struct MatfreeBufs {
+  double *X, *V, *F;  // input copy, Sigma^{-T} X (transposed only), f
+  double *Zf, *Zb;    // padded volumes: a-chain and b-chain planes
+  double *y;          // output
+};
+
+void make_matfree_tables(const ddst_op *op, const void *G, bool trans, const MatfreeBufs &b,
+                         MatfreeTables &t) {
+  const int m = op->m, ld = op->ld;
+  const size_t mb = op->mat_bytes;
+  const double *data = trans ? b.V : b.X;  // Dirichlet data of the chains
+  t.chain.assign(m - 1, 0);
+  t.nchain = 2 * std::max(op->n_slabs - 2, 0);
+  for (int i = 1; i <= m - 1; ++i) {
+    std::vector<GemvJob> jobs;
+    for (int s = 1; s <= op->n_slabs - 2; ++s) {
+      int k = i, P = s * m + k;
+      GemvJob a{};
+      a.G = mat(const_cast<void *>(G), (size_t)s * (m - 1) + (k - 1), mb);
+      a.e = trans ? op->Ep + (size_t)(P - 1) * ld : op->Em + (size_t)P * ld;
+      a.x2 = (k == 1) ? data + (size_t)(s - 1) * ld : b.Zf + (size_t)(P - 2) * ld;
+      a.out = b.Zf + (size_t)(P - 1) * ld;
+      jobs.push_back(a);
+      k = m - i;
+      P = s * m + k;
+      GemvJob z{};
+      z.G = mat(const_cast<void *>(G), (size_t)s * (m - 1) + (k - 1), mb);
+      z.e = trans ? op->Em + (size_t)(P + 1) * ld : op->Ep + (size_t)P * ld;
+      z.x2 = (k == m - 1) ? data + (size_t)s * ld : b.Zb + (size_t)P * ld;
+      z.out = b.Zb + (size_t)(P - 1) * ld;
+      jobs.push_back(z);
+    }
+    t.chain[i - 1] = t.tab.add(jobs);
+  }
+  std::vector<GemvJob> sj;
+  for (int j = 1; j <= op->n_ds; ++j) {
+    GemvJob g{};
+    g.G = mat(op->Sinv, j - 1, mb);
+    if (!trans) {  // y = X - Sigma^{-1} f
+      g.x1 = b.F + (size_t)(j - 1) * ld;
+      g.w = b.X + (size_t)(j - 1) * ld;
+      g.out = b.y + (size_t)(j - 1) * ld;
+    } else {  // V = Sigma^{-T} X
+      g.x1 = b.X + (size_t)(j - 1) * ld;
+      g.out = b.V + (size_t)(j - 1) * ld;
+    }
+    sj.push_back(g);
+  }
+  t.sinv = t.tab.add(sj);
+}
+
+// y = S X (or S^T X) with the tables above; Zf and Zb must hold zeros in
+// the planes no chain writes (fill them once per set of tables).
+template <typename T>
+void run_matfree(const ddst_op *op, const MatfreeTables &t, bool trans, const MatfreeBufs &b,
+                 double *part, hipStream_t s) {
+  const int ld = op->ld, M = op->M;
+  const size_t len = (size_t)op->n_ds * ld;
+  if (trans) launch_gemv<T>(t.tab.at<GemvJob>(t.sinv), op->n_ds, ld, M, 1, 1.0, part, s);
+  if (t.nchain > 0)
+    for (int i = 1; i <= op->m - 1; ++i)
+      launch_gemv<T>(t.tab.at<GemvJob>(t.chain[i - 1]), t.nchain, ld, M, trans ? 1 : 0, 1.0,
+                     part, s);
+  if (!trans) {
+    launch_interface_rhs(nullptr, b.Zf, b.Zb, op->Em, op->Ep, op->n_ds, op->m, ld, 0, 0, b.F,
+                         s);
+    launch_gemv<T>(t.tab.at<GemvJob>(t.sinv), op->n_ds, ld, M, 0, -1.0, part, s);
+  } else {
+    launch_interface_rhs(nullptr, b.Zf, b.Zb, op->Ep, op->Em, op->n_ds, op->m, ld, -1, +1,
+                         b.F, s);
+    HIPCHK(hipMemcpyAsync(b.y, b.X, len * 8, hipMemcpyDeviceToDevice, s));
+    launch_axpy(b.y, b.F, -1.0, len, s);
+  }
+}
+
 // Unrestarted GMRES with classical Gram-Schmidt applied twice (FP64).
 // Basis vectors are padded interface vectors.  The Givens rotations run on
 // the device (one tiny kernel per iteration) and the host reads the
@@ -641,8 +748,8 @@ std::vector<GemvJob> sinv_jobs(const ddst_op *op, const double *x, double *y) {
 constexpr int kGmresCheck = 8;
 
 template <typename T>
-int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int max_iter,
-          bool trans, bool hodlr, double *relres, hipStream_t s) {
+int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
+          int max_iter, bool trans, int form, double *relres, hipStream_t s) {
   const size_t len = w.ifc;
   double *hh = op->hbuf_host;
   launch_norm(rhs, len, w.nrm, w.dpart, s);
@@ -656,10 +763,18 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
   // matvec tables for every basis vector
   JobTable tab;
   std::vector<size_t> offs(max_iter);
-  if (!hodlr)
+  if (form == DDST_APPLY_DENSE)
     for (int k = 0; k < max_iter; ++k)
       offs[k] = tab.add(interface_jobs(op, w.V + (size_t)k * len, w.W, trans));
   tab.upload(s);
+  MatfreeTables mf;
+  const MatfreeBufs mb{w.mfx, w.mfv, w.mff, w.Zf, w.Zb, w.W};
+  if (form == DDST_APPLY_MATFREE) {
+    make_matfree_tables(op, G, trans, mb, mf);
+    mf.tab.upload(s);
+    launch_fill(w.Zf, 0.0, w.vol, s);
+    launch_fill(w.Zb, 0.0, w.vol, s);
+  }
   GmresDev d = w.gm;
   int used = 0;
   double res = 1.0;
@@ -668,9 +783,12 @@ int gmres(ddst_op *op, SolveWs &w, const double *rhs, double *x, double tol, int
   double prev_res = 1.0;
   for (int k = 0; k < max_iter && used == 0; ++k) {
     const double *vk = w.V + (size_t)k * len;
-    if (hodlr) {
+    if (form == DDST_APPLY_HODLR) {
       int st = hodlr_apply_jobs(op, vk, w.W, trans ? 1 : 0, s);
       if (st) throw HipError("compressed apply failed");
+    } else if (form == DDST_APPLY_MATFREE) {
+      HIPCHK(hipMemcpyAsync(w.mfx, vk, len * 8, hipMemcpyDeviceToDevice, s));
+      run_matfree<T>(op, mf, trans, mb, w.part, s);
     } else {
       launch_gemv<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, trans ? 1 : 0, -1.0,
                      w.part, s);
@@ -739,15 +857,15 @@ void ensure_host(ddst_op *op, int max_iter) {
 // writing the correction volume into w.D; returns GMRES iterations.
 template <typename T>
 int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const double *tol_inner,
-                  int max_iter, bool hodlr, double *relres, SlabTables &loads,
+                  int max_iter, int form, double *relres, SlabTables &loads,
                   SlabTables &recon, hipStream_t s) {
   // z = A_II^{-1} r_I
   run_slab_solve<T>(op, loads, trans, w.part, s);
   // f_J = r_J - A_JI z
   if (!trans)
-    launch_interface_rhs(w.R, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ, s);
+    launch_interface_rhs(w.R, w.Z, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ, s);
   else
-    launch_interface_rhs(w.R, w.Z, op->Ep, op->Em, op->n_ds, op->m, op->ld, -1, +1, w.fJ, s);
+    launch_interface_rhs(w.R, w.Z, w.Z, op->Ep, op->Em, op->n_ds, op->m, op->ld, -1, +1, w.fJ, s);
   int it;
   if (!trans) {
     // hhat = Sigma^{-1} f_J ; S d_J = hhat
@@ -755,10 +873,10 @@ int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const doub
     const size_t o = tb.add(sinv_jobs(op, w.fJ, w.hh));
     tb.upload(s);
     launch_gemv<T>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 0, 1.0, w.part, s);
-    it = gmres<T>(op, w, w.hh, w.xg, *tol_inner, max_iter, false, hodlr, relres, s);
+    it = gmres<T>(op, w, G, w.hh, w.xg, *tol_inner, max_iter, false, form, relres, s);
   } else {
     // S^T mu = f_J ; d_J = Sigma^{-T} mu
-    it = gmres<T>(op, w, w.fJ, w.hh, *tol_inner, max_iter, true, hodlr, relres, s);
+    it = gmres<T>(op, w, G, w.fJ, w.hh, *tol_inner, max_iter, true, form, relres, s);
     JobTable tb;
     const size_t o = tb.add(sinv_jobs(op, w.hh, w.xg));
     tb.upload(s);
@@ -768,8 +886,13 @@ int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const doub
   // traces into the correction volume, then the slab interiors
   launch_copy_planes(w.xg, 1, 0, w.D, op->m, op->m - 1, op->n_ds, op->ld, op->M, s);
   run_slab_solve<T>(op, recon, trans, w.part, s);
-  (void)G;
   return it;
+}
+
+// How GMRES applies S: the dense blocks, the compressed form or the
+// matrix-free sweeps.
+inline int apply_form(const ddst_solve_opts_t &o) {
+  return o.use_hodlr ? DDST_APPLY_HODLR : o.matrix_free ? DDST_APPLY_MATFREE : DDST_APPLY_DENSE;
 }
 
 struct RefineOut {
@@ -797,8 +920,8 @@ int refine(ddst_op *op, const void *G, const double *f, const double *g, bool tr
     if (outer == 0) r0 = dev_norm(op, w.R, w.vol, w.nrm, w.dpart, s);
     launch_fill(w.D, 0.0, w.vol, s);
     double rr = 0;
-    const int it = dd_correction<T>(op, w, G, trans, &o.inner_tol, o.max_iter,
-                                    o.use_hodlr != 0, &rr, loads, recon, s);
+    const int it = dd_correction<T>(op, w, G, trans, &o.inner_tol, o.max_iter, apply_form(o),
+                                    &rr, loads, recon, s);
     ro.gm_total += it;
     ro.gm_last = it;
     ro.relres = rr;
@@ -837,6 +960,7 @@ ddst_solve_opts_t solve_defaults(const ddst_op *op) {
   o.max_iter = 300;
   o.max_outer = 4;
   o.use_hodlr = 0;
+  o.matrix_free = 0;
   return o;
 }
 
@@ -845,6 +969,10 @@ int check_solve_opts(const ddst_solve_opts_t &o) {
   if (o.max_iter < 1 || o.max_iter > kMaxGmresIter)
     return fail(DDST_EINVAL, "max_iter in [1, " + std::to_string(kMaxGmresIter) + "]");
   if (o.max_outer < 1 || o.max_outer > 100) return fail(DDST_EINVAL, "max_outer in [1, 100]");
+  if ((o.use_hodlr != 0 && o.use_hodlr != 1) || (o.matrix_free != 0 && o.matrix_free != 1))
+    return fail(DDST_EINVAL, "use_hodlr and matrix_free must be 0 or 1");
+  if (o.use_hodlr && o.matrix_free)
+    return fail(DDST_EINVAL, "use_hodlr and matrix_free are exclusive");
   return DDST_OK;
 }
 
@@ -1090,11 +1218,13 @@ int ddst_apply(const ddst_op_t *cop, int32_t transpose, int32_t which, const dou
                double *y, hipStream_t stream) {
   g_err.clear();
   if (!cop || !x || !y) return fail(DDST_EINVAL, "op, x and y must be non-NULL");
-  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR)
-    return fail(DDST_EINVAL, "which must be DENSE or HODLR");
+  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR && which != DDST_APPLY_MATFREE)
+    return fail(DDST_EINVAL, "which must be DENSE, HODLR or MATFREE");
   ddst_op *op = const_cast<ddst_op *>(cop);
   if (which == DDST_APPLY_HODLR && !hodlr_ready(op))
     return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  if (which == DDST_APPLY_MATFREE && !op->G)
+    return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
   return guarded([&]() -> int {
     DeviceMem buf((size_t)op->n_ds * op->ld * 8 * 2);
     double *xp = static_cast<double *>(buf.p), *yp = xp + (size_t)op->n_ds * op->ld;
@@ -1114,9 +1244,28 @@ int ddst_apply(const ddst_op_t *cop, int32_t transpose, int32_t which, const dou
       launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(stream));
-    } else {
+    } else if (which == DDST_APPLY_HODLR) {
       const int st = hodlr_apply_jobs(op, xp, yp, transpose, stream);
       if (st) return st;
+      launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(stream));
+    } else {
+      const size_t ifc = (size_t)op->n_ds * op->ld, vol = (size_t)op->n * op->ld;
+      const int nchunk = std::min(op->ld / kGemvChunk, 64);
+      const size_t npart = (size_t)2 * op->n_slabs * nchunk * op->ld;
+      DeviceMem tmp((2 * vol + 2 * ifc + npart) * 8);
+      double *Zf = static_cast<double *>(tmp.p), *Zb = Zf + vol, *V = Zb + vol, *F = V + ifc;
+      double *part = F + ifc;
+      const MatfreeBufs b{xp, V, F, Zf, Zb, yp};
+      MatfreeTables t;
+      make_matfree_tables(op, op->G, transpose != 0, b, t);
+      t.tab.upload(stream);
+      launch_fill(Zf, 0.0, 2 * vol, stream);
+      if (op->prec == DDST_FP32)
+        run_matfree<float>(op, t, transpose != 0, b, part, stream);
+      else
+        run_matfree<double>(op, t, transpose != 0, b, part, stream);
       launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(stream));
@@ -1145,12 +1294,12 @@ int ddst_loads(const ddst_op_t *cop, const double *f, const double *g, double *h
     tb.upload(stream);
     if (op->prec == DDST_FP32) {
       run_slab_solve<float>(op, loads, false, w.part, stream);
-      launch_interface_rhs(w.R, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ,
+      launch_interface_rhs(w.R, w.Z, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ,
                            stream);
       launch_gemv<float>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 0, 1.0, w.part, stream);
     } else {
       run_slab_solve<double>(op, loads, false, w.part, stream);
-      launch_interface_rhs(w.R, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ,
+      launch_interface_rhs(w.R, w.Z, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ,
                            stream);
       launch_gemv<double>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 0, 1.0, w.part, stream);
     }

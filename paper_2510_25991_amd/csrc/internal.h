@@ -176,11 +176,12 @@ void launch_unpad(const double *src, double *dst, int rows, int M, int ld, hipSt
 template <typename T>
 void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, double alpha,
                  double *partial, hipStream_t s);
-// out_j = x_j - ... elementwise helpers for the interface right-hand sides:
-//   out[j] = v[plane_j] - a[j] .* Z[plane_j - 1] - b[j] .* Z[plane_j + 1]
-void launch_interface_rhs(const double *vol, const double *Z, const double *Ea,
-                          const double *Eb, int n_ds, int m, int ld, int a_off, int b_off,
-                          double *out, hipStream_t s);
+// Interface right-hand sides from the planes next to each interface:
+//   out[j] = v[pl] - Ea[pl + a_off] .* Zl[pl - 1] - Eb[pl + b_off] .* Zr[pl + 1],
+// pl = j m the interface plane (1-based), v = vol (0 if vol is NULL).
+void launch_interface_rhs(const double *vol, const double *Zl, const double *Zr,
+                          const double *Ea, const double *Eb, int n_ds, int m, int ld,
+                          int a_off, int b_off, double *out, hipStream_t s);
 void launch_copy_planes(const double *src, int src_stride, int src_off, double *dst,
                         int dst_stride, int dst_off, int count, int ld, int M,
                         hipStream_t s);

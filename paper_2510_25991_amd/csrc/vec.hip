@@ -356,16 +356,16 @@ __global__ void k_gemv_t_reduce(const GemvJob *__restrict__ jobs, int ld, int nc
   gp(J.out)[c] = (J.w ? gp(J.w)[c] : 0.0) + alpha * s;
 }
 
-__global__ void k_interface_rhs(const double *__restrict__ vol, const double *__restrict__ Z,
-                                const double *__restrict__ Ea, const double *__restrict__ Eb,
-                                int n_ds, int m, int ld, int a_off, int b_off,
-                                double *__restrict__ out) {
+__global__ void k_interface_rhs(const double *__restrict__ vol, const double *__restrict__ Zl,
+                                const double *__restrict__ Zr, const double *__restrict__ Ea,
+                                const double *__restrict__ Eb, int n_ds, int m, int ld,
+                                int a_off, int b_off, double *__restrict__ out) {
   const int j = blockIdx.y + 1;  // interface 1..n_ds
   const int pl = j * m;          // node plane (1-based)
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += gridDim.x * blockDim.x) {
-    const double v = vol[(size_t)(pl - 1) * ld + r] -
-                     Ea[(size_t)(pl + a_off) * ld + r] * Z[(size_t)(pl - 2) * ld + r] -
-                     Eb[(size_t)(pl + b_off) * ld + r] * Z[(size_t)pl * ld + r];
+    const double v = (vol ? vol[(size_t)(pl - 1) * ld + r] : 0.0) -
+                     Ea[(size_t)(pl + a_off) * ld + r] * Zl[(size_t)(pl - 2) * ld + r] -
+                     Eb[(size_t)(pl + b_off) * ld + r] * Zr[(size_t)pl * ld + r];
     out[(size_t)(j - 1) * ld + r] = v;
   }
 }
@@ -706,11 +706,11 @@ template void launch_gemv<float>(const GemvJob *, int, int, int, int, double, do
 template void launch_gemv<double>(const GemvJob *, int, int, int, int, double, double *,
                                   hipStream_t);
 
-void launch_interface_rhs(const double *vol, const double *Z, const double *Ea,
-                          const double *Eb, int n_ds, int m, int ld, int a_off, int b_off,
-                          double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_interface_rhs, dim3(nblk(ld), n_ds), dim3(256), 0, s, vol, Z, Ea, Eb,
-                     n_ds, m, ld, a_off, b_off, out);
+void launch_interface_rhs(const double *vol, const double *Zl, const double *Zr,
+                          const double *Ea, const double *Eb, int n_ds, int m, int ld,
+                          int a_off, int b_off, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_interface_rhs, dim3(nblk(ld), n_ds), dim3(256), 0, s, vol, Zl, Zr, Ea,
+                     Eb, n_ds, m, ld, a_off, b_off, out);
 }
 
 void launch_copy_planes(const double *src, int src_stride, int src_off, double *dst,

@@ -22,7 +22,8 @@ DDST_EINVAL, DDST_ENOMEM, DDST_EHIP, DDST_EBREAKDOWN, DDST_ERANK, DDST_ESTATE = 
 FP64, FP32 = 0, 1
 TREE_BINARY, TREE_QUAD = 0, 1
 FACTOR_BF16, FACTOR_FP32, FACTOR_FP64 = 0, 1, 2
-APPLY_DENSE, APPLY_HODLR = 0, 1
+APPLY_DENSE, APPLY_HODLR, APPLY_MATFREE = 0, 1, 2
+_APPLY_FORMS = {"dense": APPLY_DENSE, "hodlr": APPLY_HODLR, "matfree": APPLY_MATFREE}
 
 
 class DDSTError(RuntimeError):
@@ -52,7 +53,7 @@ class CompressOptsC(ctypes.Structure):
 class SolveOptsC(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
-                ("use_hodlr", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_hodlr", ctypes.c_int32), ("matrix_free", ctypes.c_int32)]
 
 
 class StatsC(ctypes.Structure):
@@ -155,6 +156,7 @@ class SolveOptions:
     max_iter: int = 300
     max_outer: int = 4
     use_hodlr: bool = False
+    matrix_free: bool = False              # apply S by sweeps with the stored factors
 
 
 class Operator:
@@ -206,7 +208,8 @@ class Operator:
     def _solve_opts(self, opts: Optional[SolveOptions]):
         o = opts or SolveOptions()
         inner = o.inner_tol if o.inner_tol is not None else (1e-4 if self.precision == "fp32" else 1e-12)
-        return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0, 0)
+        return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0,
+                          1 if o.matrix_free else 0)
 
     def solve(self, f=None, g=None, opts: Optional[SolveOptions] = None, want_gamma=True,
               allow_notconv=False):
@@ -262,10 +265,12 @@ class Operator:
         return out
 
     def apply(self, x, transpose=False, which="dense"):
+        """y = S x (or S^T x); which: "dense", "hodlr" or "matfree"."""
+        if which not in _APPLY_FORMS:
+            raise ValueError(f"which must be one of {sorted(_APPLY_FORMS)}")
         x = _dev(x).reshape(-1)
         y = torch.empty_like(x)
-        _check(load_library().ddst_apply(self._h, 1 if transpose else 0,
-                                         APPLY_HODLR if which == "hodlr" else APPLY_DENSE,
+        _check(load_library().ddst_apply(self._h, 1 if transpose else 0, _APPLY_FORMS[which],
                                          _ptr(x), _ptr(y), _stream()))
         return y.view(self.n_ds, self.M)
 
