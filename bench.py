@@ -11,7 +11,9 @@ elimination (FP32 on the matrix cores) + solve the equilibrium system by
 GMRES inside FP64 iterative refinement, to a predicted relative error of
 1e-9 (target 1e-8).  value = N / (seconds per step), N = 1023^2 DOFs.  The
 FP64 plain path (FP64 build, same solver) is timed beside it, and the
-adjoint of a sensor loss (factors recomputed) is timed once.
+adjoint of a sensor loss (factors recomputed) is timed once, and so is the
+matrix-free alternative (S applied by sweeps with the stored slab factors,
+set-up without the transfer blocks) beside the dense-block form.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -41,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain path")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-matfree", action="store_true",
+                    help="skip the matrix-free comparison (untimed, after the timed steps)")
     ap.add_argument("--n", type=int, default=None, help="reduced grid (debug only)")
     ap.add_argument("--slabs", type=int, default=None)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -228,6 +232,41 @@ def cpu_leg(prob, u_mixed, u_fp64):
     }, errs
 
 
+def matfree_leg(dd, torch, dev, prob, opts):
+    """Dense transfer blocks vs the matrix-free form (the comparison of the
+    paper's Section 5.1): device memory, set-up time, one product with S
+    (host-timed C-ABI call, mean of 10) and one refined solve, FP32 factors."""
+    full = dd.Operator(2, dev["n"], dev["n_slabs"], kappa=dev["kappa"], bvec=dev["bvec"],
+                       precision="fp32")
+    lite = dd.Operator(2, dev["n"], dev["n_slabs"], kappa=dev["kappa"], bvec=dev["bvec"],
+                       precision="fp32", transfer_blocks=False)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn(prob.n_ds * full.M, dtype=torch.float64, device="cuda", generator=g)
+
+    def apply_ms(op, which):
+        for _ in range(2):
+            op.apply(x, which=which)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            op.apply(x, which=which)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / 10 * 1e3
+
+    a_dense, a_free = apply_ms(full, "dense"), apply_ms(lite, "matfree")
+    _, _, sd = full.solve(dev["f"], opts=opts, want_gamma=False, allow_notconv=True)
+    _, _, sm = lite.solve(dev["f"], opts=opts, want_gamma=False, allow_notconv=True)
+    full.close()
+    lite.close()
+    return {"memory_gb": {"transfer_blocks": round(sd["bytes_transfer"] / 1e9, 3),
+                          "slab_factors": round(sd["bytes_factors"] / 1e9, 3)},
+            "setup_ms": {"dense": round(sd["t_build_ms"], 2), "matfree": round(sm["t_build_ms"], 2)},
+            "apply_ms": {"dense": round(a_dense, 3), "matfree": round(a_free, 3)},
+            "solve_ms": {"dense": round(sd["t_solve_ms"], 2), "matfree": round(sm["t_solve_ms"], 2)},
+            "gmres_iters": {"dense": sd["gmres_iters"], "matfree": sm["gmres_iters"]},
+            "converged": {"dense": bool(sd["status"] == 0), "matfree": bool(sm["status"] == 0)}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -294,6 +333,10 @@ def main():
                "outer_iters": sta["outer_iters"], "gmres_iters": sta["gmres_iters"],
                "converged": bool(sta["status"] == 0)}
         op.close()
+    mfree = None
+    if not args.no_matfree:
+        print("[bench] matrix-free comparison", file=sys.stderr, flush=True)
+        mfree = matfree_leg(dd, torch, dev, prob, opts)
     cpu, errs = (None, {})
     if not args.no_cpu:
         print("[bench] CPU oracle leg", file=sys.stderr, flush=True)
@@ -325,6 +368,7 @@ def main():
         "rel_err_vs_oracle": errs or None,
         "fp64_plain": out_fp64,
         "adjoint": adj,
+        "matrix_free": mfree,
         # every class timed over one extra step (untimed)
         "kernel_profile_per_step": {k: {"launches": v[0], "ms": round(v[1], 3)}
                                     for k, v in mix.items()},

@@ -83,7 +83,11 @@ typedef struct {
                                solve (required by ddst_solve); 0: drop them     */
   int32_t transpose;        /* must be 0 (reserved; the adjoint works from the
                                forward operator's transposed structure)       */
-  int32_t reserved;
+  int32_t skip_transfer;    /* 1: matrix-free set-up (Section 5.1): slab factors
+                               and interface blocks only, no transfer blocks;
+                               needs keep_factors; solves then set
+                               matrix_free, and the dense form, the compressed
+                               form and ddst_get_transfer report ESTATE       */
 } ddst_build_opts_t;
 
 typedef struct {

@@ -270,17 +270,19 @@ int check_flag(ddst_op *op, hipStream_t s, const char *what) {
   return DDST_OK;
 }
 
+// blocks = 0: the matrix-free set-up (slab factors and interface blocks
+// only; no transfer chains, no transfer blocks).
 template <typename T>
-int build_impl(ddst_op *op, int keep, hipStream_t s) {
+int build_impl(ddst_op *op, int keep, int blocks, hipStream_t s) {
   const int m = op->m, nsl = op->n_slabs, nds = op->n_ds;
   SweepPlan plan;
   int nwork = 0, ny = 0;
   for (int sl = 0; sl < nsl; ++sl) {  // left-to-right, towards Gamma_{sl+1}
-    const bool hasY = sl >= 1 && sl <= nsl - 2;
+    const bool hasY = blocks && sl >= 1 && sl <= nsl - 2;
     plan.sw.push_back({sl, +1, hasY ? ny++ : -1, keep ? -1 : nwork++});
   }
   for (int sl = 1; sl < nsl; ++sl) {  // right-to-left, towards Gamma_sl
-    const bool hasY = sl <= nsl - 2;
+    const bool hasY = blocks && sl <= nsl - 2;
     plan.sw.push_back({sl, -1, hasY ? ny++ : -1, nwork++});
   }
   plan.n_y = ny;
@@ -319,6 +321,7 @@ int build_impl(ddst_op *op, int keep, hipStream_t s) {
     a.c2 = op->Em + (size_t)(c + 1) * op->ld;
     cj.push_back(a);
     smats.push_back(a.D);
+    if (!blocks) continue;
     if (j >= 2) {
       GemmJob g{};
       g.A = a.D;
@@ -344,7 +347,8 @@ int build_impl(ddst_op *op, int keep, hipStream_t s) {
   GjStreams gs;
   HIPCHK(gs.create());
   HIPCHK(gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, gjw.p, op->flag, gs, s));
-  launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, op->M, -1.0, 0.0, s);
+  if (!sj.empty())
+    launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, op->M, -1.0, 0.0, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return check_flag(op, s, "ddst_build_transfer");
@@ -386,6 +390,11 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
   if (o.precision != DDST_FP32 && o.precision != DDST_FP64)
     return fail(DDST_EINVAL, "precision must be DDST_FP32 or DDST_FP64");
   if (o.transpose != 0) return fail(DDST_EINVAL, "transpose builds are not supported");
+  if (o.skip_transfer != 0 && o.skip_transfer != 1)
+    return fail(DDST_EINVAL, "skip_transfer must be 0 or 1");
+  if (o.skip_transfer && !o.keep_factors)
+    return fail(DDST_EINVAL, "skip_transfer needs keep_factors (the matrix-free apply reads them)");
+  const int blocks = o.skip_transfer ? 0 : 1;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -412,7 +421,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     const size_t o_em = cv.take((size_t)(op->n + 2) * op->ld * 8);
     const size_t o_ep = cv.take((size_t)(op->n + 2) * op->ld * 8);
     const size_t o_si = cv.take((size_t)op->n_ds * op->mat_bytes);
-    const size_t o_s = cv.take((size_t)2 * op->n_ds * op->mat_bytes);
+    const size_t o_s = blocks ? cv.take((size_t)2 * op->n_ds * op->mat_bytes) : 0;
     const size_t o_fl = cv.take(sizeof(int));
     if (hipMalloc(&op->arena, cv.off) != hipSuccess) {
       op->arena = nullptr;
@@ -426,10 +435,10 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     op->Em = reinterpret_cast<double *>(at(o_em));
     op->Ep = reinterpret_cast<double *>(at(o_ep));
     op->Sinv = at(o_si);
-    op->S = at(o_s);
+    op->S = blocks ? at(o_s) : nullptr;
     op->flag = reinterpret_cast<int *>(at(o_fl));
     HIPCHK(hipMemsetAsync(op->flag, 0, sizeof(int), s));
-    HIPCHK(hipMemsetAsync(op->S, 0, (size_t)2 * op->n_ds * op->mat_bytes, s));
+    if (op->S) HIPCHK(hipMemsetAsync(op->S, 0, (size_t)2 * op->n_ds * op->mat_bytes, s));
     if (op->kappa) {
       HIPCHK(hipMemcpyAsync(op->kappa, prob->kappa, ncell * 8, hipMemcpyDeviceToDevice, s));
       launch_check_finite(op->kappa, ncell, 0.0, op->flag, s);
@@ -448,8 +457,9 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     launch_setup_coef(op->kappa, op->c, op->bvec, op->dim, op->n, op->h, op->coef, nullptr, s);
     launch_fill_couplings(op->coef, op->dim, op->n, op->M, op->ld, op->Em, op->Ep, s);
     HIPCHK(hipGetLastError());
-    st = (op->prec == DDST_FP32) ? build_impl<float>(op, o.keep_factors ? 1 : 0, s)
-                                 : build_impl<double>(op, o.keep_factors ? 1 : 0, s);
+    const int keep = o.keep_factors ? 1 : 0;
+    st = (op->prec == DDST_FP32) ? build_impl<float>(op, keep, blocks, s)
+                                 : build_impl<double>(op, keep, blocks, s);
     if (st) {
       destroy_op(op);
       return st;
@@ -459,7 +469,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     op->last_build.t_build_ms = ms;
-    op->last_build.bytes_transfer = (double)2 * op->n_ds * op->mat_bytes;
+    op->last_build.bytes_transfer = op->S ? (double)2 * op->n_ds * op->mat_bytes : 0;
     op->last_build.bytes_factors = op->G ? (double)op->n_slabs * (op->m - 1) * op->mat_bytes : 0;
   } catch (...) {
     destroy_op(op);
@@ -981,6 +991,8 @@ int solve_impl(ddst_op *op, const double *f, const double *g, const ddst_solve_o
                double *u_gamma, double *u_vol, ddst_stats_t *st, hipStream_t s) {
   if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
   if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  if (apply_form(o) == DDST_APPLY_DENSE && !op->S)
+    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build): set matrix_free");
   ensure_host(op, o.max_iter);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1019,6 +1031,8 @@ int adjoint_impl(ddst_op *op, const double *u_vol, const double *g, const double
                  const ddst_solve_opts_t &o, double *dkappa, double *lambda, ddst_stats_t *st,
                  hipStream_t s) {
   if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  if (apply_form(o) == DDST_APPLY_DENSE && !op->S)
+    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build): set matrix_free");
   ensure_host(op, o.max_iter);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1122,6 +1136,7 @@ int ddst_adjoint(const ddst_op_t *cop, const double *u_vol, const double *g, con
 int ddst_compress(ddst_op_t *op, const ddst_compress_opts_t *opts, hipStream_t stream) {
   g_err.clear();
   if (!op || !opts) return fail(DDST_EINVAL, "op and opts must be non-NULL");
+  if (!op->S) return fail(DDST_ESTATE, "no transfer blocks to compress (matrix-free build)");
   const ddst_compress_opts_t &o = *opts;
   if (o.tree != DDST_TREE_BINARY && o.tree != DDST_TREE_QUAD)
     return fail(DDST_EINVAL, "tree must be BINARY or QUAD");
@@ -1201,6 +1216,7 @@ int ddst_get_transfer(const ddst_op_t *op, int32_t j, double *S_left, double *S_
   g_err.clear();
   if (!op) return fail(DDST_EINVAL, "op is NULL");
   if (j < 1 || j > op->n_ds) return fail(DDST_EINVAL, "interface index out of range");
+  if (!op->S) return fail(DDST_ESTATE, "no transfer blocks (matrix-free build)");
   return guarded([&]() -> int {
     if (S_left)
       launch_extract_block(mat(op->S, 2 * (j - 1) + 0, op->mat_bytes), op->prec, op->M, op->ld,
@@ -1225,6 +1241,8 @@ int ddst_apply(const ddst_op_t *cop, int32_t transpose, int32_t which, const dou
     return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
   if (which == DDST_APPLY_MATFREE && !op->G)
     return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
+  if (which == DDST_APPLY_DENSE && !op->S)
+    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build)");
   return guarded([&]() -> int {
     DeviceMem buf((size_t)op->n_ds * op->ld * 8 * 2);
     double *xp = static_cast<double *>(buf.p), *yp = xp + (size_t)op->n_ds * op->ld;

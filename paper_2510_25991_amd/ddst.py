@@ -40,7 +40,7 @@ class ProblemC(ctypes.Structure):
 
 class BuildOptsC(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("keep_factors", ctypes.c_int32),
-                ("transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("transpose", ctypes.c_int32), ("skip_transfer", ctypes.c_int32)]
 
 
 class CompressOptsC(ctypes.Structure):
@@ -163,7 +163,10 @@ class Operator:
     """A built equilibrium operator (transfer blocks + slab factors) on the GPU."""
 
     def __init__(self, dim, n, n_slabs, kappa=None, bvec=(0.0, 0.0, 0.0), c=None,
-                 precision: str = "fp32", keep_factors: bool = True):
+                 precision: str = "fp32", keep_factors: bool = True,
+                 transfer_blocks: bool = True):
+        """transfer_blocks=False: the matrix-free set-up (slab factors and
+        interface blocks only); solves then apply S matrix-free."""
         if not torch.cuda.is_available():
             raise RuntimeError("ddst needs a ROCm GPU; no device is visible")
         L = load_library()
@@ -174,7 +177,9 @@ class Operator:
         b = list(bvec) + [0.0] * 3
         self._prob = ProblemC(self.dim, self.n, self.n_slabs, _ptr(self._kappa),
                               (ctypes.c_double * 3)(*[float(v) for v in b[:3]]), _ptr(self._c))
-        opts = BuildOptsC(FP32 if precision == "fp32" else FP64, 1 if keep_factors else 0, 0, 0)
+        self.transfer_blocks = bool(transfer_blocks)
+        opts = BuildOptsC(FP32 if precision == "fp32" else FP64, 1 if keep_factors else 0, 0,
+                          0 if transfer_blocks else 1)
         h = ctypes.c_void_p()
         _check(L.ddst_build_transfer(ctypes.byref(self._prob), ctypes.byref(opts), _stream(),
                                      ctypes.byref(h)))
@@ -185,9 +190,10 @@ class Operator:
         self.M, self.n_ds, self.ld = M.value, nds.value, ld.value
 
     @classmethod
-    def from_problem(cls, prob, precision="fp32", keep_factors=True):
+    def from_problem(cls, prob, precision="fp32", keep_factors=True, transfer_blocks=True):
         return cls(prob.dim, prob.n, prob.n_slabs, kappa=prob.kappa, bvec=prob.bvec, c=prob.c,
-                   precision=precision, keep_factors=keep_factors)
+                   precision=precision, keep_factors=keep_factors,
+                   transfer_blocks=transfer_blocks)
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -208,8 +214,10 @@ class Operator:
     def _solve_opts(self, opts: Optional[SolveOptions]):
         o = opts or SolveOptions()
         inner = o.inner_tol if o.inner_tol is not None else (1e-4 if self.precision == "fp32" else 1e-12)
+        # an operator without transfer blocks applies S matrix-free
+        mf = o.matrix_free or not (self.transfer_blocks or o.use_hodlr)
         return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0,
-                          1 if o.matrix_free else 0)
+                          1 if mf else 0)
 
     def solve(self, f=None, g=None, opts: Optional[SolveOptions] = None, want_gamma=True,
               allow_notconv=False):

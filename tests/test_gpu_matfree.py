@@ -141,6 +141,50 @@ def test_matfree_errors():
     op.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["cfg2s", "cfg4s", "m2", "two_slabs"])
+def test_matfree_setup(name, precision):
+    """The matrix-free set-up (no transfer chains, no blocks) holds the same
+    slab factors and interface blocks as the full build: its matrix-free
+    products are bit-identical, and its solves match the global direct one."""
+    p = prob(name)
+    banner(f"matrix-free set-up {name} {precision}")
+    dd = ddst()
+    full = dd.Operator.from_problem(p, precision=precision)
+    op = dd.Operator.from_problem(p, precision=precision, transfer_blocks=False)
+    x = torch.tensor(np.random.default_rng(22).standard_normal(p.n_ds * op.M), device="cuda")
+    for trans in (False, True):
+        a = op.apply(x, transpose=trans, which="matfree")
+        b = full.apply(x, transpose=trans, which="matfree")
+        assert torch.equal(a, b)
+    _, _, st_full = full.solve(p.f, p.g)
+    ref = ofd.solve_global(p)
+    u, _, st = op.solve(p.f, p.g)
+    err = rel(u.cpu().numpy().ravel(), ref)
+    print(f"  rel err {err:.3e} gmres {st['gmres_iters']} build {st['t_build_ms']:.1f} ms "
+          f"(with blocks {st_full['t_build_ms']:.1f} ms)")
+    assert st["status"] == 0 and err <= (1e-10 if precision == "fp64" else 1e-8)
+    assert st["bytes_transfer"] == 0 and st["bytes_factors"] == st_full["bytes_factors"]
+    full.close()
+    op.close()
+
+
+def test_matfree_setup_errors():
+    dd = ddst()
+    p = prob("m2")
+    with pytest.raises(dd.DDSTError) as ei:
+        dd.Operator.from_problem(p, keep_factors=False, transfer_blocks=False)
+    assert ei.value.code == dd.DDST_EINVAL
+    op = dd.Operator.from_problem(p, transfer_blocks=False)
+    x = torch.zeros(p.n_ds * op.M, dtype=torch.float64, device="cuda")
+    for call in (lambda: op.apply(x, which="dense"), lambda: op.transfer(1),
+                 lambda: op.compress()):
+        with pytest.raises(dd.DDSTError) as ei:
+            call()
+        assert ei.value.code == dd.DDST_ESTATE
+    op.close()
+
+
 def test_matfree_full_size_cfg2():
     """The benchmarked workload at full size (1023^2, 32 slabs, FP32 factors):
     the matrix-free product against the dense blocks' product on every
