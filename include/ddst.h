@@ -60,6 +60,8 @@ enum { DDST_FP64 = 0, DDST_FP32 = 1 };
 enum { DDST_TREE_BINARY = 0, DDST_TREE_QUAD = 1 };
 /* Storage type of the compressed low-rank factors. */
 enum { DDST_FACTOR_BF16 = 0, DDST_FACTOR_FP32 = 1, DDST_FACTOR_FP64 = 2 };
+/* Largest number of right-hand sides of ddst_solve_many. */
+enum { DDST_MAX_RHS = 16 };
 /* Which representation ddst_apply uses: the dense transfer blocks, their
  * compressed form, or no blocks at all (matrix-free: sweeps with the stored
  * single-slab factors and the interface blocks, Sections 2.2 and 5.1). */
@@ -176,6 +178,26 @@ int ddst_compress(ddst_op_t *op, const ddst_compress_opts_t *opts, hipStream_t s
 int ddst_solve(const ddst_op_t *op, const double *f, const double *g,
                const ddst_solve_opts_t *opts, double *u_gamma, double *u_vol,
                ddst_stats_t *stats, hipStream_t stream);
+
+/*
+ * ddst_solve_many -- nrhs problems with the same operator and different data
+ * solved together: the case of many right-hand sides for which forming the
+ * transfer blocks pays (Section 2.2, the first reason listed for forming S;
+ * Example 1 reuses S over time steps).  The interface systems of all of them
+ * form one block-diagonal system diag(S, ..., S) solved by one GMRES (one
+ * Krylov polynomial, inner products summed over all right-hand sides), so
+ * each product reads every block of S, and each slab sweep every factor, once
+ * for all of them; the FP64 refinement runs until every right-hand side meets
+ * the stopping rule of ddst_solve.
+ * nrhs: 1..DDST_MAX_RHS.  f: device nrhs * n^dim, right-hand side v at
+ * f + v n^dim (NULL: all 0); g: device nrhs * (n+2)^dim node boxes, likewise
+ * (NULL: all 0); u_vol: device nrhs * n^dim output.  stats: as ddst_solve,
+ * with correction_rel and residual_rel the largest over the right-hand sides.
+ * Errors: as ddst_solve.
+ */
+int ddst_solve_many(const ddst_op_t *op, int32_t nrhs, const double *f, const double *g,
+                    const ddst_solve_opts_t *opts, double *u_vol, ddst_stats_t *stats,
+                    hipStream_t stream);
 
 /*
  * ddst_adjoint -- gradient of a loss L(u) with respect to the cellwise

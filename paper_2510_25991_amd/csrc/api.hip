@@ -495,7 +495,8 @@ struct SolveWs {
   double *dpart;             // dot-product partial sums
   double *nrm;               // norms
   GmresDev gm;               // device GMRES state
-  size_t vol, ifc;
+  size_t vol, ifc;           // one right-hand side's volume / interface length
+  int nr;                    // right-hand sides held (vectors nr * vol, nr * ifc)
 };
 
 void ensure_ws(ddst_op *op, size_t bytes) {
@@ -511,8 +512,9 @@ void ensure_ws(ddst_op *op, size_t bytes) {
   op->ws_bytes = bytes;
 }
 
-SolveWs carve_ws(ddst_op *op, int max_iter) {
-  const size_t vol = (size_t)op->n * op->ld, ifc = (size_t)op->n_ds * op->ld;
+SolveWs carve_ws(ddst_op *op, int max_iter, int nr = 1) {
+  const size_t vol1 = (size_t)op->n * op->ld, ifc1 = (size_t)op->n_ds * op->ld;
+  const size_t vol = vol1 * nr, ifc = ifc1 * nr;
   const int nchunk = std::min(op->ld / kGemvChunk, 64);
   // transposed GEMVs: at most 2 n_slabs jobs (the matrix-free chains)
   const size_t part = (size_t)2 * op->n_slabs * nchunk * op->ld;
@@ -525,7 +527,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   o[8] = cv.take((size_t)(max_iter + 1) * ifc * 8);
   o[9] = cv.take((size_t)(4 * max_iter + 16) * 8);
   o[10] = cv.take(part * 8);
-  o[11] = cv.take(16 * 8);
+  o[11] = cv.take(64 * 8);
   // partial sums: up to max_iter + 2 interface-length dots, or one volume norm
   o[12] = cv.take(std::max(dots_part_len(ifc, max_iter + 2), dots_part_len(vol, 1)) * 8);
   const size_t o_gm = cv.take(GmresDev::doubles(max_iter) * 8);
@@ -542,8 +544,9 @@ SolveWs carve_ws(ddst_op *op, int max_iter) {
   w.gm.carve(at(o_gm), max_iter);
   w.Zf = at(o_zf); w.Zb = at(o_zb);
   w.mfx = at(o_mx); w.mfv = at(o_mv); w.mff = at(o_mf);
-  w.vol = vol;
-  w.ifc = ifc;
+  w.vol = vol1;
+  w.ifc = ifc1;
+  w.nr = nr;
   return w;
 }
 
@@ -601,17 +604,21 @@ void make_slab_tables(const ddst_op *op, const void *G, const double *R, double 
   }
 }
 
+// nr right-hand sides: volume v of each is v * vs after the tables' volumes
+// (transposed sweeps take one).
 template <typename T>
 void run_slab_solve(const ddst_op *op, const SlabTables &t, bool transpose, double *part,
-                    hipStream_t s) {
+                    hipStream_t s, int nr = 1, size_t vs = 0) {
   const int m = op->m;
-  for (int k = 1; k <= m - 1; ++k)
-    launch_gemv<T>(t.tab.at<GemvJob>(t.fwd[k]), t.nfwd[k], op->ld, op->M, transpose, 1.0, part,
-                   s);
+  auto go = [&](size_t off, int n) {
+    if (transpose)
+      launch_gemv<T>(t.tab.at<GemvJob>(off), n, op->ld, op->M, 1, 1.0, part, s);
+    else
+      launch_gemv_many<T>(t.tab.at<GemvJob>(off), n, op->ld, op->M, 1.0, nr, vs, part, s);
+  };
+  for (int k = 1; k <= m - 1; ++k) go(t.fwd[k], t.nfwd[k]);
   for (int k = m - 1; k >= 1; --k)
-    if (t.nbwd[k] > 0)
-      launch_gemv<T>(t.tab.at<GemvJob>(t.bwd[k]), t.nbwd[k], op->ld, op->M, transpose, 1.0,
-                     part, s);
+    if (t.nbwd[k] > 0) go(t.bwd[k], t.nbwd[k]);
 }
 
 // Interface operator jobs: y = S x (or S^T x) for a fixed pair (x, y).
@@ -754,13 +761,19 @@ void run_matfree(const ddst_op *op, const MatfreeTables &t, bool trans, const Ma
 // the observed reduction rate predicts the tolerance), so the GPU is fed
 // several iterations ahead; iterations past the stopping point are computed
 // and discarded (they touch only later columns).
+// With several right-hand sides (w.nr > 1) the basis vectors are their
+// interface vectors stacked, i.e. GMRES on the block-diagonal system
+// diag(S, ..., S) (one Krylov polynomial for all, inner products summed
+// over all: the "global" GMRES of several right-hand sides), so that each
+// product reads every block of S once for all of them.
 // Returns the iterations used.
 constexpr int kGmresCheck = 8;
 
 template <typename T>
 int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
           int max_iter, bool trans, int form, double *relres, hipStream_t s) {
-  const size_t len = w.ifc;
+  const int nr = w.nr;
+  const size_t len = w.ifc * nr;
   double *hh = op->hbuf_host;
   launch_norm(rhs, len, w.nrm, w.dpart, s);
   HIPCHK(hipMemcpyAsync(hh, w.nrm, 8, hipMemcpyDeviceToHost, s));
@@ -777,13 +790,17 @@ int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, 
     for (int k = 0; k < max_iter; ++k)
       offs[k] = tab.add(interface_jobs(op, w.V + (size_t)k * len, w.W, trans));
   tab.upload(s);
-  MatfreeTables mf;
-  const MatfreeBufs mb{w.mfx, w.mfv, w.mff, w.Zf, w.Zb, w.W};
-  if (form == DDST_APPLY_MATFREE) {
-    make_matfree_tables(op, G, trans, mb, mf);
-    mf.tab.upload(s);
-    launch_fill(w.Zf, 0.0, w.vol, s);
-    launch_fill(w.Zb, 0.0, w.vol, s);
+  std::vector<MatfreeTables> mf(form == DDST_APPLY_MATFREE ? nr : 0);
+  std::vector<MatfreeBufs> mb;
+  for (int v = 0; v < (int)mf.size(); ++v) {
+    const size_t oi = (size_t)v * w.ifc, ov = (size_t)v * w.vol;
+    mb.push_back({w.mfx + oi, w.mfv + oi, w.mff + oi, w.Zf + ov, w.Zb + ov, w.W + oi});
+    make_matfree_tables(op, G, trans, mb[v], mf[v]);
+    mf[v].tab.upload(s);
+  }
+  if (!mf.empty()) {
+    launch_fill(w.Zf, 0.0, w.vol * nr, s);
+    launch_fill(w.Zb, 0.0, w.vol * nr, s);
   }
   GmresDev d = w.gm;
   int used = 0;
@@ -794,14 +811,19 @@ int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, 
   for (int k = 0; k < max_iter && used == 0; ++k) {
     const double *vk = w.V + (size_t)k * len;
     if (form == DDST_APPLY_HODLR) {
-      int st = hodlr_apply_jobs(op, vk, w.W, trans ? 1 : 0, s);
-      if (st) throw HipError("compressed apply failed");
+      for (int v = 0; v < nr; ++v) {
+        const size_t oi = (size_t)v * w.ifc;
+        int st = hodlr_apply_jobs(op, vk + oi, w.W + oi, trans ? 1 : 0, s);
+        if (st) throw HipError("compressed apply failed");
+      }
     } else if (form == DDST_APPLY_MATFREE) {
       HIPCHK(hipMemcpyAsync(w.mfx, vk, len * 8, hipMemcpyDeviceToDevice, s));
-      run_matfree<T>(op, mf, trans, mb, w.part, s);
+      for (int v = 0; v < nr; ++v) run_matfree<T>(op, mf[v], trans, mb[v], w.part, s);
+    } else if (trans) {
+      launch_gemv<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, 1, -1.0, w.part, s);
     } else {
-      launch_gemv<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, trans ? 1 : 0, -1.0,
-                     w.part, s);
+      launch_gemv_many<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, -1.0, nr, w.ifc,
+                          w.part, s);
     }
     launch_arnoldi_step(w.V, len, k, w.W, len, w.hd, w.V + (size_t)(k + 1) * len, w.dpart, d,
                         beta, s);
@@ -841,14 +863,6 @@ int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, 
   return used;
 }
 
-double dev_norm(ddst_op *op, const double *v, size_t len, double *scratch, double *part,
-                hipStream_t s) {
-  launch_norm(v, len, scratch, part, s);
-  HIPCHK(hipMemcpyAsync(op->hbuf_host, scratch, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return op->hbuf_host[0];
-}
-
 // Pinned host staging for GMRES scalars: 2 (max_iter + 1) + 1 doubles per
 // Arnoldi step and max_iter coefficients at the end.
 void ensure_host(ddst_op *op, int max_iter) {
@@ -864,25 +878,32 @@ void ensure_host(ddst_op *op, int max_iter) {
 }
 
 // One DD solve of A d = r (transpose: A^T d = r) with zero boundary data,
-// writing the correction volume into w.D; returns GMRES iterations.
+// writing the correction volume into w.D (for each of the w.nr right-hand
+// sides; the transposed solve takes one); returns GMRES iterations.
 template <typename T>
 int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const double *tol_inner,
                   int max_iter, int form, double *relres, SlabTables &loads,
                   SlabTables &recon, hipStream_t s) {
+  const int nr = w.nr;
   // z = A_II^{-1} r_I
-  run_slab_solve<T>(op, loads, trans, w.part, s);
+  run_slab_solve<T>(op, loads, trans, w.part, s, nr, w.vol);
   // f_J = r_J - A_JI z
-  if (!trans)
-    launch_interface_rhs(w.R, w.Z, w.Z, op->Em, op->Ep, op->n_ds, op->m, op->ld, 0, 0, w.fJ, s);
-  else
-    launch_interface_rhs(w.R, w.Z, w.Z, op->Ep, op->Em, op->n_ds, op->m, op->ld, -1, +1, w.fJ, s);
+  for (int v = 0; v < nr; ++v) {
+    const size_t ov = (size_t)v * w.vol, oi = (size_t)v * w.ifc;
+    if (!trans)
+      launch_interface_rhs(w.R + ov, w.Z + ov, w.Z + ov, op->Em, op->Ep, op->n_ds, op->m, op->ld,
+                           0, 0, w.fJ + oi, s);
+    else
+      launch_interface_rhs(w.R + ov, w.Z + ov, w.Z + ov, op->Ep, op->Em, op->n_ds, op->m, op->ld,
+                           -1, +1, w.fJ + oi, s);
+  }
   int it;
   if (!trans) {
     // hhat = Sigma^{-1} f_J ; S d_J = hhat
     JobTable tb;
     const size_t o = tb.add(sinv_jobs(op, w.fJ, w.hh));
     tb.upload(s);
-    launch_gemv<T>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 0, 1.0, w.part, s);
+    launch_gemv_many<T>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 1.0, nr, w.ifc, w.part, s);
     it = gmres<T>(op, w, G, w.hh, w.xg, *tol_inner, max_iter, false, form, relres, s);
   } else {
     // S^T mu = f_J ; d_J = Sigma^{-T} mu
@@ -894,8 +915,10 @@ int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const doub
     HIPCHK(hipStreamSynchronize(s));
   }
   // traces into the correction volume, then the slab interiors
-  launch_copy_planes(w.xg, 1, 0, w.D, op->m, op->m - 1, op->n_ds, op->ld, op->M, s);
-  run_slab_solve<T>(op, recon, trans, w.part, s);
+  for (int v = 0; v < nr; ++v)
+    launch_copy_planes(w.xg + (size_t)v * w.ifc, 1, 0, w.D + (size_t)v * w.vol, op->m, op->m - 1,
+                       op->n_ds, op->ld, op->M, s);
+  run_slab_solve<T>(op, recon, trans, w.part, s, nr, w.vol);
   return it;
 }
 
@@ -907,28 +930,47 @@ inline int apply_form(const ddst_solve_opts_t &o) {
 
 struct RefineOut {
   int outer = 0, gm_total = 0, gm_last = 0, converged = 0;
-  double relres = 0, corr = 0, resrel = 0;
+  double relres = 0, corr = 0, resrel = 0;  // the largest over right-hand sides
 };
 
-// FP64 refinement loop shared by the solve (A) and the adjoint (A^T).
+// Norms of `count` vectors of length len, stride apart, into host out[]
+// (one read-back).
+void dev_norms(ddst_op *op, SolveWs &w, const double *v, size_t stride, size_t len, int count,
+               double *out, hipStream_t s) {
+  for (int i = 0; i < count; ++i) launch_norm(v + (size_t)i * stride, len, w.nrm + i, w.dpart, s);
+  HIPCHK(hipMemcpyAsync(op->hbuf_host, w.nrm, (size_t)count * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(out, op->hbuf_host, (size_t)count * 8);
+}
+
+// FP64 refinement loop shared by the solve (A) and the adjoint (A^T), for
+// the w.nr right-hand sides f + v N, g + v (n+2)^dim; passes run until every
+// one meets the stopping rule.
 template <typename T>
 int refine(ddst_op *op, const void *G, const double *f, const double *g, bool trans,
            const ddst_solve_opts_t &o, SolveWs &w, RefineOut &ro, hipStream_t s) {
+  const int nr = w.nr;
+  const size_t box = (size_t)std::pow((double)(op->n + 2), op->dim) + 0.5;
   SlabTables loads, recon;
   make_slab_tables(op, G, w.R, w.Z, false, trans, loads);
   make_slab_tables(op, G, w.R, w.D, true, trans, recon);
   loads.tab.upload(s);
   recon.tab.upload(s);
-  launch_fill(w.X, 0.0, w.vol, s);
-  launch_fill(w.Z, 0.0, w.vol, s);
-  launch_fill(w.R, 0.0, w.vol, s);  // padding of R must stay zero
-  double prev = 0.0, r0 = 0.0;
+  launch_fill(w.X, 0.0, w.vol * nr, s);
+  launch_fill(w.Z, 0.0, w.vol * nr, s);
+  launch_fill(w.R, 0.0, w.vol * nr, s);  // padding of R must stay zero
+  auto residuals = [&]() {
+    for (int v = 0; v < nr; ++v)
+      launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f ? f + (size_t)v * op->N : nullptr,
+                      (trans || !g) ? nullptr : g + (size_t)v * box, w.X + (size_t)v * w.vol,
+                      w.R + (size_t)v * w.vol, trans ? 1 : 0, s);
+  };
+  std::vector<double> prev(nr, 0.0), r0(nr, 0.0), dn(nr), xn(nr), rf(nr);
   int status = DDST_OK;
   for (int outer = 0; outer < o.max_outer; ++outer) {
-    launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f, trans ? nullptr : g, w.X, w.R,
-                    trans ? 1 : 0, s);
-    if (outer == 0) r0 = dev_norm(op, w.R, w.vol, w.nrm, w.dpart, s);
-    launch_fill(w.D, 0.0, w.vol, s);
+    residuals();
+    if (outer == 0) dev_norms(op, w, w.R, w.vol, w.vol, nr, r0.data(), s);
+    launch_fill(w.D, 0.0, w.vol * nr, s);
     double rr = 0;
     const int it = dd_correction<T>(op, w, G, trans, &o.inner_tol, o.max_iter, apply_form(o),
                                     &rr, loads, recon, s);
@@ -936,27 +978,31 @@ int refine(ddst_op *op, const void *G, const double *f, const double *g, bool tr
     ro.gm_last = it;
     ro.relres = rr;
     if (rr > o.inner_tol) status = DDST_ENOTCONV;
-    launch_axpy(w.X, w.D, 1.0, w.vol, s);
-    const double dn = dev_norm(op, w.D, w.vol, w.nrm, w.dpart, s);
-    const double xn = dev_norm(op, w.X, w.vol, w.nrm + 1, w.dpart, s);
+    launch_axpy(w.X, w.D, 1.0, w.vol * nr, s);
+    dev_norms(op, w, w.D, w.vol, w.vol, nr, dn.data(), s);
+    dev_norms(op, w, w.X, w.vol, w.vol, nr, xn.data(), s);
     ro.outer = outer + 1;
-    ro.corr = (xn > 0) ? dn / xn : 0.0;
-    bool done = ro.corr <= o.tol;
-    if (outer >= 1 && prev > 0 && dn < prev) {
-      const double rho = dn / prev;
-      if (rho * ro.corr <= o.tol) done = true;
+    ro.corr = 0.0;
+    bool all_done = true;
+    for (int v = 0; v < nr; ++v) {
+      const double corr = (xn[v] > 0) ? dn[v] / xn[v] : 0.0;
+      ro.corr = std::max(ro.corr, corr);
+      bool done = corr <= o.tol;
+      if (outer >= 1 && prev[v] > 0 && dn[v] < prev[v] && (dn[v] / prev[v]) * corr <= o.tol)
+        done = true;
+      if (xn[v] == 0.0) done = true;
+      prev[v] = dn[v];
+      all_done = all_done && done;
     }
-    prev = dn;
-    if (xn == 0.0) done = true;
-    if (done) {
+    if (all_done) {
       ro.converged = 1;
       break;
     }
   }
-  launch_residual(op->coef, op->dim, op->n, op->M, op->ld, f, trans ? nullptr : g, w.X, w.R,
-                  trans ? 1 : 0, s);
-  const double rf = dev_norm(op, w.R, w.vol, w.nrm, w.dpart, s);
-  ro.resrel = (r0 > 0) ? rf / r0 : 0.0;
+  residuals();
+  dev_norms(op, w, w.R, w.vol, w.vol, nr, rf.data(), s);
+  ro.resrel = 0.0;
+  for (int v = 0; v < nr; ++v) ro.resrel = std::max(ro.resrel, r0[v] > 0 ? rf[v] / r0[v] : 0.0);
   if (!ro.converged) status = DDST_ENOTCONV;
   return status;
 }
@@ -988,7 +1034,7 @@ int check_solve_opts(const ddst_solve_opts_t &o) {
 
 template <typename T>
 int solve_impl(ddst_op *op, const double *f, const double *g, const ddst_solve_opts_t &o,
-               double *u_gamma, double *u_vol, ddst_stats_t *st, hipStream_t s) {
+               double *u_gamma, double *u_vol, ddst_stats_t *st, hipStream_t s, int nr = 1) {
   if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
   if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
   if (apply_form(o) == DDST_APPLY_DENSE && !op->S)
@@ -998,11 +1044,13 @@ int solve_impl(ddst_op *op, const double *f, const double *g, const ddst_solve_o
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, s));
-  SolveWs w = carve_ws(op, o.max_iter);
+  SolveWs w = carve_ws(op, o.max_iter, nr);
   RefineOut ro;
   const int status = refine<T>(op, op->G, f, g, false, o, w, ro, s);
-  if (u_vol) launch_unpad(w.X, u_vol, op->n, op->M, op->ld, s);
-  if (u_gamma) {
+  if (u_vol)
+    for (int v = 0; v < nr; ++v)
+      launch_unpad(w.X + (size_t)v * w.vol, u_vol + (size_t)v * op->N, op->n, op->M, op->ld, s);
+  if (u_gamma && nr == 1) {
     launch_copy_planes(w.X, op->m, op->m - 1, w.xg, 1, 0, op->n_ds, op->ld, op->M, s);
     launch_unpad(w.xg, u_gamma, op->n_ds, op->M, op->ld, s);
   }
@@ -1113,6 +1161,24 @@ int ddst_solve(const ddst_op_t *cop, const double *f, const double *g,
   return guarded([&]() -> int {
     return op->prec == DDST_FP32 ? solve_impl<float>(op, f, g, o, u_gamma, u_vol, stats, stream)
                                  : solve_impl<double>(op, f, g, o, u_gamma, u_vol, stats, stream);
+  });
+}
+
+int ddst_solve_many(const ddst_op_t *cop, int32_t nrhs, const double *f, const double *g,
+                    const ddst_solve_opts_t *opts, double *u_vol, ddst_stats_t *stats,
+                    hipStream_t stream) {
+  g_err.clear();
+  if (!cop) return fail(DDST_EINVAL, "op is NULL");
+  if (nrhs < 1 || nrhs > DDST_MAX_RHS)
+    return fail(DDST_EINVAL, "nrhs in [1, " + std::to_string(DDST_MAX_RHS) + "]");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  ddst_solve_opts_t o = opts ? *opts : solve_defaults(op);
+  int st = check_solve_opts(o);
+  if (st) return st;
+  return guarded([&]() -> int {
+    return op->prec == DDST_FP32
+               ? solve_impl<float>(op, f, g, o, nullptr, u_vol, stats, stream, nrhs)
+               : solve_impl<double>(op, f, g, o, nullptr, u_vol, stats, stream, nrhs);
   });
 }
 

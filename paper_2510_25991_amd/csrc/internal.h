@@ -176,6 +176,11 @@ void launch_unpad(const double *src, double *dst, int rows, int M, int ld, hipSt
 template <typename T>
 void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, double alpha,
                  double *partial, hipStream_t s);
+// The same non-transposed products for nv right-hand sides, vector v of every
+// job shifted by v * vs (matrices and couplings shared); nv <= 1 is launch_gemv.
+template <typename T>
+void launch_gemv_many(const GemvJob *jobs, int njobs, int ld, int M, double alpha, int nv,
+                      size_t vs, double *partial, hipStream_t s);
 // Interface right-hand sides from the planes next to each interface:
 //   out[j] = v[pl] - Ea[pl + a_off] .* Zl[pl - 1] - Eb[pl + b_off] .* Zr[pl + 1],
 // pl = j m the interface plane (1-based), v = vol (0 if vol is NULL).

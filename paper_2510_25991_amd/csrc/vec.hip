@@ -303,6 +303,80 @@ __global__ __launch_bounds__(256) void k_gemv_n_f64(const GemvJob *__restrict__ 
   gemv_n_body<double>(jobs, ld, alpha);
 }
 
+// Several right-hand sides per launch: vector v of a job is the job's vector
+// shifted by v * vs (x1, x2, x3, w and out; the matrices and e are shared),
+// grid z picks a group of NV vectors.  Each chunk of a matrix's rows is
+// loaded into registers once and multiplied with every vector of the group
+// (all staged in LDS together), so the matrix is read from HBM once per group
+// instead of once per vector.  Two rows per wavefront: the converted matrix
+// entries stay live across the vectors of the group.
+constexpr int kGemvNvRows = 2;
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_gemv_nv(const GemvJob *__restrict__ jobs, int ld,
+                                                 double alpha, int nv, size_t vs) {
+  constexpr int R = kGemvNvRows;
+  __shared__ double xs[NV][kGemvCh];
+  const GemvJob J = jobs[blockIdx.y];
+  const T *G = static_cast<const T *>(J.G);
+  const T *G2 = static_cast<const T *>(J.G2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.x * (4 * R) + wave * R;
+  const size_t ro = (size_t)row0 * ld;
+  const int v0 = blockIdx.z * NV;
+  const int nvg = min(NV, nv - v0);
+  if (!G && !G2) {  // no matrix term: out = w
+    if (lane < R)
+      for (int v = 0; v < nvg; ++v) {
+        const size_t o = (size_t)(v0 + v) * vs + row0 + lane;
+        gp(J.out)[o] = J.w ? gp(J.w)[o] : 0.0;
+      }
+    return;
+  }
+  double acc[NV][R];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[v][q] = 0.0;
+  T g[R][kGemvCh / 256][4];
+  for (int c0 = 0; c0 < ld; c0 += kGemvCh) {
+    const int cn = min(kGemvCh, ld - c0);
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const T *Mt = pass == 0 ? G : G2;
+      if (!Mt) continue;
+      gemv_rows_load<T, R>(Mt, ro, ld, c0, cn, lane, g);
+      __syncthreads();  // the previous x is no longer read
+      const double *xa = pass == 0 ? J.x1 : J.x3;
+      const double *xe = pass == 0 ? J.e : nullptr;
+#pragma unroll 1
+      for (int idx = threadIdx.x; idx < NV * kGemvCh; idx += 256) {
+        const int v = idx / kGemvCh, c = idx % kGemvCh;
+        double x = 0.0;
+        if (c < cn && v < nvg) {
+          const size_t o = (size_t)(v0 + v) * vs + c0 + c;
+          x = xa ? gp(xa)[o] : 0.0;
+          if (xe) x -= gp(xe)[c0 + c] * gp(J.x2)[o];
+        }
+        xs[v][c] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) gemv_rows_fma<T, R>(g, xs[v], lane, acc[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double sum = wave_sum(acc[v][q]);
+      if (lane == 0 && v < nvg) {
+        const size_t o = (size_t)(v0 + v) * vs + row0 + q;
+        gp(J.out)[o] = (J.w ? gp(J.w)[o] : 0.0) + alpha * sum;
+      }
+    }
+  }
+}
+
 // Transposed product, partial sums over row chunks:
 // part[(job*nchunk + chunk)*ld + c] = sum_{r in chunk} G[r,c] xe[r] + G2[r,c] x3[r]
 template <typename T>
@@ -701,6 +775,27 @@ void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, d
   // matrix bytes dominate: one or two M x M matrices per job (upper bound 1)
   prof_close(ps, KK_GEMV, (double)njobs * M * M * sizeof(T));
 }
+// vectors per group of the multi-vector GEMV (accumulators: NV x 4 doubles)
+template <typename T> constexpr int gemv_nv() { return 8; }
+
+template <typename T>
+void launch_gemv_many(const GemvJob *jobs, int njobs, int ld, int M, double alpha, int nv,
+                      size_t vs, double *partial, hipStream_t s) {
+  if (nv <= 1) {
+    launch_gemv<T>(jobs, njobs, ld, M, 0, alpha, partial, s);
+    return;
+  }
+  if (njobs <= 0) return;
+  constexpr int NV = gemv_nv<T>();
+  const ProfSpan ps = prof_open(KK_GEMV);
+  hipExtLaunchKernelGGL(k_gemv_nv<T, NV>, dim3(ld / (4 * kGemvNvRows), njobs, (nv + NV - 1) / NV),
+                        dim3(256), 0, s, ps.a, ps.b, 0, jobs, ld, alpha, nv, vs);
+  prof_close(ps, KK_GEMV, (double)njobs * ((nv + NV - 1) / NV) * M * M * sizeof(T));
+}
+template void launch_gemv_many<float>(const GemvJob *, int, int, int, double, int, size_t,
+                                      double *, hipStream_t);
+template void launch_gemv_many<double>(const GemvJob *, int, int, int, double, int, size_t,
+                                       double *, hipStream_t);
 template void launch_gemv<float>(const GemvJob *, int, int, int, int, double, double *,
                                  hipStream_t);
 template void launch_gemv<double>(const GemvJob *, int, int, int, int, double, double *,

@@ -23,6 +23,7 @@ FP64, FP32 = 0, 1
 TREE_BINARY, TREE_QUAD = 0, 1
 FACTOR_BF16, FACTOR_FP32, FACTOR_FP64 = 0, 1, 2
 APPLY_DENSE, APPLY_HODLR, APPLY_MATFREE = 0, 1, 2
+MAX_RHS = 16
 _APPLY_FORMS = {"dense": APPLY_DENSE, "hodlr": APPLY_HODLR, "matfree": APPLY_MATFREE}
 
 
@@ -70,7 +71,7 @@ class StatsC(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_adjoint",
+EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_solve_many", "ddst_adjoint",
            "ddst_release_factors", "ddst_destroy", "ddst_last_error", "ddst_op_info",
            "ddst_get_transfer", "ddst_apply", "ddst_loads", "ddst_get_factor",
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
@@ -93,6 +94,7 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_build_transfer.argtypes = [P(ProblemC), P(BuildOptsC), vp, P(vp)]
     L.ddst_compress.argtypes = [vp, P(CompressOptsC), vp]
     L.ddst_solve.argtypes = [vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
+    L.ddst_solve_many.argtypes = [vp, i32, vp, vp, P(SolveOptsC), vp, P(StatsC), vp]
     L.ddst_adjoint.argtypes = [vp, vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
     L.ddst_release_factors.argtypes = [vp]
     L.ddst_destroy.argtypes = [vp]
@@ -236,6 +238,24 @@ class Operator:
         return (u.view((self.n,) * self.dim),
                 None if ug is None else ug.view(self.n_ds, self.M), d)
 
+    def solve_many(self, F, G=None, opts: Optional[SolveOptions] = None, allow_notconv=False):
+        """Solves for nrhs right-hand sides at once: F (nrhs, n, ...) loads,
+        G (nrhs, n+2, ...) boundary boxes or None.  Returns (U (nrhs, n, ...),
+        stats dict)."""
+        F = _dev(F)
+        G = _dev(G)
+        nrhs = int(F.shape[0])
+        N = self.n ** self.dim
+        U = torch.empty(nrhs * N, dtype=torch.float64, device="cuda")
+        st = StatsC()
+        o = self._solve_opts(opts)
+        code = load_library().ddst_solve_many(self._h, nrhs, _ptr(F), _ptr(G), ctypes.byref(o),
+                                              _ptr(U), ctypes.byref(st), _stream())
+        _check(code, allow_notconv)
+        d = st.as_dict()
+        d["status"] = code
+        return U.view((nrhs,) + (self.n,) * self.dim), d
+
     def adjoint(self, u, gbar, g=None, opts: Optional[SolveOptions] = None, want_lambda=False,
                 allow_notconv=False):
         """dL/dkappa on the (n+1)^dim cells for dL/du = gbar."""
@@ -288,7 +308,7 @@ class Operator:
         _check(load_library().ddst_loads(self._h, _ptr(f), _ptr(g), _ptr(out), _stream()))
         return out.view(self.n_ds, self.M)
 
-    def compress(self, tol=1e-8, leaf=128, oversample=10, max_rank=128, tree=None,
+    def compress(self, tol=1e-8, leaf=128, oversample=10, max_rank=112, tree=None,
                  factor_dtype="bf16", seed=0):
         tree = (TREE_BINARY if self.dim == 2 else TREE_QUAD) if tree is None else tree
         fd = {"bf16": FACTOR_BF16, "fp32": FACTOR_FP32, "fp64": FACTOR_FP64}[factor_dtype]
