@@ -305,74 +305,88 @@ __global__ __launch_bounds__(256) void k_gemv_n_f64(const GemvJob *__restrict__ 
 
 // Several right-hand sides per launch: vector v of a job is the job's vector
 // shifted by v * vs (x1, x2, x3, w and out; the matrices and e are shared),
-// grid z picks a group of NV vectors.  Each chunk of a matrix's rows is
-// loaded into registers once and multiplied with every vector of the group
-// (all staged in LDS together), so the matrix is read from HBM once per group
-// instead of once per vector.  Two rows per wavefront: the converted matrix
-// entries stay live across the vectors of the group.
-constexpr int kGemvNvRows = 2;
+// grid z picks a group of NV vectors.  A work-group owns kGemvNvBlk row
+// blocks of 16 rows (4 per wavefront) and stages each column chunk of all NV
+// vectors in LDS once for all of them; every chunk of a matrix row is loaded
+// into registers once and multiplied with the NV vectors, so the matrix is
+// read from HBM once per group instead of once per vector.  Row sums are
+// collected in LDS across chunks.
+constexpr int kGemvNvRows = 4;
+constexpr int kGemvNvBlk = 4;
 template <typename T, int NV>
 __global__ __launch_bounds__(256) void k_gemv_nv(const GemvJob *__restrict__ jobs, int ld,
                                                  double alpha, int nv, size_t vs) {
-  constexpr int R = kGemvNvRows;
+  constexpr int R = kGemvNvRows, RB = 4 * R * kGemvNvBlk;
   __shared__ double xs[NV][kGemvCh];
+  __shared__ double sums[RB][NV];
   const GemvJob J = jobs[blockIdx.y];
   const T *G = static_cast<const T *>(J.G);
   const T *G2 = static_cast<const T *>(J.G2);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row0 = blockIdx.x * (4 * R) + wave * R;
-  const size_t ro = (size_t)row0 * ld;
+  const int rowb = blockIdx.x * RB;  // first row of the work-group
   const int v0 = blockIdx.z * NV;
   const int nvg = min(NV, nv - v0);
-  if (!G && !G2) {  // no matrix term: out = w
-    if (lane < R)
-      for (int v = 0; v < nvg; ++v) {
-        const size_t o = (size_t)(v0 + v) * vs + row0 + lane;
-        gp(J.out)[o] = J.w ? gp(J.w)[o] : 0.0;
-      }
-    return;
-  }
-  double acc[NV][R];
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[v][q] = 0.0;
-  T g[R][kGemvCh / 256][4];
+  for (int e = threadIdx.x; e < RB * NV; e += 256) (&sums[0][0])[e] = 0.0;
   for (int c0 = 0; c0 < ld; c0 += kGemvCh) {
     const int cn = min(kGemvCh, ld - c0);
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
       const T *Mt = pass == 0 ? G : G2;
       if (!Mt) continue;
-      gemv_rows_load<T, R>(Mt, ro, ld, c0, cn, lane, g);
-      __syncthreads();  // the previous x is no longer read
       const double *xa = pass == 0 ? J.x1 : J.x3;
       const double *xe = pass == 0 ? J.e : nullptr;
+      __syncthreads();  // the previous x is no longer read
+      // per column: the coupling once, then every vector's entries (all of
+      // a column's loads in flight together)
 #pragma unroll 1
-      for (int idx = threadIdx.x; idx < NV * kGemvCh; idx += 256) {
-        const int v = idx / kGemvCh, c = idx % kGemvCh;
-        double x = 0.0;
-        if (c < cn && v < nvg) {
+      for (int c = threadIdx.x; c < kGemvCh; c += 256) {
+        const bool in = c < cn;
+        const double ec = (in && xe) ? gp(xe)[c0 + c] : 0.0;
+        double xv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
           const size_t o = (size_t)(v0 + v) * vs + c0 + c;
-          x = xa ? gp(xa)[o] : 0.0;
-          if (xe) x -= gp(xe)[c0 + c] * gp(J.x2)[o];
+          xv[v] = 0.0;
+          if (in && v < nvg) {
+            xv[v] = xa ? gp(xa)[o] : 0.0;
+            if (xe) xv[v] -= ec * gp(J.x2)[o];
+          }
         }
-        xs[v][c] = x;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xs[v][c] = xv[v];
       }
       __syncthreads();
+#pragma unroll 1
+      for (int b = 0; b < kGemvNvBlk; ++b) {
+        // re-read x from LDS per row block: keeping all of it in registers
+        // across the blocks would take every register
+        asm volatile("" ::: "memory");
+        const int lr = b * 4 * R + wave * R;  // first local row of this wavefront
+        T g[R][kGemvCh / 256][4];
+        gemv_rows_load<T, R>(Mt, (size_t)(rowb + lr) * ld, ld, c0, cn, lane, g);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) gemv_rows_fma<T, R>(g, xs[v], lane, acc[v]);
+        for (int v = 0; v < NV; ++v) {
+          if (v >= nvg) break;  // uniform over the work-group
+          double acc[R];
+#pragma unroll
+          for (int q = 0; q < R; ++q) acc[q] = 0.0;
+          gemv_rows_fma<T, R>(g, xs[v], lane, acc);
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            const double sm = wave_sum(acc[q]);
+            if (lane == 0) sums[lr + q][v] += sm;  // rows of this wavefront only
+          }
+        }
+      }
     }
   }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const double sum = wave_sum(acc[v][q]);
-      if (lane == 0 && v < nvg) {
-        const size_t o = (size_t)(v0 + v) * vs + row0 + q;
-        gp(J.out)[o] = (J.w ? gp(J.w)[o] : 0.0) + alpha * sum;
-      }
+  __syncthreads();
+  for (int e = threadIdx.x; e < RB * NV; e += 256) {
+    const int r = e / NV, v = e % NV;
+    if (v < nvg) {
+      const size_t o = (size_t)(v0 + v) * vs + rowb + r;
+      const double base = J.w ? gp(J.w)[o] : 0.0;
+      gp(J.out)[o] = (G || G2) ? base + alpha * sums[r][v] : base;
     }
   }
 }
@@ -788,8 +802,9 @@ void launch_gemv_many(const GemvJob *jobs, int njobs, int ld, int M, double alph
   if (njobs <= 0) return;
   constexpr int NV = gemv_nv<T>();
   const ProfSpan ps = prof_open(KK_GEMV);
-  hipExtLaunchKernelGGL(k_gemv_nv<T, NV>, dim3(ld / (4 * kGemvNvRows), njobs, (nv + NV - 1) / NV),
-                        dim3(256), 0, s, ps.a, ps.b, 0, jobs, ld, alpha, nv, vs);
+  constexpr int RB = 4 * kGemvNvRows * kGemvNvBlk;  // rows per work-group (ld % 64 == 0)
+  hipExtLaunchKernelGGL(k_gemv_nv<T, NV>, dim3(ld / RB, njobs, (nv + NV - 1) / NV), dim3(256), 0,
+                        s, ps.a, ps.b, 0, jobs, ld, alpha, nv, vs);
   prof_close(ps, KK_GEMV, (double)njobs * ((nv + NV - 1) / NV) * M * M * sizeof(T));
 }
 template void launch_gemv_many<float>(const GemvJob *, int, int, int, double, int, size_t,
