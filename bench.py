@@ -13,7 +13,8 @@ GMRES inside FP64 iterative refinement, to a predicted relative error of
 FP64 plain path (FP64 build, same solver) is timed beside it, and the
 adjoint of a sensor loss (factors recomputed) is timed once, and so is the
 matrix-free alternative (S applied by sweeps with the stored slab factors,
-set-up without the transfer blocks) beside the dense-block form.
+set-up without the transfer blocks) beside the dense-block form, and one
+solve of 8 right-hand sides together beside single solves.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -45,6 +46,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-matfree", action="store_true",
                     help="skip the matrix-free comparison (untimed, after the timed steps)")
+    ap.add_argument("--no-many", action="store_true",
+                    help="skip the many-right-hand-side solve (untimed, after the timed steps)")
     ap.add_argument("--n", type=int, default=None, help="reduced grid (debug only)")
     ap.add_argument("--slabs", type=int, default=None)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -267,6 +270,27 @@ def matfree_leg(dd, torch, dev, prob, opts):
             "converged": {"dense": bool(sd["status"] == 0), "matfree": bool(sm["status"] == 0)}}
 
 
+def many_leg(dd, torch, dev, prob, opts, nrhs=8):
+    """nrhs seeded N(0,1) loads on the benchmark operator solved together
+    (ddst_solve_many) beside one solve of the first alone (library solve
+    times, the solve's own HIP events)."""
+    op = dd.Operator(2, dev["n"], dev["n_slabs"], kappa=dev["kappa"], bvec=dev["bvec"],
+                     precision="fp32")
+    g = torch.Generator(device="cuda").manual_seed(7)
+    F = torch.randn(nrhs, prob.n, prob.n, dtype=torch.float64, device="cuda", generator=g)
+    op.solve(F[0], opts=opts, want_gamma=False, allow_notconv=True)
+    _, _, s1 = op.solve(F[0], opts=opts, want_gamma=False, allow_notconv=True)
+    op.solve_many(F, opts=opts, allow_notconv=True)
+    _, sm = op.solve_many(F, opts=opts, allow_notconv=True)
+    op.close()
+    return {"nrhs": nrhs, "solve_ms_together": round(sm["t_solve_ms"], 2),
+            "solve_ms_per_rhs": round(sm["t_solve_ms"] / nrhs, 2),
+            "solve_ms_single": round(s1["t_solve_ms"], 2),
+            "throughput_gain": round(s1["t_solve_ms"] * nrhs / sm["t_solve_ms"], 2),
+            "gmres_iters": {"together": sm["gmres_iters"], "single": s1["gmres_iters"]},
+            "converged": bool(sm["status"] == 0)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -337,6 +361,10 @@ def main():
     if not args.no_matfree:
         print("[bench] matrix-free comparison", file=sys.stderr, flush=True)
         mfree = matfree_leg(dd, torch, dev, prob, opts)
+    many = None
+    if not args.no_many:
+        print("[bench] many right-hand sides", file=sys.stderr, flush=True)
+        many = many_leg(dd, torch, dev, prob, opts)
     cpu, errs = (None, {})
     if not args.no_cpu:
         print("[bench] CPU oracle leg", file=sys.stderr, flush=True)
@@ -369,6 +397,7 @@ def main():
         "fp64_plain": out_fp64,
         "adjoint": adj,
         "matrix_free": mfree,
+        "many_rhs": many,
         # every class timed over one extra step (untimed)
         "kernel_profile_per_step": {k: {"launches": v[0], "ms": round(v[1], 3)}
                                     for k, v in mix.items()},
