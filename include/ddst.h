@@ -260,6 +260,28 @@ int ddst_loads(const ddst_op_t *op, const double *f, const double *g, double *hh
                hipStream_t stream);
 
 /*
+ * Diagnostics of the equilibrium system (the iteration counts and condition
+ * numbers of Section 5.2, Tables fd_poisson_fixedH, fd_shrinkingH and
+ * fd_other_models).
+ * ddst_gmres: x = S^{-1} b (transpose 1: S^{-T} b) by unrestarted GMRES from
+ *   x = 0 to a relative residual <= tol (FP64 Arnoldi), S applied through form
+ *   `which` (DDST_APPLY_*); b, x device N_ds*M float64; iters, relres: host,
+ *   may be NULL.  ENOTCONV (+1) if max_iter (<= 20000) was reached first.
+ * ddst_cond_est: the extreme singular values of S by power iteration on
+ *   S^T S and inverse iteration on (S^T S)^{-1} (two GMRES solves to
+ *   gmres_tol per step), each stopped when the eigenvalue estimate changes by
+ *   <= tol relative or after max_iter steps, from a fixed pseudo-random start;
+ *   kappa_2(S) = smax / smin.  iters: host, steps of the last iteration.
+ * Errors: EINVAL, ESTATE (form not held), ENOMEM, EHIP.
+ */
+int ddst_gmres(const ddst_op_t *op, int32_t transpose, int32_t which, const double *b,
+               double *x, double tol, int32_t max_iter, int32_t *iters, double *relres,
+               hipStream_t stream);
+int ddst_cond_est(const ddst_op_t *op, int32_t which, int32_t max_iter, double tol,
+                  double gmres_tol, double *smax, double *smin, int32_t *iters,
+                  hipStream_t stream);
+
+/*
  * Inspection hooks for the intermediate state of the build.
  * ddst_get_factor: G_k = D_k^{-1}, the inverse Schur complement after k
  *   planes of the left-to-right elimination of single slab `slab`

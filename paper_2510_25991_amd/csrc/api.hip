@@ -1123,6 +1123,59 @@ int adjoint_impl(ddst_op *op, const double *u_vol, const double *g, const double
   return status;
 }
 
+// The form `which` is held by the operator (0), or the error to report.
+int check_form(const ddst_op *op, int which) {
+  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR && which != DDST_APPLY_MATFREE)
+    return fail(DDST_EINVAL, "which must be DENSE, HODLR or MATFREE");
+  if (which == DDST_APPLY_HODLR && !hodlr_ready(op))
+    return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  if (which == DDST_APPLY_MATFREE && !op->G)
+    return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
+  if (which == DDST_APPLY_DENSE && !op->S)
+    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build)");
+  return DDST_OK;
+}
+
+// yp = S xp (or S^T xp), padded interface vectors, through form `which`
+// (temporaries allocated per call).
+int apply_padded(ddst_op *op, int which, bool trans, const double *xp, double *yp,
+                 hipStream_t stream) {
+  const bool f32 = op->prec == DDST_FP32;
+  if (which == DDST_APPLY_DENSE) {
+    JobTable t;
+    const size_t o = t.add(interface_jobs(op, xp, yp, trans));
+    t.upload(stream);
+    const int nchunk = std::min(op->ld / kGemvChunk, 64);
+    DeviceMem part((size_t)op->n_ds * nchunk * op->ld * 8);
+    double *pp = static_cast<double *>(part.p);
+    if (f32)
+      launch_gemv<float>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, trans, -1.0, pp, stream);
+    else
+      launch_gemv<double>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, trans, -1.0, pp, stream);
+    HIPCHK(hipStreamSynchronize(stream));  // keeps the job table alive until done
+    return DDST_OK;
+  }
+  if (which == DDST_APPLY_HODLR) return hodlr_apply_jobs(op, xp, yp, trans ? 1 : 0, stream);
+  const size_t ifc = (size_t)op->n_ds * op->ld, vol = (size_t)op->n * op->ld;
+  const int nchunk = std::min(op->ld / kGemvChunk, 64);
+  const size_t npart = (size_t)2 * op->n_slabs * nchunk * op->ld;
+  DeviceMem tmp((2 * vol + 3 * ifc + npart) * 8);
+  double *Zf = static_cast<double *>(tmp.p), *Zb = Zf + vol, *X = Zb + vol, *V = X + ifc;
+  double *F = V + ifc, *part = F + ifc;
+  HIPCHK(hipMemcpyAsync(X, xp, ifc * 8, hipMemcpyDeviceToDevice, stream));
+  const MatfreeBufs b{X, V, F, Zf, Zb, yp};
+  MatfreeTables t;
+  make_matfree_tables(op, op->G, trans, b, t);
+  t.tab.upload(stream);
+  launch_fill(Zf, 0.0, 2 * vol, stream);
+  if (f32)
+    run_matfree<float>(op, t, trans, b, part, stream);
+  else
+    run_matfree<double>(op, t, trans, b, part, stream);
+  HIPCHK(hipStreamSynchronize(stream));
+  return DDST_OK;
+}
+
 template <typename Fn>
 int guarded(Fn &&fn) {
   try {
@@ -1300,60 +1353,125 @@ int ddst_apply(const ddst_op_t *cop, int32_t transpose, int32_t which, const dou
                double *y, hipStream_t stream) {
   g_err.clear();
   if (!cop || !x || !y) return fail(DDST_EINVAL, "op, x and y must be non-NULL");
-  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR && which != DDST_APPLY_MATFREE)
-    return fail(DDST_EINVAL, "which must be DENSE, HODLR or MATFREE");
   ddst_op *op = const_cast<ddst_op *>(cop);
-  if (which == DDST_APPLY_HODLR && !hodlr_ready(op))
-    return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
-  if (which == DDST_APPLY_MATFREE && !op->G)
-    return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
-  if (which == DDST_APPLY_DENSE && !op->S)
-    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build)");
+  const int st = check_form(op, which);
+  if (st) return st;
   return guarded([&]() -> int {
     DeviceMem buf((size_t)op->n_ds * op->ld * 8 * 2);
     double *xp = static_cast<double *>(buf.p), *yp = xp + (size_t)op->n_ds * op->ld;
     launch_pad(x, xp, op->n_ds, op->M, op->ld, stream);
-    if (which == DDST_APPLY_DENSE) {
-      JobTable t;
-      const size_t o = t.add(interface_jobs(op, xp, yp, transpose != 0));
-      t.upload(stream);
-      const int nchunk = std::min(op->ld / kGemvChunk, 64);
-      DeviceMem part((size_t)op->n_ds * nchunk * op->ld * 8);
-      if (op->prec == DDST_FP32)
-        launch_gemv<float>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, transpose, -1.0,
-                           static_cast<double *>(part.p), stream);
+    const int r = apply_padded(op, which, transpose != 0, xp, yp, stream);
+    if (r) return r;
+    launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return DDST_OK;
+  });
+}
+
+int ddst_gmres(const ddst_op_t *cop, int32_t transpose, int32_t which, const double *b, double *x,
+               double tol, int32_t max_iter, int32_t *iters, double *relres,
+               hipStream_t stream) {
+  g_err.clear();
+  if (!cop || !b || !x) return fail(DDST_EINVAL, "op, b and x must be non-NULL");
+  if (!(tol > 0)) return fail(DDST_EINVAL, "tol must be > 0");
+  if (max_iter < 1 || max_iter > kMaxGmresIter)
+    return fail(DDST_EINVAL, "max_iter in [1, " + std::to_string(kMaxGmresIter) + "]");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  const int st = check_form(op, which);
+  if (st) return st;
+  return guarded([&]() -> int {
+    ensure_host(op, max_iter);
+    SolveWs w = carve_ws(op, max_iter);
+    launch_pad(b, w.fJ, op->n_ds, op->M, op->ld, stream);
+    double rr = 0.0;
+    const int it = op->prec == DDST_FP32
+                       ? gmres<float>(op, w, op->G, w.fJ, w.xg, tol, max_iter, transpose != 0,
+                                      which, &rr, stream)
+                       : gmres<double>(op, w, op->G, w.fJ, w.xg, tol, max_iter, transpose != 0,
+                                       which, &rr, stream);
+    launch_unpad(w.xg, x, op->n_ds, op->M, op->ld, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    return rr <= tol ? DDST_OK : DDST_ENOTCONV;
+  });
+}
+
+int ddst_cond_est(const ddst_op_t *cop, int32_t which, int32_t max_iter, double tol,
+                  double gmres_tol, double *smax, double *smin, int32_t *iters,
+                  hipStream_t stream) {
+  g_err.clear();
+  if (!cop || !smax || !smin) return fail(DDST_EINVAL, "op, smax and smin must be non-NULL");
+  if (max_iter < 1 || !(tol > 0) || !(gmres_tol > 0))
+    return fail(DDST_EINVAL, "need max_iter >= 1, tol > 0, gmres_tol > 0");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  const int st = check_form(op, which);
+  if (st) return st;
+  return guarded([&]() -> int {
+    const int kInner = 2000;  // GMRES cap of each inverse-iteration solve
+    ensure_host(op, kInner);
+    SolveWs w = carve_ws(op, kInner);
+    const size_t len = w.ifc;
+    // fixed start vector: uniform in (-1, 1) from a 64-bit xorshift, zero
+    // in the padding
+    std::vector<double> h0(len, 0.0);
+    uint64_t r = 0x9E3779B97F4A7C15ull;
+    for (int j = 0; j < op->n_ds; ++j)
+      for (int i = 0; i < op->M; ++i) {
+        r ^= r << 13;
+        r ^= r >> 7;
+        r ^= r << 17;
+        h0[(size_t)j * op->ld + i] = (double)(r >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+      }
+    double *v = w.hh, *y = w.D, *z = w.Z;  // buffers GMRES does not touch
+    int total = 0;
+    // largest eigenvalue of S^T S by power iteration (forward), of
+    // (S^T S)^{-1} = S^{-1} S^{-T} by inverse iteration (GMRES solves)
+    for (int inv = 0; inv < 2; ++inv) {
+      HIPCHK(hipMemcpyAsync(v, h0.data(), len * 8, hipMemcpyHostToDevice, stream));
+      launch_norm(v, len, w.nrm, w.dpart, stream);
+      launch_scale_by_inv(v, v, w.nrm, len, stream);
+      double lam = 0.0, prev = 0.0;
+      for (int k = 0; k < max_iter; ++k) {
+        if (!inv) {
+          int e = apply_padded(op, which, false, v, y, stream);
+          if (!e) e = apply_padded(op, which, true, y, z, stream);
+          if (e) return e;
+        } else {
+          double rr = 0.0;
+          HIPCHK(hipMemcpyAsync(w.fJ, v, len * 8, hipMemcpyDeviceToDevice, stream));
+          const bool f32 = op->prec == DDST_FP32;
+          total += f32 ? gmres<float>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, true, which,
+                                      &rr, stream)
+                       : gmres<double>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, true, which,
+                                       &rr, stream);
+          HIPCHK(hipMemcpyAsync(w.fJ, w.xg, len * 8, hipMemcpyDeviceToDevice, stream));
+          total += f32 ? gmres<float>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, false, which,
+                                      &rr, stream)
+                       : gmres<double>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, false, which,
+                                       &rr, stream);
+          HIPCHK(hipMemcpyAsync(z, w.xg, len * 8, hipMemcpyDeviceToDevice, stream));
+        }
+        // v has unit norm, so ||z|| -> the dominant eigenvalue
+        launch_norm(z, len, w.nrm, w.dpart, stream);
+        HIPCHK(hipMemcpyAsync(op->hbuf_host, w.nrm, 8, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        lam = op->hbuf_host[0];
+        if (!(lam > 0.0) || !std::isfinite(lam)) return fail(DDST_EHIP, "power iteration failed");
+        launch_scale_by_inv(v, z, w.nrm, len, stream);
+        if (iters) *iters = k + 1;
+        if (k > 0 && std::fabs(lam - prev) <= tol * lam) break;
+        prev = lam;
+      }
+      if (!inv)
+        *smax = std::sqrt(lam);
       else
-        launch_gemv<double>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, transpose, -1.0,
-                            static_cast<double *>(part.p), stream);
-      launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(stream));
-    } else if (which == DDST_APPLY_HODLR) {
-      const int st = hodlr_apply_jobs(op, xp, yp, transpose, stream);
-      if (st) return st;
-      launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(stream));
-    } else {
-      const size_t ifc = (size_t)op->n_ds * op->ld, vol = (size_t)op->n * op->ld;
-      const int nchunk = std::min(op->ld / kGemvChunk, 64);
-      const size_t npart = (size_t)2 * op->n_slabs * nchunk * op->ld;
-      DeviceMem tmp((2 * vol + 2 * ifc + npart) * 8);
-      double *Zf = static_cast<double *>(tmp.p), *Zb = Zf + vol, *V = Zb + vol, *F = V + ifc;
-      double *part = F + ifc;
-      const MatfreeBufs b{xp, V, F, Zf, Zb, yp};
-      MatfreeTables t;
-      make_matfree_tables(op, op->G, transpose != 0, b, t);
-      t.tab.upload(stream);
-      launch_fill(Zf, 0.0, 2 * vol, stream);
-      if (op->prec == DDST_FP32)
-        run_matfree<float>(op, t, transpose != 0, b, part, stream);
-      else
-        run_matfree<double>(op, t, transpose != 0, b, part, stream);
-      launch_unpad(yp, y, op->n_ds, op->M, op->ld, stream);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(stream));
+        *smin = 1.0 / std::sqrt(lam);
     }
+    (void)total;
+    HIPCHK(hipStreamSynchronize(stream));
     return DDST_OK;
   });
 }

@@ -76,7 +76,7 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_solve_man
            "ddst_get_transfer", "ddst_apply", "ddst_loads", "ddst_get_factor",
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
            "ddst_profile_enable", "ddst_profile_select", "ddst_profile_read",
-           "ddst_profile_busy", "ddst_compress_info"]
+           "ddst_profile_busy", "ddst_compress_info", "ddst_gmres", "ddst_cond_est"]
 KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv"}
 
 _lib = None
@@ -95,6 +95,10 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_compress.argtypes = [vp, P(CompressOptsC), vp]
     L.ddst_solve.argtypes = [vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
     L.ddst_solve_many.argtypes = [vp, i32, vp, vp, P(SolveOptsC), vp, P(StatsC), vp]
+    L.ddst_gmres.argtypes = [vp, i32, i32, vp, vp, ctypes.c_double, i32, P(i32),
+                             P(ctypes.c_double), vp]
+    L.ddst_cond_est.argtypes = [vp, i32, i32, ctypes.c_double, ctypes.c_double,
+                                P(ctypes.c_double), P(ctypes.c_double), P(i32), vp]
     L.ddst_adjoint.argtypes = [vp, vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
     L.ddst_release_factors.argtypes = [vp]
     L.ddst_destroy.argtypes = [vp]
@@ -301,6 +305,29 @@ class Operator:
         _check(load_library().ddst_apply(self._h, 1 if transpose else 0, _APPLY_FORMS[which],
                                          _ptr(x), _ptr(y), _stream()))
         return y.view(self.n_ds, self.M)
+
+    def gmres(self, b, tol=1e-8, max_iter=1000, which="dense", transpose=False,
+              allow_notconv=False):
+        """x = S^{-1} b (or S^{-T} b) by unrestarted GMRES from zero; returns
+        (x (n_ds, M), iterations, relative residual)."""
+        if which not in _APPLY_FORMS:
+            raise ValueError(f"which must be one of {sorted(_APPLY_FORMS)}")
+        b = _dev(b).reshape(-1)
+        x = torch.empty_like(b)
+        it, rr = ctypes.c_int32(), ctypes.c_double()
+        code = load_library().ddst_gmres(self._h, 1 if transpose else 0, _APPLY_FORMS[which],
+                                         _ptr(b), _ptr(x), float(tol), int(max_iter),
+                                         ctypes.byref(it), ctypes.byref(rr), _stream())
+        _check(code, allow_notconv)
+        return x.view(self.n_ds, self.M), it.value, rr.value
+
+    def cond_estimate(self, which="dense", max_iter=500, tol=1e-10, gmres_tol=1e-12):
+        """(sigma_max, sigma_min, kappa_2) of S by power and inverse iteration."""
+        smax, smin, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(load_library().ddst_cond_est(self._h, _APPLY_FORMS[which], int(max_iter),
+                                            float(tol), float(gmres_tol), ctypes.byref(smax),
+                                            ctypes.byref(smin), ctypes.byref(it), _stream()))
+        return smax.value, smin.value, smax.value / smin.value
 
     def loads(self, f=None, g=None):
         f, g = _dev(f), _dev(g)
