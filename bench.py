@@ -281,14 +281,25 @@ def many_leg(dd, torch, dev, prob, opts, nrhs=8):
     op.solve(F[0], opts=opts, want_gamma=False, allow_notconv=True)
     _, _, s1 = op.solve(F[0], opts=opts, want_gamma=False, allow_notconv=True)
     op.solve_many(F, opts=opts, allow_notconv=True)
+    # the multi-vector products timed live (HIP events on their stream)
+    dd.profile_enable(True, kinds=["gemv_many"])
     _, sm = op.solve_many(F, opts=opts, allow_notconv=True)
+    n, ms, work = dd.profile_read()["gemv_many"]
+    dd.profile_enable(False)
     op.close()
+    gbs = work / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     return {"nrhs": nrhs, "solve_ms_together": round(sm["t_solve_ms"], 2),
             "solve_ms_per_rhs": round(sm["t_solve_ms"] / nrhs, 2),
             "solve_ms_single": round(s1["t_solve_ms"], 2),
             "throughput_gain": round(s1["t_solve_ms"] * nrhs / sm["t_solve_ms"], 2),
             "gmres_iters": {"together": sm["gmres_iters"], "single": s1["gmres_iters"]},
-            "converged": bool(sm["status"] == 0)}
+            "converged": bool(sm["status"] == 0),
+            # k_gemv_nv: matrix bytes (one read per group of 8 vectors; interface
+            # products count one of their two blocks, so a lower bound) per launch
+            "gemv_many": {"launches": n, "avg_launch_us": round(ms / max(n, 1) * 1e3, 2),
+                          "matrix_bytes_per_launch": work / max(n, 1),
+                          "achieved_gbs": round(gbs, 1),
+                          "frac_hbm": round(gbs / PEAK["hbm_gbs"], 4)}}
 
 
 def main():

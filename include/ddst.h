@@ -328,7 +328,9 @@ enum {
   DDST_K_GJ_UPDATE = 1, /* Gauss-Jordan rank-128 update, MFMA         (flops) */
   DDST_K_GEMM = 2,      /* transfer chains / blocks, MFMA             (flops) */
   DDST_K_ASSEMBLE = 3,  /* plane-block (Schur recursion) assembly     (bytes) */
-  DDST_K_GEMV = 4       /* slab sweeps and interface products         (bytes) */
+  DDST_K_GEMV = 4,      /* slab sweeps and interface products         (bytes) */
+  DDST_K_GEMV_MANY = 5  /* the same for several right-hand sides: matrix
+                           bytes, once per group of 8 vectors         (bytes) */
 };
 int ddst_profile_select(uint32_t kinds);
 int ddst_profile_enable(int32_t on);

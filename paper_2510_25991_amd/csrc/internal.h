@@ -102,7 +102,8 @@ enum KernelKind {
   KK_GEMM = 2,       // transfer-chain / transfer-block GEMM on MFMA (flops)
   KK_ASSEMBLE = 3,   // plane-block assembly (work: bytes)
   KK_GEMV = 4,       // slab sweeps and interface products (work: bytes)
-  KK_COUNT = 5
+  KK_GEMV_MANY = 5,  // the same products for several right-hand sides (bytes)
+  KK_COUNT = 6
 };
 // Start/stop events of one timed launch (both null when its class is off).
 // Single-kernel launches pass them to hipExtLaunchKernelGGL; a sequence of

@@ -789,7 +789,7 @@ void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, d
   // matrix bytes dominate: one or two M x M matrices per job (upper bound 1)
   prof_close(ps, KK_GEMV, (double)njobs * M * M * sizeof(T));
 }
-// vectors per group of the multi-vector GEMV (accumulators: NV x 4 doubles)
+// vectors per group of the multi-vector GEMV (LDS: NV x kGemvCh doubles)
 template <typename T> constexpr int gemv_nv() { return 8; }
 
 template <typename T>
@@ -801,11 +801,12 @@ void launch_gemv_many(const GemvJob *jobs, int njobs, int ld, int M, double alph
   }
   if (njobs <= 0) return;
   constexpr int NV = gemv_nv<T>();
-  const ProfSpan ps = prof_open(KK_GEMV);
+  const ProfSpan ps = prof_open(KK_GEMV_MANY);
   constexpr int RB = 4 * kGemvNvRows * kGemvNvBlk;  // rows per work-group (ld % 64 == 0)
   hipExtLaunchKernelGGL(k_gemv_nv<T, NV>, dim3(ld / RB, njobs, (nv + NV - 1) / NV), dim3(256), 0,
                         s, ps.a, ps.b, 0, jobs, ld, alpha, nv, vs);
-  prof_close(ps, KK_GEMV, (double)njobs * ((nv + NV - 1) / NV) * M * M * sizeof(T));
+  // one M x M matrix per job and group (interface jobs read two: a lower bound)
+  prof_close(ps, KK_GEMV_MANY, (double)njobs * ((nv + NV - 1) / NV) * M * M * sizeof(T));
 }
 template void launch_gemv_many<float>(const GemvJob *, int, int, int, double, int, size_t,
                                       double *, hipStream_t);

@@ -77,7 +77,8 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_solve_man
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
            "ddst_profile_enable", "ddst_profile_select", "ddst_profile_read",
            "ddst_profile_busy", "ddst_compress_info", "ddst_gmres", "ddst_cond_est"]
-KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv"}
+KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv",
+                  5: "gemv_many"}
 
 _lib = None
 
