@@ -178,7 +178,8 @@ template <typename T>
 void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, double alpha,
                  double *partial, hipStream_t s);
 // The same non-transposed products for nv right-hand sides, vector v of every
-// job shifted by v * vs (matrices and couplings shared); nv <= 1 is launch_gemv.
+// job shifted by v * vs (matrices and couplings shared), nv <= 16 (matrix
+// cores); nv <= 1 is launch_gemv.
 template <typename T>
 void launch_gemv_many(const GemvJob *jobs, int njobs, int ld, int M, double alpha, int nv,
                       size_t vs, double *partial, hipStream_t s);

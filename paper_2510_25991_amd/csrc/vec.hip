@@ -5,6 +5,8 @@
 // The stencil follows the FD model problem: on every grid edge the
 // coefficient is the mean of the 2^(dim-1) cells sharing the edge,
 // convection uses centred differences, and boundary neighbours carry g.
+#include <stdexcept>
+
 #include "internal.h"
 
 namespace ddst {
@@ -303,90 +305,105 @@ __global__ __launch_bounds__(256) void k_gemv_n_f64(const GemvJob *__restrict__ 
   gemv_n_body<double>(jobs, ld, alpha);
 }
 
-// Several right-hand sides per launch: vector v of a job is the job's vector
-// shifted by v * vs (x1, x2, x3, w and out; the matrices and e are shared),
-// grid z picks a group of NV vectors.  A work-group owns kGemvNvBlk row
-// blocks of 16 rows (4 per wavefront) and stages each column chunk of all NV
-// vectors in LDS once for all of them; every chunk of a matrix row is loaded
-// into registers once and multiplied with the NV vectors, so the matrix is
-// read from HBM once per group instead of once per vector.  Row sums are
-// collected in LDS across chunks.
-constexpr int kGemvNvRows = 4;
-constexpr int kGemvNvBlk = 4;
-template <typename T, int NV>
-__global__ __launch_bounds__(256) void k_gemv_nv(const GemvJob *__restrict__ jobs, int ld,
-                                                 double alpha, int nv, size_t vs) {
-  constexpr int R = kGemvNvRows, RB = 4 * R * kGemvNvBlk;
-  __shared__ double xs[NV][kGemvCh];
-  __shared__ double sums[RB][NV];
+// Several right-hand sides per launch, on the matrix cores: vector v of a job
+// is the job's vector shifted by v * vs (x1, x2, x3, w and out; the matrices
+// and e are shared), up to 16 per launch.  Y = Mat X is a product of the
+// matrix rows with a 16-column block of vectors, done by the FP64
+// 16 x 16 x 4 MFMA (matrix entries converted exactly to FP64, FP64
+// accumulation, as in the one-vector kernel): each wavefront owns a strip
+// of 16 rows; per 16-column step lane l loads four
+// consecutive entries of row l % 16 (columns 4 (l / 16) + 0..3), which feed
+// the A operand of four MFMAs, the i-th taking columns {4 q + i}; the B
+// operand is the matching entries of the 16 vectors, staged column-major in
+// LDS per chunk of columns (zero for vectors past nv); the next chunk's
+// matrix entries are loaded while a chunk is used.  The FP64 output holds
+// vector l % 16 of rows 4 r + l / 16 in register r.
+typedef double f64x4v __attribute__((ext_vector_type(4)));
+constexpr int kMvLd = 17;  // LDS row stride (doubles) of the staged block
+// columns staged per chunk: a divisor of every leading dimension (a multiple
+// of 128)
+constexpr int kMvCh = 128;
+
+template <typename T, int NS>
+__device__ __forceinline__ void mv_load(const T *Mt, size_t row_off, int c0, int kq,
+                                        T (&a)[NS][4]) {
+  constexpr int V = 16 / sizeof(T);
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    const T *src = Mt + row_off + c0 + 16 * st + 4 * kq;
+#pragma unroll
+    for (int h = 0; h < 4 / V; ++h) {
+      const typename V16<T>::type v = ld16(src + V * h);
+#pragma unroll
+      for (int e = 0; e < V; ++e) a[st][V * h + e] = v[e];
+    }
+  }
+}
+
+// W wavefronts (16-row strips) per work-group: 8 share each staged block of
+// x over 128 rows (fewer staging loads per row, better from 8 vectors on),
+// 4 give twice the work-groups (better for 2 to 4 vectors).
+template <typename T, int W>
+__global__ __launch_bounds__(64 * W) void k_gemv_mfma(const GemvJob *__restrict__ jobs, int ld,
+                                                      double alpha, int nv, size_t vs) {
+  constexpr int CH = kMvCh, NS = CH / 16, RB = 16 * W;
+  __shared__ double xt[CH * kMvLd];
   const GemvJob J = jobs[blockIdx.y];
   const T *G = static_cast<const T *>(J.G);
   const T *G2 = static_cast<const T *>(J.G2);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
   const int rowb = blockIdx.x * RB;  // first row of the work-group
-  const int v0 = blockIdx.z * NV;
-  const int nvg = min(NV, nv - v0);
-  for (int e = threadIdx.x; e < RB * NV; e += 256) (&sums[0][0])[e] = 0.0;
-  for (int c0 = 0; c0 < ld; c0 += kGemvCh) {
-    const int cn = min(kGemvCh, ld - c0);
+  const int roww = rowb + wave * 16;  // first row of this wavefront's strip
+  if (!G && !G2) {  // no matrix term: out = w
+    for (int e = threadIdx.x; e < RB * nv; e += 64 * W) {
+      const size_t o = (size_t)(e / RB) * vs + rowb + e % RB;
+      gp(J.out)[o] = J.w ? gp(J.w)[o] : 0.0;
+    }
+    return;
+  }
+  f64x4v acc = {0.0, 0.0, 0.0, 0.0};
+  const size_t row_off = (size_t)(roww + m) * ld;
 #pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-      const T *Mt = pass == 0 ? G : G2;
-      if (!Mt) continue;
-      const double *xa = pass == 0 ? J.x1 : J.x3;
-      const double *xe = pass == 0 ? J.e : nullptr;
-      __syncthreads();  // the previous x is no longer read
-      // per column: the coupling once, then every vector's entries (all of
-      // a column's loads in flight together)
-#pragma unroll 1
-      for (int c = threadIdx.x; c < kGemvCh; c += 256) {
-        const bool in = c < cn;
-        const double ec = (in && xe) ? gp(xe)[c0 + c] : 0.0;
-        double xv[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const size_t o = (size_t)(v0 + v) * vs + c0 + c;
-          xv[v] = 0.0;
-          if (in && v < nvg) {
-            xv[v] = xa ? gp(xa)[o] : 0.0;
-            if (xe) xv[v] -= ec * gp(J.x2)[o];
-          }
+  for (int pass = 0; pass < 2; ++pass) {
+    const T *Mt = pass == 0 ? G : G2;
+    if (!Mt) continue;
+    const double *xa = pass == 0 ? J.x1 : J.x3;
+    const double *xe = pass == 0 ? J.e : nullptr;
+    T a[NS][4], an[NS][4];
+    mv_load<T, NS>(Mt, row_off, 0, kq, a);
+    for (int c0 = 0; c0 < ld; c0 += CH) {
+      // the next chunk's matrix entries go out before this chunk is used
+      if (c0 + CH < ld) mv_load<T, NS>(Mt, row_off, c0 + CH, kq, an);
+      __syncthreads();  // the previous block of x is no longer read
+      for (int idx = threadIdx.x; idx < 16 * CH; idx += 64 * W) {
+        const int v = idx / CH, c = idx % CH;
+        double x = 0.0;
+        if (v < nv) {
+          const size_t o = (size_t)v * vs + c0 + c;
+          x = xa ? gp(xa)[o] : 0.0;
+          if (xe) x -= gp(xe)[c0 + c] * gp(J.x2)[o];
         }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) xs[v][c] = xv[v];
+        xt[c * kMvLd + v] = x;
       }
       __syncthreads();
-#pragma unroll 1
-      for (int b = 0; b < kGemvNvBlk; ++b) {
-        // re-read x from LDS per row block: keeping all of it in registers
-        // across the blocks would take every register
-        asm volatile("" ::: "memory");
-        const int lr = b * 4 * R + wave * R;  // first local row of this wavefront
-        T g[R][kGemvCh / 256][4];
-        gemv_rows_load<T, R>(Mt, (size_t)(rowb + lr) * ld, ld, c0, cn, lane, g);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          if (v >= nvg) break;  // uniform over the work-group
-          double acc[R];
+      for (int st = 0; st < NS; ++st)
 #pragma unroll
-          for (int q = 0; q < R; ++q) acc[q] = 0.0;
-          gemv_rows_fma<T, R>(g, xs[v], lane, acc);
+        for (int i = 0; i < 4; ++i)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              (double)a[st][i], xt[(16 * st + 4 * kq + i) * kMvLd + m], acc, 0, 0, 0);
 #pragma unroll
-          for (int q = 0; q < R; ++q) {
-            const double sm = wave_sum(acc[q]);
-            if (lane == 0) sums[lr + q][v] += sm;  // rows of this wavefront only
-          }
-        }
-      }
+      for (int st = 0; st < NS; ++st)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[st][i] = an[st][i];
     }
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < RB * NV; e += 256) {
-    const int r = e / NV, v = e % NV;
-    if (v < nvg) {
-      const size_t o = (size_t)(v0 + v) * vs + rowb + r;
-      const double base = J.w ? gp(J.w)[o] : 0.0;
-      gp(J.out)[o] = (G || G2) ? base + alpha * sums[r][v] : base;
+  if (m < nv) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const size_t o = (size_t)m * vs + roww + 4 * r + kq;
+      gp(J.out)[o] = (J.w ? gp(J.w)[o] : 0.0) + alpha * acc[r];
     }
   }
 }
@@ -789,9 +806,6 @@ void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, d
   // matrix bytes dominate: one or two M x M matrices per job (upper bound 1)
   prof_close(ps, KK_GEMV, (double)njobs * M * M * sizeof(T));
 }
-// vectors per group of the multi-vector GEMV (LDS: NV x kGemvCh doubles)
-template <typename T> constexpr int gemv_nv() { return 8; }
-
 template <typename T>
 void launch_gemv_many(const GemvJob *jobs, int njobs, int ld, int M, double alpha, int nv,
                       size_t vs, double *partial, hipStream_t s) {
@@ -800,13 +814,18 @@ void launch_gemv_many(const GemvJob *jobs, int njobs, int ld, int M, double alph
     return;
   }
   if (njobs <= 0) return;
-  constexpr int NV = gemv_nv<T>();
+  // one launch takes up to 16 vectors (the most ddst_solve_many allows)
+  if (nv > 16) throw std::invalid_argument("launch_gemv_many: more than 16 vectors");
   const ProfSpan ps = prof_open(KK_GEMV_MANY);
-  constexpr int RB = 4 * kGemvNvRows * kGemvNvBlk;  // rows per work-group (ld % 64 == 0)
-  hipExtLaunchKernelGGL(k_gemv_nv<T, NV>, dim3(ld / RB, njobs, (nv + NV - 1) / NV), dim3(256), 0,
-                        s, ps.a, ps.b, 0, jobs, ld, alpha, nv, vs);
-  // one M x M matrix per job and group (interface jobs read two: a lower bound)
-  prof_close(ps, KK_GEMV_MANY, (double)njobs * ((nv + NV - 1) / NV) * M * M * sizeof(T));
+  // 64 or 128 rows per work-group (ld % 128 == 0: whole work-groups and chunks)
+  if (nv <= 4)
+    hipExtLaunchKernelGGL(k_gemv_mfma<T, 4>, dim3(ld / 64, njobs), dim3(256), 0, s, ps.a, ps.b,
+                          0, jobs, ld, alpha, nv, vs);
+  else
+    hipExtLaunchKernelGGL(k_gemv_mfma<T, 8>, dim3(ld / 128, njobs), dim3(512), 0, s, ps.a, ps.b,
+                          0, jobs, ld, alpha, nv, vs);
+  // one M x M matrix per job (interface jobs read two: a lower bound)
+  prof_close(ps, KK_GEMV_MANY, (double)njobs * M * M * sizeof(T));
 }
 template void launch_gemv_many<float>(const GemvJob *, int, int, int, double, int, size_t,
                                       double *, hipStream_t);
