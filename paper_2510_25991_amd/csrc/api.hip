@@ -610,6 +610,7 @@ template <typename T>
 void run_slab_solve(const ddst_op *op, const SlabTables &t, bool transpose, double *part,
                     hipStream_t s, int nr = 1, size_t vs = 0) {
   const int m = op->m;
+  if (transpose && nr > 1) throw std::logic_error("transposed sweeps take one right-hand side");
   auto go = [&](size_t off, int n) {
     if (transpose)
       launch_gemv<T>(t.tab.at<GemvJob>(off), n, op->ld, op->M, 1, 1.0, part, s);
@@ -773,6 +774,7 @@ template <typename T>
 int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
           int max_iter, bool trans, int form, double *relres, hipStream_t s) {
   const int nr = w.nr;
+  if (trans && nr > 1) throw std::logic_error("the transposed solve takes one right-hand side");
   const size_t len = w.ifc * nr;
   double *hh = op->hbuf_host;
   launch_norm(rhs, len, w.nrm, w.dpart, s);
@@ -1426,7 +1428,6 @@ int ddst_cond_est(const ddst_op_t *cop, int32_t which, int32_t max_iter, double 
         h0[(size_t)j * op->ld + i] = (double)(r >> 11) * (2.0 / 9007199254740992.0) - 1.0;
       }
     double *v = w.hh, *y = w.D, *z = w.Z;  // buffers GMRES does not touch
-    int total = 0;
     // largest eigenvalue of S^T S by power iteration (forward), of
     // (S^T S)^{-1} = S^{-1} S^{-T} by inverse iteration (GMRES solves)
     for (int inv = 0; inv < 2; ++inv) {
@@ -1443,15 +1444,15 @@ int ddst_cond_est(const ddst_op_t *cop, int32_t which, int32_t max_iter, double 
           double rr = 0.0;
           HIPCHK(hipMemcpyAsync(w.fJ, v, len * 8, hipMemcpyDeviceToDevice, stream));
           const bool f32 = op->prec == DDST_FP32;
-          total += f32 ? gmres<float>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, true, which,
-                                      &rr, stream)
-                       : gmres<double>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, true, which,
-                                       &rr, stream);
+          if (f32)
+            gmres<float>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, true, which, &rr, stream);
+          else
+            gmres<double>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, true, which, &rr, stream);
           HIPCHK(hipMemcpyAsync(w.fJ, w.xg, len * 8, hipMemcpyDeviceToDevice, stream));
-          total += f32 ? gmres<float>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, false, which,
-                                      &rr, stream)
-                       : gmres<double>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, false, which,
-                                       &rr, stream);
+          if (f32)
+            gmres<float>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, false, which, &rr, stream);
+          else
+            gmres<double>(op, w, op->G, w.fJ, w.xg, gmres_tol, kInner, false, which, &rr, stream);
           HIPCHK(hipMemcpyAsync(z, w.xg, len * 8, hipMemcpyDeviceToDevice, stream));
         }
         // v has unit norm, so ||z|| -> the dominant eigenvalue
@@ -1470,7 +1471,6 @@ int ddst_cond_est(const ddst_op_t *cop, int32_t which, int32_t max_iter, double 
       else
         *smin = 1.0 / std::sqrt(lam);
     }
-    (void)total;
     HIPCHK(hipStreamSynchronize(stream));
     return DDST_OK;
   });
