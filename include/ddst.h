@@ -230,6 +230,22 @@ int ddst_release_factors(ddst_op_t *op);
 /* Destroy an operator; NULL is a no-op.  Synchronises the device. */
 void ddst_destroy(ddst_op_t *op);
 
+/*
+ * ddst_set_allocator -- device memory for everything the library allocates
+ * (operators, factors, compressed forms, workspaces, temporaries) from the
+ * caller's allocator, e.g. a framework's caching allocator, instead of
+ * hipMalloc / hipFree.  alloc(bytes, ctx) returns device memory on the
+ * current device, 256-byte aligned, or NULL (reported as ENOMEM);
+ * free(ptr, ctx) releases it.  Both NULL restores hipMalloc / hipFree.  As
+ * with hipFree, the device is synchronized before every free, so the block
+ * may be reused at once.  Process-wide; call it while no operator
+ * exists and no other call is running (ESTATE otherwise); EINVAL if exactly
+ * one of alloc and free is NULL.
+ */
+typedef void *(*ddst_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*ddst_free_fn)(void *ptr, void *ctx);
+int ddst_set_allocator(ddst_alloc_fn alloc, ddst_free_fn free_fn, void *ctx);
+
 /* Text of the last error on this thread ("" if none). */
 const char *ddst_last_error(void);
 

@@ -19,7 +19,9 @@
 //     hhat = Sigma^{-1} (r_J - A_JI z);   S delta_J = hhat (GMRES, CGS2, FP64);
 //     delta_I = A_II^{-1}(r_I - A_IJ delta_J);   u += delta.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -27,6 +29,50 @@
 #include <vector>
 
 #include "internal.h"
+
+namespace ddst {
+namespace {
+// device allocator: hipMalloc / hipFree unless the caller set hooks
+ddst_alloc_fn g_alloc = nullptr;
+ddst_free_fn g_free = nullptr;
+void *g_ctx = nullptr;
+std::atomic<long long> g_live{0};  // library allocations not yet freed
+}  // namespace
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;
+  if (g_alloc) {
+    *p = g_alloc(bytes, g_ctx);
+    if (!*p) return hipErrorOutOfMemory;
+    if (reinterpret_cast<uintptr_t>(*p) & 255) {  // the kernels need 256-byte alignment
+      g_free(*p, g_ctx);
+      *p = nullptr;
+      return hipErrorInvalidValue;
+    }
+  } else {
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return e;
+    }
+  }
+  ++g_live;
+  return hipSuccess;
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  if (g_free) {
+    // as hipFree does: no work that may still read the block is in flight
+    (void)hipDeviceSynchronize();
+    g_free(p, g_ctx);
+  } else {
+    (void)hipFree(p);
+  }
+  --g_live;
+}
+}  // namespace ddst
 
 using namespace ddst;
 
@@ -58,7 +104,7 @@ struct DeviceMem {
   void alloc(size_t b) {
     release();
     if (b == 0) return;
-    if (hipMalloc(&p, b) != hipSuccess) {
+    if (dev_malloc(&p, b) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
       throw std::bad_alloc();
@@ -66,7 +112,7 @@ struct DeviceMem {
     bytes = b;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     bytes = 0;
   }
@@ -289,7 +335,7 @@ int build_impl(ddst_op *op, int keep, int blocks, hipStream_t s) {
   plan.n_work = nwork;
   SweepBuffers buf;
   if (keep) {
-    if (hipMalloc(&op->G, (size_t)nsl * (m - 1) * op->mat_bytes) != hipSuccess) {
+    if (dev_malloc(&op->G, (size_t)nsl * (m - 1) * op->mat_bytes) != hipSuccess) {
       op->G = nullptr;
       (void)hipGetLastError();
       throw std::bad_alloc();
@@ -372,9 +418,9 @@ void destroy_op(ddst_op *op) {
   if (!op) return;
   (void)hipDeviceSynchronize();
   hodlr_free(op);
-  if (op->G) (void)hipFree(op->G);
-  if (op->arena) (void)hipFree(op->arena);
-  if (op->ws) (void)hipFree(op->ws);
+  if (op->G) dev_free(op->G);
+  if (op->arena) dev_free(op->arena);
+  if (op->ws) dev_free(op->ws);
   if (op->hbuf_host) (void)hipHostFree(op->hbuf_host);
   delete op;
 }
@@ -423,7 +469,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     const size_t o_si = cv.take((size_t)op->n_ds * op->mat_bytes);
     const size_t o_s = blocks ? cv.take((size_t)2 * op->n_ds * op->mat_bytes) : 0;
     const size_t o_fl = cv.take(sizeof(int));
-    if (hipMalloc(&op->arena, cv.off) != hipSuccess) {
+    if (dev_malloc(&op->arena, cv.off) != hipSuccess) {
       op->arena = nullptr;
       (void)hipGetLastError();
       throw std::bad_alloc();
@@ -501,10 +547,10 @@ struct SolveWs {
 
 void ensure_ws(ddst_op *op, size_t bytes) {
   if (op->ws_bytes >= bytes) return;
-  if (op->ws) (void)hipFree(op->ws);
+  if (op->ws) dev_free(op->ws);
   op->ws = nullptr;
   op->ws_bytes = 0;
-  if (hipMalloc(&op->ws, bytes) != hipSuccess) {
+  if (dev_malloc(&op->ws, bytes) != hipSuccess) {
     op->ws = nullptr;
     (void)hipGetLastError();
     throw std::bad_alloc();
@@ -1312,7 +1358,7 @@ int ddst_release_factors(ddst_op_t *op) {
   if (!op) return fail(DDST_EINVAL, "op is NULL");
   if (op->G) {
     (void)hipDeviceSynchronize();
-    (void)hipFree(op->G);
+    dev_free(op->G);
     op->G = nullptr;
   }
   return DDST_OK;
@@ -1349,6 +1395,18 @@ int ddst_get_transfer(const ddst_op_t *op, int32_t j, double *S_left, double *S_
     HIPCHK(hipStreamSynchronize(stream));
     return DDST_OK;
   });
+}
+
+int ddst_set_allocator(ddst_alloc_fn alloc, ddst_free_fn free_fn, void *ctx) {
+  g_err.clear();
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(DDST_EINVAL, "alloc and free must both be set or both be NULL");
+  if (g_live.load() != 0)
+    return fail(DDST_ESTATE, "library memory is allocated: destroy every operator first");
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_ctx = ctx;
+  return DDST_OK;
 }
 
 int ddst_apply(const ddst_op_t *cop, int32_t transpose, int32_t which, const double *x,

@@ -549,14 +549,14 @@ struct HipErr : std::runtime_error {
 struct DMem {
   void *p = nullptr;
   explicit DMem(size_t b) {
-    if (b && hipMalloc(&p, b) != hipSuccess) {
+    if (b && dev_malloc(&p, b) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
       throw std::bad_alloc();
     }
   }
   ~DMem() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   }
   template <typename X>
   X *as() const { return static_cast<X *>(p); }
@@ -651,10 +651,10 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     keep.clear();
   };
   auto drop = [&]() {
-    if (H->d_perm) (void)hipFree(H->d_perm);
-    if (H->factors) (void)hipFree(H->factors);
-    if (H->jobs) (void)hipFree(H->jobs);
-    if (H->pbuf) (void)hipFree(H->pbuf);
+    if (H->d_perm) dev_free(H->d_perm);
+    if (H->factors) dev_free(H->factors);
+    if (H->jobs) dev_free(H->jobs);
+    if (H->pbuf) dev_free(H->pbuf);
     delete H;
   };
   try {
@@ -671,10 +671,11 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     for (int i = 0; i < op->M; ++i) identity = identity && H->perm[i] == i;
     const int *d_perm = nullptr;
     if (!identity) {
-      HCHK(hipMalloc(&H->d_perm, op->M * sizeof(int)));
+      HCHK(dev_malloc(reinterpret_cast<void **>(&H->d_perm), op->M * sizeof(int)));
       HCHK(hipMemcpyAsync(H->d_perm, H->perm.data(), op->M * sizeof(int), hipMemcpyHostToDevice,
                           st));
-      HCHK(hipMalloc(&H->pbuf, (size_t)2 * op->n_ds * op->ld * sizeof(double)));
+      HCHK(dev_malloc(reinterpret_cast<void **>(&H->pbuf),
+                      (size_t)2 * op->n_ds * op->ld * sizeof(double)));
       d_perm = H->d_perm;
     }
     // transfer matrices that exist
@@ -879,7 +880,7 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     }
     // ---- pack factors
     H->bytes = store_elems * sizeof(F);
-    HCHK(hipMalloc(&H->factors, std::max<size_t>(H->bytes, 16)));
+    HCHK(dev_malloc(&H->factors, std::max<size_t>(H->bytes, 16)));
     F *store = static_cast<F *>(H->factors);
     std::vector<LeafJob> lj;
     for (const HBlock &b : H->blocks)
@@ -959,7 +960,7 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     }
     const size_t bytes_jobs = jobs.size() * sizeof(LrJob);
     H->off_con = (bytes_jobs + 255) & ~size_t(255);
-    HCHK(hipMalloc(&H->jobs, H->off_con + std::max<size_t>(con.size(), 1) * sizeof(Contrib)));
+    HCHK(dev_malloc(&H->jobs, H->off_con + std::max<size_t>(con.size(), 1) * sizeof(Contrib)));
     if (!jobs.empty())
       HCHK(hipMemcpyAsync(H->jobs, jobs.data(), bytes_jobs, hipMemcpyHostToDevice, st));
     if (!con.empty())
@@ -983,10 +984,10 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
 void hodlr_free(ddst_op *op) {
   if (!op || !op->hodlr) return;
   Hodlr *H = op->hodlr;
-  if (H->d_perm) (void)hipFree(H->d_perm);
-  if (H->factors) (void)hipFree(H->factors);
-  if (H->jobs) (void)hipFree(H->jobs);
-  if (H->pbuf) (void)hipFree(H->pbuf);
+  if (H->d_perm) dev_free(H->d_perm);
+  if (H->factors) dev_free(H->factors);
+  if (H->jobs) dev_free(H->jobs);
+  if (H->pbuf) dev_free(H->pbuf);
   delete H;
   op->hodlr = nullptr;
 }

@@ -177,6 +177,11 @@ void launch_unpad(const double *src, double *dst, int rows, int M, int ld, hipSt
 template <typename T>
 void launch_gemv(const GemvJob *jobs, int njobs, int ld, int M, int transpose, double alpha,
                  double *partial, hipStream_t s);
+// Device memory of the library: hipMalloc / hipFree, or the caller's
+// allocator set with ddst_set_allocator.  0 bytes gives nullptr.
+hipError_t dev_malloc(void **p, size_t bytes);
+void dev_free(void *p);
+
 // The same non-transposed products for nv right-hand sides, vector v of every
 // job shifted by v * vs (matrices and couplings shared), nv <= 16 (matrix
 // cores); nv <= 1 is launch_gemv.

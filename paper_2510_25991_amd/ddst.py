@@ -76,11 +76,50 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_solve_man
            "ddst_get_transfer", "ddst_apply", "ddst_loads", "ddst_get_factor",
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
            "ddst_profile_enable", "ddst_profile_select", "ddst_profile_read",
-           "ddst_profile_busy", "ddst_compress_info", "ddst_gmres", "ddst_cond_est"]
+           "ddst_profile_busy", "ddst_compress_info", "ddst_gmres", "ddst_cond_est",
+           "ddst_set_allocator"]
 KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv",
                   5: "gemv_many"}
 
 _lib = None
+
+# device allocator hooks (ddst_set_allocator): blocks from torch's caching
+# allocator, kept alive here until the library frees them
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_torch_blocks = {}
+
+
+def _torch_alloc(nbytes, ctx):
+    try:
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    except RuntimeError:
+        return None  # NULL: the library reports ENOMEM
+    _torch_blocks[t.data_ptr()] = t
+    return t.data_ptr()
+
+
+def _torch_free(ptr, ctx):
+    _torch_blocks.pop(ptr, None)
+
+
+_ALLOC_CB = _ALLOC_T(_torch_alloc)
+_FREE_CB = _FREE_T(_torch_free)
+
+
+def use_torch_allocator(on: bool = True):
+    """Take the library's device memory from torch's caching allocator (on)
+    or from hipMalloc again (off).  Call while no Operator exists."""
+    L = load_library()
+    if on:
+        _check(L.ddst_set_allocator(_ALLOC_CB, _FREE_CB, None))
+    else:
+        _check(L.ddst_set_allocator(_ALLOC_T(), _FREE_T(), None))
+
+
+def torch_allocator_blocks() -> int:
+    """Library blocks currently held from torch's allocator."""
+    return len(_torch_blocks)
 
 
 def load_library(path: str = _LIB_PATH):
@@ -96,6 +135,7 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_compress.argtypes = [vp, P(CompressOptsC), vp]
     L.ddst_solve.argtypes = [vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
     L.ddst_solve_many.argtypes = [vp, i32, vp, vp, P(SolveOptsC), vp, P(StatsC), vp]
+    L.ddst_set_allocator.argtypes = [_ALLOC_T, _FREE_T, vp]
     L.ddst_gmres.argtypes = [vp, i32, i32, vp, vp, ctypes.c_double, i32, P(i32),
                              P(ctypes.c_double), vp]
     L.ddst_cond_est.argtypes = [vp, i32, i32, ctypes.c_double, ctypes.c_double,
