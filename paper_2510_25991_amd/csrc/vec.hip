@@ -501,12 +501,13 @@ __global__ void k_fill(double *__restrict__ y, double v, size_t len) {
 // the chunk of w staged in LDS), then out[i] = sum over chunks (fixed order,
 // deterministic).  A null V means w itself (squared norm).
 constexpr int kDotChunk = 256;
+constexpr int kDotVecs = 8;  // basis vectors per wavefront and round
 
 // Partial dot products of one kDotChunk chunk (in LDS, zero past the end)
 // with V_0..V_{nvec-1} (V null: the chunk with itself), one wavefront per
 // vector: part[chunk * nvec + i].
-// Each wavefront takes four vectors at a time with independent sums, their
-// loads issued together (entries past the chunk re-read its last element
+// Each wavefront takes kDotVecs vectors at a time with independent sums,
+// their loads issued together (entries past the chunk re-read its last element
 // and meet a zero of ws).
 __device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t stride,
                                            int nvec, const double *ws, size_t base, int cn,
@@ -526,10 +527,12 @@ __device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t 
     }
     return;
   }
-  for (int i0 = wave; i0 < nvec; i0 += 16) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = wave; i0 < nvec; i0 += 4 * kDotVecs) {
+    double s[kDotVecs];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kDotVecs; ++u) s[u] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kDotVecs; ++u) {
       const int i = i0 + 4 * u;
       if (i < nvec) {
         const double *v = V + (size_t)i * stride + base;
@@ -541,7 +544,7 @@ __device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t 
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kDotVecs; ++u) {
       const int i = i0 + 4 * u;
       const double r = wave_sum(s[u]);
       if (lane == 0 && i < nvec) part[(size_t)blockIdx.x * nvec + i] = r;
@@ -577,9 +580,16 @@ __global__ __launch_bounds__(256) void k_mgs_update_dots(double *__restrict__ w,
   const int e = threadIdx.x;  // kDotChunk == blockDim.x
   double we = 0.0;
   if (e < cn) {
-    double s = 0.0;
-    for (int i = 0; i < nvec; ++i) s += V[(size_t)i * stride + base + e] * h[i];
-    we = w[base + e] + sign * s;
+    // eight independent partial sums: eight basis-vector loads in flight
+    const double *v = V + base + e;
+    double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = 0;
+    for (; i + 8 <= nvec; i += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] += v[(size_t)(i + u) * stride] * h[i + u];
+    for (; i < nvec; ++i) t[0] += v[(size_t)i * stride] * h[i];
+    const double sum = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    we = w[base + e] + sign * sum;
     w[base + e] = we;
   }
   ws[e] = we;
