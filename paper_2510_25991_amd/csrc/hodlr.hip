@@ -467,13 +467,25 @@ __global__ __launch_bounds__(256) void k_hodlr_apply(const LrJob *__restrict__ j
     const int ncol = C.c1 - C.c0;
     if (C.rank < 0) {  // dense (square) leaf, stored row-major
       const F *Lf = store + C.off_u;
-      for (int r = threadIdx.x; r < rows; r += 256) {
-        Acc acc = 0;
-        if (!C.trans)
-          for (int c = 0; c < ncol; ++c) acc += (Acc)FactorIO<F>::get(Lf[(size_t)r * ncol + c]) * (Acc)xin[c];
-        else
-          for (int c = 0; c < ncol; ++c) acc += (Acc)FactorIO<F>::get(Lf[(size_t)c * rows + r]) * (Acc)xin[c];
-        yo[r] -= (double)acc;
+      if (!C.trans) {
+        // one wavefront per row, lanes along it (coalesced row reads)
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int r = wave; r < rows; r += 4) {
+          Acc acc = 0;
+          for (int c = lane; c < ncol; c += 64)
+            acc += (Acc)FactorIO<F>::get(Lf[(size_t)r * ncol + c]) * (Acc)xin[c];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+          if (lane == 0) yo[r] -= (double)acc;
+        }
+      } else {
+        // one thread per row: column c of the leaf is contiguous over rows
+        for (int r = threadIdx.x; r < rows; r += 256) {
+          Acc acc = 0;
+          for (int c = 0; c < ncol; ++c)
+            acc += (Acc)FactorIO<F>::get(Lf[(size_t)c * rows + r]) * (Acc)xin[c];
+          yo[r] -= (double)acc;
+        }
       }
       __syncthreads();
       continue;
