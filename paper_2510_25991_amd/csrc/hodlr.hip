@@ -10,8 +10,9 @@
 //      counter generator + Box-Muller), Y = B Omega                 (GEMM)
 //   2. Householder QR of Y, explicit Q (m x s)                     (FP64)
 //   3. X = B^T Q (n x s), so that B ~ Q X^T                         (GEMM)
-//   4. one-sided Jacobi on the columns of X: X V = Xt with orthogonal
-//      columns, sigma_k = |Xt_k| (relative-accurate singular values)
+//   4. Householder QR X = Q2 R (R s x s), one-sided Jacobi on the columns
+//      of R: R V = Rt with orthogonal columns, sigma_k = |Rt_k|, and
+//      Xt = X V = Q2 Rt (the rotations run on s rows instead of n)
 //   5. keep sigma_k > tol * ||S_{j,j'}||_2 (norm by power iteration):
 //      U = Q V_sel (m x r), Vt = Xt_sel^T (r x n), packed in BF16/FP32/FP64.
 // Apply: one work-group per (interface, row cluster) at each level sums all
@@ -202,6 +203,7 @@ __device__ double block_reduce_sum(double v, double *sh) {
 struct QrJob {
   double *A;  // m x s column-major
   int m;
+  double *R;  // optional: receives R (s x s, column-major, zero below the diagonal)
 };
 
 __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__ jobs, int s) {
@@ -251,6 +253,13 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
       const double w = t * dots[c];
       for (int i = j + 1 + threadIdx.x; i < m; i += 256) ac[i] -= w * a[i];
       if (threadIdx.x == 0) ac[j] -= w;
+    }
+    __syncthreads();
+  }
+  if (J.R) {  // R: the upper triangle left by the elimination
+    for (int e = threadIdx.x; e < s * s; e += 256) {
+      const int i = e % s, c = e / s;
+      J.R[e] = (i <= c && i < kmax) ? A[(size_t)c * m + i] : 0.0;
     }
     __syncthreads();
   }
@@ -367,6 +376,52 @@ __global__ __launch_bounds__(256) void k_col_norms(const JacJob *__restrict__ jo
     if (threadIdx.x == 0) sigma[(size_t)blockIdx.x * s + k] = sqrt(t);
     __syncthreads();
   }
+}
+
+// --------------------------------------------------- batched dense product
+// C (m x s) = A (m x s) B (s x s), all column-major FP64 (the orthogonalised
+// sample block Q R' after the Jacobi rotations of R).
+struct DenseGemmJob {
+  const double *A, *B;
+  double *C;
+  int m;
+};
+
+__global__ __launch_bounds__(256) void k_dense_gemm(const DenseGemmJob *__restrict__ jobs,
+                                                    int s) {
+  constexpr int TM = 64, TK = 32;
+  __shared__ double As[TK][TM + 1];  // A tile, k-major
+  __shared__ double Bs[TK][129];     // B rows k0.., s <= 128 columns
+  const DenseGemmJob J = jobs[blockIdx.y];
+  const int row0 = blockIdx.x * TM;
+  if (row0 >= J.m) return;
+  const int tid = threadIdx.x, tr = tid & 63, tc = tid >> 6;
+  double acc[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+  for (int k0 = 0; k0 < s; k0 += TK) {
+    __syncthreads();
+    for (int e = tid; e < TK * TM; e += 256) {
+      const int kk = e / TM, ii = e % TM, i = row0 + ii, k = k0 + kk;
+      As[kk][ii] = (i < J.m && k < s) ? J.A[(size_t)k * J.m + i] : 0.0;
+    }
+    for (int e = tid; e < TK * s; e += 256) {
+      const int kk = e / s, q = e % s, k = k0 + kk;
+      Bs[kk][q] = (k < s) ? J.B[(size_t)q * s + k] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < TK; ++kk) {
+      const double a = As[kk][tr];
+#pragma unroll
+      for (int q = 0; q < 32; ++q)
+        if (tc + 4 * q < s) acc[q] += a * Bs[kk][tc + 4 * q];
+    }
+  }
+  const int i = row0 + tr;
+  if (i < J.m)
+#pragma unroll
+    for (int q = 0; q < 32; ++q)
+      if (tc + 4 * q < s) J.C[(size_t)(tc + 4 * q) * J.m + i] = acc[q];
 }
 
 // ----------------------------------------------------------------- packing
@@ -775,6 +830,7 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     // ---- compress level by level (FP64 staging kept until packing)
     struct LevelData {
       DMem *Y = nullptr, *X = nullptr, *V = nullptr, *sig = nullptr, *sel = nullptr;
+      DMem *R = nullptr, *XR = nullptr;  // R of X = Q2 R, and X rotated (Q2 R J)
       int s = 0;
       std::vector<HBlock> blocks;
       std::vector<size_t> offY, offX;
@@ -818,35 +874,47 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       D.Y = new DMem(totY * 8); keep.push_back(D.Y);
       D.X = new DMem(totX * 8); keep.push_back(D.X);
       D.V = new DMem((size_t)nbk * s * s * 8); keep.push_back(D.V);
+      D.R = new DMem((size_t)nbk * s * s * 8); keep.push_back(D.R);
+      D.XR = new DMem(totX * 8); keep.push_back(D.XR);
       D.sig = new DMem((size_t)nbk * s * 8); keep.push_back(D.sig);
       DMem om((size_t)nmax * s * 8);
       hipLaunchKernelGGL(k_gaussian, dim3(nb((size_t)nmax * s)), dim3(256), 0, st,
                          static_cast<double *>(om.p), nmax, s, (unsigned long long)o.seed, (int)L);
       std::vector<BlockGemmJob> gy, gx;
-      std::vector<QrJob> qr;
+      std::vector<QrJob> qr, qx;
       std::vector<JacJob> jac;
+      std::vector<DenseGemmJob> rot;
       for (int b = 0; b < nbk; ++b) {
         const HBlock &hb = D.blocks[b];
         const int m = hb.r1 - hb.r0, n = hb.c1 - hb.c0;
         double *Yb = static_cast<double *>(D.Y->p) + D.offY[b];
         double *Xb = static_cast<double *>(D.X->p) + D.offX[b];
+        double *Rb = static_cast<double *>(D.R->p) + (size_t)b * s * s;
         gy.push_back({Sptr(hb.smat), hb.r0, hb.c0, m, n, Yb, static_cast<double *>(om.p)});
         gx.push_back({Sptr(hb.smat), hb.r0, hb.c0, m, n, Xb, Yb});
-        qr.push_back({Yb, m});
-        jac.push_back({Xb, static_cast<double *>(D.V->p) + (size_t)b * s * s, n});
+        qr.push_back({Yb, m, nullptr});
+        // X = Q2 R: the Jacobi rotations run on the s x s R instead of the
+        // n x s X (same singular values and rotations), then X J = Q2 (R J)
+        qx.push_back({Xb, n, Rb});
+        jac.push_back({Rb, static_cast<double *>(D.V->p) + (size_t)b * s * s, s});
+        rot.push_back({Xb, Rb, static_cast<double *>(D.XR->p) + D.offX[b], n});
       }
       const BlockGemmJob *dgy = static_cast<const BlockGemmJob *>(upload(gy, st, keep));
       const BlockGemmJob *dgx = static_cast<const BlockGemmJob *>(upload(gx, st, keep));
       const QrJob *dqr = static_cast<const QrJob *>(upload(qr, st, keep));
       const JacJob *djac = static_cast<const JacJob *>(upload(jac, st, keep));
+      const QrJob *dqx = static_cast<const QrJob *>(upload(qx, st, keep));
+      const DenseGemmJob *drot = static_cast<const DenseGemmJob *>(upload(rot, st, keep));
       hipLaunchKernelGGL(k_block_gemm<T>, dim3((mmax + 63) / 64, nbk), dim3(256), 0, st, dgy,
                          d_perm, op->ld, s, 0);
       hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(256), 0, st, dqr, s);
       hipLaunchKernelGGL(k_block_gemm<T>, dim3((nmax + 63) / 64, nbk), dim3(256), 0, st, dgx,
                          d_perm, op->ld, s, 1);
+      hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(256), 0, st, dqx, s);
       hipLaunchKernelGGL(k_jacobi, dim3(nbk), dim3(256), 0, st, djac, s, 30, (int *)nullptr);
       hipLaunchKernelGGL(k_col_norms, dim3(nbk), dim3(256), 0, st, djac, s,
                          static_cast<double *>(D.sig->p));
+      hipLaunchKernelGGL(k_dense_gemm, dim3((nmax + 63) / 64, nbk), dim3(256), 0, st, drot, s);
       HCHK(hipGetLastError());
       std::vector<double> sig((size_t)nbk * s);
       HCHK(hipMemcpyAsync(sig.data(), D.sig->p, sig.size() * 8, hipMemcpyDeviceToHost, st));
@@ -907,7 +975,7 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       std::vector<PackJob> pj;
       for (int b = 0; b < nbk; ++b) {
         const HBlock &hb = D.blocks[b];
-        pj.push_back({static_cast<double *>(D.Y->p) + D.offY[b], static_cast<double *>(D.X->p) + D.offX[b],
+        pj.push_back({static_cast<double *>(D.Y->p) + D.offY[b], static_cast<double *>(D.XR->p) + D.offX[b],
                       static_cast<double *>(D.V->p) + (size_t)b * D.s * D.s, static_cast<int *>(D.sel->p) + D.selofs[b],
                       hb.r1 - hb.r0, hb.c1 - hb.c0, hb.rank, (long long)hb.off_u,
                       (long long)hb.off_v});
