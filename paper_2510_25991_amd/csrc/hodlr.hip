@@ -295,22 +295,28 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
 }
 
 // -------------------------------------------------- one-sided Jacobi SVD
-// X (n x s, column-major) -> X V with mutually orthogonal columns; V (s x s,
-// column-major) accumulates the rotations.  Round-robin pair ordering, four
-// threads per pair; stops when a sweep performs no rotation.
+// X (n x s, column-major, n * s <= 128 * 128) -> X V with mutually
+// orthogonal columns; V (s x s, column-major) accumulates the rotations.
+// Round-robin pair ordering, four threads per pair; stops when a sweep
+// performs no rotation.
 struct JacJob {
   double *X;
   double *V;
   int n;
 };
 
+// The columns being rotated live in LDS (n * s <= kJacLds: the s x s R
+// factor of the sample block); V stays in global memory.
+constexpr int kJacLds = 128 * 128;
 __global__ __launch_bounds__(256) void k_jacobi(const JacJob *__restrict__ jobs, int s,
                                                 int max_sweeps, int *__restrict__ sweeps_out) {
   __shared__ int rotated;
+  __shared__ double X[kJacLds];
   const JacJob J = jobs[blockIdx.x];
   const int n = J.n;
-  double *X = J.X, *V = J.V;
+  double *V = J.V;
   for (int e = threadIdx.x; e < s * s; e += 256) V[e] = (e / s == e % s) ? 1.0 : 0.0;
+  for (int e = threadIdx.x; e < n * s; e += 256) X[e] = J.X[e];
   __syncthreads();
   const int grp = threadIdx.x >> 2, sub = threadIdx.x & 3;  // 64 pairs x 4 threads
   const int npairs = s / 2;
@@ -358,6 +364,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const JacJob *__restrict__ jobs,
     if (!rotated) break;
     __syncthreads();
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * s; e += 256) J.X[e] = X[e];
   if (threadIdx.x == 0 && sweeps_out) sweeps_out[blockIdx.x] = sweep;
 }
 
