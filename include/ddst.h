@@ -107,12 +107,16 @@ typedef struct {
   double tol;               /* target relative error of the refined solution   */
   double inner_tol;         /* relative residual of the interface GMRES per    */
                             /* refinement pass (default 1e-4 FP32, 1e-12 FP64) */
-  int32_t max_iter;         /* GMRES iteration cap (unrestarted; <= 20000; the */
+  int32_t max_iter;         /* GMRES iteration cap per pass (<= 20000; the     */
                             /* basis takes (max_iter+1)*N_ds*ld*8 device bytes) */
   int32_t max_outer;        /* FP64 refinement passes (>= 1)                   */
   int32_t use_hodlr;        /* 1: apply S through the compressed form          */
   int32_t matrix_free;      /* 1: apply S by sweeps with the stored factors,
                                without its blocks (exclusive with use_hodlr)   */
+  int32_t restart;          /* 0: unrestarted GMRES (the paper's); k > 0:
+                               restart every k iterations from the explicit
+                               residual (0 <= k <= max_iter)                   */
+  int32_t reserved;         /* must be 0                                       */
 } ddst_solve_opts_t;
 
 typedef struct {

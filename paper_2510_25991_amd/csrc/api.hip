@@ -535,6 +535,7 @@ struct SolveWs {
   double *fJ, *hh, *W, *xg;  // interface vectors (n_ds*ld)
   double *Zf, *Zb;           // padded volumes of the matrix-free apply's chains
   double *mfx, *mfv, *mff;   // interface vectors of the matrix-free apply
+  double *rr, *dx;           // restarted GMRES: residual and cycle correction
   double *V;                 // Krylov basis (max_iter+1) * n_ds*ld
   double *hd;                // small scalars
   double *part;              // transposed-GEMV partial sums
@@ -579,6 +580,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter, int nr = 1) {
   const size_t o_gm = cv.take(GmresDev::doubles(max_iter) * 8);
   const size_t o_zf = cv.take(vol * 8), o_zb = cv.take(vol * 8);
   const size_t o_mx = cv.take(ifc * 8), o_mv = cv.take(ifc * 8), o_mf = cv.take(ifc * 8);
+  const size_t o_rr = cv.take(ifc * 8), o_dx = cv.take(ifc * 8);
   ensure_ws(op, cv.off);
   auto at = [&](size_t x) {
     return reinterpret_cast<double *>(static_cast<unsigned char *>(op->ws) + x);
@@ -590,6 +592,7 @@ SolveWs carve_ws(ddst_op *op, int max_iter, int nr = 1) {
   w.gm.carve(at(o_gm), max_iter);
   w.Zf = at(o_zf); w.Zb = at(o_zb);
   w.mfx = at(o_mx); w.mfv = at(o_mv); w.mff = at(o_mf);
+  w.rr = at(o_rr); w.dx = at(o_dx);
   w.vol = vol1;
   w.ifc = ifc1;
   w.nr = nr;
@@ -817,8 +820,8 @@ void run_matfree(const ddst_op *op, const MatfreeTables &t, bool trans, const Ma
 constexpr int kGmresCheck = 8;
 
 template <typename T>
-int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
-          int max_iter, bool trans, int form, double *relres, hipStream_t s) {
+int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
+                int max_iter, bool trans, int form, double *relres, hipStream_t s) {
   const int nr = w.nr;
   if (trans && nr > 1) throw std::logic_error("the transposed solve takes one right-hand side");
   const size_t len = w.ifc * nr;
@@ -911,6 +914,89 @@ int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, 
   return used;
 }
 
+// out = S in (or S^T in) for the w.nr stacked interface vectors, through
+// form `form` (tables built per call: once per restart cycle).
+template <typename T>
+void stacked_apply(ddst_op *op, SolveWs &w, const void *G, int form, bool trans,
+                   const double *in, double *out, hipStream_t s) {
+  const int nr = w.nr;
+  if (form == DDST_APPLY_HODLR) {
+    for (int v = 0; v < nr; ++v) {
+      const size_t oi = (size_t)v * w.ifc;
+      if (hodlr_apply_jobs(op, in + oi, out + oi, trans ? 1 : 0, s))
+        throw HipError("compressed apply failed");
+    }
+  } else if (form == DDST_APPLY_MATFREE) {
+    launch_fill(w.Zf, 0.0, w.vol * nr, s);
+    launch_fill(w.Zb, 0.0, w.vol * nr, s);
+    for (int v = 0; v < nr; ++v) {
+      const size_t oi = (size_t)v * w.ifc, ov = (size_t)v * w.vol;
+      const MatfreeBufs b{const_cast<double *>(in) + oi, w.mfv + oi, w.mff + oi, w.Zf + ov,
+                          w.Zb + ov, out + oi};
+      MatfreeTables t;
+      make_matfree_tables(op, G, trans, b, t);
+      t.tab.upload(s);
+      run_matfree<T>(op, t, trans, b, w.part, s);
+      HIPCHK(hipStreamSynchronize(s));  // keeps the tables alive until done
+    }
+  } else {
+    JobTable t;
+    const size_t o = t.add(interface_jobs(op, in, out, trans));
+    t.upload(s);
+    if (trans)
+      launch_gemv<T>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, 1, -1.0, w.part, s);
+    else
+      launch_gemv_many<T>(t.at<GemvJob>(o), op->n_ds, op->ld, op->M, -1.0, nr, w.ifc, w.part,
+                          s);
+    HIPCHK(hipStreamSynchronize(s));
+  }
+}
+
+// GMRES for S x = rhs from x = 0: unrestarted (restart 0, or >= max_iter),
+// else cycles of at most `restart` iterations, each started from the
+// explicit residual rhs - S x, until the residual relative to ||rhs|| is
+// <= tol or max_iter iterations in all.  Returns the iterations used.
+template <typename T>
+int gmres(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
+          int max_iter, bool trans, int form, double *relres, hipStream_t s, int restart = 0) {
+  if (restart <= 0 || restart >= max_iter)
+    return gmres_cycle<T>(op, w, G, rhs, x, tol, max_iter, trans, form, relres, s);
+  const size_t len = w.ifc * w.nr;
+  launch_norm(rhs, len, w.nrm, w.dpart, s);
+  HIPCHK(hipMemcpyAsync(op->hbuf_host, w.nrm, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double beta0 = op->hbuf_host[0];
+  launch_fill(x, 0.0, len, s);
+  *relres = 0.0;
+  if (!(beta0 > 0.0)) return 0;
+  HIPCHK(hipMemcpyAsync(w.rr, rhs, len * 8, hipMemcpyDeviceToDevice, s));
+  double rnorm = beta0, res = 1.0;
+  int total = 0;
+  while (total < max_iter) {
+    const int m = std::min(restart, max_iter - total);
+    double rc = 0.0;
+    const int it = gmres_cycle<T>(op, w, G, w.rr, w.dx, tol * beta0 / rnorm, m, trans, form,
+                                  &rc, s);
+    launch_axpy(x, w.dx, 1.0, len, s);
+    total += it;
+    res = rc * rnorm / beta0;
+    if (res <= tol || it < m) break;  // converged, or the Krylov space ran out
+    // explicit residual for the next cycle
+    stacked_apply<T>(op, w, G, form, trans, x, w.W, s);
+    HIPCHK(hipMemcpyAsync(w.rr, rhs, len * 8, hipMemcpyDeviceToDevice, s));
+    launch_axpy(w.rr, w.W, -1.0, len, s);
+    launch_norm(w.rr, len, w.nrm, w.dpart, s);
+    HIPCHK(hipMemcpyAsync(op->hbuf_host, w.nrm, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rnorm = op->hbuf_host[0];
+    res = rnorm / beta0;
+    if (res <= tol) break;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  *relres = res;
+  return total;
+}
+
 // Pinned host staging for GMRES scalars: 2 (max_iter + 1) + 1 doubles per
 // Arnoldi step and max_iter coefficients at the end.
 void ensure_host(ddst_op *op, int max_iter) {
@@ -931,7 +1017,7 @@ void ensure_host(ddst_op *op, int max_iter) {
 template <typename T>
 int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const double *tol_inner,
                   int max_iter, int form, double *relres, SlabTables &loads,
-                  SlabTables &recon, hipStream_t s) {
+                  SlabTables &recon, hipStream_t s, int restart) {
   const int nr = w.nr;
   // z = A_II^{-1} r_I
   run_slab_solve<T>(op, loads, trans, w.part, s, nr, w.vol);
@@ -952,10 +1038,10 @@ int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const doub
     const size_t o = tb.add(sinv_jobs(op, w.fJ, w.hh));
     tb.upload(s);
     launch_gemv_many<T>(tb.at<GemvJob>(o), op->n_ds, op->ld, op->M, 1.0, nr, w.ifc, w.part, s);
-    it = gmres<T>(op, w, G, w.hh, w.xg, *tol_inner, max_iter, false, form, relres, s);
+    it = gmres<T>(op, w, G, w.hh, w.xg, *tol_inner, max_iter, false, form, relres, s, restart);
   } else {
     // S^T mu = f_J ; d_J = Sigma^{-T} mu
-    it = gmres<T>(op, w, G, w.fJ, w.hh, *tol_inner, max_iter, true, form, relres, s);
+    it = gmres<T>(op, w, G, w.fJ, w.hh, *tol_inner, max_iter, true, form, relres, s, restart);
     JobTable tb;
     const size_t o = tb.add(sinv_jobs(op, w.hh, w.xg));
     tb.upload(s);
@@ -1021,7 +1107,7 @@ int refine(ddst_op *op, const void *G, const double *f, const double *g, bool tr
     launch_fill(w.D, 0.0, w.vol * nr, s);
     double rr = 0;
     const int it = dd_correction<T>(op, w, G, trans, &o.inner_tol, o.max_iter, apply_form(o),
-                                    &rr, loads, recon, s);
+                                    &rr, loads, recon, s, o.restart);
     ro.gm_total += it;
     ro.gm_last = it;
     ro.relres = rr;
@@ -1065,6 +1151,8 @@ ddst_solve_opts_t solve_defaults(const ddst_op *op) {
   o.max_outer = 4;
   o.use_hodlr = 0;
   o.matrix_free = 0;
+  o.restart = 0;
+  o.reserved = 0;
   return o;
 }
 
@@ -1077,6 +1165,9 @@ int check_solve_opts(const ddst_solve_opts_t &o) {
     return fail(DDST_EINVAL, "use_hodlr and matrix_free must be 0 or 1");
   if (o.use_hodlr && o.matrix_free)
     return fail(DDST_EINVAL, "use_hodlr and matrix_free are exclusive");
+  if (o.restart < 0 || o.restart > o.max_iter)
+    return fail(DDST_EINVAL, "restart in [0, max_iter]");
+  if (o.reserved != 0) return fail(DDST_EINVAL, "reserved must be 0");
   return DDST_OK;
 }
 

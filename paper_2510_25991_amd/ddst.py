@@ -54,7 +54,8 @@ class CompressOptsC(ctypes.Structure):
 class SolveOptsC(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
-                ("use_hodlr", ctypes.c_int32), ("matrix_free", ctypes.c_int32)]
+                ("use_hodlr", ctypes.c_int32), ("matrix_free", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class StatsC(ctypes.Structure):
@@ -204,6 +205,7 @@ class SolveOptions:
     max_outer: int = 4
     use_hodlr: bool = False
     matrix_free: bool = False              # apply S by sweeps with the stored factors
+    restart: int = 0                       # 0: unrestarted GMRES; k: restart every k
 
 
 class Operator:
@@ -264,7 +266,7 @@ class Operator:
         # an operator without transfer blocks applies S matrix-free
         mf = o.matrix_free or not (self.transfer_blocks or o.use_hodlr)
         return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0,
-                          1 if mf else 0)
+                          1 if mf else 0, int(o.restart), 0)
 
     def solve(self, f=None, g=None, opts: Optional[SolveOptions] = None, want_gamma=True,
               allow_notconv=False):

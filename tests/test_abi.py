@@ -39,15 +39,34 @@ def test_binding_declares_every_export():
     ddst.load_library()
 
 
+def _c_sizes(names):
+    """sizeof of the header's structs as the C compiler lays them out."""
+    import subprocess
+    import tempfile
+    src = "#include <stdio.h>\n#include \"ddst.h\"\nint main(void) {\n"
+    src += "".join(f'  printf("%zu\\n", sizeof({n}));\n' for n in names) + "  return 0;\n}\n"
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "sizes.c"), os.path.join(d, "sizes")
+        open(c, "w").write(src)
+        inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+        r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", inc, "-I", "/opt/rocm/include",
+                            c, "-o", exe], capture_output=True, text=True)
+        if r.returncode != 0:
+            pytest.skip("cannot compile against the header: " + r.stderr[:200])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    return [int(v) for v in out.split()]
+
+
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libddst.so not built")
 def test_struct_layouts_match_header():
     """The ctypes mirrors have the sizes the C compiler gives the structs."""
     from paper_2510_25991_amd import ddst
-    assert ctypes.sizeof(ddst.ProblemC) == 56
-    assert ctypes.sizeof(ddst.BuildOptsC) == 16
-    assert ctypes.sizeof(ddst.CompressOptsC) == 40
-    assert ctypes.sizeof(ddst.SolveOptsC) == 32
-    assert ctypes.sizeof(ddst.StatsC) == 104
+    pairs = [("ddst_problem_t", ddst.ProblemC), ("ddst_build_opts_t", ddst.BuildOptsC),
+             ("ddst_compress_opts_t", ddst.CompressOptsC), ("ddst_solve_opts_t", ddst.SolveOptsC),
+             ("ddst_stats_t", ddst.StatsC)]
+    sizes = _c_sizes([n for n, _ in pairs])
+    for (name, cls), size in zip(pairs, sizes):
+        assert ctypes.sizeof(cls) == size, name
 
 
 def test_no_cpu_fallback_without_gpu():
