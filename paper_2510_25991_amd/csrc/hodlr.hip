@@ -531,15 +531,19 @@ __global__ __launch_bounds__(256) void k_hodlr_apply(const LrJob *__restrict__ j
     if (C.rank < 0) {  // dense (square) leaf, stored row-major
       const F *Lf = store + C.off_u;
       if (!C.trans) {
-        // one wavefront per row, lanes along it (coalesced row reads)
+        // 16 lanes per row, four rows per wavefront at a time (coalesced row
+        // reads, independent loads, a 16-lane reduction per row)
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (int r = wave; r < rows; r += 4) {
+        const int sub = lane >> 4, l16 = lane & 15;
+        for (int r0 = 4 * wave; r0 < rows; r0 += 16) {
+          const int r = r0 + sub;
           Acc acc = 0;
-          for (int c = lane; c < ncol; c += 64)
-            acc += (Acc)FactorIO<F>::get(Lf[(size_t)r * ncol + c]) * (Acc)xin[c];
+          if (r < rows)
+            for (int c = l16; c < ncol; c += 16)
+              acc += (Acc)FactorIO<F>::get(Lf[(size_t)r * ncol + c]) * (Acc)xin[c];
 #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-          if (lane == 0) yo[r] -= (double)acc;
+          for (int off = 8; off > 0; off >>= 1) acc += __shfl_down(acc, off, 16);
+          if (l16 == 0 && r < rows) yo[r] -= (double)acc;
         }
       } else {
         // one thread per row: column c of the leaf is contiguous over rows
