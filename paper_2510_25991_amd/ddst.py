@@ -129,7 +129,7 @@ def load_library(path: str = _LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{path} is missing: build it with paper_2510_25991_amd.build_lib.build()")
     L = ctypes.CDLL(path)
     vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER
     L.ddst_build_transfer.argtypes = [P(ProblemC), P(BuildOptsC), vp, P(vp)]
