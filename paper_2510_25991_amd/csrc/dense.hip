@@ -150,9 +150,10 @@ __device__ __forceinline__ int acc_col(int j) {
   return (wave & 1) * 64 + j * 16 + (lane & 15);
 }
 
+// FP64: at least two wavefronts per SIMD, as for the update
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm(const GemmJob *__restrict__ jobs, int ld,
-                                              int tiles_per_mat, T alpha, T beta) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gemm(
+    const GemmJob *__restrict__ jobs, int ld, int tiles_per_mat, T alpha, T beta) {
   __shared__ T As[BK][LW];
   __shared__ T Bs[BK][LW];
   const int total = gridDim.x;
@@ -533,8 +534,11 @@ __device__ __forceinline__ void sel_tile(int sel, int nt, int q, int t, int &tr,
   }
 }
 
+// FP64: at least two wavefronts per SIMD (its accumulators would otherwise
+// take the register file of two)
 template <typename T>
-__global__ __launch_bounds__(256) void k_gj_update(void *const *__restrict__ mats,
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gj_update(
+    void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
                                                    const T *__restrict__ Cbuf,
                                                    T *__restrict__ Cnext, int ld, int p,
