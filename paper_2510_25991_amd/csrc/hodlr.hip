@@ -206,10 +206,17 @@ struct QrJob {
   double *R;  // optional: receives R (s x s, column-major, zero below the diagonal)
 };
 
+__device__ __forceinline__ double qr_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;  // lane 0 holds the sum
+}
+
 __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__ jobs, int s) {
   __shared__ double tau[128];
   __shared__ double sh[8];
   __shared__ double dots[128];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const QrJob J = jobs[blockIdx.x];
   double *A = J.A;
   const int m = J.m;
@@ -239,13 +246,14 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
       tau[j] = t;
     }
     __syncthreads();
-    // apply H_j = I - t v v^T to the remaining columns
-    for (int c = j + 1; c < s; ++c) {
+    // apply H_j = I - t v v^T to the remaining columns: one wavefront per
+    // column for the dot products (no work-group barrier per column)
+    for (int c = j + 1 + wave; c < s; c += 4) {
       const double *ac = A + (size_t)c * m;
       double p2 = 0.0;
-      for (int i = j + 1 + threadIdx.x; i < m; i += 256) p2 += a[i] * ac[i];
-      const double d = block_reduce_sum(p2, sh) + ac[j];
-      if (threadIdx.x == 0) dots[c] = d;
+      for (int i = j + 1 + lane; i < m; i += 64) p2 += a[i] * ac[i];
+      p2 = qr_wave_sum(p2);
+      if (lane == 0) dots[c] = p2 + ac[j];
     }
     __syncthreads();
     for (int c = j + 1; c < s; ++c) {
@@ -268,12 +276,12 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
     const double t = tau[j];
     double *a = A + (size_t)j * m;
     // columns c > j currently hold Q's columns (rows >= j+1 meaningful, rows <= j set)
-    for (int c = j + 1; c < s; ++c) {
+    for (int c = j + 1 + wave; c < s; c += 4) {
       const double *ac = A + (size_t)c * m;
       double p2 = 0.0;
-      for (int i = j + 1 + threadIdx.x; i < m; i += 256) p2 += a[i] * ac[i];
-      const double d = block_reduce_sum(p2, sh);  // row j of column c is 0
-      if (threadIdx.x == 0) dots[c] = d;
+      for (int i = j + 1 + lane; i < m; i += 64) p2 += a[i] * ac[i];
+      p2 = qr_wave_sum(p2);  // row j of column c is 0
+      if (lane == 0) dots[c] = p2;
     }
     __syncthreads();
     for (int c = j + 1; c < s; ++c) {
