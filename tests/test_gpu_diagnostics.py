@@ -1,7 +1,8 @@
 """Diagnostics of the equilibrium system on the GPU (Section 5.2, Tables
-fd_poisson_fixedH and fd_shrinkingH): unrestarted GMRES iteration counts at
-relative tolerance 1e-8 and kappa_2(S_H) by power / inverse iteration,
-through the C-ABI, for the 3D Poisson problem on the unit cube.
+fd_poisson_fixedH, fd_shrinkingH and the Helmholtz block of fd_other_models):
+unrestarted GMRES iteration counts at relative tolerance 1e-8 and
+kappa_2(S_H) by power / inverse iteration, through the C-ABI, for the 3D
+Poisson and constant-wavenumber Helmholtz problems on the unit cube.
 
 Pins: kappa_2 against the separation-of-variables closed form (itself pinned
 to both printed tables by the CPU tests) to 1e-8 relative, and against the
@@ -43,8 +44,17 @@ def rows():
 
 
 def check_row(n, n_slabs, its_paper, kap_paper, precision):
+    ref = closed_form_kappa(n, n_slabs)
+    kap = check_solves(Problem(3, n, n_slabs), precision, ref, lambda it: abs(it - its_paper) <= 3,
+                       f"paper {its_paper}")
+    assert abs(kap - kap_paper) < 0.01
+
+
+def check_solves(p, precision, ref, its_ok, paper_note):
+    """GMRES on S for three seeded right-hand sides (true residual and the
+    iteration-count check its_ok) and kappa_2(S) against the closed form ref;
+    returns kappa_2."""
     dd = ddst()
-    p = Problem(3, n, n_slabs)
     op = dd.Operator.from_problem(p, precision=precision, keep_factors=False)
     its = []
     for seed in range(3):
@@ -57,15 +67,14 @@ def check_row(n, n_slabs, its_paper, kap_paper, precision):
         assert float(res.norm() / b.norm()) <= 1.01e-8
         its.append(it)
     smax, smin, kap = op.cond_estimate()
-    ref = closed_form_kappa(n, n_slabs)
-    print(f"  GMRES iterations {its} (paper {its_paper}); kappa {kap:.8f} closed form "
-          f"{ref:.8f} (paper {kap_paper})")
-    assert all(abs(it - its_paper) <= 3 for it in its)
+    print(f"  GMRES iterations {its} ({paper_note}); kappa {kap:.8f} closed form {ref:.8f}")
+    assert all(its_ok(it) for it in its)
     # FP32 blocks at m = 16 carry entry errors up to ~1e-4 relative (the
-    # transfer-block tolerance), which move kappa_2 by ~6e-4 here
-    assert abs(kap - ref) <= (1e-8 if precision == "fp64" else 2e-3) * ref
-    assert abs(kap - kap_paper) < 0.01
+    # transfer-block tolerance), which move kappa_2 by ~6e-4 for Poisson and
+    # by ~3e-3 for the near-resonant Helmholtz modes (N_lambda = 2)
+    assert abs(kap - ref) <= (1e-8 if precision == "fp64" else 4e-3) * ref
     op.close()
+    return kap
 
 
 @pytest.mark.parametrize("n,n_slabs,its_paper,kap_paper",
@@ -81,6 +90,50 @@ def test_fd_poisson_fixedH_largest_row():
     n, n_slabs, its_paper, kap_paper = [r for r in rows() if r[0] == 127][0]
     banner(f"Poisson 3D n={n} H=1/{n_slabs} (FP32 blocks)")
     check_row(n, n_slabs, its_paper, kap_paper, "fp32")
+
+
+def helmholtz(n, n_lambda):
+    """-Laplace(u) - k^2 u, k = 2 pi N_lambda, H = 1/8 (Table fd_other_models)."""
+    k2 = (2.0 * np.pi * n_lambda) ** 2
+    return Problem(3, n, 8, c=-k2 * np.ones((n,) * 3)), k2
+
+
+def check_helmholtz(n, n_lambda, precision):
+    """Iteration counts against the printed 128^3 ones within 15% (the
+    right-hand side is not stated; observed 26 / 58-60 at 32^3-64^3 and
+    25 / 67-68 at 128^3 against 27 / 61), kappa_2 against the closed form."""
+    its_paper = {r[0]: int(r[2]) for r in paper_tables()["fd_other_models_helmholtz"]}[n_lambda]
+    p, k2 = helmholtz(n, n_lambda)
+    check_solves(p, precision, closed_form_kappa(n, 8, k2),
+                 lambda it: abs(it - its_paper) <= 0.15 * its_paper,
+                 f"paper {its_paper} at 128^3")
+
+
+@pytest.mark.parametrize("n_lambda", [1, 2])
+@pytest.mark.parametrize("n", [31, 63])
+def test_fd_other_models_helmholtz(n, n_lambda):
+    banner(f"Helmholtz 3D n={n} H=1/8 N_lambda={n_lambda}: iterations and kappa_2(S_H)")
+    check_helmholtz(n, n_lambda, "fp64")
+
+
+def test_fd_other_models_helmholtz_indefinite_rejected():
+    """At N_lambda = 3, k^2 exceeds the lowest Dirichlet eigenvalue of a
+    double slab 1/4 wide (about 177.6), so the local problems are indefinite
+    and the elimination without pivoting reports them."""
+    banner("Helmholtz 3D n=31 H=1/8 N_lambda=3: indefinite double slabs")
+    dd = ddst()
+    p, _ = helmholtz(31, 3)
+    with pytest.raises(dd.DDSTError) as ei:
+        dd.Operator.from_problem(p, precision="fp64", keep_factors=False)
+    assert ei.value.code == dd.DDST_EBREAKDOWN
+
+
+@pytest.mark.skipif(os.environ.get("DDST_SLOW_TESTS") != "1",
+                    reason="N = 128^3 (about 80 s of GPU time); set DDST_SLOW_TESTS=1")
+@pytest.mark.parametrize("n_lambda", [1, 2])
+def test_fd_other_models_helmholtz_paper_size(n_lambda):
+    banner(f"Helmholtz 3D n=127 H=1/8 N_lambda={n_lambda} (FP32 blocks)")
+    check_helmholtz(127, n_lambda, "fp32")
 
 
 def test_gmres_forms_agree():

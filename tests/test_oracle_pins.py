@@ -34,18 +34,23 @@ def dst_transfer(n, m, dim):
     return W @ np.diag(1.0 / (2.0 * np.cosh(m * theta))) @ W.T
 
 
-def closed_form_kappa(n, n_slabs):
-    """kappa_2 of the 3D Poisson equilibrium matrix from its spectrum:
-    S = I - K with K block-tridiagonal with the same symmetric block s on both
-    off-diagonals, so its eigenvalues are 1 - 2 s_q cos(rho pi/(N_ds+1))."""
+def closed_form_kappa(n, n_slabs, k2=0.0):
+    """kappa_2 of the 3D equilibrium matrix of -Laplace(u) - k2 u from its
+    spectrum: S = I - K with K block-tridiagonal with the same symmetric block
+    s on both off-diagonals, so S is symmetric with eigenvalues
+    1 - 2 s_q cos(rho pi/(N_ds+1)).  Per tangential mode the centre value of
+    the double-slab recurrence is 1 / (2 T_m(z)), z = 1 + (lam - k2 h^2) / 2,
+    T_m the Chebyshev polynomial: cosh(m arccosh z) for z >= 1 (Poisson),
+    cos(m arccos z) where a shifted mode oscillates across the slab."""
     q = np.arange(1, n + 1)
     h = 1.0 / (n + 1)
     m = (n + 1) // n_slabs
     lam1 = 4.0 * np.sin(q * np.pi * h / 2) ** 2
     lam = (lam1[:, None] + lam1[None, :]).ravel()
-    s = 1.0 / (2.0 * np.cosh(m * np.arccosh(1.0 + lam / 2.0)))
+    z = 1.0 + (lam - k2 * h * h) / 2.0
+    s = 1.0 / (2.0 * np.polynomial.chebyshev.chebval(z, [0.0] * m + [1.0]))
     rho = np.arange(1, n_slabs)
-    ev = 1.0 - 2.0 * s[:, None] * np.cos(rho[None, :] * np.pi / n_slabs)
+    ev = np.abs(1.0 - 2.0 * s[:, None] * np.cos(rho[None, :] * np.pi / n_slabs))
     return ev.max() / ev.min()
 
 
@@ -87,6 +92,22 @@ def test_oracle_kappa_matches_paper_table(N):
     S = dd.DDOracle(Problem(3, n, 8)).assemble_S()
     kap = _kappa2(S)
     assert row[2] <= kap < row[2] + 0.01
+
+
+@pytest.mark.parametrize("n_lambda", [1, 2, 3])
+def test_oracle_helmholtz_kappa_matches_closed_form(n_lambda):
+    """The Chebyshev form of the closed form for -Laplace(u) - k^2 u (the
+    Helmholtz block of Table fd_other_models, k = 2 pi N_lambda) against
+    kappa_2 of the oracle's S from sparse local solves, including N_lambda = 3,
+    whose double slabs are indefinite; S is symmetric as the form says."""
+    n = 15
+    k2 = (2.0 * np.pi * n_lambda) ** 2
+    p = Problem(3, n, 8, c=-k2 * np.ones((n,) * 3))
+    S = dd.DDOracle(p).assemble_S()
+    assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+    ev = np.abs(np.linalg.eigvalsh(S))
+    assert abs(ev.max() / ev.min() - closed_form_kappa(n, 8, k2)) <= 1e-10 * ev.max() / ev.min()
+    assert abs(_kappa2(S) / closed_form_kappa(n, 8, k2) - 1.0) <= 1e-8
 
 
 def test_oracle_gmres_iterations_match_paper_table():
