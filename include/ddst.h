@@ -49,7 +49,8 @@ enum {
   DDST_EINVAL = -1,      /* bad shape, divisibility, NaN or kappa <= 0, NULL  */
   DDST_ENOMEM = -2,      /* device allocation failed                          */
   DDST_EHIP = -3,        /* a HIP runtime call failed                         */
-  DDST_EBREAKDOWN = -4,  /* non-finite or non-positive pivot in a local solve */
+  DDST_EBREAKDOWN = -4,  /* non-finite (or, by default, non-positive) pivot in a
+                            local solve */
   DDST_ERANK = -5,       /* HODLR rank cap exceeded                           */
   DDST_ESTATE = -6       /* operation not available in this operator state    */
 };
@@ -90,6 +91,13 @@ typedef struct {
                                needs keep_factors; solves then set
                                matrix_free, and the dense form, the compressed
                                form and ddst_get_transfer report ESTATE       */
+  int32_t indefinite;       /* 0: a non-positive pivot is a breakdown (the local
+                               problems are taken to be definite, as for
+                               diffusion and low-frequency Helmholtz); 1:
+                               negative pivots are accepted, for indefinite but
+                               nonsingular local problems (Helmholtz above the
+                               first double-slab resonance, Section 5.2); the
+                               elimination still does not pivot               */
 } ddst_build_opts_t;
 
 typedef struct {
@@ -141,12 +149,13 @@ typedef struct {
  * T_jj (Section 2.1, eq. efewin) and, if keep_factors, the per-plane inverse
  * Schur complements of a left-to-right sweep of every single slab.
  * prob: host struct; its device arrays are read during the call only.
- * opts: host struct or NULL (defaults: FP32, keep_factors=1).
+ * opts: host struct or NULL (defaults: FP32, keep_factors=1, the rest 0).
  * out: receives the new operator, or NULL on error.
  * Errors: EINVAL (shape/divisibility, kappa <= 0 or non-finite, c non-finite),
- *         ENOMEM, EHIP, EBREAKDOWN (a local elimination met a non-positive or
- *         non-finite pivot: the local problem is degenerate, cf. the remark on
- *         degenerate local problems in Section 2.2).
+ *         ENOMEM, EHIP, EBREAKDOWN (a local elimination met a non-finite pivot,
+ *         or a non-positive one unless opts->indefinite: the local problem is
+ *         degenerate, cf. the remark on degenerate local problems in Section
+ *         2.2, or indefinite).
  */
 int ddst_build_transfer(const ddst_problem_t *prob, const ddst_build_opts_t *opts,
                         hipStream_t stream, ddst_op_t **out);

@@ -280,8 +280,8 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
       launch_assemble<T>(tab.at<AsmJob>(off_asm[k - 1]), nsw, op->coef, op->n, op->dim, op->M,
                          ld, s);
       if (k >= 2) chain(k - 1);
-      HIPCHK(gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, gjw.p, op->flag, gs,
-                          s));
+      HIPCHK(gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, gjw.p, op->flag,
+                          op->indefinite, gs, s));
     }
     chain(m - 1);
     if (chains) HIPCHK(hipStreamWaitEvent(s, ev_y[m - 1], 0));
@@ -309,9 +309,13 @@ int check_flag(ddst_op *op, hipStream_t s, const char *what) {
   HIPCHK(hipStreamSynchronize(s));
   if (h) {
     HIPCHK(hipMemsetAsync(op->flag, 0, sizeof(int), s));
-    return fail(DDST_EBREAKDOWN, std::string(what) +
-                                     ": non-positive or non-finite pivot in a local "
-                                     "elimination (degenerate local problem)");
+    return fail(DDST_EBREAKDOWN,
+                std::string(what) +
+                    (op->indefinite ? ": zero or non-finite pivot in a local elimination "
+                                      "(degenerate local problem)"
+                                    : ": non-positive or non-finite pivot in a local "
+                                      "elimination (degenerate or indefinite local problem; "
+                                      "indefinite = 1 accepts the latter)"));
   }
   return DDST_OK;
 }
@@ -392,7 +396,8 @@ int build_impl(ddst_op *op, int keep, int blocks, hipStream_t s) {
   DeviceMem gjw(gj_workspace_bytes(nds, op->ld, sizeof(T)));
   GjStreams gs;
   HIPCHK(gs.create());
-  HIPCHK(gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, gjw.p, op->flag, gs, s));
+  HIPCHK(gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, gjw.p, op->flag, op->indefinite,
+                      gs, s));
   if (!sj.empty())
     launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, op->M, -1.0, 0.0, s);
   HIPCHK(hipGetLastError());
@@ -431,7 +436,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
   *out = nullptr;
   int st = validate_problem(prob);
   if (st) return st;
-  ddst_build_opts_t o{DDST_FP32, 1, 0, 0};
+  ddst_build_opts_t o{DDST_FP32, 1, 0, 0, 0};
   if (opts) o = *opts;
   if (o.precision != DDST_FP32 && o.precision != DDST_FP64)
     return fail(DDST_EINVAL, "precision must be DDST_FP32 or DDST_FP64");
@@ -440,6 +445,8 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     return fail(DDST_EINVAL, "skip_transfer must be 0 or 1");
   if (o.skip_transfer && !o.keep_factors)
     return fail(DDST_EINVAL, "skip_transfer needs keep_factors (the matrix-free apply reads them)");
+  if (o.indefinite != 0 && o.indefinite != 1)
+    return fail(DDST_EINVAL, "indefinite must be 0 or 1");
   const int blocks = o.skip_transfer ? 0 : 1;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -457,6 +464,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     op->N = (size_t)op->M * op->n;
     op->h = 1.0 / (prob->n + 1);
     op->prec = o.precision;
+    op->indefinite = o.indefinite;
     for (int a = 0; a < 3; ++a) op->bvec[a] = prob->bvec[a];
     op->mat_bytes = (size_t)op->ld * op->ld * esize(op->prec);
     const size_t ncell = (size_t)std::pow((double)(op->n + 1), op->dim) + 0.5;
@@ -1744,9 +1752,9 @@ int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipS
     HIPCHK(gs.create());
     int *flag = static_cast<int *>(fl.p);
     if (precision == DDST_FP32)
-      HIPCHK(gj_invert<float>(t.at<void *>(o), batch, ld, ld, w.p, flag, gs, stream));
+      HIPCHK(gj_invert<float>(t.at<void *>(o), batch, ld, ld, w.p, flag, 0, gs, stream));
     else
-      HIPCHK(gj_invert<double>(t.at<void *>(o), batch, ld, ld, w.p, flag, gs, stream));
+      HIPCHK(gj_invert<double>(t.at<void *>(o), batch, ld, ld, w.p, flag, 0, gs, stream));
     HIPCHK(hipGetLastError());
     int h = 0;
     HIPCHK(hipMemcpyAsync(&h, fl.p, sizeof(int), hipMemcpyDeviceToHost, stream));

@@ -214,7 +214,9 @@ __device__ __forceinline__ double row_bcast(double x, int k) {
 // held by one wavefront: lane l holds row l % 16, columns l / 16 + 4c in
 // v[c].  That is the A-operand layout of four chained 16x16x4 FP64 MFMAs
 // (v[c] feeds k = 4c + l / 16), so the inverse multiplies without a
-// reshuffle.  Returns false if a pivot is not positive and finite.
+// reshuffle.  Returns false if a pivot is not finite, or not positive
+// unless ANY_SIGN (indefinite, nonsingular blocks).
+template <bool ANY_SIGN>
 __device__ __forceinline__ bool leaf_invert16(double (&v)[4]) {
   const int l = threadIdx.x & 63;
   const int i = l & 15, g = l >> 4;
@@ -227,7 +229,7 @@ __device__ __forceinline__ bool leaf_invert16(double (&v)[4]) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) prow[c] = row_bcast(v[c], k);  // P[k][g + 4c]
     const double piv = bcast_lane(v[kc], kg * 16 + k);
-    ok = ok && piv > 0.0 && isfinite(piv);
+    ok = ok && isfinite(piv) && (ANY_SIGN ? piv != 0.0 : piv > 0.0);
     const double inv = 1.0 / piv;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -272,7 +274,7 @@ constexpr int kCqS = 20;        // LDS row stride of the column block (doubles)
 constexpr int kRqS = kNB + 16;  // LDS row stride of the row block (doubles)
 static_assert(kNB == 128, "the register layout below assumes 128-wide pivots");
 
-template <typename T>
+template <typename T, bool ANY_SIGN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj_pivot(void *const *__restrict__ mats,
                                                   T *__restrict__ Pinv,
                                                   const T *__restrict__ Rprev,
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj
     double v[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = Rq[buf][lc][16 * q + lr + 4 * c];
-    ok = leaf_invert16(v) && ok;
+    ok = leaf_invert16<ANY_SIGN>(v) && ok;
     f64x4 R[2];
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) {
@@ -761,7 +763,7 @@ GjStreams::~GjStreams() {
 // panel(q) waits for Ux(p).  The last step updates all tiles on s.
 template <typename T>
 hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
-                     GjStreams &gs, hipStream_t s) {
+                     int any_sign, GjStreams &gs, hipStream_t s) {
   if (nmat <= 0) return hipSuccess;
   static_assert(kNB == kTile, "one pivot block per tile row");
   const int nt = ld / kTile;
@@ -780,8 +782,8 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
     const ProfSpan ps = prof_open(KK_GJ_PANEL);
     const T *Rp = p >= 1 ? Rb[(p - 1) & 1] : nullptr;
     const T *Cp = p >= 1 ? Cb[(p - 1) & 1] : nullptr;
-    hipExtLaunchKernelGGL(k_gj_pivot<T>, dim3(nmat), dim3(256), 0, s, ps.a, ps.b, 0, mats,
-                          PinvT, Rp, Cp, ld, p, flag);
+    hipExtLaunchKernelGGL(any_sign ? k_gj_pivot<T, true> : k_gj_pivot<T, false>, dim3(nmat),
+                          dim3(256), 0, s, ps.a, ps.b, 0, mats, PinvT, Rp, Cp, ld, p, flag);
     prof_close(ps, KK_GJ_PANEL, (p >= 1 ? 4.0 : 2.0) * nmat * (double)kNB * kNB * kNB);
   };
   auto panel = [&](int p, hipEvent_t done) {
@@ -839,8 +841,8 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
                                    hipStream_t);                                           \
   template void launch_scale_cols<T>(const GemmJob *, int, int, double, hipStream_t);       \
   template void launch_gemm<T>(const GemmJob *, int, int, int, double, double, hipStream_t); \
-  template hipError_t gj_invert<T>(void *const *, int, int, int, void *, int *, GjStreams &, \
-                                   hipStream_t);
+  template hipError_t gj_invert<T>(void *const *, int, int, int, void *, int *, int,        \
+                                   GjStreams &, hipStream_t);
 DDST_INST(float)
 DDST_INST(double)
 #undef DDST_INST

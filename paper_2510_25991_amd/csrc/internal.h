@@ -152,11 +152,12 @@ struct GjStreams {
 // update to their own row block (on s), while the update of every other
 // tile of step p runs on gs.h.  work: gj_workspace_bytes
 // bytes (two R and two column panels, the pivot inverses); flag: device int
-// set to 1 when a pivot is non-positive or non-finite.  Everything is
-// ordered before later work on s when the call returns.
+// set to 1 when a pivot is non-finite, or non-positive unless any_sign is
+// non-zero.  Everything is ordered before later work on s when the call
+// returns.
 template <typename T>
 hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
-                     GjStreams &gs, hipStream_t s);
+                     int any_sign, GjStreams &gs, hipStream_t s);
 // Bytes of Gauss-Jordan workspace for nmat matrices.
 inline size_t gj_workspace_bytes(int nmat, int ld, size_t esz) {
   return (size_t)nmat * kNB * ld * esz * 4 + (size_t)nmat * kNB * kNB * esz;
@@ -277,6 +278,7 @@ struct ddst_op {
   void *S = nullptr;          // 2 n_ds matrices: S_{j,j-1}, S_{j,j+1}
   void *G = nullptr;          // n_slabs*(m-1) factor matrices (own allocation)
   int *flag = nullptr;        // device breakdown flag
+  int indefinite = 0;         // 1: negative pivots accepted (indefinite local problems)
   // compressed form (hodlr.hip)
   ddst::Hodlr *hodlr = nullptr;
   // reusable solve workspace (grown on demand)

@@ -41,7 +41,8 @@ class ProblemC(ctypes.Structure):
 
 class BuildOptsC(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("keep_factors", ctypes.c_int32),
-                ("transpose", ctypes.c_int32), ("skip_transfer", ctypes.c_int32)]
+                ("transpose", ctypes.c_int32), ("skip_transfer", ctypes.c_int32),
+                ("indefinite", ctypes.c_int32)]
 
 
 class CompressOptsC(ctypes.Structure):
@@ -213,9 +214,11 @@ class Operator:
 
     def __init__(self, dim, n, n_slabs, kappa=None, bvec=(0.0, 0.0, 0.0), c=None,
                  precision: str = "fp32", keep_factors: bool = True,
-                 transfer_blocks: bool = True):
+                 transfer_blocks: bool = True, indefinite: bool = False):
         """transfer_blocks=False: the matrix-free set-up (slab factors and
-        interface blocks only); solves then apply S matrix-free."""
+        interface blocks only); solves then apply S matrix-free.
+        indefinite=True: accept negative pivots (indefinite, nonsingular local
+        problems); by default they are reported as DDST_EBREAKDOWN."""
         if not torch.cuda.is_available():
             raise RuntimeError("ddst needs a ROCm GPU; no device is visible")
         L = load_library()
@@ -228,7 +231,7 @@ class Operator:
                               (ctypes.c_double * 3)(*[float(v) for v in b[:3]]), _ptr(self._c))
         self.transfer_blocks = bool(transfer_blocks)
         opts = BuildOptsC(FP32 if precision == "fp32" else FP64, 1 if keep_factors else 0, 0,
-                          0 if transfer_blocks else 1)
+                          0 if transfer_blocks else 1, 1 if indefinite else 0)
         h = ctypes.c_void_p()
         _check(L.ddst_build_transfer(ctypes.byref(self._prob), ctypes.byref(opts), _stream(),
                                      ctypes.byref(h)))
@@ -239,10 +242,11 @@ class Operator:
         self.M, self.n_ds, self.ld = M.value, nds.value, ld.value
 
     @classmethod
-    def from_problem(cls, prob, precision="fp32", keep_factors=True, transfer_blocks=True):
+    def from_problem(cls, prob, precision="fp32", keep_factors=True, transfer_blocks=True,
+                     indefinite=False):
         return cls(prob.dim, prob.n, prob.n_slabs, kappa=prob.kappa, bvec=prob.bvec, c=prob.c,
                    precision=precision, keep_factors=keep_factors,
-                   transfer_blocks=transfer_blocks)
+                   transfer_blocks=transfer_blocks, indefinite=indefinite)
 
     # -- lifetime --------------------------------------------------------
     def close(self):
