@@ -17,8 +17,8 @@ import pytest
 import torch
 
 from tests.golden.fixtures import paper_tables
-from problems import Problem
-from tests.test_oracle_pins import closed_form_kappa
+from problems import Problem, make_config
+from tests.test_oracle_pins import closed_form_kappa, mode_kappa
 
 pytestmark = pytest.mark.gpu
 
@@ -178,6 +178,42 @@ def test_indefinite_solve_matches_global_direct():
 def test_fd_other_models_helmholtz_paper_size(n_lambda):
     banner(f"Helmholtz 3D n=127 H=1/8 N_lambda={n_lambda} (FP32 blocks)")
     check_helmholtz(127, n_lambda, "fp32")
+
+
+@pytest.mark.parametrize("n", [31, 63])
+def test_fd_other_models_convection_diffusion(n):
+    """Convection-diffusion block of Table fd_other_models (its velocity is
+    not stated; b = (10, 0, 0) here): kappa_2 against the per-mode
+    decomposition (pinned to the oracle on the CPU) and the iteration counts
+    within 25% of the printed 20 (16-18 observed)."""
+    banner(f"convection-diffusion 3D n={n} H=1/8 b=(10,0,0)")
+    p = Problem(3, n, 8, bvec=(10.0, 0.0, 0.0))
+    check_solves(p, "fp64", mode_kappa(n, 8, 0.0, 10.0), lambda it: abs(it - 20) <= 5,
+                 "paper 20 for its unstated velocity")
+
+
+@pytest.mark.parametrize("n", [31, 63])
+def test_fd_other_models_variable_coefficient(n):
+    """Variable-coefficient diffusion block of Table fd_other_models (its
+    field is not stated; the 3D workload's log-normal field here): iteration
+    counts within +-3 of the printed 19; kappa_2 has no closed form and is
+    only printed."""
+    banner(f"variable-coefficient diffusion 3D n={n} H=1/8")
+    p = make_config("cfg4", n=n, n_slabs=8)
+    dd = ddst()
+    op = dd.Operator.from_problem(p, precision="fp64", keep_factors=False)
+    its = []
+    for seed in range(3):
+        b = torch.tensor(np.random.default_rng(seed).standard_normal(p.n_ds * op.M),
+                         device="cuda")
+        x, it, rr = op.gmres(b, tol=1e-8)
+        res = op.apply(x.reshape(-1)).reshape(-1) - b
+        assert float(res.norm() / b.norm()) <= 1.01e-8
+        its.append(it)
+    _, _, kap = op.cond_estimate()
+    print(f"  GMRES iterations {its} (paper 19); kappa {kap:.4f}")
+    assert all(abs(it - 19) <= 3 for it in its)
+    op.close()
 
 
 def test_gmres_forms_agree():

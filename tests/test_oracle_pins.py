@@ -73,6 +73,35 @@ def test_closed_form_reproduces_paper_kappa_tables():
         assert abs(closed_form_kappa(63, hinv) - kap) < 0.01, hinv
 
 
+def mode_kappa(n, n_slabs, k2=0.0, bx=0.0):
+    """kappa_2 of the 3D equilibrium matrix of -Laplace(u) + bx u_x - k2 u by
+    separation of variables without the Chebyshev shortcut: the sine modes in
+    y and z split S into one N_ds x N_ds tridiagonal Toeplitz matrix per mode,
+    I - s_l (subdiagonal) - s_r (superdiagonal), where s_l / s_r is the centre
+    value of the mode's 1D double-slab problem with unit data at its left /
+    right end (a dense 1D solve).  The change of basis is orthogonal, so the
+    singular values of S are those of the per-mode matrices (convection makes
+    them non-normal: kappa_2 is not an eigenvalue ratio)."""
+    h = 1.0 / (n + 1)
+    m = (n + 1) // n_slabs
+    q = np.arange(1, n + 1)
+    lam1 = 4.0 * np.sin(q * np.pi * h / 2) ** 2
+    lam = np.unique((lam1[:, None] + lam1[None, :]).ravel())
+    L, nds = 2 * m - 1, n_slabs - 1
+    lo, up = -(1.0 + bx * h / 2), -(1.0 - bx * h / 2)
+    smax, smin = 0.0, np.inf
+    for lq in lam:
+        T1 = (np.diag(np.full(L, 2.0 + lq - k2 * h * h)) + np.diag(np.full(L - 1, lo), -1)
+              + np.diag(np.full(L - 1, up), 1))
+        rhs = np.zeros((L, 2))
+        rhs[0, 0], rhs[-1, 1] = -lo, -up
+        s_l, s_r = np.linalg.solve(T1, rhs)[m - 1]
+        Tq = np.eye(nds) - s_l * np.eye(nds, k=-1) - s_r * np.eye(nds, k=1)
+        sv = np.linalg.svd(Tq, compute_uv=False)
+        smax, smin = max(smax, sv.max()), min(smin, sv.min())
+    return smax / smin
+
+
 def _kappa2(S):
     smax = svds(S, k=1, return_singular_vectors=False)[0]
     lu = sla.lu_factor(S)
@@ -108,6 +137,20 @@ def test_oracle_helmholtz_kappa_matches_closed_form(n_lambda):
     ev = np.abs(np.linalg.eigvalsh(S))
     assert abs(ev.max() / ev.min() - closed_form_kappa(n, 8, k2)) <= 1e-10 * ev.max() / ev.min()
     assert abs(_kappa2(S) / closed_form_kappa(n, 8, k2) - 1.0) <= 1e-8
+
+
+@pytest.mark.parametrize("k2,bx", [(0.0, 0.0), ((4 * np.pi) ** 2, 0.0), (0.0, 10.0),
+                                   (0.0, -25.0), ((2 * np.pi) ** 2, 10.0)])
+def test_oracle_kappa_matches_mode_decomposition(k2, bx):
+    """kappa_2 of the oracle's S (sparse local solves, 3D, n = 15, H = 1/8)
+    against the per-mode decomposition, which also reproduces the Chebyshev
+    closed form where that applies (no convection)."""
+    n = 15
+    p = Problem(3, n, 8, bvec=(bx, 0.0, 0.0), c=-k2 * np.ones((n,) * 3))
+    ref = mode_kappa(n, 8, k2, bx)
+    assert abs(_kappa2(dd.DDOracle(p).assemble_S()) / ref - 1.0) <= 1e-8
+    if bx == 0.0:
+        assert abs(closed_form_kappa(n, 8, k2) / ref - 1.0) <= 1e-11
 
 
 def test_oracle_gmres_iterations_match_paper_table():
