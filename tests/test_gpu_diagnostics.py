@@ -50,12 +50,13 @@ def check_row(n, n_slabs, its_paper, kap_paper, precision):
     assert abs(kap - kap_paper) < 0.01
 
 
-def check_solves(p, precision, ref, its_ok, paper_note):
+def check_solves(p, precision, ref, its_ok, paper_note, indefinite=False, kap_tol=None):
     """GMRES on S for three seeded right-hand sides (true residual and the
     iteration-count check its_ok) and kappa_2(S) against the closed form ref;
     returns kappa_2."""
     dd = ddst()
-    op = dd.Operator.from_problem(p, precision=precision, keep_factors=False)
+    op = dd.Operator.from_problem(p, precision=precision, keep_factors=False,
+                                  indefinite=indefinite)
     its = []
     for seed in range(3):
         b = torch.tensor(np.random.default_rng(seed).standard_normal(p.n_ds * op.M),
@@ -72,7 +73,9 @@ def check_solves(p, precision, ref, its_ok, paper_note):
     # FP32 blocks at m = 16 carry entry errors up to ~1e-4 relative (the
     # transfer-block tolerance), which move kappa_2 by ~6e-4 for Poisson and
     # by ~3e-3 for the near-resonant Helmholtz modes (N_lambda = 2)
-    assert abs(kap - ref) <= (1e-8 if precision == "fp64" else 4e-3) * ref
+    if kap_tol is None:
+        kap_tol = 1e-8 if precision == "fp64" else 4e-3
+    assert abs(kap - ref) <= kap_tol * ref
     op.close()
     return kap
 
@@ -98,15 +101,16 @@ def helmholtz(n, n_lambda):
     return Problem(3, n, 8, c=-k2 * np.ones((n,) * 3)), k2
 
 
-def check_helmholtz(n, n_lambda, precision):
+def check_helmholtz(n, n_lambda, precision, indefinite=False, kap_tol=None):
     """Iteration counts against the printed 128^3 ones within 15% (the
-    right-hand side is not stated; observed 26 / 58-60 at 32^3-64^3 and
-    25 / 67-68 at 128^3 against 27 / 61), kappa_2 against the closed form."""
+    right-hand side is not stated; observed 26 / 58-60 / 140-142 at
+    32^3-64^3 and 25 / 67-68 / 140 at 128^3 against 27 / 61 / 141), kappa_2
+    against the closed form."""
     its_paper = {r[0]: int(r[2]) for r in paper_tables()["fd_other_models_helmholtz"]}[n_lambda]
     p, k2 = helmholtz(n, n_lambda)
     check_solves(p, precision, closed_form_kappa(n, 8, k2),
                  lambda it: abs(it - its_paper) <= 0.15 * its_paper,
-                 f"paper {its_paper} at 128^3")
+                 f"paper {its_paper} at 128^3", indefinite, kap_tol)
 
 
 @pytest.mark.parametrize("n_lambda", [1, 2])
@@ -173,11 +177,17 @@ def test_indefinite_solve_matches_global_direct():
 
 
 @pytest.mark.skipif(os.environ.get("DDST_SLOW_TESTS") != "1",
-                    reason="N = 128^3 (about 80 s of GPU time); set DDST_SLOW_TESTS=1")
-@pytest.mark.parametrize("n_lambda", [1, 2])
-def test_fd_other_models_helmholtz_paper_size(n_lambda):
-    banner(f"Helmholtz 3D n=127 H=1/8 N_lambda={n_lambda} (FP32 blocks)")
-    check_helmholtz(127, n_lambda, "fp32")
+                    reason="N = 128^3 (40-80 s of GPU time each); set DDST_SLOW_TESTS=1")
+@pytest.mark.parametrize("n_lambda,precision", [(1, "fp32"), (2, "fp32"), (3, "fp64")])
+def test_fd_other_models_helmholtz_paper_size(n_lambda, precision):
+    """The printed size.  N_lambda = 3 takes FP64 blocks: its kappa_2 ~ 2.7e5
+    comes from a nearly resonant mode that FP32 blocks move by 13%; the
+    estimate itself is good to a few 1e-6 there (inner GMRES at 1e-12)."""
+    banner(f"Helmholtz 3D n=127 H=1/8 N_lambda={n_lambda} ({precision} blocks)")
+    if n_lambda == 3:
+        check_helmholtz(127, 3, precision, indefinite=True, kap_tol=1e-5)
+    else:
+        check_helmholtz(127, n_lambda, precision)
 
 
 @pytest.mark.parametrize("n", [31, 63])
