@@ -162,7 +162,7 @@ def test_fd_other_models_helmholtz_indefinite(n):
 def test_indefinite_solve_matches_global_direct():
     """The whole solve (FP32 blocks, FP64 refinement) of the N_lambda = 3
     Helmholtz problem with a seeded load against the oracle's sparse direct
-    solve."""
+    solve, and the adjoint gradient of a sensor loss against the oracle's."""
     from oracle import fd as ofd
     banner("indefinite Helmholtz 3D n=31 H=1/8: DD solve vs global direct")
     dd = ddst()
@@ -174,6 +174,17 @@ def test_indefinite_solve_matches_global_direct():
     err = float(np.abs(u.cpu().numpy().ravel() - ref).max() / np.abs(ref).max())
     print(f"  rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']}")
     assert st["status"] == 0 and err <= 1e-8
+    # the adjoint recomputes the slab eliminations under the same sign rule
+    from oracle import adjoint as oadj
+    from problems import sensor_nodes
+    sens = sensor_nodes(3, 31, 64, seed=1005)
+    data = np.random.default_rng(1006).standard_normal(64) * 0.01
+    gbar = oadj.sensor_loss_grad(ref, sens, data, p.N)
+    gref, _ = oadj.gradient(p, ref, gbar)
+    dk, sta = op.adjoint(u.reshape(-1), torch.tensor(gbar, device="cuda"))
+    aerr = float(np.abs(dk.cpu().numpy().ravel() - gref.ravel()).max() / np.abs(gref).max())
+    print(f"  adjoint rel err {aerr:.3e}")
+    assert sta["status"] == 0 and aerr <= 1e-8
     op.close()
 
 
