@@ -188,6 +188,27 @@ def test_indefinite_solve_matches_global_direct():
     op.close()
 
 
+def test_indefinite_oscillatory_wide_slabs():
+    """The 2D oscillatory workload (variable wavenumber, k^2 up to 3600) on
+    four slabs of 48 cells: its double slabs are half the domain wide, far
+    above their first resonance, and rejected by default; with indefinite=True
+    the solve matches the oracle's global direct one."""
+    from oracle import fd as ofd
+    banner("oscillatory 2D n=191, 4 slabs: indefinite double slabs")
+    dd = ddst()
+    p = make_config("cfg3", n=191, n_slabs=4)
+    with pytest.raises(dd.DDSTError) as ei:
+        dd.Operator.from_problem(p, precision="fp32")
+    assert ei.value.code == dd.DDST_EBREAKDOWN
+    op = dd.Operator.from_problem(p, precision="fp32", indefinite=True)
+    u, _, st = op.solve(p.f, opts=dd.SolveOptions(max_outer=20))
+    ref = ofd.solve_global(p)
+    err = float(np.abs(u.cpu().numpy().ravel() - ref).max() / np.abs(ref).max())
+    print(f"  rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']}")
+    assert st["status"] == 0 and err <= 1e-8
+    op.close()
+
+
 @pytest.mark.skipif(os.environ.get("DDST_SLOW_TESTS") != "1",
                     reason="N = 128^3 (40-80 s of GPU time each); set DDST_SLOW_TESTS=1")
 @pytest.mark.parametrize("n_lambda,precision", [(1, "fp32"), (2, "fp32"), (3, "fp64")])
