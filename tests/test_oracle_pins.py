@@ -34,6 +34,26 @@ def dst_transfer(n, m, dim):
     return W @ np.diag(1.0 / (2.0 * np.cosh(m * theta))) @ W.T
 
 
+@pytest.mark.parametrize("dim,n,n_slabs,k2", [(2, 31, 4, (6 * np.pi) ** 2),
+                                             (2, 63, 8, (20 * np.pi) ** 2),
+                                             (3, 15, 4, (3 * np.pi) ** 2)])
+def test_shifted_transfer_blocks_match_chebyshev_form(dim, n, n_slabs, k2):
+    """-Laplace(u) - k2 u with the double slabs past their first resonance
+    (indefinite local problems): the oracle's blocks against the sine-basis
+    form with centre values 1 / (2 T_m(z)), z = 1 + (lam - k2 h^2) / 2."""
+    p = Problem(dim, n, n_slabs, c=-k2 * np.ones((n,) * dim))
+    h = 1.0 / (n + 1)
+    q = np.arange(1, n + 1)
+    V = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(q, q) * np.pi / (n + 1))
+    lam1 = 4.0 * np.sin(q * np.pi * h / 2) ** 2
+    lam, W = (lam1, V) if dim == 2 else ((lam1[:, None] + lam1[None, :]).ravel(), np.kron(V, V))
+    z = 1.0 + (lam - k2 * h * h) / 2.0
+    assert z.min() < np.cos(np.pi / (2 * p.m))  # some mode oscillates past resonance
+    ref = W @ np.diag(1.0 / (2.0 * np.polynomial.chebyshev.chebval(z, [0.0] * p.m + [1.0]))) @ W.T
+    for key, B in dd.DDOracle(p).all_blocks().items():
+        assert np.abs(B - ref).max() <= 1e-11 * np.abs(ref).max(), key
+
+
 def closed_form_kappa(n, n_slabs, k2=0.0):
     """kappa_2 of the 3D equilibrium matrix of -Laplace(u) - k2 u from its
     spectrum: S = I - K with K block-tridiagonal with the same symmetric block
