@@ -188,6 +188,30 @@ def test_indefinite_solve_matches_global_direct():
     op.close()
 
 
+@pytest.mark.parametrize("dim,n,n_slabs,k2", [(2, 31, 4, (6 * np.pi) ** 2),
+                                             (2, 255, 4, (20 * np.pi) ** 2),
+                                             (3, 15, 4, (3 * np.pi) ** 2)])
+def test_indefinite_transfer_blocks_match_oracle(dim, n, n_slabs, k2):
+    """Transfer blocks (FP64) of shifted problems whose double slabs are past
+    their first resonance, under indefinite=True, against the oracle's sparse
+    local solves (which the CPU tests pin to the Chebyshev sine-basis form)."""
+    from oracle import dd as odd
+    banner(f"indefinite transfer blocks dim={dim} n={n} slabs={n_slabs} k^2={k2:.1f}")
+    p = Problem(dim, n, n_slabs, c=-k2 * np.ones((n,) * dim))
+    blocks = odd.DDOracle(p).all_blocks()
+    scale = max(np.abs(B).max() for B in blocks.values())
+    op = ddst().Operator.from_problem(p, precision="fp64", indefinite=True)
+    worst = 0.0
+    for j in range(1, p.n_ds + 1):
+        SL, SR = (t.cpu().numpy() for t in op.transfer(j))
+        refL = blocks.get((j, j - 1), np.zeros_like(SL))
+        refR = blocks.get((j, j + 1), np.zeros_like(SR))
+        worst = max(worst, np.abs(SL - refL).max() / scale, np.abs(SR - refR).max() / scale)
+    print(f"  max rel block error {worst:.3e}")
+    assert worst <= 1e-11  # the bar of the definite FP64 blocks; 6e-14-1.6e-12 observed
+    op.close()
+
+
 def test_indefinite_oscillatory_wide_slabs():
     """The 2D oscillatory workload (variable wavenumber, k^2 up to 3600) on
     four slabs of 48 cells: its double slabs are half the domain wide, far
