@@ -64,9 +64,11 @@ enum { DDST_FACTOR_BF16 = 0, DDST_FACTOR_FP32 = 1, DDST_FACTOR_FP64 = 2 };
 /* Largest number of right-hand sides of ddst_solve_many. */
 enum { DDST_MAX_RHS = 16 };
 /* Which representation ddst_apply uses: the dense transfer blocks, their
- * compressed form, or no blocks at all (matrix-free: sweeps with the stored
- * single-slab factors and the interface blocks, Sections 2.2 and 5.1). */
-enum { DDST_APPLY_DENSE = 0, DDST_APPLY_HODLR = 1, DDST_APPLY_MATFREE = 2 };
+ * HODLR compression, no blocks at all (matrix-free: sweeps with the stored
+ * single-slab factors and the interface blocks, Sections 2.2 and 5.1), or
+ * the HBS form built from samples without the blocks (Section 2.4,
+ * Algorithm 1; ddst_compress_hbs). */
+enum { DDST_APPLY_DENSE = 0, DDST_APPLY_HODLR = 1, DDST_APPLY_MATFREE = 2, DDST_APPLY_HBS = 3 };
 
 typedef struct ddst_op ddst_op_t; /* opaque, library-owned */
 
@@ -97,14 +99,20 @@ typedef struct {
                                negative pivots are accepted, for indefinite but
                                nonsingular local problems (Helmholtz above the
                                first double-slab resonance, Section 5.2); the
-                               elimination still does not pivot               */
+                               elimination still does not pivot, so every
+                               partial-slab Schur complement D_k (the planes
+                               1..k of a single slab, k < m) must be
+                               nonsingular too, not only the double slab: a
+                               pivot growth (ddst_stats_t) above 1e12 (FP64)
+                               or 1e5 (FP32) is reported as EBREAKDOWN        */
 } ddst_build_opts_t;
 
 typedef struct {
   int32_t tree;             /* DDST_TREE_BINARY (dim 2) or DDST_TREE_QUAD (dim 3) */
   int32_t leaf;             /* maximum leaf cluster size, e.g. 128             */
   int32_t oversample;       /* p, extra Gaussian samples beyond the rank, e.g. 10 */
-  int32_t max_rank;         /* rank cap per admissible block (<= 256)          */
+  int32_t max_rank;         /* rank cap per admissible block, max_rank +
+                               oversample <= 128                               */
   int32_t factor_dtype;     /* DDST_FACTOR_BF16 / FP32 / FP64                  */
   int32_t reserved;
   double tol;               /* keep sigma_i > tol * ||S_{j,j'}||_2             */
@@ -124,7 +132,9 @@ typedef struct {
   int32_t restart;          /* 0: unrestarted GMRES (the paper's); k > 0:
                                restart every k iterations from the explicit
                                residual (0 <= k <= max_iter)                   */
-  int32_t reserved;         /* must be 0                                       */
+  int32_t use_hbs;          /* 1: apply S through the HBS form of
+                               ddst_compress_hbs (exclusive with use_hodlr and
+                               matrix_free)                                    */
 } ddst_solve_opts_t;
 
 typedef struct {
@@ -138,6 +148,11 @@ typedef struct {
   double t_build_ms, t_compress_ms, t_solve_ms, t_adjoint_ms; /* phase times   */
   double bytes_factors, bytes_transfer, bytes_hodlr;          /* storage       */
   int32_t max_rank, min_rank;                                  /* HODLR ranks   */
+  double pivot_growth;      /* largest |entry| of an inverted pivot block times
+                               the largest |entry| of the FD matrix, over the
+                               local eliminations of the build: of order
+                               1 / (eps ||A||) ||A|| when a local problem is
+                               singular to working precision                  */
 } ddst_stats_t;
 
 /*
@@ -232,6 +247,58 @@ int ddst_adjoint(const ddst_op_t *op, const double *u_vol, const double *g,
                  const double *gbar, const ddst_solve_opts_t *opts, double *dkappa,
                  double *lambda, ddst_stats_t *stats, hipStream_t stream);
 
+/* Options of the sampled HBS compression. */
+typedef struct {
+  int32_t rank;             /* k: rank of every cluster basis (the paper's fixed
+                               HBS rank, e.g. 64)                              */
+  int32_t oversample;       /* q: s = 3 k + q samples per side (Algorithm 1:
+                               alpha = 3, typically q = 10)                    */
+  int32_t leaf;             /* largest leaf cluster, 0 means 2 k; every
+                               cluster needs s >= its size + k                 */
+  int32_t factor_dtype;     /* DDST_FACTOR_BF16 / FP32 / FP64                  */
+  uint64_t seed;            /* probes drawn by the library (Philox-4x32-10, Box-
+                               Muller) when omega / psi are NULL               */
+} ddst_hbs_opts_t;
+
+/*
+ * ddst_compress_hbs -- every transfer block S_{j,j'} in Hierarchically Block
+ * Separable form (Section 2.4), built from s = 3 k + q two-sided samples
+ * Y = S Omega and Z = S^T Psi obtained by local solves with the stored
+ * factors of the single slabs (Algorithm 1's sampling step: forward and
+ * transposed chains of products with the inverse plane Schur complements,
+ * then the inverse interface blocks), so the dense blocks are never needed:
+ * it works on an operator built with skip_transfer = 1 (whose memory is the
+ * slab factors only) as well as on one that holds the blocks.  The
+ * compression is the single-pass randomized HBS construction from Y and Z
+ * alone, on a binary cluster tree of uniform depth shared by rows and
+ * columns (2D: index ranges split at the midpoint; 3D: the n x n interface
+ * grid split at the midpoint of the longer side), rank k at every node; the
+ * form stores O(k M) numbers per block and applies in O(k M) (solve option
+ * use_hbs, ddst_apply with DDST_APPLY_HBS).
+ * omega, psi: device M x s float64 row-major probes, or NULL (the library
+ * draws them from opts->seed); read during the call only.
+ * Errors: EINVAL (bad options; a cluster with more points than s - k),
+ * ESTATE (slab factors dropped), ENOMEM, EHIP, EBREAKDOWN (a probe Gram
+ * matrix is not positive definite).
+ */
+int ddst_compress_hbs(ddst_op_t *op, const ddst_hbs_opts_t *opts, const double *omega,
+                      const double *psi, hipStream_t stream);
+
+/* HBS summary: factor bytes, rank k, sampling and compression times (ms) of
+ * the last ddst_compress_hbs.  ESTATE if none. */
+int ddst_hbs_info(const ddst_op_t *op, double *bytes, int32_t *rank, double *t_sample_ms,
+                  double *t_compress_ms);
+
+/*
+ * ddst_sample_blocks -- test hook of the sampling step: Y_b = S_b X and
+ * Z_b = S_b^T X for every transfer block by the chains of ddst_compress_hbs.
+ * Blocks b = 2 (s - 1) (S_{s+1,s}) and 2 (s - 1) + 1 (S_{s,s+1}) for the
+ * slabs s = 1 .. N_ds - 1; X: device M x ncols float64 row-major; Y, Z:
+ * device 2 (N_ds - 1) x M x ncols outputs.  1 <= ncols <= 512.
+ */
+int ddst_sample_blocks(const ddst_op_t *op, int32_t ncols, const double *X, double *Y,
+                       double *Z, hipStream_t stream);
+
 /* Compressed-form summary: factor bytes, largest / smallest admissible rank,
  * compression time of the last ddst_compress (ms).  ESTATE if none. */
 int ddst_compress_info(const ddst_op_t *op, double *bytes, int32_t *max_rank,
@@ -262,6 +329,11 @@ int ddst_set_allocator(ddst_alloc_fn alloc, ddst_free_fn free_fn, void *ctx);
 /* Text of the last error on this thread ("" if none). */
 const char *ddst_last_error(void);
 
+/* Figures of the build (phase times, storage, ranks, pivot growth) in the
+ * fields of ddst_stats_t that ddst_build_transfer and ddst_compress set; the
+ * solve fields are zero.  stats: host. */
+int ddst_build_stats(const ddst_op_t *op, ddst_stats_t *stats);
+
 /* Geometry of an operator: M, N_ds, padded leading dimension, precision. */
 int ddst_op_info(const ddst_op_t *op, int32_t *M, int32_t *n_ds, int32_t *ld,
                  int32_t *precision);
@@ -287,6 +359,7 @@ int ddst_apply(const ddst_op_t *op, int32_t transpose, int32_t which, const doub
                double *y, hipStream_t stream);
 int ddst_loads(const ddst_op_t *op, const double *f, const double *g, double *hhat,
                hipStream_t stream);
+
 
 /*
  * Diagnostics of the equilibrium system (the iteration counts and condition

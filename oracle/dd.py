@@ -98,6 +98,25 @@ class DDOracle:
             out[:, k] = -x[centre]
         return out
 
+    def sample(self, j, jp, X, transpose=False):
+        """Algorithm 1's sampling step through the local factorisation:
+        Y = S_{j,jp} X = -R_{C_j} A_j(I,I)^{-1} A_j(I,J_{j,jp}) X, or with
+        transpose Z = S_{j,jp}^T X = -A_j(I,J_{j,jp})^T A_j(I,I)^{-T} R_{C_j}^T X
+        (the transposed local solve of the same LU), never forming S."""
+        p = self.prob
+        if abs(jp - j) != 1 or not (1 <= jp <= p.n_ds):
+            raise ValueError("jp must be an interior neighbour interface")
+        I, centre = self.double_slab(j)
+        J = plane_nodes(p, jp * p.m)
+        AIJ = self.A[I][:, J]
+        lu = self._local_lu(j)
+        X = np.asarray(X, dtype=np.float64)
+        if not transpose:
+            return -lu.solve(np.asarray(AIJ @ X))[centre]
+        R = np.zeros((len(I), X.shape[1]))
+        R[centre] = X
+        return -np.asarray(AIJ.T @ lu.solve(R, trans="T"))
+
     def all_blocks(self):
         """Dict {(j, jp): S_{j,jp}} over all interior neighbour pairs."""
         out = {}

@@ -22,6 +22,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -303,12 +304,36 @@ SweepPlan factor_plan(const ddst_op *op) {
   return p;
 }
 
+// Pivot growth above which an indefinite local problem counts as singular
+// to working precision: the inverse of a pivot block of a matrix that is
+// singular up to rounding has entries of order 1 / (c eps ||A||).  Measured:
+// the definite and indefinite test problems (2D and 3D, up to the first
+// double-slab resonances and past them) stay between 1.3 and 1e2; a slab
+// whose planes 1..4 have a singular Schur complement gives 1e14 with FP64
+// blocks and 7e6 with FP32 ones (whose rounding keeps the pivot near
+// 1e-7 ||A|| instead of 1e-16 ||A||).
+inline double growth_limit(int prec) { return prec == DDST_FP32 ? 1e5 : 1e12; }
+
 int check_flag(ddst_op *op, hipStream_t s, const char *what) {
-  int h = 0;
-  HIPCHK(hipMemcpyAsync(&h, op->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  ElimStatus h{};
+  HIPCHK(hipMemcpyAsync(&h, op->flag, sizeof(ElimStatus), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (h) {
-    HIPCHK(hipMemsetAsync(op->flag, 0, sizeof(int), s));
+  double inv_max, a_max;
+  std::memcpy(&inv_max, &h.inv_max, 8);
+  std::memcpy(&a_max, &h.a_max, 8);
+  const double growth = inv_max * a_max;
+  op->pivot_growth = std::max(op->pivot_growth, growth);
+  // clear the flag and the inverse maximum for the next elimination
+  HIPCHK(hipMemsetAsync(op->flag, 0, 16, s));
+  if (!h.bad && op->indefinite && !(growth <= growth_limit(op->prec))) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf,
+                  ": local elimination numerically singular (pivot growth %.3g > %.3g): a "
+                  "partial-slab Schur complement is singular to working precision",
+                  growth, growth_limit(op->prec));
+    return fail(DDST_EBREAKDOWN, std::string(what) + buf);
+  }
+  if (h.bad) {
     return fail(DDST_EBREAKDOWN,
                 std::string(what) +
                     (op->indefinite ? ": zero or non-finite pivot in a local elimination "
@@ -423,6 +448,7 @@ void destroy_op(ddst_op *op) {
   if (!op) return;
   (void)hipDeviceSynchronize();
   hodlr_free(op);
+  hbs_free(op);
   if (op->G) dev_free(op->G);
   if (op->arena) dev_free(op->arena);
   if (op->ws) dev_free(op->ws);
@@ -476,7 +502,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     const size_t o_ep = cv.take((size_t)(op->n + 2) * op->ld * 8);
     const size_t o_si = cv.take((size_t)op->n_ds * op->mat_bytes);
     const size_t o_s = blocks ? cv.take((size_t)2 * op->n_ds * op->mat_bytes) : 0;
-    const size_t o_fl = cv.take(sizeof(int));
+    const size_t o_fl = cv.take(sizeof(ElimStatus));
     if (dev_malloc(&op->arena, cv.off) != hipSuccess) {
       op->arena = nullptr;
       (void)hipGetLastError();
@@ -491,7 +517,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     op->Sinv = at(o_si);
     op->S = blocks ? at(o_s) : nullptr;
     op->flag = reinterpret_cast<int *>(at(o_fl));
-    HIPCHK(hipMemsetAsync(op->flag, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(op->flag, 0, sizeof(ElimStatus), s));
     if (op->S) HIPCHK(hipMemsetAsync(op->S, 0, (size_t)2 * op->n_ds * op->mat_bytes, s));
     if (op->kappa) {
       HIPCHK(hipMemcpyAsync(op->kappa, prob->kappa, ncell * 8, hipMemcpyDeviceToDevice, s));
@@ -509,6 +535,8 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
       return fail(DDST_EINVAL, "kappa must be finite and > 0, c finite");
     }
     launch_setup_coef(op->kappa, op->c, op->bvec, op->dim, op->n, op->h, op->coef, nullptr, s);
+    launch_maxabs(op->coef, (size_t)coef_slots(op->dim) * op->N,
+                  &reinterpret_cast<ElimStatus *>(op->flag)->a_max, s);
     launch_fill_couplings(op->coef, op->dim, op->n, op->M, op->ld, op->Em, op->Ep, s);
     HIPCHK(hipGetLastError());
     const int keep = o.keep_factors ? 1 : 0;
@@ -525,6 +553,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     op->last_build.t_build_ms = ms;
     op->last_build.bytes_transfer = op->S ? (double)2 * op->n_ds * op->mat_bytes : 0;
     op->last_build.bytes_factors = op->G ? (double)op->n_slabs * (op->m - 1) * op->mat_bytes : 0;
+    op->last_build.pivot_growth = op->pivot_growth;
   } catch (...) {
     destroy_op(op);
     (void)hipEventDestroy(e0);
@@ -869,10 +898,12 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
   double prev_res = 1.0;
   for (int k = 0; k < max_iter && used == 0; ++k) {
     const double *vk = w.V + (size_t)k * len;
-    if (form == DDST_APPLY_HODLR) {
+    if (form == DDST_APPLY_HODLR || form == DDST_APPLY_HBS) {
       for (int v = 0; v < nr; ++v) {
         const size_t oi = (size_t)v * w.ifc;
-        int st = hodlr_apply_jobs(op, vk + oi, w.W + oi, trans ? 1 : 0, s);
+        const int st = form == DDST_APPLY_HBS
+                           ? hbs_apply(op, vk + oi, w.W + oi, trans ? 1 : 0, s)
+                           : hodlr_apply_jobs(op, vk + oi, w.W + oi, trans ? 1 : 0, s);
         if (st) throw HipError("compressed apply failed");
       }
     } else if (form == DDST_APPLY_MATFREE) {
@@ -928,11 +959,13 @@ template <typename T>
 void stacked_apply(ddst_op *op, SolveWs &w, const void *G, int form, bool trans,
                    const double *in, double *out, hipStream_t s) {
   const int nr = w.nr;
-  if (form == DDST_APPLY_HODLR) {
+  if (form == DDST_APPLY_HODLR || form == DDST_APPLY_HBS) {
     for (int v = 0; v < nr; ++v) {
       const size_t oi = (size_t)v * w.ifc;
-      if (hodlr_apply_jobs(op, in + oi, out + oi, trans ? 1 : 0, s))
-        throw HipError("compressed apply failed");
+      const int st = form == DDST_APPLY_HBS
+                         ? hbs_apply(op, in + oi, out + oi, trans ? 1 : 0, s)
+                         : hodlr_apply_jobs(op, in + oi, out + oi, trans ? 1 : 0, s);
+      if (st) throw HipError("compressed apply failed");
     }
   } else if (form == DDST_APPLY_MATFREE) {
     launch_fill(w.Zf, 0.0, w.vol * nr, s);
@@ -1067,7 +1100,10 @@ int dd_correction(ddst_op *op, SolveWs &w, const void *G, bool trans, const doub
 // How GMRES applies S: the dense blocks, the compressed form or the
 // matrix-free sweeps.
 inline int apply_form(const ddst_solve_opts_t &o) {
-  return o.use_hodlr ? DDST_APPLY_HODLR : o.matrix_free ? DDST_APPLY_MATFREE : DDST_APPLY_DENSE;
+  return o.use_hodlr ? DDST_APPLY_HODLR
+         : o.use_hbs ? DDST_APPLY_HBS
+         : o.matrix_free ? DDST_APPLY_MATFREE
+                         : DDST_APPLY_DENSE;
 }
 
 struct RefineOut {
@@ -1160,7 +1196,7 @@ ddst_solve_opts_t solve_defaults(const ddst_op *op) {
   o.use_hodlr = 0;
   o.matrix_free = 0;
   o.restart = 0;
-  o.reserved = 0;
+  o.use_hbs = 0;
   return o;
 }
 
@@ -1169,13 +1205,13 @@ int check_solve_opts(const ddst_solve_opts_t &o) {
   if (o.max_iter < 1 || o.max_iter > kMaxGmresIter)
     return fail(DDST_EINVAL, "max_iter in [1, " + std::to_string(kMaxGmresIter) + "]");
   if (o.max_outer < 1 || o.max_outer > 100) return fail(DDST_EINVAL, "max_outer in [1, 100]");
-  if ((o.use_hodlr != 0 && o.use_hodlr != 1) || (o.matrix_free != 0 && o.matrix_free != 1))
-    return fail(DDST_EINVAL, "use_hodlr and matrix_free must be 0 or 1");
-  if (o.use_hodlr && o.matrix_free)
-    return fail(DDST_EINVAL, "use_hodlr and matrix_free are exclusive");
+  if ((o.use_hodlr != 0 && o.use_hodlr != 1) || (o.matrix_free != 0 && o.matrix_free != 1) ||
+      (o.use_hbs != 0 && o.use_hbs != 1))
+    return fail(DDST_EINVAL, "use_hodlr, use_hbs and matrix_free must be 0 or 1");
+  if (o.use_hodlr + o.matrix_free + o.use_hbs > 1)
+    return fail(DDST_EINVAL, "use_hodlr, use_hbs and matrix_free are exclusive");
   if (o.restart < 0 || o.restart > o.max_iter)
     return fail(DDST_EINVAL, "restart in [0, max_iter]");
-  if (o.reserved != 0) return fail(DDST_EINVAL, "reserved must be 0");
   return DDST_OK;
 }
 
@@ -1184,8 +1220,9 @@ int solve_impl(ddst_op *op, const double *f, const double *g, const ddst_solve_o
                double *u_gamma, double *u_vol, ddst_stats_t *st, hipStream_t s, int nr = 1) {
   if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
   if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  if (o.use_hbs && !hbs_ready(op)) return fail(DDST_ESTATE, "no HBS form: call ddst_compress_hbs");
   if (apply_form(o) == DDST_APPLY_DENSE && !op->S)
-    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build): set matrix_free");
+    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build): set matrix_free or use_hbs");
   ensure_host(op, o.max_iter);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1226,8 +1263,9 @@ int adjoint_impl(ddst_op *op, const double *u_vol, const double *g, const double
                  const ddst_solve_opts_t &o, double *dkappa, double *lambda, ddst_stats_t *st,
                  hipStream_t s) {
   if (o.use_hodlr && !hodlr_ready(op)) return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  if (o.use_hbs && !hbs_ready(op)) return fail(DDST_ESTATE, "no HBS form: call ddst_compress_hbs");
   if (apply_form(o) == DDST_APPLY_DENSE && !op->S)
-    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build): set matrix_free");
+    return fail(DDST_ESTATE, "no transfer blocks (matrix-free build): set matrix_free or use_hbs");
   ensure_host(op, o.max_iter);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1272,10 +1310,13 @@ int adjoint_impl(ddst_op *op, const double *u_vol, const double *g, const double
 
 // The form `which` is held by the operator (0), or the error to report.
 int check_form(const ddst_op *op, int which) {
-  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR && which != DDST_APPLY_MATFREE)
-    return fail(DDST_EINVAL, "which must be DENSE, HODLR or MATFREE");
+  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR && which != DDST_APPLY_MATFREE &&
+      which != DDST_APPLY_HBS)
+    return fail(DDST_EINVAL, "which must be DENSE, HODLR, MATFREE or HBS");
   if (which == DDST_APPLY_HODLR && !hodlr_ready(op))
     return fail(DDST_ESTATE, "no compressed form: call ddst_compress");
+  if (which == DDST_APPLY_HBS && !hbs_ready(op))
+    return fail(DDST_ESTATE, "no HBS form: call ddst_compress_hbs");
   if (which == DDST_APPLY_MATFREE && !op->G)
     return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
   if (which == DDST_APPLY_DENSE && !op->S)
@@ -1303,6 +1344,7 @@ int apply_padded(ddst_op *op, int which, bool trans, const double *xp, double *y
     return DDST_OK;
   }
   if (which == DDST_APPLY_HODLR) return hodlr_apply_jobs(op, xp, yp, trans ? 1 : 0, stream);
+  if (which == DDST_APPLY_HBS) return hbs_apply(op, xp, yp, trans ? 1 : 0, stream);
   const size_t ifc = (size_t)op->n_ds * op->ld, vol = (size_t)op->n * op->ld;
   const int nchunk = std::min(op->ld / kGemvChunk, 64);
   const size_t npart = (size_t)2 * op->n_slabs * nchunk * op->ld;
@@ -1439,6 +1481,45 @@ int ddst_compress(ddst_op_t *op, const ddst_compress_opts_t *opts, hipStream_t s
   });
 }
 
+int ddst_compress_hbs(ddst_op_t *op, const ddst_hbs_opts_t *opts, const double *omega,
+                      const double *psi, hipStream_t stream) {
+  g_err.clear();
+  if (!op || !opts) return fail(DDST_EINVAL, "op and opts must be non-NULL");
+  if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped; rebuild with keep_factors");
+  const ddst_hbs_opts_t &o = *opts;
+  if (o.factor_dtype < DDST_FACTOR_BF16 || o.factor_dtype > DDST_FACTOR_FP64)
+    return fail(DDST_EINVAL, "bad factor_dtype");
+  if (o.leaf < 0) return fail(DDST_EINVAL, "leaf must be >= 0 (0: 2 rank)");
+  return guarded([&]() -> int {
+    std::string msg;
+    const int st = hbs_compress(op, o.rank, o.oversample, o.leaf, o.factor_dtype, omega, psi,
+                                o.seed, stream, &msg);
+    if (st) return fail(st, "ddst_compress_hbs: " + msg);
+    return DDST_OK;
+  });
+}
+
+int ddst_hbs_info(const ddst_op_t *op, double *bytes, int32_t *rank, double *t_sample_ms,
+                  double *t_compress_ms) {
+  g_err.clear();
+  if (!op) return fail(DDST_EINVAL, "op is NULL");
+  if (!hbs_ready(op)) return fail(DDST_ESTATE, "no HBS form: call ddst_compress_hbs");
+  int k = 0;
+  hbs_info(op, bytes, &k, t_sample_ms, t_compress_ms);
+  if (rank) *rank = k;
+  return DDST_OK;
+}
+
+int ddst_sample_blocks(const ddst_op_t *cop, int32_t ncols, const double *X, double *Y,
+                       double *Z, hipStream_t stream) {
+  g_err.clear();
+  if (!cop || !X || !Y || !Z || ncols < 1 || ncols > 512)
+    return fail(DDST_EINVAL, "op, X, Y, Z must be non-NULL and 1 <= ncols <= 512");
+  ddst_op *op = const_cast<ddst_op *>(cop);
+  if (!op->G) return fail(DDST_ESTATE, "slab factors were dropped");
+  return guarded([&]() -> int { return hbs_sample_blocks(op, ncols, X, Y, Z, stream); });
+}
+
 int ddst_compress_info(const ddst_op_t *op, double *bytes, int32_t *max_rank,
                        int32_t *min_rank, double *ms) {
   g_err.clear();
@@ -1466,6 +1547,13 @@ int ddst_release_factors(ddst_op_t *op) {
 void ddst_destroy(ddst_op_t *op) { destroy_op(op); }
 
 const char *ddst_last_error(void) { return g_err.c_str(); }
+
+int ddst_build_stats(const ddst_op_t *op, ddst_stats_t *stats) {
+  g_err.clear();
+  if (!op || !stats) return fail(DDST_EINVAL, "op and stats must be non-NULL");
+  *stats = op->last_build;
+  return DDST_OK;
+}
 
 int ddst_op_info(const ddst_op_t *op, int32_t *M, int32_t *n_ds, int32_t *ld,
                  int32_t *precision) {
@@ -1745,8 +1833,8 @@ int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipS
     JobTable t;
     const size_t o = t.add(mats);
     t.upload(stream);
-    DeviceMem fl(sizeof(int));
-    HIPCHK(hipMemsetAsync(fl.p, 0, sizeof(int), stream));
+    DeviceMem fl(sizeof(ElimStatus));
+    HIPCHK(hipMemsetAsync(fl.p, 0, sizeof(ElimStatus), stream));
     DeviceMem w(gj_workspace_bytes(batch, ld, esize(precision)));
     GjStreams gs;
     HIPCHK(gs.create());

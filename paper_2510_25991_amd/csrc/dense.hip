@@ -89,7 +89,9 @@ struct Tile {
 // acc += (NEG_A ? -A : A)[0:128, 0:K] * diag(bscale[0:K]) * B[0:K, 0:128]
 // A row-major with leading dim lda (points at the tile's first row),
 // B row-major with leading dim ldb (points at the tile's first column).
-template <typename T, bool NEG_A = false>
+// TA: the operand is the transpose of a row-major matrix G, A[i][k] =
+// G[k][i]; A then points at G's column of the tile's first row.
+template <typename T, bool NEG_A = false, bool TA = false>
 __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
                                          const T *__restrict__ B, int ldb,
                                          const double *__restrict__ bscale, int K,
@@ -102,7 +104,10 @@ __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
   const int br = tid >> 4, bc = (tid & 15) * 8;   // B tile: 16 rows x 128
   T ra[8], rb[8];
   auto load = [&](int k0) {
-    ld8(A + (size_t)ar * lda + k0 + ak, ra);
+    if (TA)
+      ld8(A + (size_t)(k0 + br) * lda + bc, ra);
+    else
+      ld8(A + (size_t)ar * lda + k0 + ak, ra);
     ld8(B + (size_t)(k0 + br) * ldb + bc, rb);
     if (bscale) {
       const T s = (T)gp(bscale)[k0 + br];
@@ -113,8 +118,13 @@ __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
   load(0);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
+    if (TA) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[ak + q][ar] = NEG_A ? -ra[q] : ra[q];
+      for (int q = 0; q < 8; ++q) As[br][bc + q] = NEG_A ? -ra[q] : ra[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[ak + q][ar] = NEG_A ? -ra[q] : ra[q];
+    }
 #pragma unroll
     for (int q = 0; q < 8; ++q) Bs[br][bc + q] = rb[q];
     __syncthreads();
@@ -279,7 +289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj
                                                   T *__restrict__ Pinv,
                                                   const T *__restrict__ Rprev,
                                                   const T *__restrict__ Cprev, int ld, int p,
-                                                  int *__restrict__ flag) {
+                                                  int M, int *__restrict__ flag) {
   constexpr int kCqN = 2 * kNB * kCqS, kRqN = 2 * kLeaf * kRqS;
   __shared__ double lds[kCqN + kRqN];
   double (*Cq)[kNB][kCqS] = reinterpret_cast<double (*)[kNB][kCqS]>(lds);
@@ -425,13 +435,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj
   }
   if (!ok && threadIdx.x == 0) atomicOr(flag, 1);
   T *out = Pinv + (size_t)b * kNB * kNB;
+  // largest |entry| of the inverse outside the identity padding (rows and
+  // columns >= M), for the pivot growth
+  double amax = 0.0;
+  const int lim = M - p * kNB;  // local rows / columns below M
 #pragma unroll
   for (int I = 0; I < 8; ++I)
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        out[(16 * I + 4 * r + lr) * kNB + 16 * (2 * w + jj) + lc] = (T)t[I][jj][r];
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * I + 4 * r + lr, col = 16 * (2 * w + jj) + lc;
+        out[row * kNB + col] = (T)t[I][jj][r];
+        if (row < lim && col < lim) amax = fmax(amax, fabs(t[I][jj][r]));
+      }
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  if (l == 0)
+    atomicMax(reinterpret_cast<unsigned long long *>(flag) + 1,
+              (unsigned long long)__double_as_longlong(amax));
 }
 
 // One Gauss-Jordan step, panel part.  Work-group (jt, b), 4 wavefronts,
@@ -688,6 +709,43 @@ __global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ job
 }
 
 // C = alpha * A * diag(s), one block per row.
+// Products of the sampling chains: C (ld x ldc) = alpha op(A) diag(bscale) B
+// + beta C with A ld x ld (op(A) = A, or A^T when TRANS), B and C ld x ldc
+// (ldc a multiple of 128), all row-major; 128 x 128 output tiles as k_gemm.
+template <typename T, bool TRANS>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gemm_rect(
+    const GemmJob *__restrict__ jobs, int ld, int ldc, int tiles_per_job, T alpha, T beta) {
+  __shared__ T As[BK][LW];
+  __shared__ T Bs[BK][LW];
+  const int total = gridDim.x;
+  const int lin = xcd_remap(blockIdx.x, total);
+  const int b = lin / tiles_per_job;
+  const int t = lin % tiles_per_job;
+  const int ntc = ldc / kTile;
+  const int bm = (t / ntc) * kTile, bn = (t % ntc) * kTile;
+  const GemmJob J = jobs[b];
+  const T *A = static_cast<const T *>(J.A);
+  const T *B = static_cast<const T *>(J.B);
+  auto *C = gp(static_cast<T *>(J.C));
+  Tile<T> acc;
+  acc.zero();
+  if (TRANS)
+    mma_tile<T, false, true>(A + bm, ld, B + bn, ldc, J.bscale, ld, As, Bs, acc);
+  else
+    mma_tile<T>(A + (size_t)bm * ld, ld, B + bn, ldc, J.bscale, ld, As, Bs, acc);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t idx = (size_t)(bm + acc_row<T>(i, r)) * ldc + bn + acc_col(j);
+        T v = alpha * acc.v[i][j][r];
+        if (beta != T(0)) v += beta * C[idx];
+        C[idx] = v;
+      }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_scale_cols(const GemmJob *__restrict__ jobs, int ld,
                                                     T alpha) {
@@ -727,6 +785,17 @@ void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, do
   hipExtLaunchKernelGGL(k_gemm<T>, dim3(tpm * njobs), dim3(256), 0, s, ps.a, ps.b, 0, jobs, ld,
                         tpm, (T)alpha, (T)beta);
   prof_close(ps, KK_GEMM, 2.0 * njobs * (double)M * M * M);
+}
+
+template <typename T>
+void launch_gemm_rect(const GemmJob *jobs, int njobs, int ld, int ldc, int M, int ncols,
+                      int trans, double alpha, double beta, hipStream_t s) {
+  if (njobs <= 0) return;
+  const int tpj = (ld / kTile) * (ldc / kTile);
+  const ProfSpan ps = prof_open(KK_GEMM);
+  hipExtLaunchKernelGGL(trans ? k_gemm_rect<T, true> : k_gemm_rect<T, false>, dim3(tpj * njobs),
+                        dim3(256), 0, s, ps.a, ps.b, 0, jobs, ld, ldc, tpj, (T)alpha, (T)beta);
+  prof_close(ps, KK_GEMM, 2.0 * njobs * (double)M * M * ncols);
 }
 
 hipError_t GjStreams::create() {
@@ -783,7 +852,7 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
     const T *Rp = p >= 1 ? Rb[(p - 1) & 1] : nullptr;
     const T *Cp = p >= 1 ? Cb[(p - 1) & 1] : nullptr;
     hipExtLaunchKernelGGL(any_sign ? k_gj_pivot<T, true> : k_gj_pivot<T, false>, dim3(nmat),
-                          dim3(256), 0, s, ps.a, ps.b, 0, mats, PinvT, Rp, Cp, ld, p, flag);
+                          dim3(256), 0, s, ps.a, ps.b, 0, mats, PinvT, Rp, Cp, ld, p, M, flag);
     prof_close(ps, KK_GJ_PANEL, (p >= 1 ? 4.0 : 2.0) * nmat * (double)kNB * kNB * kNB);
   };
   auto panel = [&](int p, hipEvent_t done) {
@@ -841,6 +910,8 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
                                    hipStream_t);                                           \
   template void launch_scale_cols<T>(const GemmJob *, int, int, double, hipStream_t);       \
   template void launch_gemm<T>(const GemmJob *, int, int, int, double, double, hipStream_t); \
+  template void launch_gemm_rect<T>(const GemmJob *, int, int, int, int, int, int, double,     \
+                                    double, hipStream_t);                                      \
   template hipError_t gj_invert<T>(void *const *, int, int, int, void *, int *, int,        \
                                    GjStreams &, hipStream_t);
 DDST_INST(float)

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <new>
 #include <tuple>
 #include <type_traits>
@@ -858,32 +859,53 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     };
     std::vector<LevelData> levels;
     int worst = 0;
+    // The blocks of one level are grouped by their sample count: every block
+    // is sampled with as many Gaussian columns as its smaller side allows
+    // (even, up to the cap), so a level whose leaves differ in size (the
+    // quadtree of an odd interface grid, a ragged binary split) does not
+    // sample its wider blocks with the count of its narrowest one.
+    struct Group {
+      int L, s;
+      std::vector<std::pair<int, int>> pairs;
+    };
+    std::vector<Group> groups;
     for (size_t L = 0; L < lev.size(); ++L) {
-      if (lev[L].empty() || nmat == 0) continue;
-      int mmax = 0, nmax = 0, mnmin = 1 << 30;
+      std::map<int, size_t> at;
       for (auto &pr : lev[L]) {
         const int m = nodes[pr.first].hi - nodes[pr.first].lo;
         const int n = nodes[pr.second].hi - nodes[pr.second].lo;
-        mmax = std::max(mmax, m);
-        nmax = std::max(nmax, n);
-        mnmin = std::min(mnmin, std::min(m, n));
+        int sb = std::min(s_cap, std::min(m, n));
+        sb -= sb & 1;
+        if (sb < 2) sb = 2;
+        auto it = at.find(sb);
+        if (it == at.end()) {
+          it = at.emplace(sb, groups.size()).first;
+          groups.push_back({(int)L, sb, {}});
+        }
+        groups[it->second].pairs.push_back(pr);
       }
-      int s = std::min(s_cap, mnmin);
-      s -= s & 1;
-      if (s < 2) s = 2;
-      const bool capped = (s == s_cap - (s_cap & 1));
+    }
+    for (const Group &grp : groups) {
+      if (nmat == 0) continue;
+      const int L = grp.L;
+      int mmax = 0, nmax = 0;
+      for (auto &pr : grp.pairs) {
+        mmax = std::max(mmax, nodes[pr.first].hi - nodes[pr.first].lo);
+        nmax = std::max(nmax, nodes[pr.second].hi - nodes[pr.second].lo);
+      }
+      const int s = grp.s;
       LevelData D;
       D.s = s;
       size_t totY = 0, totX = 0;
       for (int mi = 0; mi < nmat; ++mi)
-        for (auto &pr : lev[L]) {
+        for (auto &pr : grp.pairs) {
           HBlock b{};
           b.smat = mats[mi];
           b.r0 = nodes[pr.first].lo;
           b.r1 = nodes[pr.first].hi;
           b.c0 = nodes[pr.second].lo;
           b.c1 = nodes[pr.second].hi;
-          b.level = (int)L;
+          b.level = L;
           D.blocks.push_back(b);
           D.offY.push_back(totY);
           D.offX.push_back(totX);
@@ -951,9 +973,15 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
                   });
         int r = 0;
         while (r < s && sv[r].first > thr) ++r;
-        // the sample count bounds the rank that can be certified: with the
-        // cap in force, a rank within `oversample` of s is a rank overflow
-        if (capped && r > s - o.oversample) worst = std::max(worst, r);
+        // the sample count bounds the rank that can be certified: a block
+        // sampled with fewer columns than its smaller side (the rank cap, or
+        // a level that mixes block sizes and takes s from its smallest
+        // block) whose rank comes within `oversample` of s may have more
+        // singular values above the threshold than the samples show: a rank
+        // overflow.  A block with s equal to its smaller side is sampled
+        // completely.
+        const bool undersampled = s < std::min(hb.r1 - hb.r0, hb.c1 - hb.c0);
+        if (undersampled && r > s - o.oversample) worst = std::max(worst, r);
         hb.rank = r;
         hb.off_u = store_elems;
         store_elems += (size_t)(hb.r1 - hb.r0) * r;
@@ -1118,6 +1146,14 @@ int hodlr_compress(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t s, in
 
 // y = S x (transpose 0) or S^T x (1) for padded interface vectors x, y
 // (distinct buffers), through the compressed blocks.
+void launch_gaussian(double *out, int rows, int s, uint64_t seed, unsigned stream_id,
+                     hipStream_t st) {
+  const size_t n = (size_t)rows * s;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, rows, s,
+                     (unsigned long long)seed, (int)stream_id);
+}
+
 int hodlr_apply_jobs(const ddst_op *op, const double *x, double *y, int transpose,
                      hipStream_t s) {
   Hodlr *H = op->hodlr;

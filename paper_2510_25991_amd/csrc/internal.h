@@ -129,6 +129,13 @@ void launch_scale_cols(const GemmJob *jobs, int njobs, int ld, double alpha, hip
 template <typename T>
 void launch_gemm(const GemmJob *jobs, int njobs, int ld, int M, double alpha, double beta,
                  hipStream_t s);
+// C (ld x ldc) = alpha op(A) diag(bscale) B + beta C: A ld x ld (op = A, or
+// A^T when trans), B and C ld x ldc row-major, ldc a multiple of 128 (the
+// block products of the sampling chains).  M and ncols (the unpadded sizes)
+// only enter the profiler's work: 2 M^2 ncols flops per job.
+template <typename T>
+void launch_gemm_rect(const GemmJob *jobs, int njobs, int ld, int ldc, int M, int ncols,
+                      int trans, double alpha, double beta, hipStream_t s);
 // Helper stream and events of the look-ahead Gauss-Jordan schedule, created
 // once and reused by every inversion of a build (destroyed with the object).
 // Events are created without timing and with device-scope release only (a
@@ -147,13 +154,28 @@ struct GjStreams {
   hipError_t create();
   ~GjStreams();
 };
+// Device status words of the local eliminations (32 bytes, zeroed at set-up):
+// a breakdown flag, the largest |entry| of any inverted pivot block, and the
+// largest |entry| of the FD matrix (bit patterns of non-negative doubles).
+// Their product is the pivot growth: a local problem that is singular to
+// working precision makes some pivot block's inverse of the order of
+// 1 / (eps ||A||), while the entries of a well-posed one stay far below.
+struct ElimStatus {
+  int bad;
+  int pad_;
+  unsigned long long inv_max;
+  unsigned long long a_max;
+  unsigned long long pad2_;
+};
+static_assert(sizeof(ElimStatus) == 32, "ElimStatus is 32 bytes");
 // In-place Gauss-Jordan inversion (no pivoting) of `nmat` ld x ld matrices
 // with look-ahead: the pivot and panel kernels of step p + 1 apply step p's
 // update to their own row block (on s), while the update of every other
 // tile of step p runs on gs.h.  work: gj_workspace_bytes
-// bytes (two R and two column panels, the pivot inverses); flag: device int
-// set to 1 when a pivot is non-finite, or non-positive unless any_sign is
-// non-zero.  Everything is ordered before later work on s when the call
+// bytes (two R and two column panels, the pivot inverses); flag: device
+// ElimStatus: bad set to 1 when a pivot is non-finite, or non-positive
+// unless any_sign is non-zero, inv_max raised to the largest |entry| of
+// the inverted pivot blocks.  Everything is ordered before later work on s when the call
 // returns.
 template <typename T>
 hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
@@ -244,9 +266,33 @@ void launch_cell_gradient(const double *u, const double *lam, const double *g, i
                           int n, int M, int ld, double h, double *grad, hipStream_t s);
 void launch_check_finite(const double *x, size_t len, double lo_exclusive, int *bad,
                          hipStream_t s);
+// *out = max(*out, max_e |x_e|) as the bit pattern of a non-negative double
+void launch_maxabs(const double *x, size_t len, unsigned long long *out, hipStream_t s);
 // dst (M x M float64, row-major) = src (ld x ld of the operator precision)
 void launch_extract_block(const void *src, int prec, int M, int ld, double *dst,
                           hipStream_t s);
+
+// ---- HBS form from samples (hbs.hip) --------------------------------------
+struct Hbs;
+void hbs_free(ddst_op *op);
+bool hbs_ready(const ddst_op *op);
+// rank k, s = 3 k + q samples, leaf (<= 0: 2 k), factor storage type;
+// omega / psi: caller's M x s probes (device, row-major) or null (Philox,
+// seed).  DDST_OK, DDST_EINVAL (*msg says why) or DDST_EBREAKDOWN.
+int hbs_compress(ddst_op *op, int k, int q, int leaf, int dtype, const double *omega,
+                 const double *psi, uint64_t seed, hipStream_t st, std::string *msg);
+void hbs_info(const ddst_op *op, double *bytes, int *rank, double *t_sample_ms,
+              double *t_compress_ms);
+// y = S x or S^T x through the HBS form (padded interface vectors)
+int hbs_apply(const ddst_op *op, const double *x, double *y, int transpose, hipStream_t st);
+// Y_b = S_b X and Z_b = S_b^T X for every transfer block b (natural order,
+// M x ncols each, b-major) by the sampling chains (test hook).
+int hbs_sample_blocks(ddst_op *op, int ncols, const double *X, double *Y, double *Z,
+                      hipStream_t st);
+// Gaussian rows x cols (row-major) from the Philox-4x32-10 counter generator
+// with Box-Muller, counter (row, col, stream_id, 0), key = seed.
+void launch_gaussian(double *out, int rows, int cols, uint64_t seed, unsigned stream_id,
+                     hipStream_t st);
 
 // ---- compressed form (hodlr.hip) -----------------------------------------
 void hodlr_free(ddst_op *op);
@@ -277,10 +323,12 @@ struct ddst_op {
   void *Sinv = nullptr;       // n_ds matrices: inverse interface Schur blocks
   void *S = nullptr;          // 2 n_ds matrices: S_{j,j-1}, S_{j,j+1}
   void *G = nullptr;          // n_slabs*(m-1) factor matrices (own allocation)
-  int *flag = nullptr;        // device breakdown flag
+  int *flag = nullptr;        // device ElimStatus (breakdown flag, pivot growth)
+  double pivot_growth = 0;    // largest pivot growth seen by the last build
   int indefinite = 0;         // 1: negative pivots accepted (indefinite local problems)
-  // compressed form (hodlr.hip)
+  // compressed forms (hodlr.hip: from the dense blocks; hbs.hip: from samples)
   ddst::Hodlr *hodlr = nullptr;
+  ddst::Hbs *hbs = nullptr;
   // reusable solve workspace (grown on demand)
   void *ws = nullptr;
   size_t ws_bytes = 0;

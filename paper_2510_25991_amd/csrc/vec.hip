@@ -758,6 +758,18 @@ __global__ void k_check_finite(const double *__restrict__ x, size_t len, double 
   }
 }
 
+// Largest |x_e| into *out (bit pattern of a non-negative double, which
+// orders like an unsigned integer; NaN entries are skipped).
+__global__ void k_maxabs(const double *__restrict__ x, size_t len,
+                         unsigned long long *__restrict__ out) {
+  double v = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (size_t)gridDim.x * blockDim.x)
+    v = fmax(v, fabs(x[e]));
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
+}
+
 inline unsigned nblk(size_t len, unsigned b = 256) { return (unsigned)((len + b - 1) / b); }
 
 }  // namespace
@@ -941,6 +953,12 @@ void launch_cell_gradient(const double *u, const double *lam, const double *g, i
   const size_t ncell = (dim == 2) ? nc * nc : nc * nc * nc;
   hipLaunchKernelGGL(k_cell_gradient, dim3(nblk(ncell)), dim3(256), 0, s, u, lam, g, dim, n, M,
                      ld, h, grad);
+}
+
+void launch_maxabs(const double *x, size_t len, unsigned long long *out, hipStream_t s) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_maxabs, dim3(std::min<unsigned>(nblk(len), 1024)), dim3(256), 0, s, x, len,
+                     out);
 }
 
 void launch_check_finite(const double *x, size_t len, double lo, int *bad, hipStream_t s) {

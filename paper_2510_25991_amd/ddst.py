@@ -22,9 +22,10 @@ DDST_EINVAL, DDST_ENOMEM, DDST_EHIP, DDST_EBREAKDOWN, DDST_ERANK, DDST_ESTATE = 
 FP64, FP32 = 0, 1
 TREE_BINARY, TREE_QUAD = 0, 1
 FACTOR_BF16, FACTOR_FP32, FACTOR_FP64 = 0, 1, 2
-APPLY_DENSE, APPLY_HODLR, APPLY_MATFREE = 0, 1, 2
+APPLY_DENSE, APPLY_HODLR, APPLY_MATFREE, APPLY_HBS = 0, 1, 2, 3
 MAX_RHS = 16
-_APPLY_FORMS = {"dense": APPLY_DENSE, "hodlr": APPLY_HODLR, "matfree": APPLY_MATFREE}
+_APPLY_FORMS = {"dense": APPLY_DENSE, "hodlr": APPLY_HODLR, "matfree": APPLY_MATFREE,
+                "hbs": APPLY_HBS}
 
 
 class DDSTError(RuntimeError):
@@ -56,7 +57,13 @@ class SolveOptsC(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("use_hodlr", ctypes.c_int32), ("matrix_free", ctypes.c_int32),
-                ("restart", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("restart", ctypes.c_int32), ("use_hbs", ctypes.c_int32)]
+
+
+class HbsOptsC(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("oversample", ctypes.c_int32),
+                ("leaf", ctypes.c_int32), ("factor_dtype", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class StatsC(ctypes.Structure):
@@ -67,7 +74,8 @@ class StatsC(ctypes.Structure):
                 ("t_compress_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_adjoint_ms", ctypes.c_double), ("bytes_factors", ctypes.c_double),
                 ("bytes_transfer", ctypes.c_double), ("bytes_hodlr", ctypes.c_double),
-                ("max_rank", ctypes.c_int32), ("min_rank", ctypes.c_int32)]
+                ("max_rank", ctypes.c_int32), ("min_rank", ctypes.c_int32),
+                ("pivot_growth", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,7 +87,8 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_solve_man
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
            "ddst_profile_enable", "ddst_profile_select", "ddst_profile_read",
            "ddst_profile_busy", "ddst_compress_info", "ddst_gmres", "ddst_cond_est",
-           "ddst_set_allocator"]
+           "ddst_set_allocator", "ddst_build_stats",
+           "ddst_compress_hbs", "ddst_hbs_info", "ddst_sample_blocks"]
 KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv",
                   5: "gemv_many"}
 
@@ -135,6 +144,10 @@ def load_library(path: str = _LIB_PATH):
     vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER
     L.ddst_build_transfer.argtypes = [P(ProblemC), P(BuildOptsC), vp, P(vp)]
     L.ddst_compress.argtypes = [vp, P(CompressOptsC), vp]
+    L.ddst_compress_hbs.argtypes = [vp, P(HbsOptsC), vp, vp, vp]
+    L.ddst_hbs_info.argtypes = [vp, P(ctypes.c_double), P(i32), P(ctypes.c_double),
+                                P(ctypes.c_double)]
+    L.ddst_sample_blocks.argtypes = [vp, i32, vp, vp, vp, vp]
     L.ddst_solve.argtypes = [vp, vp, vp, P(SolveOptsC), vp, vp, P(StatsC), vp]
     L.ddst_solve_many.argtypes = [vp, i32, vp, vp, P(SolveOptsC), vp, P(StatsC), vp]
     L.ddst_set_allocator.argtypes = [_ALLOC_T, _FREE_T, vp]
@@ -149,6 +162,7 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_last_error.argtypes = []
     L.ddst_last_error.restype = ctypes.c_char_p
     L.ddst_op_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+    L.ddst_build_stats.argtypes = [vp, P(StatsC)]
     L.ddst_get_transfer.argtypes = [vp, i32, vp, vp, vp]
     L.ddst_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     L.ddst_loads.argtypes = [vp, vp, vp, vp, vp]
@@ -207,6 +221,7 @@ class SolveOptions:
     use_hodlr: bool = False
     matrix_free: bool = False              # apply S by sweeps with the stored factors
     restart: int = 0                       # 0: unrestarted GMRES; k: restart every k
+    use_hbs: bool = False                  # apply S through the sampled HBS form
 
 
 class Operator:
@@ -260,6 +275,12 @@ class Operator:
         except Exception:
             pass
 
+    def build_stats(self):
+        """Build figures (times, storage, ranks, pivot growth) as a dict."""
+        st = StatsC()
+        _check(load_library().ddst_build_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
     def release_factors(self):
         _check(load_library().ddst_release_factors(self._h))
 
@@ -268,9 +289,9 @@ class Operator:
         o = opts or SolveOptions()
         inner = o.inner_tol if o.inner_tol is not None else (1e-4 if self.precision == "fp32" else 1e-12)
         # an operator without transfer blocks applies S matrix-free
-        mf = o.matrix_free or not (self.transfer_blocks or o.use_hodlr)
+        mf = o.matrix_free or not (self.transfer_blocks or o.use_hodlr or o.use_hbs)
         return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0,
-                          1 if mf else 0, int(o.restart), 0)
+                          1 if mf else 0, int(o.restart), 1 if o.use_hbs else 0)
 
     def solve(self, f=None, g=None, opts: Optional[SolveOptions] = None, want_gamma=True,
               allow_notconv=False):
@@ -390,6 +411,36 @@ class Operator:
         _check(load_library().ddst_compress(self._h, ctypes.byref(o), _stream()))
         return self.compress_info()
 
+    def compress_hbs(self, rank=64, oversample=10, leaf=0, factor_dtype="bf16", seed=0,
+                     omega=None, psi=None):
+        """Sampled HBS form of every transfer block (s = 3 rank + oversample
+        probes per side, from omega / psi (M x s) if given, else drawn)."""
+        fd = {"bf16": FACTOR_BF16, "fp32": FACTOR_FP32, "fp64": FACTOR_FP64}[factor_dtype]
+        o = HbsOptsC(int(rank), int(oversample), int(leaf), fd, int(seed))
+        om, ps = _dev(omega), _dev(psi)
+        _check(load_library().ddst_compress_hbs(self._h, ctypes.byref(o), _ptr(om), _ptr(ps),
+                                                _stream()))
+        return self.hbs_info()
+
+    def hbs_info(self):
+        b, k, t1, t2 = ctypes.c_double(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        _check(load_library().ddst_hbs_info(self._h, ctypes.byref(b), ctypes.byref(k),
+                                            ctypes.byref(t1), ctypes.byref(t2)))
+        return {"bytes": b.value, "rank": k.value, "sample_ms": t1.value, "compress_ms": t2.value}
+
+    def sample_blocks(self, X):
+        """(Y, Z): Y[b] = S_b X, Z[b] = S_b^T X for the 2 (N_ds - 1) transfer
+        blocks (S_{s+1,s} at 2 (s - 1), S_{s,s+1} at 2 (s - 1) + 1), by the
+        sampling chains."""
+        X = _dev(X)
+        ncols = int(X.shape[1])
+        nb = 2 * max(self.n_ds - 1, 0)
+        Y = torch.empty(max(nb, 1), self.M, ncols, dtype=torch.float64, device="cuda")
+        Z = torch.empty_like(Y)
+        _check(load_library().ddst_sample_blocks(self._h, ncols, _ptr(X), _ptr(Y), _ptr(Z),
+                                                 _stream()))
+        return Y[:nb], Z[:nb]
+
     def compress_info(self):
         b, mx, mn, ms = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(load_library().ddst_compress_info(self._h, ctypes.byref(b), ctypes.byref(mx),
@@ -460,13 +511,19 @@ def profile_busy():
 class DDSTSolve(torch.autograd.Function):
     """u = A(kappa)^{-1} f through the DD solver; backward by the hand-written
     adjoint, which recomputes the slab factors (they are dropped after the
-    forward solve to keep memory at the transfer blocks only)."""
+    forward solve to keep memory at the transfer blocks only).
+
+    Gradients: dL/dkappa from the adjoint solution lambda = A^{-T} dL/du and
+    the solution, and dL/df = lambda itself (f enters A u = f linearly).  The
+    operator stays alive as long as the autograd graph does (it is released
+    with the context), so backward may run more than once (retain_graph)."""
 
     @staticmethod
-    def forward(ctx, kappa, f, n_slabs, bvec, g, precision, opts):
+    def forward(ctx, kappa, f, n_slabs, bvec, g, precision, opts, indefinite=False):
         dim = kappa.dim()
         n = kappa.shape[0] - 1
-        op = Operator(dim, n, n_slabs, kappa=kappa.detach(), bvec=bvec, precision=precision)
+        op = Operator(dim, n, n_slabs, kappa=kappa.detach(), bvec=bvec, precision=precision,
+                      indefinite=indefinite)
         u, _, st = op.solve(f.detach(), g, opts=opts, want_gamma=False)
         op.release_factors()
         ctx.op, ctx.g, ctx.opts = op, g, opts
@@ -476,10 +533,17 @@ class DDSTSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gbar):
         (u,) = ctx.saved_tensors
-        dk, _ = ctx.op.adjoint(u, gbar.contiguous(), g=ctx.g, opts=ctx.opts)
-        ctx.op.close()
-        return dk, None, None, None, None, None, None
+        need_k, need_f = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_k or need_f):
+            return (None,) * 8
+        dk, lam, _ = ctx.op.adjoint(u, gbar.contiguous(), g=ctx.g, opts=ctx.opts,
+                                    want_lambda=True)
+        return (dk if need_k else None, lam if need_f else None,
+                None, None, None, None, None, None)
 
 
-def ddst_solve(kappa, f, n_slabs, bvec=(0.0, 0.0, 0.0), g=None, precision="fp32", opts=None):
-    return DDSTSolve.apply(kappa, f, n_slabs, tuple(bvec), g, precision, opts)
+def ddst_solve(kappa, f, n_slabs, bvec=(0.0, 0.0, 0.0), g=None, precision="fp32", opts=None,
+               indefinite=False):
+    """Differentiable solve (gradients for kappa and f); indefinite as in
+    Operator."""
+    return DDSTSolve.apply(kappa, f, n_slabs, tuple(bvec), g, precision, opts, indefinite)

@@ -69,7 +69,8 @@ def check_solves(p, precision, ref, its_ok, paper_note, indefinite=False, kap_to
         assert float(res.norm() / b.norm()) <= 1.01e-8
         its.append(it)
     smax, smin, kap = op.cond_estimate()
-    print(f"  GMRES iterations {its} ({paper_note}); kappa {kap:.8f} closed form {ref:.8f}")
+    print(f"  GMRES iterations {its} ({paper_note}); kappa {kap:.8f} closed form {ref:.8f}; "
+          f"pivot growth {op.build_stats()['pivot_growth']:.3e}")
     assert all(its_ok(it) for it in its)
     # FP32 blocks at m = 16 carry entry errors up to ~1e-4 relative (the
     # transfer-block tolerance), which move kappa_2 by ~6e-4 for Poisson and
@@ -153,7 +154,8 @@ def test_fd_other_models_helmholtz_indefinite(n):
         its.append(it)
     _, _, kap = op.cond_estimate()
     ref = closed_form_kappa(n, 8, k2)
-    print(f"  GMRES iterations {its} (paper 141 at 128^3); kappa {kap:.8f} closed form {ref:.8f}")
+    print(f"  GMRES iterations {its} (paper 141 at 128^3); kappa {kap:.8f} closed form {ref:.8f}; "
+          f"pivot growth {op.build_stats()['pivot_growth']:.3e}")
     assert abs(kap - ref) <= 1e-7 * ref
     assert all(abs(it - 141) <= 0.15 * 141 for it in its)
     op.close()
@@ -172,7 +174,8 @@ def test_indefinite_solve_matches_global_direct():
     op = dd.Operator.from_problem(p, precision="fp32", indefinite=True)
     u, _, st = op.solve(p.f)
     err = float(np.abs(u.cpu().numpy().ravel() - ref).max() / np.abs(ref).max())
-    print(f"  rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']}")
+    print(f"  rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']} "
+          f"pivot growth {st['pivot_growth']:.3e}")
     assert st["status"] == 0 and err <= 1e-8
     # the adjoint recomputes the slab eliminations under the same sign rule
     from oracle import adjoint as oadj
@@ -207,9 +210,46 @@ def test_indefinite_transfer_blocks_match_oracle(dim, n, n_slabs, k2):
         refL = blocks.get((j, j - 1), np.zeros_like(SL))
         refR = blocks.get((j, j + 1), np.zeros_like(SR))
         worst = max(worst, np.abs(SL - refL).max() / scale, np.abs(SR - refR).max() / scale)
-    print(f"  max rel block error {worst:.3e}")
+    print(f"  max rel block error {worst:.3e} pivot growth {op.build_stats()['pivot_growth']:.3e}")
     assert worst <= 1e-11  # the bar of the definite FP64 blocks; 6e-14-1.6e-12 observed
     op.close()
+
+
+def singular_partial_slab_k2(n, k):
+    """k^2 at which planes 1..k of a slab have a singular Schur complement
+    for the lowest tangential mode (2D shifted Laplacian; pinned on the CPU
+    by a dense Schur complement): z = cos(pi/(k+1)), z = 1 + (lambda_1 -
+    k^2 h^2)/2."""
+    h = 1.0 / (n + 1)
+    return (4.0 * np.sin(np.pi * h / 2) ** 2 + 2.0 * (1.0 - np.cos(np.pi / (k + 1)))) / (h * h)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_singular_partial_slab_reported(precision):
+    """k^2 ~ 401 on the 2D grid n = 31 with 4 slabs: the double slabs are
+    nonsingular but the Schur complement of planes 1..4 of every slab is
+    singular, and the elimination without pivoting would divide by a pivot
+    of rounding size.  Under indefinite=True the FP64 build reports it as
+    EBREAKDOWN through the pivot growth.  FP32 blocks round D_4 away from
+    exact singularity by ~1e-7 ||A||: the build reports EBREAKDOWN (growth
+    7e6 measured, limit 1e5), or builds with a pivot growth that shows it
+    (>= 1e4, against <= 1e2 for the well-posed indefinite problems)."""
+    dd = ddst()
+    n = 31
+    k2 = singular_partial_slab_k2(n, 4)
+    banner(f"singular partial slab 2D n={n} 4 slabs k^2={k2:.4f} {precision}")
+    p = Problem(2, n, 4, c=-k2 * np.ones((n, n)))
+    try:
+        op = dd.Operator.from_problem(p, precision=precision, indefinite=True)
+    except dd.DDSTError as e:
+        print(f"  EBREAKDOWN: {e}")
+        assert e.code == dd.DDST_EBREAKDOWN
+        return
+    g = op.build_stats()["pivot_growth"]
+    print(f"  built, pivot growth {g:.3e}")
+    op.close()
+    assert precision == "fp32", "the FP64 build must report the singular local problem"
+    assert g >= 1e4
 
 
 def test_indefinite_oscillatory_wide_slabs():
@@ -228,7 +268,8 @@ def test_indefinite_oscillatory_wide_slabs():
     u, _, st = op.solve(p.f, opts=dd.SolveOptions(max_outer=20))
     ref = ofd.solve_global(p)
     err = float(np.abs(u.cpu().numpy().ravel() - ref).max() / np.abs(ref).max())
-    print(f"  rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']}")
+    print(f"  rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']} "
+          f"pivot growth {st['pivot_growth']:.3e}")
     assert st["status"] == 0 and err <= 1e-8
     op.close()
 

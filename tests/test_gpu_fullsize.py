@@ -17,6 +17,8 @@ import numpy as np
 import pytest
 import torch
 
+from tests.tol import fp32_block_tol
+
 from problems import make_config, sensor_nodes, fd_directions, perturbed_kappa
 from oracle import adjoint as oadj
 from oracle import dd as odd
@@ -131,7 +133,7 @@ def test_full_size_cfg3_hodlr():
     S = odd.DDOracle(p).transfer_block(j, j + 1)
     berr = rel(SR, S)
     print(f"  S_{j},{j+1} rel err {berr:.3e}")
-    assert berr <= max(1e-5, 4e-7 * p.m * p.m)
+    assert berr <= fp32_block_tol(p.m, p.M)
     # compression (leaf 128, tol 1e-8 with the FP32 floor 1e-6, oversampling 10)
     info = op.compress(tol=1e-8, leaf=128, oversample=10, max_rank=118, factor_dtype="bf16")
     nS = np.linalg.norm(S, 2)
@@ -163,12 +165,13 @@ def test_full_size_cfg3_hodlr():
     bw = float(np.abs(r).max() / (nA * np.abs(x).max()))
     print(f"  scaled FD residual {bw:.3e}")
     assert bw <= 1e-10
-    if os.environ.get("DDST_SLOW_TESTS") == "1":
-        print("  global direct solve (slow)", flush=True)
-        err = rel(x, ofd.solve_global(p))
-        print(f"  rel err vs global direct {err:.3e}")
-        assert err <= 1e-8
     op.close()
+    # the backward error does not bound the forward error of this
+    # near-resonant operator: compare with the oracle's global direct solve
+    print("  global direct solve (4.2M unknowns, about a minute)", flush=True)
+    err = rel(x, ofd.solve_global(p, ordering="MMD_AT_PLUS_A"))
+    print(f"  rel err vs global direct {err:.3e}")
+    assert err <= 1e-8
 
 
 def test_full_size_cfg4_3d_quadtree():
@@ -187,7 +190,7 @@ def test_full_size_cfg4_3d_quadtree():
     ref = odd.DDOracle(p).transfer_columns(j, j + 1, cols)
     berr = rel(SR, ref)
     print(f"  S_{j},{j+1}[:, 16 seeded columns] rel err {berr:.3e}")
-    assert berr <= max(1e-5, 4e-7 * p.m * p.m)
+    assert berr <= fp32_block_tol(p.m, p.M)
     info = op.compress(tol=1e-7, leaf=128, oversample=10, max_rank=118, factor_dtype="bf16")
     print(f"  ranks {info['min_rank']}..{info['max_rank']}, {info['bytes'] / 2**20:.1f} MiB, "
           f"{info['ms']:.0f} ms")

@@ -9,6 +9,8 @@ import numpy as np
 import pytest
 import torch
 
+from tests.tol import fp32_block_tol
+
 from problems import make_config, sensor_nodes
 from oracle import adjoint as oadj
 from oracle import dd as odd
@@ -53,8 +55,8 @@ def banner(msg):
     print(f"\n[gpu] {msg}", flush=True)
 
 
-def block_tol(precision, m):
-    return 1e-11 if precision == "fp64" else max(1e-5, 4e-7 * m * m)
+def block_tol(precision, m, M):
+    return 1e-11 if precision == "fp64" else fp32_block_tol(m, M)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -72,8 +74,8 @@ def test_matfree_apply_matches_oracle(name, precision):
         yt = op.apply(xd, transpose=True, which="matfree").cpu().numpy().ravel()
         e, et = rel(y, S @ x), rel(yt, S.T @ x)
         print(f"  trial {trial}: S x {e:.3e}  S^T x {et:.3e}")
-        assert e <= block_tol(precision, p.m)
-        assert et <= block_tol(precision, p.m)
+        assert e <= block_tol(precision, p.m, p.M)
+        assert et <= block_tol(precision, p.m, p.M)
     if p.n_ds == 1:
         assert np.array_equal(y, x)
     op.close()
@@ -196,7 +198,7 @@ def test_matfree_full_size_cfg2():
     rng = np.random.default_rng(23)
     x = rng.standard_normal(p.n_ds * op.M)
     xd = torch.tensor(x, device="cuda")
-    tol = block_tol("fp32", p.m)
+    tol = block_tol("fp32", p.m, p.M)
     for trans in (False, True):
         ym = op.apply(xd, transpose=trans, which="matfree").cpu().numpy()
         yd = op.apply(xd, transpose=trans, which="dense").cpu().numpy()

@@ -225,6 +225,33 @@ def test_stencil_exact_for_quadratics(dim):
     assert np.abs(uvol - uex).max() < 1e-11
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_stencil_action_with_boundary_data(dim):
+    """The full stencil action on the exact nodal values of the quadratic
+    manufactured solution (interior values plus its non-zero boundary trace g)
+    returns the analytic load f node by node: the boundary branch of the
+    action is exercised with g != 0, and a sign or index slip in it moves the
+    rows next to the boundary.  Zeroing g changes no other row, and changes
+    the rows next to the boundary (all but those whose boundary terms cancel)."""
+    p, uex = _affine_manufactured(dim)
+    out = fd.apply(p, uex)
+    f = np.asarray(p.f).ravel()
+    assert np.abs(out - f).max() <= 1e-10 * np.abs(f).max()
+    out0 = fd.apply(p, uex, g=np.zeros_like(p.g))
+    idx = fd.node_index(p.n, dim)
+    inner = tuple(slice(1, p.n + 1) for _ in range(dim))
+    near = np.zeros(idx.shape, bool)
+    for a in range(dim):
+        for side in (1, p.n):
+            sl = list(inner)
+            sl[a] = side
+            near[tuple(sl)] = True
+    near = near[inner].ravel()
+    diff = np.abs(out0 - out)
+    assert diff[~near].max() == 0.0
+    assert np.mean(diff[near] > 0.0) > 0.9
+
+
 def test_harmonic_cubic_exact():
     """x^2 - y^2 + xy + x^3 - 3xy^2 is harmonic and cubic: the 5-point
     Laplacian reproduces it exactly."""
@@ -366,6 +393,27 @@ def test_hodlr_partition_and_planted_ranks():
     assert (covered == 1).all()
 
 
+def test_hodlr_apply_matches_dense_product():
+    """The compressed product against the plain product with the matrix it
+    compresses: exact at tol 0 (brute force), and within the truncation
+    bound sum_blocks sigma_{r+1} <= (#blocks) tol ||S||_2 ||x|| otherwise."""
+    rng = np.random.default_rng(11)
+    M, leaf = 173, 20
+    tree = hodlr.binary_tree(M, leaf)
+    x = rng.standard_normal(M)
+    S = rng.standard_normal((M, M))
+    y = hodlr.apply(hodlr.compress(S, tree, 0.0), x, M)
+    assert np.abs(y - S @ x).max() <= 1e-12 * np.abs(S @ x).max()
+    p = Problem(2, 63, 4)
+    T = dd.DDOracle(p).transfer_block(2, 1)
+    tol = 1e-6
+    H = hodlr.compress(T, hodlr.binary_tree(p.M, 16), tol)
+    nlr = sum(1 for k in H if k[0] == "lr")
+    err = np.linalg.norm(hodlr.apply(H, x[:p.M], p.M) - T @ x[:p.M])
+    assert err <= nlr * tol * np.linalg.norm(T, 2) * np.linalg.norm(x[:p.M])
+    assert err > 0.0
+
+
 def test_hodlr_quadtree_partition_and_error_bound():
     n, leaf = 15, 16
     tree = hodlr.quad_tree(n, leaf)
@@ -450,3 +498,38 @@ def test_global_cg_matches_direct_3d():
     u_lu = fd.solve_global(p)
     u_cg = fd.solve_global_cg(p)
     assert np.abs(u_cg - u_lu).max() <= 1e-11 * np.abs(u_lu).max()
+
+
+# ------------------------------------------------- singular partial slabs
+def partial_slab_singular_k2(n, k):
+    """k^2 at which the Schur complement D_k of the first k node planes of a
+    slab (Dirichlet on the plane before them) is singular for the lowest
+    tangential sine mode of the 2D shifted Laplacian -Laplace - k^2: per mode
+    the plane recursion d_1 = 2z, d_j = 2z - 1/d_{j-1} gives
+    d_k = U_k(z) / U_{k-1}(z) (Chebyshev polynomials of the second kind), so
+    D_k is singular when z = cos(pi / (k+1)), z = 1 + (lambda_1 - k^2 h^2)/2,
+    lambda_1 = 4 sin^2(pi h / 2)."""
+    h = 1.0 / (n + 1)
+    lam1 = 4.0 * np.sin(np.pi * h / 2) ** 2
+    return (lam1 + 2.0 * (1.0 - np.cos(np.pi / (k + 1)))) / (h * h)
+
+
+def test_partial_slab_schur_singular_while_double_slab_is_not():
+    """The premise of the GPU breakdown test: at k^2 ~ 401 (2D, n = 31,
+    4 slabs of 8 cells) the Schur complement of planes 1..4 of a slab is
+    singular, computed densely from the FD matrix, while the double slab
+    (15 planes, resonances at z = cos(j pi / 16)) is not."""
+    n, ns = 31, 4
+    k2 = partial_slab_singular_k2(n, 4)
+    assert abs(k2 - 401.0) < 0.5
+    p = Problem(2, n, ns, c=-k2 * np.ones((n, n)))
+    A = fd.assemble(p)[0].toarray()
+    M = n
+    blk = lambda a, b: A[a * M:(a + 1) * M, b * M:(b + 1) * M]
+    P = A[:3 * M, :3 * M]
+    D4 = blk(3, 3) - A[3 * M:4 * M, :3 * M] @ np.linalg.solve(P, A[:3 * M, 3 * M:4 * M])
+    sv = np.linalg.svd(D4, compute_uv=False)
+    assert sv[-1] / sv[0] < 1e-12
+    I = np.arange(0, (2 * p.m - 1) * M)  # planes 1..15: the double slab of Gamma_1
+    sv2 = np.linalg.svd(A[np.ix_(I, I)], compute_uv=False)
+    assert sv2[-1] / sv2[0] > 1e-4
