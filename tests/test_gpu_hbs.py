@@ -1,0 +1,171 @@
+"""Sampled construction without the dense blocks and its HBS form (through
+the C-ABI), against the oracle.
+
+* The sampling step (Algorithm 1: Y = S Om by forward and Z = S^T Ps by
+  transposed local solves, here chains of products with the stored slab
+  factors) against the oracle's sparse local solves, block by block: FP64
+  1e-11, FP32 the transfer-block bound of tests/tol.py.
+* The HBS form built from the same probes as the oracle's (the probes are an
+  input of both) against the oracle's HBS form of its own samples: the
+  products agree to 1e-9 (FP64 samples and factors), and both are as close
+  to the dense operator as the rank allows.
+* Solves through the HBS form of an operator built without transfer blocks
+  (FP32 build, BF16 factors, FP64 refinement) against the oracle's global
+  solve: 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+from problems import make_config
+from oracle import dd as odd
+from oracle import fd as ofd
+from oracle import hbs as ohbs
+from tests.tol import fp32_block_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def ddst():
+    from paper_2510_25991_amd import ddst as mod
+    return mod
+
+
+def banner(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+CASES = {
+    "cfg2s": lambda: make_config("cfg2", n=255, n_slabs=8),   # 2D, M = 255, m = 32
+    "cfg3s": lambda: make_config("cfg3", n=191, n_slabs=48),  # 2D oscillatory, m = 4
+    "cfg4s": lambda: make_config("cfg4", n=23, n_slabs=4),    # 3D, M = 529, m = 6
+}
+
+
+def blocks_of(p):
+    """(b, j, jp) of the 2 (N_ds - 1) transfer blocks in the library's order."""
+    out = []
+    for s in range(1, p.n_slabs - 1):
+        out.append((2 * (s - 1), s + 1, s))
+        out.append((2 * (s - 1) + 1, s, s + 1))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_sampling_matches_oracle_local_solves(name, precision):
+    p = CASES[name]()
+    banner(f"sampling chains {name} n={p.n} slabs={p.n_slabs} {precision}")
+    op = ddst().Operator.from_problem(p, precision=precision, transfer_blocks=False)
+    X = np.random.default_rng(31).standard_normal((p.M, 9))
+    Y, Z = (t.cpu().numpy() for t in op.sample_blocks(X))
+    o = odd.DDOracle(p)
+    tol = 1e-11 if precision == "fp64" else fp32_block_tol(p.m, p.M)
+    worst = 0.0
+    for b, j, jp in blocks_of(p):
+        worst = max(worst, rel(Y[b], o.sample(j, jp, X)), rel(Z[b], o.sample(j, jp, X, True)))
+    print(f"  {len(blocks_of(p))} blocks, worst rel err {worst:.3e} (bound {tol:.1e})")
+    assert worst <= tol
+    op.close()
+
+
+def oracle_hbs(p, o, k, leaf, Om, Ps):
+    grid = p.n if p.dim == 3 else None
+    tree = ohbs.kd_tree(p.M, leaf, grid)
+    H = {}
+    for b, j, jp in blocks_of(p):
+        H[(j, jp)] = ohbs.compress(Om, Ps, o.sample(j, jp, Om), o.sample(j, jp, Ps, True), k,
+                                   tree)
+    return H
+
+
+def k_apply(p, H, x, trans=False):
+    """x - (sum of the interface couplings) through per-block maps H."""
+    X = x.reshape(p.n_ds, p.M)
+    Y = X.copy()
+    for (j, jp), h in H.items():
+        if not trans:
+            Y[j - 1] -= h(X[jp - 1], False)
+        else:
+            Y[jp - 1] -= h(X[j - 1], True)
+    return Y.ravel()
+
+
+@pytest.mark.parametrize("name,k,leaf", [("cfg2s", 16, 32), ("cfg4s", 16, 32)])
+def test_hbs_matches_oracle_hbs(name, k, leaf):
+    p = CASES[name]()
+    banner(f"HBS from samples {name} rank {k} leaf {leaf} (fp64 build and factors)")
+    s = 3 * k + 10
+    rng = np.random.default_rng(41)
+    Om, Ps = rng.standard_normal((p.M, s)), rng.standard_normal((p.M, s))
+    op = ddst().Operator.from_problem(p, precision="fp64")
+    info = op.compress_hbs(rank=k, oversample=10, leaf=leaf, factor_dtype="fp64", omega=Om,
+                           psi=Ps)
+    o = odd.DDOracle(p)
+    Ho = oracle_hbs(p, o, k, leaf, Om, Ps)
+    dense = o.all_blocks()
+    fo = {key: (lambda v, t, h=h: ohbs.apply(h, v, t)) for key, h in Ho.items()}
+    fd_ = {key: (lambda v, t, B=B: (B.T if t else B) @ v) for key, B in dense.items()}
+    x = rng.standard_normal(p.n_ds * p.M)
+    for trans in (False, True):
+        yg = op.apply(torch.tensor(x, device="cuda"), transpose=trans,
+                      which="hbs").cpu().numpy().ravel()
+        yo = k_apply(p, fo, x, trans)
+        yd = k_apply(p, fd_, x, trans)
+        e_go, e_od, e_gd = rel(yg, yo), rel(yo, yd), rel(yg, yd)
+        print(f"  transpose={trans}: GPU vs oracle HBS {e_go:.3e}; oracle HBS vs dense "
+              f"{e_od:.3e}; GPU vs dense {e_gd:.3e}; {info['bytes'] / 2**20:.2f} MiB, "
+              f"sample {info['sample_ms']:.1f} ms, compress {info['compress_ms']:.1f} ms")
+        assert e_go <= 1e-9
+        assert e_gd <= 2 * e_od + 1e-12
+    op.close()
+
+
+@pytest.mark.parametrize("name,k,opts", [
+    ("cfg2s", 16, {}),
+    ("cfg4", 64, {"n": 31, "n_slabs": 8}),
+])
+def test_solve_without_dense_blocks(name, k, opts):
+    """FP32 build without transfer blocks (the slab factors and interface
+    blocks only), HBS form from samples with BF16 factors, FP64 refinement:
+    the solution of the FD problem to 1e-8."""
+    dd = ddst()
+    p = CASES[name]() if name in CASES else make_config(name, **opts)
+    banner(f"solve through HBS without dense blocks: {name} n={p.n} slabs={p.n_slabs} rank {k}")
+    op = dd.Operator.from_problem(p, precision="fp32", transfer_blocks=False)
+    info = op.compress_hbs(rank=k, oversample=10, factor_dtype="bf16", seed=7)
+    u, _, st = op.solve(p.f, opts=dd.SolveOptions(use_hbs=True, tol=1e-10, max_outer=12,
+                                                   max_iter=400))
+    ref = ofd.solve_global(p)
+    err = rel(u.cpu().numpy().ravel(), ref)
+    print(f"  rel err {err:.3e} outer {st['outer_iters']} gmres {st['gmres_iters']}; HBS "
+          f"{info['bytes'] / 2**20:.2f} MiB (dense blocks would be "
+          f"{2 * (p.n_ds - 1) * p.M * p.M * 4 / 2**20:.2f} MiB in FP32)")
+    assert st["status"] == 0 and err <= 1e-8
+    op.close()
+
+
+def test_hbs_errors():
+    dd = ddst()
+    banner("HBS option and state errors")
+    p = make_config("cfg2", n=63, n_slabs=4)
+    op = dd.Operator.from_problem(p, precision="fp64")
+    with pytest.raises(dd.DDSTError) as e:  # leaf 100 > s - k = 3*8+10-8
+        op.compress_hbs(rank=8, oversample=10, leaf=100)
+    assert e.value.code == dd.DDST_EINVAL
+    with pytest.raises(dd.DDSTError) as e:
+        op.solve(p.f, opts=dd.SolveOptions(use_hbs=True))
+    assert e.value.code == dd.DDST_ESTATE
+    with pytest.raises(dd.DDSTError) as e:
+        op.solve(p.f, opts=dd.SolveOptions(use_hbs=True, use_hodlr=True))
+    assert e.value.code == dd.DDST_EINVAL
+    op.release_factors()
+    with pytest.raises(dd.DDSTError) as e:
+        op.compress_hbs(rank=8)
+    assert e.value.code == dd.DDST_ESTATE
+    op.close()
