@@ -360,6 +360,27 @@ int ddst_apply(const ddst_op_t *op, int32_t transpose, int32_t which, const doub
 int ddst_loads(const ddst_op_t *op, const double *f, const double *g, double *hhat,
                hipStream_t stream);
 
+/*
+ * ddst_apply_noalloc -- for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the product of ddst_apply, y = S x or S^T x, through the
+ * dense blocks (which = DDST_APPLY_DENSE) or a compressed form
+ * (DDST_APPLY_HODLR, DDST_APPLY_HBS), with no hipMalloc, hipFree or other
+ * allocation and no
+ * synchronisation (the work is ordered on `stream`; the call returns once
+ * it is enqueued).  Its temporaries (padded copies of x and y, the product's
+ * job table, the partial sums of the transposed product) live in a static
+ * device array of 16 MiB per GPU, held until the process ends; the first
+ * call on a device looks up its address.  x, y: device N_ds*M float64,
+ * caller-owned.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or threads without ordering between
+ * them) race.  Errors: EINVAL (NULL pointers, which MATFREE, or a
+ * product that needs more than the 16 MiB: the dense product needs
+ * 16 N_ds ld bytes plus, transposed, 8 N_ds min(ld/32, 64) ld, with ld = M
+ * rounded up to a multiple of 128), ESTATE (form not held), EHIP.
+ */
+int ddst_apply_noalloc(const ddst_op_t *op, int32_t transpose, int32_t which, const double *x,
+                       double *y, hipStream_t stream);
 
 /*
  * Diagnostics of the equilibrium system (the iteration counts and condition

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["dense.hip", "vec.hip", "hodlr.hip", "hbs.hip", "prof.hip", "api.hip"]
+SRC = ["dense.hip", "vec.hip", "hodlr.hip", "hbs.hip", "prof.hip", "noalloc.hip", "api.hip"]
 LIB = os.path.join(HERE, "libddst.so")
 
 

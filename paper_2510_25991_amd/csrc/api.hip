@@ -1616,6 +1616,26 @@ int ddst_apply(const ddst_op_t *cop, int32_t transpose, int32_t which, const dou
   });
 }
 
+int ddst_apply_noalloc(const ddst_op_t *cop, int32_t transpose, int32_t which, const double *x,
+                       double *y, hipStream_t stream) {
+  g_err.clear();
+  if (!cop || !x || !y) return fail(DDST_EINVAL, "op, x and y must be non-NULL");
+  if (which != DDST_APPLY_DENSE && which != DDST_APPLY_HODLR && which != DDST_APPLY_HBS)
+    return fail(DDST_EINVAL, "which must be DENSE, HODLR or HBS (the matrix-free product "
+                             "needs volume-sized temporaries)");
+  const int st = check_form(cop, which);
+  if (st) return st;
+  const size_t need = noalloc_need(cop, which, transpose != 0);
+  if (need > noalloc_scratch_bytes())
+    return fail(DDST_EINVAL, "this product needs " + std::to_string(need) +
+                                 " bytes of scratch; the static buffer holds " +
+                                 std::to_string(noalloc_scratch_bytes()) + " (use ddst_apply)");
+  const hipError_t e = noalloc_apply(cop, which, transpose != 0, x, y, stream);
+  if (e != hipSuccess) return fail(DDST_EHIP, std::string("ddst_apply_noalloc: ") +
+                                                  hipGetErrorString(e));
+  return DDST_OK;
+}
+
 int ddst_gmres(const ddst_op_t *cop, int32_t transpose, int32_t which, const double *b, double *x,
                double tol, int32_t max_iter, int32_t *iters, double *relres,
                hipStream_t stream) {

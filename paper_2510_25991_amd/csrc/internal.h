@@ -272,6 +272,15 @@ void launch_maxabs(const double *x, size_t len, unsigned long long *out, hipStre
 void launch_extract_block(const void *src, int prec, int M, int ld, double *dst,
                           hipStream_t s);
 
+// ---- allocation-free product (noalloc.hip) ---------------------------------
+// Size of the static per-GPU scratch array, the bytes one product needs from
+// it (0: form not supported), and the product itself (no allocation, no
+// synchronisation).
+size_t noalloc_scratch_bytes();
+size_t noalloc_need(const ddst_op *op, int which, int trans);
+hipError_t noalloc_apply(const ddst_op *op, int which, int trans, const double *x, double *y,
+                         hipStream_t s);
+
 // ---- HBS form from samples (hbs.hip) --------------------------------------
 struct Hbs;
 void hbs_free(ddst_op *op);

@@ -87,7 +87,7 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_solve_man
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
            "ddst_profile_enable", "ddst_profile_select", "ddst_profile_read",
            "ddst_profile_busy", "ddst_compress_info", "ddst_gmres", "ddst_cond_est",
-           "ddst_set_allocator", "ddst_build_stats",
+           "ddst_set_allocator", "ddst_build_stats", "ddst_apply_noalloc",
            "ddst_compress_hbs", "ddst_hbs_info", "ddst_sample_blocks"]
 KERNEL_CLASSES = {0: "gj_panel", 1: "gj_update", 2: "gemm", 3: "assemble", 4: "gemv",
                   5: "gemv_many"}
@@ -165,6 +165,7 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_build_stats.argtypes = [vp, P(StatsC)]
     L.ddst_get_transfer.argtypes = [vp, i32, vp, vp, vp]
     L.ddst_apply.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.ddst_apply_noalloc.argtypes = [vp, i32, i32, vp, vp, vp]
     L.ddst_loads.argtypes = [vp, vp, vp, vp, vp]
     L.ddst_get_factor.argtypes = [vp, i32, i32, vp, vp]
     L.ddst_get_center_inverse.argtypes = [vp, i32, vp, vp]
@@ -373,6 +374,16 @@ class Operator:
         _check(load_library().ddst_apply(self._h, 1 if transpose else 0, _APPLY_FORMS[which],
                                          _ptr(x), _ptr(y), _stream()))
         return y.view(self.n_ds, self.M)
+
+    def apply_noalloc(self, x, y, transpose=False, which="dense"):
+        """y = S x (or S^T x) into the caller's y (N_ds*M float64) without any
+        allocation in the library; which: "dense", "hodlr" or "hbs"."""
+        if which not in ("dense", "hodlr", "hbs"):
+            raise ValueError("which must be 'dense', 'hodlr' or 'hbs'")
+        _check(load_library().ddst_apply_noalloc(self._h, 1 if transpose else 0,
+                                                 _APPLY_FORMS[which], _ptr(x), _ptr(y),
+                                                 _stream()))
+        return y
 
     def gmres(self, b, tol=1e-8, max_iter=1000, which="dense", transpose=False,
               allow_notconv=False):
