@@ -4,10 +4,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def paper_tables():
-    """{table_name: [(col0, col1, col2), ...]} from paper_fd_tables.txt."""
+def paper_tables(name="paper_fd_tables.txt"):
+    """{table_name: [(col0, col1, col2), ...]} from a table fixture."""
     out, cur = {}, None
-    with open(os.path.join(HERE, "paper_fd_tables.txt")) as fh:
+    with open(os.path.join(HERE, name)) as fh:
         for line in fh:
             line = line.strip()
             if not line or line.startswith("#"):
