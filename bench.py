@@ -14,9 +14,17 @@ FP64 plain path (FP64 build, same solver) is timed beside it, and the
 adjoint of a sensor loss (factors recomputed) is timed once, and so is the
 matrix-free alternative (S applied by sweeps with the stored slab factors,
 set-up without the transfer blocks) beside the dense-block form, and one
-solve of 8 right-hand sides together beside single solves.
+solve of 8 right-hand sides together beside single solves.  The two
+largest workloads (2D oscillatory 2047^2 on 64 slabs, 3D variable
+coefficient 127^3 on 16 slabs) are each timed once end to end by two
+routes: the dense transfer blocks compressed as HODLR, and the paper's
+sampled construction (Algorithm 1) without dense blocks, compressed as HBS.
+Hardware counters of the dominant kernel (HBM bytes, executed matrix-core
+flops) come from rocprofv3 passes over child runs of this same script,
+before the timed runs.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-pmc]
+                       [--no-large]
 """
 from __future__ import annotations
 
@@ -53,6 +61,14 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one device-to-device copy of this many bytes first (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
+    ap.add_argument("--no-pmc", action="store_true",
+                    help="skip the hardware-counter passes (rocprofv3 over child runs)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2047^2 and 127^3 workloads (timed once each)")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the 2047^2 and 127^3 workloads and print their JSON object")
+    ap.add_argument("--pmc-child", action="store_true",
+                    help="internal: one calibration copy and one step, nothing printed")
     return ap.parse_args()
 
 
@@ -98,29 +114,121 @@ def timed(dd, torch, dev, precision, opts, steps, warmup, profile):
     return (t1 - t0) / steps, stats, u, prof, mix
 
 
-def _measured_traffic(kernel, key="traffic_bytes_per_launch"):
-    """A figure (by default the calibrated HBM bytes per launch) from the
-    committed rocprofv3 PMC summary of `kernel`, valid only while the library
-    sources hash to the measured ones."""
+PMC_COPY_BYTES = 256 << 20  # calibration copy of the counter passes
+PMC_KERNEL = "k_gj_update"
+
+
+def _pmc_rows(outdir):
+    """Rows of every rocprofv3 counter-collection CSV under outdir."""
+    import csv
     import glob
-    import hashlib
-    import re
-    summ = glob.glob(os.path.join(ROOT, "profiles", f"pmc_{kernel}_*.md"))
-    if not summ:
-        return None
-    text = open(summ[0]).read()
-    m = re.search(key + r": (\S+)", text)
-    hsh = re.search(r"source_sha256_csrc: (\S+)", text)
-    if not (m and hsh):
-        return None
-    csrc = os.path.join(ROOT, "paper_2510_25991_amd", "csrc")
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip"))) + [os.path.join(csrc, "internal.h")]:
-        h.update(open(f, "rb").read())
-    return float(m.group(1)) if h.hexdigest() == hsh.group(1) else None
+    rows = []
+    for f in glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
 
 
-def roofline(prof, precision, M):
+def _per_dispatch(rows, kernel_sub, counter):
+    """{dispatch id: summed counter value} of the dispatches whose kernel name
+    contains kernel_sub."""
+    out = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        if kernel_sub not in name or r.get("Counter_Name") != counter:
+            continue
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        out[d] = out.get(d, 0.0) + float(r.get("Counter_Value", 0.0))
+    return out
+
+
+def pmc_measure(root):
+    """Hardware counters of the dominant kernel, measured now: three rocprofv3
+    passes (one counter set each, as the profiler requires) over a child run
+    of this script (one 256 MiB device copy, then one step).  Byte counters
+    are calibrated by the copy kernel (its true traffic is known):
+    bytes = raw KiB x 1024 x (copy bytes / copy's raw bytes).  Returns a dict
+    (entries None when a pass fails)."""
+    import shutil
+    import subprocess
+    import tempfile
+    res = {"traffic_bytes_per_launch": None, "fetch_scale": None, "write_scale": None,
+           "mfma_flops_per_launch": None, "mfma_busy_serialised": None, "launches": None,
+           "error": None}
+    prof = shutil.which("rocprofv3")
+    if prof is None:
+        res["error"] = "rocprofv3 not found"
+        return res
+    passes = {"fetch": ["FETCH_SIZE"], "write": ["WRITE_SIZE"],
+              "mfma": ["SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_VALU_MFMA_BUSY_CYCLES",
+                       "GRBM_GUI_ACTIVE"]}
+    rows = {}
+    tmp = tempfile.mkdtemp(prefix="ddst_pmc_", dir="/tmp")
+    env = dict(os.environ, TMPDIR="/tmp")
+    for name, counters in passes.items():
+        out = os.path.join(tmp, name)
+        cmd = ["timeout", "-s", "KILL", "150", prof, "--pmc", *counters, "-f", "csv", "-d", out,
+               "-o", name, "--", sys.executable, os.path.join(root, "bench.py"), "--pmc-child"]
+        print(f"[bench] counter pass {name}: {' '.join(counters)}", file=sys.stderr, flush=True)
+        try:
+            r = subprocess.run(cmd, cwd="/tmp", env=env, capture_output=True, text=True,
+                               timeout=170)
+            rows[name] = _pmc_rows(out)
+            if not rows[name]:
+                res["error"] = f"pass {name}: no counter rows (rc {r.returncode}): " + \
+                    (r.stderr or "")[-300:]
+        except Exception as e:  # noqa: BLE001 - reported, never fatal
+            rows[name] = []
+            res["error"] = f"pass {name}: {e}"
+    shutil.rmtree(tmp, ignore_errors=True)
+
+    def scale(counter, rws):
+        copy = _per_dispatch(rws, "copyBuffer", counter)
+        big = [v for v in copy.values() if v * 1024 > PMC_COPY_BYTES / 4]
+        return PMC_COPY_BYTES / (big[0] * 1024) if big else None
+
+    f = _per_dispatch(rows.get("fetch", []), PMC_KERNEL, "FETCH_SIZE")
+    w = _per_dispatch(rows.get("write", []), PMC_KERNEL, "WRITE_SIZE")
+    fs, ws = scale("FETCH_SIZE", rows.get("fetch", [])), scale("WRITE_SIZE", rows.get("write", []))
+    res["fetch_scale"], res["write_scale"] = fs, ws
+    if f and w and fs and ws:
+        res["launches"] = len(f)
+        res["traffic_bytes_per_launch"] = (sum(f.values()) / len(f) * fs
+                                           + sum(w.values()) / len(w) * ws) * 1024.0
+    mr = rows.get("mfma", [])
+    mops = _per_dispatch(mr, PMC_KERNEL, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    busy = _per_dispatch(mr, PMC_KERNEL, "SQ_VALU_MFMA_BUSY_CYCLES")
+    act = _per_dispatch(mr, PMC_KERNEL, "GRBM_GUI_ACTIVE")
+    if mops:
+        # the counter counts matrix-core operations in units of 512 flops
+        res["mfma_flops_per_launch"] = 512.0 * sum(mops.values()) / len(mops)
+    if busy and act and sum(act.values()) > 0:
+        # busy cycles summed over the SIMDs; active cycles summed over the
+        # 8 XCDs: fraction = busy / (active / 8 x 1024 SIMDs)
+        res["mfma_busy_serialised"] = sum(busy.values()) / (sum(act.values()) / 8.0 * 1024.0)
+    return res
+
+
+def pmc_child():
+    """One calibration copy and one step of the benchmark workload (run under
+    rocprofv3 by pmc_measure)."""
+    import torch
+    from problems import make_config
+    from paper_2510_25991_amd import ddst as dd
+    src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    prob = make_config("cfg2")
+    dev = {"n": prob.n, "n_slabs": prob.n_slabs, "bvec": prob.bvec,
+           "kappa": torch.tensor(prob.kappa, dtype=torch.float64, device="cuda"),
+           "f": torch.tensor(prob.f, dtype=torch.float64, device="cuda")}
+    step(dd, dev, "fp32", dd.SolveOptions(tol=1e-9, max_outer=6))
+    torch.cuda.synchronize()
+
+
+def roofline(prof, precision, M, pmc=None):
     """Dominant kernel class (the only class timed in the timed region, else
     the longest); achieved = algorithmic work per launch / average launch
     duration (HIP events on the stream each launch runs on).
@@ -154,16 +262,24 @@ def roofline(prof, precision, M):
         bytes_per_launch = flops_per_launch * bytes_per_flop
         hbm_floor = bytes_per_launch / (PEAK["hbm_gbs"] * 1e9)
         mfma_floor = flops_per_launch / (mpeak * 1e12)
-        tr = _measured_traffic("gj_update") if precision == "fp32" else None
-        busy = (_measured_traffic("gj_update", "mfma_busy_fraction_serialised")
-                if precision == "fp32" else None)
+        pm = pmc if (pmc and precision == "fp32") else {}
+        tr = pm.get("traffic_bytes_per_launch")
+        ex = pm.get("mfma_flops_per_launch")
         extra = {"traffic": tr, "bytes_per_launch": bytes_per_launch,
+                 "traffic_ratio": round(tr / bytes_per_launch, 3) if tr else None,
                  "flops_per_launch": flops_per_launch,
+                 # executed matrix-core flops from SQ_INSTS_VALU_MFMA_MOPS_F32
+                 "flops_executed_per_launch": ex,
+                 "executed_over_algorithmic": round(ex / flops_per_launch, 3) if ex else None,
                  "hbm_gbs": round(bytes_per_launch / avg_s / 1e9, 1),
                  # matrix-core busy fraction of the same launches when rocprofv3
                  # serialises them (the two look-ahead halves otherwise overlap,
                  # which lengthens each launch's duration above)
-                 "mfma_busy_serialised": busy,
+                 "mfma_busy_serialised": (round(pm["mfma_busy_serialised"], 4)
+                                          if pm.get("mfma_busy_serialised") else None),
+                 "counters": ({"launches": pm.get("launches"), "fetch_scale": pm.get("fetch_scale"),
+                               "write_scale": pm.get("write_scale"), "error": pm.get("error")}
+                              if pm else None),
                  "mfma_tflops": round(flops_per_launch / avg_s / 1e12, 3)}
         if mfma_floor >= hbm_floor:
             achieved = flops_per_launch / avg_s / 1e12
@@ -225,14 +341,130 @@ def cpu_leg(prob, u_mixed, u_fp64):
     return {
         "value": round(prob.N / t_total, 1), "unit": "DOF/s", "cores": 1,
         "kind": "oracle",
-        "sample": (f"transfer blocks of double slabs {sample_ds} (sparse LU + {2 * prob.M} "
-                   f"dense solves each), scaled x{prob.n_ds}/{len(sample_ds)}, + all loads + "
-                   f"all slab reconstructions; the dense interface solve is left out "
-                   f"(favours the CPU). SuperLU is single-threaded; BLAS threads "
-                   f"{blas_threads}"),
+        "sample": (f"the oracle's DD route: transfer blocks of double slabs {sample_ds} "
+                   f"(sparse LU + {2 * prob.M} dense solves each), scaled x{prob.n_ds}/"
+                   f"{len(sample_ds)}, + all loads + all slab reconstructions; the dense "
+                   f"interface solve is left out (favours the CPU). SuperLU runs on one "
+                   f"thread; BLAS threads {blas_threads}"),
         "seconds_extrapolated": round(t_total, 2),
+        # the oracle's plain global sparse direct solve of the same problem
+        # (its reference solution), timed in full on the same host
         "global_direct_s": round(t_direct, 2),
+        "global_direct_dof_per_s": round(prob.N / t_direct, 1),
+        "host": host_info(),
     }, errs
+
+
+def host_info():
+    """The host the CPU leg ran on: logical CPUs, the CPUs this process may
+    use, and the processor model."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:  # noqa: BLE001 - informational only
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = None
+    return {"nproc": os.cpu_count(), "cpus_allowed": allowed, "model": model}
+
+
+def large_leg(dd, torch, name):
+    """One end-to-end run of a large workload by two routes: the dense
+    transfer blocks compressed as HODLR (the workload's definition), and the
+    sampled construction without dense blocks compressed as HBS (the paper's
+    Algorithm 1).  FP32 build, BF16 factors, FP64 refinement to a predicted
+    relative error of 1e-9; times from the host clock around the calls (inputs
+    resident in HBM), the library's own phase times beside them."""
+    from problems import make_config
+    p = make_config(name)
+    t = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device="cuda")
+    kap, c, f = t(p.kappa), t(p.c), t(p.f)
+    F_build = p.n_ds * (2 * p.m - 1) * (14.0 / 3.0) * float(p.M) ** 3
+    M3, steps = float(p.M) ** 3, p.m - 1
+    # algorithmic work of each route's build: Gauss-Jordan inverses 2 M^3
+    # (left-to-right sweeps of every slab, right-to-left sweeps of the
+    # interior ones, the interface blocks), transfer chains 2 M^3 per step
+    # of the interior slabs' two sweeps and the blocks S = Sigma^{-1} R
+    # (dense route) or the sampling chains 2 M^2 s per step of four chains
+    # per interior slab plus the final and W products (sampled route)
+    inv = ((p.n_slabs + p.n_ds) * steps + p.n_ds) * 2.0 * M3
+    flops = {"dense_hodlr": inv + (2 * (p.n_slabs - 2) * steps + 2 * (p.n_ds - 1)) * 2.0 * M3}
+    out = {"workload": f"{p.dim}D {name} {p.n}^{p.dim}, {p.n_slabs} slabs, M={p.M}, N_ds={p.n_ds}",
+           "N": p.N, "s_build_nominal_flops": F_build}
+    opts = dd.SolveOptions(tol=1e-9, max_iter=3000, max_outer=12)
+    for route in ("dense_hodlr", "sampled_hbs"):
+        print(f"[bench] {name} route {route}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        t0 = time.perf_counter()
+        op = dd.Operator(p.dim, p.n, p.n_slabs, kappa=kap, bvec=p.bvec, c=c, precision="fp32",
+                         transfer_blocks=(route == "dense_hodlr"))
+        if route == "dense_hodlr":
+            info = op.compress(tol=1e-8 if p.dim == 2 else 1e-7, leaf=128, oversample=10,
+                               max_rank=118, factor_dtype="bf16")
+            o = dataclasses_replace(opts, use_hodlr=True)
+        else:
+            k = 32 if p.dim == 2 else 64
+            info = op.compress_hbs(rank=k, oversample=10, factor_dtype="bf16", seed=11)
+            o = dataclasses_replace(opts, use_hbs=True)
+            smp = (4 * (p.n_slabs - 2) * steps + 2 * (p.n_ds - 1) + p.n_ds) * 2.0 * p.M ** 2 * (
+                3 * k + 10)
+            flops["sampled_hbs"] = inv + smp
+        torch.cuda.synchronize()
+        held = (free0 - torch.cuda.mem_get_info()[0]) / 1e9
+        u, _, st = op.solve(f, opts=o, want_gamma=False, allow_notconv=True)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        bs = op.build_stats()
+        op.close()
+        del u
+        bt = bs["t_build_ms"] / 1e3
+        r = {"total_s": round(total, 3), "dof_per_s": round(p.N / total, 1),
+             "build_ms": round(bs["t_build_ms"], 1),
+             # the workload's nominal S-build work (forming S) over this
+             # route's build time; the sampled route does less than that
+             "s_build_tflops_nominal": round(F_build / bt / 1e12, 2),
+             "build_flops": flops[route],
+             "build_tflops": round(flops[route] / bt / 1e12, 2)
+             if route == "dense_hodlr" else None,
+             "solve_ms": round(st["t_solve_ms"], 1), "outer_iters": st["outer_iters"],
+             "gmres_iters": st["gmres_iters"], "fd_residual_rel": st["residual_rel"],
+             "correction_rel": st["correction_rel"], "converged": bool(st["status"] == 0),
+             "device_gb_held": round(held, 2),
+             "bytes_dense_blocks": bs["bytes_transfer"], "bytes_factors": bs["bytes_factors"],
+             "compressed_bytes": info["bytes"]}
+        if route == "dense_hodlr":
+            r.update({"compress_ms": round(info["ms"], 1), "ranks": [info["min_rank"],
+                                                                     info["max_rank"]]})
+        else:
+            # sampling runs in ddst_compress_hbs: the build's work over the
+            # build and sampling times together
+            r.update({"sample_ms": round(info["sample_ms"], 1),
+                      "compress_ms": round(info["compress_ms"], 1), "rank": info["rank"],
+                      "build_tflops": round(flops[route] / (bt + info["sample_ms"] / 1e3) / 1e12,
+                                            2)})
+        out[route] = r
+        torch.cuda.empty_cache()
+    return out
+
+
+def dataclasses_replace(o, **kw):
+    import dataclasses
+    return dataclasses.replace(o, **kw)
 
 
 def matfree_leg(dd, torch, dev, prob, opts):
@@ -304,11 +536,22 @@ def many_leg(dd, torch, dev, prob, opts, nrhs=8):
 
 def main():
     args = parse()
+    if args.pmc_child:
+        pmc_child()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               f"(the multi-GPU slab sharding is a design, not part of this build)",
               file=sys.stderr)
         sys.exit(2)
+    if args.only_large:
+        import torch
+        from paper_2510_25991_amd import ddst as dd
+        print(json.dumps({"oscillatory_2d_2047": large_leg(dd, torch, "cfg3"),
+                          "var_kappa_3d_127": large_leg(dd, torch, "cfg4")}), flush=True)
+        return
+    # hardware counters first, in child processes, before this one uses the GPU
+    pmc = None if args.no_pmc else pmc_measure(ROOT)
     import numpy as np
     import torch
     from problems import make_config
@@ -335,7 +578,7 @@ def main():
                                                 args.warmup, True)
     tb = float(np.mean([s["t_build_ms"] for s in st_mix])) / 1e3
     ts = float(np.mean([s["t_solve_ms"] for s in st_mix])) / 1e3
-    kname, roof = roofline(prof_mix, "fp32", M)
+    kname, roof = roofline(prof_mix, "fp32", M, pmc)
     out_fp64 = None
     u64 = None
     if not args.no_fp64:
@@ -376,6 +619,10 @@ def main():
     if not args.no_many:
         print("[bench] many right-hand sides", file=sys.stderr, flush=True)
         many = many_leg(dd, torch, dev, prob, opts)
+    large = None
+    if not args.no_large:
+        large = {"oscillatory_2d_2047": large_leg(dd, torch, "cfg3"),
+                 "var_kappa_3d_127": large_leg(dd, torch, "cfg4")}
     cpu, errs = (None, {})
     if not args.no_cpu:
         print("[bench] CPU oracle leg", file=sys.stderr, flush=True)
@@ -409,6 +656,7 @@ def main():
         "adjoint": adj,
         "matrix_free": mfree,
         "many_rhs": many,
+        "large_workloads": large,
         # every class timed over one extra step (untimed)
         "kernel_profile_per_step": {k: {"launches": v[0], "ms": round(v[1], 3)}
                                     for k, v in mix.items()},

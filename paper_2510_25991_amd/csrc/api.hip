@@ -165,12 +165,15 @@ struct Sweep {
   int slab;
   int dir;      // +1 left-to-right (towards plane (s+1)m), -1 right-to-left
   int y_index;  // index into the transfer-chain buffers, -1 if no chain
-  int work;     // index into ping-pong work buffers, -1 if stored in the factor store
+  int work;     // first of its work buffers, -1 if stored in the factor store
+  int nbuf;     // work buffers: 2 (ping-pong: a transfer chain reads G_k while
+                // plane k+1 is formed) or 1 (no chain: plane k+1 is assembled
+                // over G_k in place, element by element)
 };
 
 struct SweepPlan {
   std::vector<Sweep> sw;
-  int n_y = 0, n_work = 0;
+  int n_y = 0, n_work = 0;  // chain buffer pairs, work buffers
 };
 
 // Plane (1-based) of local step k of a sweep.
@@ -180,13 +183,13 @@ inline int sweep_plane(const ddst_op *op, const Sweep &w, int k) {
 
 struct SweepBuffers {
   void *store = nullptr;  // factor store (n_slabs*(m-1) matrices) or null
-  void *work = nullptr;   // 2 * n_work matrices
+  void *work = nullptr;   // n_work matrices
   void *ybuf = nullptr;   // 2 * n_y matrices
 };
 
 inline void *sweep_G(const ddst_op *op, const Sweep &w, int k, const SweepBuffers &b) {
   if (w.work < 0) return mat(b.store, (size_t)w.slab * (op->m - 1) + (k - 1), op->mat_bytes);
-  return mat(b.work, (size_t)w.work * 2 + (k & 1), op->mat_bytes);
+  return mat(b.work, (size_t)w.work + (w.nbuf == 2 ? (k & 1) : 0), op->mat_bytes);
 }
 inline void *sweep_Y(const ddst_op *op, const Sweep &w, int k, const SweepBuffers &b) {
   return mat(b.ybuf, (size_t)w.y_index * 2 + (k & 1), op->mat_bytes);
@@ -300,7 +303,7 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
 // of the build the solve and the adjoint need.
 SweepPlan factor_plan(const ddst_op *op) {
   SweepPlan p;
-  for (int s = 0; s < op->n_slabs; ++s) p.sw.push_back({s, +1, -1, -1});
+  for (int s = 0; s < op->n_slabs; ++s) p.sw.push_back({s, +1, -1, -1, 0});
   return p;
 }
 
@@ -352,13 +355,20 @@ int build_impl(ddst_op *op, int keep, int blocks, hipStream_t s) {
   const int m = op->m, nsl = op->n_slabs, nds = op->n_ds;
   SweepPlan plan;
   int nwork = 0, ny = 0;
+  auto take = [&](bool hasY) {  // work buffers of a sweep that is not stored
+    const int first = nwork;
+    nwork += hasY ? 2 : 1;
+    return first;
+  };
   for (int sl = 0; sl < nsl; ++sl) {  // left-to-right, towards Gamma_{sl+1}
     const bool hasY = blocks && sl >= 1 && sl <= nsl - 2;
-    plan.sw.push_back({sl, +1, hasY ? ny++ : -1, keep ? -1 : nwork++});
+    const int wk = keep ? -1 : take(hasY);
+    plan.sw.push_back({sl, +1, hasY ? ny++ : -1, wk, hasY ? 2 : 1});
   }
   for (int sl = 1; sl < nsl; ++sl) {  // right-to-left, towards Gamma_sl
     const bool hasY = blocks && sl <= nsl - 2;
-    plan.sw.push_back({sl, -1, hasY ? ny++ : -1, nwork++});
+    const int wk = take(hasY);
+    plan.sw.push_back({sl, -1, hasY ? ny++ : -1, wk, hasY ? 2 : 1});
   }
   plan.n_y = ny;
   plan.n_work = nwork;
@@ -371,7 +381,7 @@ int build_impl(ddst_op *op, int keep, int blocks, hipStream_t s) {
     }
     buf.store = op->G;
   }
-  DeviceMem work((size_t)2 * nwork * op->mat_bytes);
+  DeviceMem work((size_t)nwork * op->mat_bytes);
   DeviceMem ybuf((size_t)2 * std::max(ny, 1) * op->mat_bytes);
   buf.work = work.p;
   buf.ybuf = ybuf.p;
