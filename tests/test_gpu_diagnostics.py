@@ -11,7 +11,6 @@ printed two-decimal values within 0.01 (the tables truncate some values,
 +-3 (the paper does not state its right-hand side; seeded N(0,1) ones here).
 The paper's grid has N = (1/h)^3 nodes: n = N^(1/3) - 1 interior nodes."""
 import ctypes
-import os
 
 import numpy as np
 import pytest
@@ -89,8 +88,6 @@ def test_fd_poisson_tables(n, n_slabs, its_paper, kap_paper):
     check_row(n, n_slabs, its_paper, kap_paper, "fp64")
 
 
-@pytest.mark.skipif(os.environ.get("DDST_SLOW_TESTS") != "1",
-                    reason="N = 128^3 (about a minute of GPU time); set DDST_SLOW_TESTS=1")
 def test_fd_poisson_fixedH_largest_row():
     n, n_slabs, its_paper, kap_paper = [r for r in rows() if r[0] == 127][0]
     banner(f"Poisson 3D n={n} H=1/{n_slabs} (FP32 blocks)")
@@ -274,18 +271,18 @@ def test_indefinite_oscillatory_wide_slabs():
     op.close()
 
 
-@pytest.mark.skipif(os.environ.get("DDST_SLOW_TESTS") != "1",
-                    reason="N = 128^3 (40-80 s of GPU time each); set DDST_SLOW_TESTS=1")
-@pytest.mark.parametrize("n_lambda,precision", [(1, "fp32"), (2, "fp32"), (3, "fp64")])
+@pytest.mark.parametrize("n_lambda,precision", [(1, "fp32"), (2, "fp64"), (3, "fp64")])
 def test_fd_other_models_helmholtz_paper_size(n_lambda, precision):
-    """The printed size.  N_lambda = 3 takes FP64 blocks: its kappa_2 ~ 2.7e5
-    comes from a nearly resonant mode that FP32 blocks move by 13%; the
-    estimate itself is good to a few 1e-6 there (inner GMRES at 1e-12)."""
+    """The printed size.  N_lambda = 2 and 3 take FP64 blocks: their nearly
+    resonant modes amplify the rounding of FP32 blocks (kappa_2 ~ 1.1e5 and
+    2.7e5; FP32 blocks move it by 0.3% and 13%, and the iteration counts by
+    10-15%); the estimate itself is good to a few 1e-6 there (inner GMRES at
+    1e-12)."""
     banner(f"Helmholtz 3D n=127 H=1/8 N_lambda={n_lambda} ({precision} blocks)")
     if n_lambda == 3:
         check_helmholtz(127, 3, precision, indefinite=True, kap_tol=1e-5)
     else:
-        check_helmholtz(127, n_lambda, precision)
+        check_helmholtz(127, n_lambda, precision, kap_tol=1e-5 if precision == "fp64" else None)
 
 
 @pytest.mark.parametrize("n", [31, 63])

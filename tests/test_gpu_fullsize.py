@@ -7,11 +7,11 @@ Outputs the oracle can produce in seconds are compared element by element
 (the adjoint gradient; sampled transfer blocks or columns; the 3D solution
 against a conjugate-gradient reference); the rest is checked by
 properties that hold at any size (operator error of the compressed form,
-backward error of the refined solution).  The global direct solve of the
-oscillatory workload (about 2.5 minutes of CPU) runs only when
-DDST_SLOW_TESTS=1.
+backward error of the refined solution), and the solutions against the
+oracle's global direct solve (oscillatory workload) or conjugate gradients
+(3D workload), each computed once and shared by the dense-block (HODLR)
+and the sampled (HBS, no dense blocks) routes.
 """
-import os
 
 import numpy as np
 import pytest
@@ -122,6 +122,21 @@ def test_full_size_cfg5_central_differences():
     assert worst <= 1e-5
 
 
+_REF = {}
+
+
+def global_reference(name, p):
+    """The oracle's solution of a full-size workload, computed once."""
+    if name not in _REF:
+        if name == "cfg3":
+            print("  global direct solve (4.2M unknowns, about a minute)", flush=True)
+            _REF[name] = ofd.solve_global(p, ordering="MMD_AT_PLUS_A")
+        else:
+            print("  global reference by conjugate gradients", flush=True)
+            _REF[name] = ofd.solve_global_cg(p)
+    return _REF[name]
+
+
 def test_full_size_cfg3_hodlr():
     p = make_config("cfg3")
     banner("full-size cfg3 2047^2 64 slabs: fp32 build, bf16 HODLR, fp64 refinement")
@@ -168,9 +183,38 @@ def test_full_size_cfg3_hodlr():
     op.close()
     # the backward error does not bound the forward error of this
     # near-resonant operator: compare with the oracle's global direct solve
-    print("  global direct solve (4.2M unknowns, about a minute)", flush=True)
-    err = rel(x, ofd.solve_global(p, ordering="MMD_AT_PLUS_A"))
+    err = rel(x, global_reference("cfg3", p))
     print(f"  rel err vs global direct {err:.3e}")
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("name,rank", [("cfg3", 32), ("cfg4", 64)])
+def test_full_size_sampled_hbs_without_dense_blocks(name, rank):
+    """The paper's construction at full size: FP32 build without transfer
+    blocks (slab factors and interface blocks only), HBS form of every block
+    from s = 3k + 10 two-sided samples by local solves, BF16 factors, FP64
+    refinement; the solution against the oracle's, and the device memory of
+    the operator against the dense-block route."""
+    p = make_config(name)
+    dd = ddst()
+    banner(f"full-size {name} n={p.n} slabs={p.n_slabs}: sampled HBS rank {rank}, no dense blocks")
+    free0 = torch.cuda.mem_get_info()[0]
+    op = dd.Operator.from_problem(p, precision="fp32", transfer_blocks=False)
+    bs = op.build_stats()
+    info = op.compress_hbs(rank=rank, oversample=10, factor_dtype="bf16", seed=5)
+    used = (free0 - torch.cuda.mem_get_info()[0]) / 1e9
+    u, _, st = op.solve(p.f, opts=dd.SolveOptions(use_hbs=True, tol=1e-9, max_iter=3000,
+                                                   max_outer=12))
+    dense_gb = 2 * (p.n_ds - 1) * p.M * p.M * 4 / 1e9
+    print(f"  build {bs['t_build_ms']:.0f} ms, sample {info['sample_ms']:.0f} ms, compress "
+          f"{info['compress_ms']:.0f} ms, solve {st['t_solve_ms']:.0f} ms (outer "
+          f"{st['outer_iters']}, gmres {st['gmres_iters']}); HBS {info['bytes'] / 2**20:.1f} MiB, "
+          f"device {used:.1f} GB held (the dense FP32 blocks alone would be {dense_gb:.1f} GB)")
+    assert st["status"] == 0
+    x = u.cpu().numpy().ravel()
+    op.close()
+    err = rel(x, global_reference(name, p))
+    print(f"  rel err vs oracle {err:.3e}")
     assert err <= 1e-8
 
 
@@ -209,8 +253,7 @@ def test_full_size_cfg4_3d_quadtree():
     assert st["status"] == 0
     x = u.cpu().numpy().ravel()
     op.close()
-    print("  global reference by conjugate gradients", flush=True)
-    err = rel(x, ofd.solve_global_cg(p))
+    err = rel(x, global_reference("cfg4", p))
     print(f"  rel err vs CG reference {err:.3e}")
     assert err <= 1e-8
 
