@@ -86,16 +86,153 @@ struct Tile {
   }
 };
 
+// FP32 products on the BF16 matrix cores.  Every FP32 operand is split
+// into three BF16 parts, x = x1 + x2 + x3 (x1 = bf16(x), x2 = bf16(x - x1),
+// x3 = bf16(x - x1 - x2); each difference is exact in FP32 and the three
+// parts carry the 24-bit significand), and a b is formed from the six
+// products whose parts carry weight down to 2^-24 relative (a1 b1, a1 b2,
+// a2 b1, a1 b3, a2 b2, a3 b1; the three dropped ones are below 2^-27),
+// each exact in the FP32 accumulators of v_mfma_f32_16x16x32_bf16, added
+// smallest first.  The result has the accuracy of an FP32 product; the
+// BF16 matrix cores do the six products in 6 x 16 cycles per 16 x 16 x 32
+// tile against 8 x 32 for the FP32 instruction (dense peaks 2.5 PFLOP/s
+// BF16 and 157.3 TFLOP/s FP32).  FP32 operands are staged 32 deep.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+struct Split3 {
+  bf16x8 h, m, l;
+};
+// Parts of eight FP32 values (x[j] = h[j] + m[j] + l[j] to 2^-26 relative).
+__device__ __forceinline__ void split8(const float (&x)[8], Split3 &s) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 h = (__bf16)x[j];
+    const float r = x[j] - (float)h;
+    const __bf16 m = (__bf16)r;
+    const float r2 = r - (float)m;
+    s.h[j] = h;
+    s.m[j] = m;
+    s.l[j] = (__bf16)r2;
+  }
+}
+__device__ __forceinline__ f32x4 mfma_x6(const Split3 &a, const Split3 &b, f32x4 c) {
+  c = mfma_bf16(a.l, b.h, c);
+  c = mfma_bf16(a.m, b.m, c);
+  c = mfma_bf16(a.h, b.l, c);
+  c = mfma_bf16(a.m, b.h, c);
+  c = mfma_bf16(a.h, b.m, c);
+  return mfma_bf16(a.h, b.h, c);
+}
+
+// LDS of one tile product: FP64 operands staged 16 deep ([16][LW] each);
+// FP32 operands as their three BF16 parts, 32 deep, in fragment order
+// ([part][row or column][k], k contiguous, rows padded to 40 entries).
+constexpr int XK = 2 * BK;       // 32: k per stage of the split products
+constexpr int XKP = XK + 8;      // padded row of one BF16 part
+template <typename T> struct MmaLds {
+  static constexpr int bytes = 2 * BK * LW * (int)sizeof(T);
+};
+template <> struct MmaLds<float> {
+  static constexpr int bytes = 2 * 3 * kTile * XKP * 2;
+};
+
+// acc += (NEG_A ? -A : A)[0:128, 0:K] * diag(bscale[0:K]) * B[0:K, 0:128]
+// with FP32 operands on the BF16 matrix cores (split products above);
+// layouts and arguments as mma_tile.  Each stage loads 32 k of both
+// operands (a thread holds 16 values of one row of A and of one column of
+// B), splits them once and stores the three parts in fragment order, so the
+// product loop reads whole 8-element fragments (16 bytes) from LDS.
+template <bool NEG_A, bool TA>
+__device__ __forceinline__ void mma_tile_x6(const float *__restrict__ A, int lda,
+                                            const float *__restrict__ B, int ldb,
+                                            const double *__restrict__ bscale, int K,
+                                            unsigned char *smem, Tile<float> &acc) {
+  typedef __bf16 Part[kTile][XKP];
+  Part *Ap = reinterpret_cast<Part *>(smem);         // Ap[part][row][k]
+  Part *Bp = Ap + 3;                                 // Bp[part][col][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int rr = tid & (kTile - 1), kh = (tid >> 7) * 16;  // row / column, k half
+  float ra[16], rb[16];
+  auto load = [&](int k0) {
+    if (TA) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) ra[e] = gp(A)[(size_t)(k0 + kh + e) * lda + rr];
+    } else {
+      ld8(A + (size_t)rr * lda + k0 + kh, ra);
+      ld8(A + (size_t)rr * lda + k0 + kh + 8, ra + 8);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) rb[e] = gp(B)[(size_t)(k0 + kh + e) * ldb + rr];
+    if (bscale) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) rb[e] *= (float)gp(bscale)[k0 + kh + e];
+    }
+  };
+  auto store = [&](Part *P, const float (&x)[16], bool neg) {
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = neg ? -x[8 * hh + e] : x[8 * hh + e];
+      Split3 sp;
+      split8(v, sp);
+      *reinterpret_cast<bf16x8 *>(&P[0][rr][kh + 8 * hh]) = sp.h;
+      *reinterpret_cast<bf16x8 *>(&P[1][rr][kh + 8 * hh]) = sp.m;
+      *reinterpret_cast<bf16x8 *>(&P[2][rr][kh + 8 * hh]) = sp.l;
+    }
+  };
+  load(0);
+  const int g = lane >> 4, c = lane & 15;
+  for (int k0 = 0; k0 < K; k0 += XK) {
+    __syncthreads();
+    store(Ap, ra, NEG_A);
+    store(Bp, rb, false);
+    __syncthreads();
+    if (k0 + XK < K) load(k0 + XK);
+    // lane l holds row / column l % 16 of its tile and k = 8 (l / 16) + 0..7
+    Split3 bs[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = wn + j * 16 + c;
+      bs[j].h = *reinterpret_cast<const bf16x8 *>(&Bp[0][col][8 * g]);
+      bs[j].m = *reinterpret_cast<const bf16x8 *>(&Bp[1][col][8 * g]);
+      bs[j].l = *reinterpret_cast<const bf16x8 *>(&Bp[2][col][8 * g]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm + i * 16 + c;
+      Split3 as;
+      as.h = *reinterpret_cast<const bf16x8 *>(&Ap[0][row][8 * g]);
+      as.m = *reinterpret_cast<const bf16x8 *>(&Ap[1][row][8 * g]);
+      as.l = *reinterpret_cast<const bf16x8 *>(&Ap[2][row][8 * g]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc.v[i][j] = mfma_x6(as, bs[j], acc.v[i][j]);
+    }
+  }
+}
+
 // acc += (NEG_A ? -A : A)[0:128, 0:K] * diag(bscale[0:K]) * B[0:K, 0:128]
 // A row-major with leading dim lda (points at the tile's first row),
 // B row-major with leading dim ldb (points at the tile's first column).
 // TA: the operand is the transpose of a row-major matrix G, A[i][k] =
 // G[k][i]; A then points at G's column of the tile's first row.
+// FP32 operands go to mma_tile_x6 (BF16 matrix cores, 32-deep stages of
+// stages), FP64 ones to the FP64 matrix cores (16 deep).
 template <typename T, bool NEG_A = false, bool TA = false>
 __device__ __forceinline__ void mma_tile(const T *__restrict__ A, int lda,
                                          const T *__restrict__ B, int ldb,
                                          const double *__restrict__ bscale, int K,
                                          T (*As)[LW], T (*Bs)[LW], Tile<T> &acc) {
+  if constexpr (std::is_same<T, float>::value) {
+    // As is the start of an MmaLds<float>::bytes buffer
+    mma_tile_x6<NEG_A, TA>(A, lda, B, ldb, bscale, K, reinterpret_cast<unsigned char *>(As), acc);
+    return;
+  }
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -162,10 +299,11 @@ __device__ __forceinline__ int acc_col(int j) {
 
 // FP64: at least two wavefronts per SIMD, as for the update
 template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gemm(
+__global__ __launch_bounds__(256, 2) void k_gemm(
     const GemmJob *__restrict__ jobs, int ld, int tiles_per_mat, T alpha, T beta) {
-  __shared__ T As[BK][LW];
-  __shared__ T Bs[BK][LW];
+  __shared__ __align__(16) unsigned char smem[MmaLds<T>::bytes];
+  T (*As)[LW] = reinterpret_cast<T (*)[LW]>(smem);
+  T (*Bs)[LW] = As + BK;
   const int total = gridDim.x;
   const int lin = xcd_remap(blockIdx.x, total);
   const int b = lin / tiles_per_mat;
@@ -464,12 +602,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(96))) void k_gj
 //    when copy_c is set; after the first step the update that produced
 //    column block p writes this copy itself.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gj_panel(void *const *__restrict__ mats,
+__global__ __launch_bounds__(256, 2) void k_gj_panel(void *const *__restrict__ mats,
                                                   const T *__restrict__ Pinv,
                                                   T *__restrict__ Rbuf, T *__restrict__ Cbuf,
                                                   int ld, int p, int copy_c) {
-  __shared__ T As[BK][LW];
-  __shared__ T Bs[BK][LW];
+  __shared__ __align__(16) unsigned char smem[MmaLds<T>::bytes];
+  T (*As)[LW] = reinterpret_cast<T (*)[LW]>(smem);
+  T (*Bs)[LW] = As + BK;
   const int b = blockIdx.y, jt = blockIdx.x, tid = threadIdx.x;
   const T *D = static_cast<const T *>(mats[b]);
   T *R = Rbuf + (size_t)b * kNB * ld;
@@ -560,7 +699,7 @@ __device__ __forceinline__ void sel_tile(int sel, int nt, int q, int t, int &tr,
 // FP64: at least two wavefronts per SIMD (its accumulators would otherwise
 // take the register file of two)
 template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gj_update(
+__global__ __launch_bounds__(256, 2) void k_gj_update(
     void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
                                                    const T *__restrict__ Cbuf,
@@ -569,10 +708,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gj_update(
   using G = UpdGeom<T>;
   constexpr int XW = kTile + 4;  // exchange row width
   constexpr int HR = kTile / 2;  // rows per exchange half
-  static_assert(HR * XW >= 2 * BK * LW, "the staging buffers live inside the exchange buffer");
-  __shared__ T lds[HR * XW];
+  // the staging buffers of the product live inside the exchange buffer
+  constexpr int LDSN = HR * XW * (int)sizeof(T) > MmaLds<T>::bytes ? HR * XW * (int)sizeof(T)
+                                                                    : MmaLds<T>::bytes;
+  __shared__ __align__(16) unsigned char smem[LDSN];
+  T *lds = reinterpret_cast<T *>(smem);
   T (*As)[LW] = reinterpret_cast<T (*)[LW]>(lds);
-  T (*Bs)[LW] = reinterpret_cast<T (*)[LW]>(lds + BK * LW);
+  T (*Bs)[LW] = As + BK;
   T (*Xs)[XW] = reinterpret_cast<T (*)[XW]>(lds);
   const int nt = ld / kTile;
   const int tiles_per_mat = sel_tiles(sel, nt);
@@ -713,10 +855,11 @@ __global__ __launch_bounds__(256) void k_assemble(const AsmJob *__restrict__ job
 // + beta C with A ld x ld (op(A) = A, or A^T when TRANS), B and C ld x ldc
 // (ldc a multiple of 128), all row-major; 128 x 128 output tiles as k_gemm.
 template <typename T, bool TRANS>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gemm_rect(
+__global__ __launch_bounds__(256, 2) void k_gemm_rect(
     const GemmJob *__restrict__ jobs, int ld, int ldc, int tiles_per_job, T alpha, T beta) {
-  __shared__ T As[BK][LW];
-  __shared__ T Bs[BK][LW];
+  __shared__ __align__(16) unsigned char smem[MmaLds<T>::bytes];
+  T (*As)[LW] = reinterpret_cast<T (*)[LW]>(smem);
+  T (*Bs)[LW] = As + BK;
   const int total = gridDim.x;
   const int lin = xcd_remap(blockIdx.x, total);
   const int b = lin / tiles_per_job;
