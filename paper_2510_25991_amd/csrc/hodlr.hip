@@ -304,33 +304,38 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
 }
 
 // -------------------------------------------------- one-sided Jacobi SVD
-// X (n x s, column-major, n * s <= 128 * 128) -> X V with mutually
-// orthogonal columns; V (s x s, column-major) accumulates the rotations.
-// Round-robin pair ordering, four threads per pair; stops when a sweep
-// performs no rotation.
+// X (n x s, column-major, n <= SMAX, s <= SMAX, s even) -> X V with
+// mutually orthogonal columns; V (s x s, column-major) accumulates the
+// rotations, and sigma_k = |(X V)_k| is written for every column.
+// Round-robin pair ordering (player 0 fixed, the others rotating), 256 / (s/2)
+// threads per pair; stops when a sweep performs no rotation.
 struct JacJob {
   double *X;
   double *V;
   int n;
 };
 
-// The columns being rotated live in LDS (n * s <= kJacLds: the s x s R
-// factor of the sample block); V stays in global memory.
-constexpr int kJacLds = 128 * 128;
+// The columns being rotated (the s x s R factor of the sample block) live in
+// LDS, and so do the rotations when they fit beside them (SMAX <= 64: two
+// 32 KB arrays, so several blocks share a CU); at SMAX = 128 V stays in
+// global memory.
+template <int SMAX>
 __global__ __launch_bounds__(256) void k_jacobi(const JacJob *__restrict__ jobs, int s,
-                                                int max_sweeps, int *__restrict__ sweeps_out) {
+                                                int max_sweeps, double *__restrict__ sigma) {
+  constexpr bool VL = SMAX <= 64;
+  constexpr int TPP = 256 / (SMAX / 2);  // threads per pair
   __shared__ int rotated;
-  __shared__ double X[kJacLds];
+  __shared__ double X[SMAX * SMAX];
+  __shared__ double Vl[VL ? SMAX * SMAX : 1];
   const JacJob J = jobs[blockIdx.x];
   const int n = J.n;
-  double *V = J.V;
+  double *V = VL ? Vl : J.V;
   for (int e = threadIdx.x; e < s * s; e += 256) V[e] = (e / s == e % s) ? 1.0 : 0.0;
   for (int e = threadIdx.x; e < n * s; e += 256) X[e] = J.X[e];
   __syncthreads();
-  const int grp = threadIdx.x >> 2, sub = threadIdx.x & 3;  // 64 pairs x 4 threads
+  const int grp = threadIdx.x / TPP, sub = threadIdx.x % TPP;
   const int npairs = s / 2;
-  int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < s - 1; ++round) {
@@ -340,12 +345,13 @@ __global__ __launch_bounds__(256) void k_jacobi(const JacJob *__restrict__ jobs,
         if (p > q) { const int t = p; p = q; q = t; }
         double *xp = X + (size_t)p * n, *xq = X + (size_t)q * n;
         double a = 0, b = 0, g = 0;
-        for (int i = sub; i < n; i += 4) {
+        for (int i = sub; i < n; i += TPP) {
           const double u = xp[i], v = xq[i];
           a += u * u; b += v * v; g += u * v;
         }
-        // combine the 4 partial sums of the group (lanes 4k..4k+3)
-        for (int off = 1; off < 4; off <<= 1) {
+        // combine the partial sums of the pair's TPP consecutive lanes
+#pragma unroll
+        for (int off = 1; off < TPP; off <<= 1) {
           a += __shfl_xor(a, off, 64);
           b += __shfl_xor(b, off, 64);
           g += __shfl_xor(g, off, 64);
@@ -354,13 +360,13 @@ __global__ __launch_bounds__(256) void k_jacobi(const JacJob *__restrict__ jobs,
           const double zeta = (b - a) / (2.0 * g);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-          for (int i = sub; i < n; i += 4) {
+          for (int i = sub; i < n; i += TPP) {
             const double u = xp[i], v = xq[i];
             xp[i] = c * u - sn * v;
             xq[i] = sn * u + c * v;
           }
           double *vp = V + (size_t)p * s, *vq = V + (size_t)q * s;
-          for (int i = sub; i < s; i += 4) {
+          for (int i = sub; i < s; i += TPP) {
             const double u = vp[i], v = vq[i];
             vp[i] = c * u - sn * v;
             vq[i] = sn * u + c * v;
@@ -375,23 +381,12 @@ __global__ __launch_bounds__(256) void k_jacobi(const JacJob *__restrict__ jobs,
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n * s; e += 256) J.X[e] = X[e];
-  if (threadIdx.x == 0 && sweeps_out) sweeps_out[blockIdx.x] = sweep;
-}
-
-// sigma_k = |X_k| for every column (sigma out: s per job)
-__global__ __launch_bounds__(256) void k_col_norms(const JacJob *__restrict__ jobs, int s,
-                                                   double *__restrict__ sigma) {
-  __shared__ double sh[8];
-  const JacJob J = jobs[blockIdx.x];
-  for (int k = 0; k < s; ++k) {
-    double p = 0.0;
-    for (int i = threadIdx.x; i < J.n; i += 256) {
-      const double v = J.X[(size_t)k * J.n + i];
-      p += v * v;
-    }
-    const double t = block_reduce_sum(p, sh);
-    if (threadIdx.x == 0) sigma[(size_t)blockIdx.x * s + k] = sqrt(t);
-    __syncthreads();
+  if (VL)
+    for (int e = threadIdx.x; e < s * s; e += 256) J.V[e] = V[e];
+  for (int k = threadIdx.x; k < s; k += 256) {
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += X[(size_t)k * n + i] * X[(size_t)k * n + i];
+    sigma[(size_t)blockIdx.x * s + k] = sqrt(t);
   }
 }
 
@@ -854,64 +849,70 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       DMem *R = nullptr, *XR = nullptr;  // R of X = Q2 R, and X rotated (Q2 R J)
       int s = 0;
       std::vector<HBlock> blocks;
+      std::vector<char> kept;  // block accepted at this sample count
       std::vector<size_t> offY, offX;
       std::vector<int> selofs;
     };
     std::vector<LevelData> levels;
     int worst = 0;
-    // The blocks of one level are grouped by their sample count: every block
-    // is sampled with as many Gaussian columns as its smaller side allows
-    // (even, up to the cap), so a level whose leaves differ in size (the
-    // quadtree of an odd interface grid, a ragged binary split) does not
-    // sample its wider blocks with the count of its narrowest one.
+    // Adaptive sample counts.  Every admissible block is first sampled with
+    // kSampleStart Gaussian columns (or all of them, when its smaller side
+    // is shorter); a block whose numerical rank comes within `oversample` of
+    // its sample count is sampled again with twice as many, up to
+    // min(rank cap + oversample, smaller side).  Blocks of one tree level
+    // and one sample count are compressed together (one group); most blocks
+    // of the workloads here are accepted at the first count, so the QR and
+    // the Jacobi sweeps (whose cost grows like s^2 and s^3) run on s = 32.
+    constexpr int kSampleStart = 32;
     struct Group {
       int L, s;
-      std::vector<std::pair<int, int>> pairs;
+      std::vector<HBlock> blocks;
+    };
+    auto full_count = [&](const HBlock &b) {  // largest useful sample count
+      int sb = std::min(s_cap, std::min(b.r1 - b.r0, b.c1 - b.c0));
+      sb -= sb & 1;
+      return std::max(sb, 2);
     };
     std::vector<Group> groups;
-    for (size_t L = 0; L < lev.size(); ++L) {
-      std::map<int, size_t> at;
-      for (auto &pr : lev[L]) {
-        const int m = nodes[pr.first].hi - nodes[pr.first].lo;
-        const int n = nodes[pr.second].hi - nodes[pr.second].lo;
-        int sb = std::min(s_cap, std::min(m, n));
-        sb -= sb & 1;
-        if (sb < 2) sb = 2;
-        auto it = at.find(sb);
-        if (it == at.end()) {
-          it = at.emplace(sb, groups.size()).first;
-          groups.push_back({(int)L, sb, {}});
+    auto add_block = [&](const HBlock &b, int sb) {
+      for (Group &g : groups)
+        if (g.L == b.level && g.s == sb) {
+          g.blocks.push_back(b);
+          return;
         }
-        groups[it->second].pairs.push_back(pr);
-      }
-    }
-    for (const Group &grp : groups) {
-      if (nmat == 0) continue;
-      const int L = grp.L;
-      int mmax = 0, nmax = 0;
-      for (auto &pr : grp.pairs) {
-        mmax = std::max(mmax, nodes[pr.first].hi - nodes[pr.first].lo);
-        nmax = std::max(nmax, nodes[pr.second].hi - nodes[pr.second].lo);
-      }
-      const int s = grp.s;
-      LevelData D;
-      D.s = s;
-      size_t totY = 0, totX = 0;
+      groups.push_back({b.level, sb, {b}});
+    };
+    for (size_t L = 0; L < lev.size(); ++L)
       for (int mi = 0; mi < nmat; ++mi)
-        for (auto &pr : grp.pairs) {
+        for (auto &pr : lev[L]) {
           HBlock b{};
           b.smat = mats[mi];
           b.r0 = nodes[pr.first].lo;
           b.r1 = nodes[pr.first].hi;
           b.c0 = nodes[pr.second].lo;
           b.c1 = nodes[pr.second].hi;
-          b.level = L;
-          D.blocks.push_back(b);
-          D.offY.push_back(totY);
-          D.offX.push_back(totX);
-          totY += (size_t)(b.r1 - b.r0) * s;
-          totX += (size_t)(b.c1 - b.c0) * s;
+          b.level = (int)L;
+          add_block(b, std::min(full_count(b), kSampleStart));
         }
+    // groups appended while this loop runs (blocks sampled again) are
+    // processed by it too; a group is never revisited once processed
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      if (nmat == 0) continue;
+      const int L = groups[gi].L;
+      const int s = groups[gi].s;
+      LevelData D;
+      D.s = s;
+      D.blocks = groups[gi].blocks;
+      int mmax = 0, nmax = 0;
+      size_t totY = 0, totX = 0;
+      for (const HBlock &b : D.blocks) {
+        mmax = std::max(mmax, b.r1 - b.r0);
+        nmax = std::max(nmax, b.c1 - b.c0);
+        D.offY.push_back(totY);
+        D.offX.push_back(totX);
+        totY += (size_t)(b.r1 - b.r0) * s;
+        totX += (size_t)(b.c1 - b.c0) * s;
+      }
       const int nbk = (int)D.blocks.size();
       D.Y = new DMem(totY * 8); keep.push_back(D.Y);
       D.X = new DMem(totX * 8); keep.push_back(D.X);
@@ -953,15 +954,21 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       hipLaunchKernelGGL(k_block_gemm<T>, dim3((nmax + 63) / 64, nbk), dim3(256), 0, st, dgx,
                          d_perm, op->ld, s, 1);
       hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(256), 0, st, dqx, s);
-      hipLaunchKernelGGL(k_jacobi, dim3(nbk), dim3(256), 0, st, djac, s, 30, (int *)nullptr);
-      hipLaunchKernelGGL(k_col_norms, dim3(nbk), dim3(256), 0, st, djac, s,
-                         static_cast<double *>(D.sig->p));
+      double *dsig = static_cast<double *>(D.sig->p);
+      if (s <= 32)
+        hipLaunchKernelGGL(k_jacobi<32>, dim3(nbk), dim3(256), 0, st, djac, s, 30, dsig);
+      else if (s <= 64)
+        hipLaunchKernelGGL(k_jacobi<64>, dim3(nbk), dim3(256), 0, st, djac, s, 30, dsig);
+      else
+        hipLaunchKernelGGL(k_jacobi<128>, dim3(nbk), dim3(256), 0, st, djac, s, 30, dsig);
       hipLaunchKernelGGL(k_dense_gemm, dim3((nmax + 63) / 64, nbk), dim3(256), 0, st, drot, s);
       HCHK(hipGetLastError());
       std::vector<double> sig((size_t)nbk * s);
       HCHK(hipMemcpyAsync(sig.data(), D.sig->p, sig.size() * 8, hipMemcpyDeviceToHost, st));
       HCHK(hipStreamSynchronize(st));
       std::vector<int> selall;
+      std::vector<HBlock> again;
+      D.kept.assign(nbk, 0);
       for (int b = 0; b < nbk; ++b) {
         HBlock &hb = D.blocks[b];
         const double thr = H->tol_used * snorm[hb.smat];
@@ -973,15 +980,24 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
                   });
         int r = 0;
         while (r < s && sv[r].first > thr) ++r;
-        // the sample count bounds the rank that can be certified: a block
-        // sampled with fewer columns than its smaller side (the rank cap, or
-        // a level that mixes block sizes and takes s from its smallest
-        // block) whose rank comes within `oversample` of s may have more
-        // singular values above the threshold than the samples show: a rank
-        // overflow.  A block with s equal to its smaller side is sampled
-        // completely.
+        // The sample count bounds the rank that can be certified: a block
+        // sampled with fewer columns than its smaller side whose rank comes
+        // within `oversample` of s may have more singular values above the
+        // threshold than the samples show.  It is sampled again with twice
+        // the count while that stays below min(cap, smaller side); at that
+        // limit (the rank cap) it is a rank overflow.  A block with s equal
+        // to its smaller side is sampled completely.
         const bool undersampled = s < std::min(hb.r1 - hb.r0, hb.c1 - hb.c0);
-        if (undersampled && r > s - o.oversample) worst = std::max(worst, r);
+        if (undersampled && r > s - o.oversample) {
+          const int sf = full_count(hb);
+          if (s < sf) {
+            again.push_back(hb);
+            D.selofs.push_back(0);
+            continue;
+          }
+          worst = std::max(worst, r);
+        }
+        D.kept[b] = 1;
         hb.rank = r;
         hb.off_u = store_elems;
         store_elems += (size_t)(hb.r1 - hb.r0) * r;
@@ -999,6 +1015,16 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
                             hipMemcpyHostToDevice, st));
       HCHK(hipStreamSynchronize(st));
       levels.push_back(std::move(D));
+      for (const HBlock &hb : again) {
+        const int s2 = std::min(full_count(hb), 2 * s);
+        bool found = false;
+        for (size_t g2 = gi + 1; g2 < groups.size() && !found; ++g2)
+          if (groups[g2].L == L && groups[g2].s == s2) {
+            groups[g2].blocks.push_back(hb);
+            found = true;
+          }
+        if (!found) groups.push_back({L, s2, {hb}});
+      }
     }
     if (worst > 0) {
       cleanup();
@@ -1022,6 +1048,7 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       const int nbk = (int)D.blocks.size();
       std::vector<PackJob> pj;
       for (int b = 0; b < nbk; ++b) {
+        if (!D.kept[b]) continue;  // sampled again with more columns
         const HBlock &hb = D.blocks[b];
         pj.push_back({static_cast<double *>(D.Y->p) + D.offY[b], static_cast<double *>(D.XR->p) + D.offX[b],
                       static_cast<double *>(D.V->p) + (size_t)b * D.s * D.s, static_cast<int *>(D.sel->p) + D.selofs[b],
@@ -1029,8 +1056,10 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
                       (long long)hb.off_v});
         H->blocks.push_back(hb);
       }
+      if (pj.empty()) continue;
       const PackJob *d = static_cast<const PackJob *>(upload(pj, st, keep));
-      hipLaunchKernelGGL(k_pack<F>, dim3(32, nbk), dim3(256), 0, st, d, D.s, store);
+      hipLaunchKernelGGL(k_pack<F>, dim3(32, (unsigned)pj.size()), dim3(256), 0, st, d, D.s,
+                         store);
     }
     HCHK(hipGetLastError());
     HCHK(hipStreamSynchronize(st));
