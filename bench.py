@@ -38,7 +38,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma_tflops": 157.3, "fp64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
+PEAK = {"fp32_mfma_tflops": 157.3, "fp64_mfma_tflops": 78.6, "bf16_mfma_tflops": 2500.0,
+        "hbm_gbs": 8000.0}
+# The FP32 products of the build run on the BF16 matrix cores: each FP32
+# operand is split into three BF16 parts and every 16x16x32 FP32 tile
+# product costs six BF16 products, so the ceiling of that arithmetic is the
+# dense BF16 peak / 6 (FP32-equivalent flops).
+X6_PRODUCTS = 6
+PEAK["fp32_via_bf16x6_tflops"] = PEAK["bf16_mfma_tflops"] / X6_PRODUCTS
 # width of the pivot blocks of the library's Gauss-Jordan inversion (the rank
 # of each update step)
 GJ_RANK = 128
@@ -153,15 +160,16 @@ def pmc_measure(root):
     import subprocess
     import tempfile
     res = {"traffic_bytes_per_launch": None, "fetch_scale": None, "write_scale": None,
-           "mfma_flops_per_launch": None, "mfma_busy_serialised": None, "launches": None,
+           "mfma_flops_per_launch": None, "mfma_bf16_flops_per_launch": None,
+           "mfma_busy_serialised": None, "launches": None,
            "error": None}
     prof = shutil.which("rocprofv3")
     if prof is None:
         res["error"] = "rocprofv3 not found"
         return res
     passes = {"fetch": ["FETCH_SIZE"], "write": ["WRITE_SIZE"],
-              "mfma": ["SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_VALU_MFMA_BUSY_CYCLES",
-                       "GRBM_GUI_ACTIVE"]}
+              "mfma": ["SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                       "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE"]}
     rows = {}
     tmp = tempfile.mkdtemp(prefix="ddst_pmc_", dir="/tmp")
     env = dict(os.environ, TMPDIR="/tmp")
@@ -197,11 +205,14 @@ def pmc_measure(root):
                                            + sum(w.values()) / len(w) * ws) * 1024.0
     mr = rows.get("mfma", [])
     mops = _per_dispatch(mr, PMC_KERNEL, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    mops16 = _per_dispatch(mr, PMC_KERNEL, "SQ_INSTS_VALU_MFMA_MOPS_BF16")
     busy = _per_dispatch(mr, PMC_KERNEL, "SQ_VALU_MFMA_BUSY_CYCLES")
     act = _per_dispatch(mr, PMC_KERNEL, "GRBM_GUI_ACTIVE")
+    # the counters count matrix-core operations in units of 512 flops
     if mops:
-        # the counter counts matrix-core operations in units of 512 flops
         res["mfma_flops_per_launch"] = 512.0 * sum(mops.values()) / len(mops)
+    if mops16:
+        res["mfma_bf16_flops_per_launch"] = 512.0 * sum(mops16.values()) / len(mops16)
     if busy and act and sum(act.values()) > 0:
         # busy cycles summed over the SIMDs; active cycles summed over the
         # 8 XCDs: fraction = busy / (active / 8 x 1024 SIMDs)
@@ -240,7 +251,13 @@ def roofline(prof, precision, M, pmc=None):
     floor is higher: HBM (algorithmic bytes / 8 TB/s) or the matrix cores
     (flops / dense MFMA peak of the precision).  At r = 128 and M = 1023 the
     intensity is about 26.5 flop/B in FP32 and 13.3 in FP64, above both
-    ridges (157.3 / 8 and 78.6 / 8), so the update is MFMA-bound.  Launches
+    ridges of the FP32 and FP64 instructions (157.3 / 8 and 78.6 / 8).  The
+    FP32 products run as six BF16 products each (three-part split), so the
+    matrix-core ceiling of the FP32 path is the BF16 dense peak / 6 =
+    416.7 TFLOP/s of FP32 work, ridge 52 flop/B: at M = 1023 the FP32 update
+    is then HBM-bound (its D read-modify-write), the FP64 one MFMA-bound.
+    The rate against the FP32 instruction's own peak is given beside it.
+    Launches
     of the look-ahead schedule cover subsets of the tiles; their work is
     summed, so the figures are averages over all update launches.  Two of
     them run at once on different streams, so the average launch duration
@@ -249,7 +266,8 @@ def roofline(prof, precision, M, pmc=None):
     name, (n, ms, work, busy_ms) = max(prof.items(), key=lambda kv: kv[1][1])
     avg_s = ms / 1e3 / max(n, 1)
     esz = 4 if precision == "fp32" else 8
-    mpeak = PEAK["fp32_mfma_tflops"] if precision == "fp32" else PEAK["fp64_mfma_tflops"]
+    mpeak = (PEAK["fp32_via_bf16x6_tflops"] if precision == "fp32"
+             else PEAK["fp64_mfma_tflops"])
     base = {"kernel": name, "launches": n, "avg_launch_us": round(avg_s * 1e6, 2)}
     if busy_ms > 0 and name in ("gj_update", "gemm", "gj_panel"):
         ach_u = work / (busy_ms / 1e3) / 1e12
@@ -271,6 +289,17 @@ def roofline(prof, precision, M, pmc=None):
                  # executed matrix-core flops from SQ_INSTS_VALU_MFMA_MOPS_F32
                  "flops_executed_per_launch": ex,
                  "executed_over_algorithmic": round(ex / flops_per_launch, 3) if ex else None,
+                 # executed BF16 matrix-core flops (SQ_INSTS_VALU_MFMA_MOPS_BF16):
+                 # six BF16 products per FP32 product
+                 "bf16_flops_executed_per_launch": pm.get("mfma_bf16_flops_per_launch"),
+                 "bf16_executed_over_algorithmic": (
+                     round(pm["mfma_bf16_flops_per_launch"] / flops_per_launch, 3)
+                     if pm.get("mfma_bf16_flops_per_launch") else None),
+                 "peak_basis": ("BF16 dense peak 2500 TFLOP/s / 6 BF16 products per FP32 "
+                                "product" if precision == "fp32" else "FP64 dense MFMA peak"),
+                 "frac_vs_fp32_instruction_peak": (
+                     round(flops_per_launch / avg_s / 1e12 / PEAK["fp32_mfma_tflops"], 4)
+                     if precision == "fp32" else None),
                  "hbm_gbs": round(bytes_per_launch / avg_s / 1e9, 1),
                  # matrix-core busy fraction of the same launches when rocprofv3
                  # serialises them (the two look-ahead halves otherwise overlap,
@@ -280,7 +309,8 @@ def roofline(prof, precision, M, pmc=None):
                  "counters": ({"launches": pm.get("launches"), "fetch_scale": pm.get("fetch_scale"),
                                "write_scale": pm.get("write_scale"), "error": pm.get("error")}
                               if pm else None),
-                 "mfma_tflops": round(flops_per_launch / avg_s / 1e12, 3)}
+                 "mfma_tflops": round(flops_per_launch / avg_s / 1e12, 3),
+                 "frac_mfma": round(flops_per_launch / avg_s / 1e12 / mpeak, 4)}
         if mfma_floor >= hbm_floor:
             achieved = flops_per_launch / avg_s / 1e12
             return name, {"bound": "mfma", "achieved": round(achieved, 3), "peak": mpeak,
@@ -292,7 +322,7 @@ def roofline(prof, precision, M, pmc=None):
                       **extra, **base}
     if name in ("gemm", "gj_panel"):
         achieved = work / max(n, 1) / avg_s / 1e12
-        peak = PEAK["fp32_mfma_tflops"] if precision == "fp32" else PEAK["fp64_mfma_tflops"]
+        peak = mpeak
         return name, {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                       "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                       "flops_per_launch": work / max(n, 1), **base}
@@ -395,14 +425,17 @@ def large_leg(dd, torch, name):
     kap, c, f = t(p.kappa), t(p.c), t(p.f)
     F_build = p.n_ds * (2 * p.m - 1) * (14.0 / 3.0) * float(p.M) ** 3
     M3, steps = float(p.M) ** 3, p.m - 1
-    # algorithmic work of each route's build: Gauss-Jordan inverses 2 M^3
-    # (left-to-right sweeps of every slab, right-to-left sweeps of the
-    # interior ones, the interface blocks), transfer chains 2 M^3 per step
-    # of the interior slabs' two sweeps and the blocks S = Sigma^{-1} R
-    # (dense route) or the sampling chains 2 M^2 s per step of four chains
-    # per interior slab plus the final and W products (sampled route)
-    inv = ((p.n_slabs + p.n_ds) * steps + p.n_ds) * 2.0 * M3
-    flops = {"dense_hodlr": inv + (2 * (p.n_slabs - 2) * steps + 2 * (p.n_ds - 1)) * 2.0 * M3}
+    # algorithmic work of each route's build: Gauss-Jordan inverses 2 M^3,
+    # or M^3 by the symmetric elimination (lower triangle only) when the
+    # operator has no convection (left-to-right sweeps of every slab,
+    # right-to-left sweeps of the interior ones, the interface blocks),
+    # transfer chains 2 M^3 per step of the interior slabs' two sweeps and
+    # the blocks S = Sigma^{-1} R (dense route) or the sampling chains
+    # 2 M^2 s per step of four chains per interior slab plus the final and W
+    # products (sampled route)
+    n_inv = (p.n_slabs + p.n_ds) * steps + p.n_ds
+    chain = (2 * (p.n_slabs - 2) * steps + 2 * (p.n_ds - 1)) * 2.0 * M3
+    flops = {}
     out = {"workload": f"{p.dim}D {name} {p.n}^{p.dim}, {p.n_slabs} slabs, M={p.M}, N_ds={p.n_ds}",
            "N": p.N, "s_build_nominal_flops": F_build}
     opts = dd.SolveOptions(tol=1e-9, max_iter=3000, max_outer=12)
@@ -413,7 +446,10 @@ def large_leg(dd, torch, name):
         t0 = time.perf_counter()
         op = dd.Operator(p.dim, p.n, p.n_slabs, kappa=kap, bvec=p.bvec, c=c, precision="fp32",
                          transfer_blocks=(route == "dense_hodlr"))
+        sym = bool(op.build_stats()["symmetric"])
+        inv = n_inv * (1.0 if sym else 2.0) * M3
         if route == "dense_hodlr":
+            flops[route] = inv + chain
             info = op.compress(tol=1e-8 if p.dim == 2 else 1e-7, leaf=128, oversample=10,
                                max_rank=118, factor_dtype="bf16")
             o = dataclasses_replace(opts, use_hodlr=True)
@@ -439,6 +475,7 @@ def large_leg(dd, torch, name):
              # route's build time; the sampled route does less than that
              "s_build_tflops_nominal": round(F_build / bt / 1e12, 2),
              "build_flops": flops[route],
+             "symmetric_elimination": sym,
              "build_tflops": round(flops[route] / bt / 1e12, 2)
              if route == "dense_hodlr" else None,
              "solve_ms": round(st["t_solve_ms"], 1), "outer_iters": st["outer_iters"],

@@ -57,6 +57,9 @@ enum {
 
 /* Arithmetic of the local eliminations, transfer blocks and factors. */
 enum { DDST_FP64 = 0, DDST_FP32 = 1 };
+/* Local elimination: symmetric when the operator is (automatic), or always
+ * the general one. */
+enum { DDST_ELIM_AUTO = 0, DDST_ELIM_GENERAL = 1 };
 /* Cluster tree for hierarchical compression. */
 enum { DDST_TREE_BINARY = 0, DDST_TREE_QUAD = 1 };
 /* Storage type of the compressed low-rank factors. */
@@ -105,6 +108,16 @@ typedef struct {
                                nonsingular too, not only the double slab: a
                                pivot growth (ddst_stats_t) above 1e12 (FP64)
                                or 1e5 (FP32) is reported as EBREAKDOWN        */
+  int32_t elimination;      /* DDST_ELIM_AUTO (0): when the operator is
+                               symmetric (no convection: bvec = 0) and the
+                               local problems definite (indefinite = 0), its
+                               plane blocks and interface blocks are
+                               symmetric and the local inverses are formed
+                               by the symmetric elimination, which updates
+                               only the lower triangle (about half the work,
+                               the factorisation remark of Section 2.5);
+                               DDST_ELIM_GENERAL (1): always the general
+                               elimination                                    */
 } ddst_build_opts_t;
 
 typedef struct {
@@ -153,6 +166,8 @@ typedef struct {
                                local eliminations of the build: of order
                                1 / (eps ||A||) ||A|| when a local problem is
                                singular to working precision                  */
+  int32_t symmetric;        /* 1 if the build used the symmetric elimination   */
+  int32_t reserved_;
 } ddst_stats_t;
 
 /*
@@ -431,6 +446,11 @@ int ddst_test_gemm(int32_t precision, int32_t ld, int32_t batch, const void *A, 
                    void *C, const double *bscale, double alpha, double beta,
                    hipStream_t stream);
 int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipStream_t stream);
+/* ddst_test_invert_sym: the same by the symmetric elimination (each A_b must
+ *   be symmetric; of its 128 x 128 tiles only those on and below the
+ *   diagonal are read, the inverse is written in full). */
+int ddst_test_invert_sym(int32_t precision, int32_t ld, int32_t batch, void *A,
+                         hipStream_t stream);
 
 /*
  * Per-kernel-class timing.  ddst_profile_select(kinds) clears the counters

@@ -285,7 +285,7 @@ void run_sweeps(ddst_op *op, const SweepPlan &plan, const SweepBuffers &buf, hip
                          ld, s);
       if (k >= 2) chain(k - 1);
       HIPCHK(gj_invert<T>(tab.at<void *>(off_mats[k - 1]), nsw, ld, op->M, gjw.p, op->flag,
-                          op->indefinite, gs, s));
+                          op->indefinite, op->sym, gs, s));
     }
     chain(m - 1);
     if (chains) HIPCHK(hipStreamWaitEvent(s, ev_y[m - 1], 0));
@@ -432,7 +432,7 @@ int build_impl(ddst_op *op, int keep, int blocks, hipStream_t s) {
   GjStreams gs;
   HIPCHK(gs.create());
   HIPCHK(gj_invert<T>(tab.at<void *>(om), nds, op->ld, op->M, gjw.p, op->flag, op->indefinite,
-                      gs, s));
+                      op->sym, gs, s));
   if (!sj.empty())
     launch_gemm<T>(tab.at<GemmJob>(os), (int)sj.size(), op->ld, op->M, -1.0, 0.0, s);
   HIPCHK(hipGetLastError());
@@ -472,7 +472,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
   *out = nullptr;
   int st = validate_problem(prob);
   if (st) return st;
-  ddst_build_opts_t o{DDST_FP32, 1, 0, 0, 0};
+  ddst_build_opts_t o{DDST_FP32, 1, 0, 0, 0, DDST_ELIM_AUTO};
   if (opts) o = *opts;
   if (o.precision != DDST_FP32 && o.precision != DDST_FP64)
     return fail(DDST_EINVAL, "precision must be DDST_FP32 or DDST_FP64");
@@ -483,6 +483,8 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     return fail(DDST_EINVAL, "skip_transfer needs keep_factors (the matrix-free apply reads them)");
   if (o.indefinite != 0 && o.indefinite != 1)
     return fail(DDST_EINVAL, "indefinite must be 0 or 1");
+  if (o.elimination != DDST_ELIM_AUTO && o.elimination != DDST_ELIM_GENERAL)
+    return fail(DDST_EINVAL, "elimination must be DDST_ELIM_AUTO or DDST_ELIM_GENERAL");
   const int blocks = o.skip_transfer ? 0 : 1;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -502,6 +504,15 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     op->prec = o.precision;
     op->indefinite = o.indefinite;
     for (int a = 0; a < 3; ++a) op->bvec[a] = prob->bvec[a];
+    // the FD matrix is symmetric without convection (diffusion with
+    // edge-averaged coefficients and a diagonal zeroth-order term), and so
+    // are its plane blocks, their Schur complements and the interface
+    // blocks.  Indefinite local problems keep the general elimination: past
+    // a double-slab resonance the transfer blocks amplify the rounding of
+    // the local inverses, and the symmetric one (which projects each input
+    // onto symmetric matrices) lost a factor ~30 there in FP64.
+    op->sym = o.elimination == DDST_ELIM_AUTO && !o.indefinite && prob->bvec[0] == 0.0 &&
+              prob->bvec[1] == 0.0 && (prob->dim == 2 || prob->bvec[2] == 0.0);
     op->mat_bytes = (size_t)op->ld * op->ld * esize(op->prec);
     const size_t ncell = (size_t)std::pow((double)(op->n + 1), op->dim) + 0.5;
     Carve cv;
@@ -564,6 +575,7 @@ int build_entry(const ddst_problem_t *prob, const ddst_build_opts_t *opts, hipSt
     op->last_build.bytes_transfer = op->S ? (double)2 * op->n_ds * op->mat_bytes : 0;
     op->last_build.bytes_factors = op->G ? (double)op->n_slabs * (op->m - 1) * op->mat_bytes : 0;
     op->last_build.pivot_growth = op->pivot_growth;
+    op->last_build.symmetric = op->sym;
   } catch (...) {
     destroy_op(op);
     (void)hipEventDestroy(e0);
@@ -1851,7 +1863,8 @@ int ddst_test_gemm(int32_t precision, int32_t ld, int32_t batch, const void *A, 
   });
 }
 
-int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipStream_t stream) {
+static int test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, int sym,
+                       hipStream_t stream) {
   g_err.clear();
   if (!A || batch < 1 || ld < kTile || ld % kTile != 0 ||
       (precision != DDST_FP32 && precision != DDST_FP64))
@@ -1870,9 +1883,9 @@ int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipS
     HIPCHK(gs.create());
     int *flag = static_cast<int *>(fl.p);
     if (precision == DDST_FP32)
-      HIPCHK(gj_invert<float>(t.at<void *>(o), batch, ld, ld, w.p, flag, 0, gs, stream));
+      HIPCHK(gj_invert<float>(t.at<void *>(o), batch, ld, ld, w.p, flag, 0, sym, gs, stream));
     else
-      HIPCHK(gj_invert<double>(t.at<void *>(o), batch, ld, ld, w.p, flag, 0, gs, stream));
+      HIPCHK(gj_invert<double>(t.at<void *>(o), batch, ld, ld, w.p, flag, 0, sym, gs, stream));
     HIPCHK(hipGetLastError());
     int h = 0;
     HIPCHK(hipMemcpyAsync(&h, fl.p, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -1880,6 +1893,15 @@ int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipS
     if (h) return fail(DDST_EBREAKDOWN, "non-positive or non-finite pivot");
     return DDST_OK;
   });
+}
+
+int ddst_test_invert(int32_t precision, int32_t ld, int32_t batch, void *A, hipStream_t stream) {
+  return test_invert(precision, ld, batch, A, 0, stream);
+}
+
+int ddst_test_invert_sym(int32_t precision, int32_t ld, int32_t batch, void *A,
+                         hipStream_t stream) {
+  return test_invert(precision, ld, batch, A, 1, stream);
 }
 
 }  // extern "C"

@@ -639,6 +639,134 @@ __global__ __launch_bounds__(256, 2) void k_gj_panel(void *const *__restrict__ m
         R[(size_t)acc_row<T>(i, r) * ld + j0 + acc_col(j)] = acc.v[i][j][r];
 }
 
+// (i, j) of the t-th tile of a lower triangle of tiles, in row order
+__device__ __forceinline__ void tri_index(int t, int &i, int &j) {
+  int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while (r > 0 && r * (r + 1) / 2 > t) --r;
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  i = r;
+  j = t - r * (r + 1) / 2;
+}
+
+// Transposed copy of a 128 x 128 tile through LDS, 32 source rows at a
+// time: dst[r][c] = sg * src[c][r] (src row-major with leading dim lds_,
+// dst with leading dim ldd).  X: 32 x (kTile + 1) elements of LDS.
+template <typename T>
+__device__ __forceinline__ void tile_transpose(const T *__restrict__ src, int lds_,
+                                               T *__restrict__ dst, int ldd, T sg,
+                                               T (*X)[kTile + 1]) {
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < kTile; c0 += 32) {
+    __syncthreads();
+    for (int e = tid; e < 32 * kTile; e += 256) {
+      const int rr = e / kTile, cc = e % kTile;
+      X[rr][cc] = gp(src)[(size_t)(c0 + rr) * lds_ + cc];
+    }
+    __syncthreads();
+    for (int e = tid; e < kTile * 32; e += 256) {
+      const int r = e / 32, cc = e % 32;
+      gp(dst)[(size_t)r * ldd + c0 + cc] = sg * X[cc][r];
+    }
+  }
+  __syncthreads();
+}
+
+// One step of the symmetric elimination, panel part (the general update's
+// layout; see k_gj_update).  Work-group (it, b) takes row block i = it:
+//  * i == p: Rbuf[:, p] = P^{-1};
+//  * otherwise C_i = D[i, p] (i > p) or -D[p, i]^T (i < p), read from the
+//    lower triangle, is copied to Cbuf rows i (the operand of the update,
+//    which overwrites column and row block p), and W_i = C_i P^{-1} is
+//    formed on the matrix cores and written transposed to Rbuf[:, i].
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gj_panel_sym(void *const *__restrict__ mats,
+                                                      const T *__restrict__ Pinv,
+                                                      T *__restrict__ Rbuf, T *__restrict__ Cbuf,
+                                                      int ld, int p) {
+  __shared__ __align__(16) unsigned char smem[MmaLds<T>::bytes];
+  static_assert(32 * (kTile + 1) * sizeof(T) <= MmaLds<T>::bytes, "transpose chunk fits");
+  T (*As)[LW] = reinterpret_cast<T (*)[LW]>(smem);
+  T (*Bs)[LW] = As + BK;
+  const int b = blockIdx.y, it = blockIdx.x, tid = threadIdx.x;
+  const T *D = static_cast<const T *>(mats[b]);
+  T *R = Rbuf + (size_t)b * kNB * ld;
+  T *Cb = Cbuf + (size_t)b * ld * kNB;
+  const T *Pi = Pinv + (size_t)b * kNB * kNB;
+  const int p0 = p * kNB, i0 = it * kTile;
+  constexpr int V = 16 / sizeof(T);
+  if (it == p) {
+    for (int e = tid * V; e < kNB * kTile; e += 256 * V) {
+      const int r = e / kTile, c = e % kTile;
+      st16(R + (size_t)r * ld + p0 + c, ld16(Pi + r * kNB + c));
+    }
+    return;
+  }
+  Tile<T> acc;
+  acc.zero();
+  if (it > p)
+    mma_tile<T>(D + (size_t)i0 * ld + p0, ld, Pi, kNB, nullptr, kNB, As, Bs, acc);
+  else
+    mma_tile<T, true, true>(D + (size_t)p0 * ld + i0, ld, Pi, kNB, nullptr, kNB, As, Bs, acc);
+  // Rbuf[c][i0 + r] = W_i[r][c]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        R[(size_t)acc_col(j) * ld + i0 + acc_row<T>(i, r)] = acc.v[i][j][r];
+  if (it > p) {
+    for (int e = tid * V; e < kTile * kNB; e += 256 * V) {
+      const int r = e / kNB, c = e % kNB;
+      st16(Cb + (size_t)(i0 + r) * kNB + c, ld16(D + (size_t)(i0 + r) * ld + p0 + c));
+    }
+  } else {
+    __syncthreads();  // the product's LDS is reused
+    tile_transpose<T>(D + (size_t)p0 * ld + i0, ld, Cb + (size_t)i0 * kNB, kNB, T(-1),
+                      reinterpret_cast<T (*)[kTile + 1]>(smem));
+  }
+}
+
+// Diagonal tiles made exactly symmetric from their lower triangle, before a
+// symmetric elimination: work-group (t, b) mirrors tile (t, t) of matrix b.
+// The elimination reads only lower tiles and assumes symmetry; an input whose
+// diagonal tiles carry rounding asymmetry (the previous plane's inverse
+// after the Schur update) is then inverted inconsistently, and along a sweep
+// of an indefinite problem that error grows geometrically with the planes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_diag(void *const *__restrict__ mats, int ld) {
+  __shared__ T X[32][kTile + 1];
+  T *D = static_cast<T *>(mats[blockIdx.y]) + (size_t)blockIdx.x * kTile * (ld + 1);
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < kTile; c0 += 32) {
+    __syncthreads();
+    for (int e = tid; e < 32 * kTile; e += 256) {
+      const int rr = e / kTile, cc = e % kTile;
+      X[rr][cc] = gp(D)[(size_t)(c0 + rr) * ld + cc];
+    }
+    __syncthreads();
+    // rows of later chunks are not written (r < c0 + cc <= c0 + 31)
+    for (int e = tid; e < kTile * 32; e += 256) {
+      const int r = e / 32, cc = e % 32;
+      if (c0 + cc > r) gp(D)[(size_t)r * ld + c0 + cc] = X[cc][r];
+    }
+  }
+}
+
+// Upper triangle of every matrix from its lower triangle (the inverse left
+// by the symmetric elimination is symmetric): work-group (t, b) copies the
+// transpose of the t-th tile strictly below the diagonal to its mirror.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mirror_lower(void *const *__restrict__ mats, int ld) {
+  __shared__ T X[32][kTile + 1];
+  T *D = static_cast<T *>(mats[blockIdx.y]);
+  int ti, tj;
+  tri_index(blockIdx.x, ti, tj);
+  ti += 1;  // strictly lower: the t-th tile of the triangle of nt - 1 rows, shifted
+  tile_transpose<T>(D + (size_t)ti * kTile * ld + tj * kTile, ld,
+                    D + (size_t)tj * kTile * ld + ti * kTile, ld, T(1), X);
+}
+
 // One Gauss-Jordan step, update part (Cbuf = old column p, R = P^{-1} D[p,:]):
 //   pivot rows               D[p, :] = R             (P^{-1} on the block p)
 //   other rows, column p     D[i, p] = -D[i, p] P^{-1}
@@ -696,9 +824,47 @@ __device__ __forceinline__ void sel_tile(int sel, int nt, int q, int t, int &tr,
   }
 }
 
+// Tile subsets of the symmetric elimination, which updates only the lower
+// triangle of tiles (tr >= tc): all of them (last step); row block q left of
+// (q, q) and column block q below it; everything outside row and column
+// block q.
+__host__ __device__ inline int sel_tiles_sym(int sel, int nt) {
+  return sel == kSelAll ? nt * (nt + 1) / 2 : sel == kSelCross ? nt - 1 : (nt - 1) * nt / 2;
+}
+__device__ __forceinline__ void sel_tile_sym(int sel, int nt, int q, int t, int &tr, int &tc) {
+  if (sel == kSelAll) {
+    tri_index(t, tr, tc);
+  } else if (sel == kSelCross) {  // (q, 0..q-1), then (q+1..nt-1, q)
+    if (t < q) {
+      tr = q;
+      tc = t;
+    } else {
+      tr = t + 1;
+      tc = q;
+    }
+  } else {  // the lower triangle of the nt - 1 blocks other than q
+    tri_index(t, tr, tc);
+    tr += tr >= q;
+    tc += tc >= q;
+  }
+}
+
 // FP64: at least two wavefronts per SIMD (its accumulators would otherwise
 // take the register file of two)
-template <typename T>
+//
+// SYM: the symmetric elimination (a symmetric matrix, Gauss-Jordan without
+// pivoting in block order).  After the steps 0..p-1 the matrix is
+//   [ A_SS^{-1}              A_SS^{-1} A_SN          ]
+//   [ -A_NS A_SS^{-1}        A_NN - A_NS A_SS^{-1} A_SN ]
+// (S the eliminated blocks, N the others): its SS and NN parts are
+// symmetric and NS = -(SN)^T, so the lower triangle of tiles determines it.
+// With C_i the current column block p (C_i = D[i, p] for i > p, -D[p, i]^T
+// for i < p) and W_i = C_i P^{-1}, a step is, on lower tiles only:
+//   D[i, j] -= s_j C_i W_j^T  (s_j = +1 for j > p, -1 for j < p)
+//   D[i, p] = -W_i (i > p),  D[p, j] = -W_j^T (j < p),  D[p, p] = P^{-1}
+// Rbuf holds W^T (kNB x ld, W_p^T taken as P^{-1}), so every product is the
+// one of the general update, only its sign and the pivot-row copy differ.
+template <typename T, bool SYM>
 __global__ __launch_bounds__(256, 2) void k_gj_update(
     void *const *__restrict__ mats,
                                                    const T *__restrict__ Rbuf,
@@ -717,11 +883,14 @@ __global__ __launch_bounds__(256, 2) void k_gj_update(
   T (*Bs)[LW] = As + BK;
   T (*Xs)[XW] = reinterpret_cast<T (*)[XW]>(lds);
   const int nt = ld / kTile;
-  const int tiles_per_mat = sel_tiles(sel, nt);
+  const int tiles_per_mat = SYM ? sel_tiles_sym(sel, nt) : sel_tiles(sel, nt);
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int b = lin / tiles_per_mat;
   int tr, tc;
-  sel_tile(sel, nt, p + 1, lin % tiles_per_mat, tr, tc);
+  if (SYM)
+    sel_tile_sym(sel, nt, p + 1, lin % tiles_per_mat, tr, tc);
+  else
+    sel_tile(sel, nt, p + 1, lin % tiles_per_mat, tr, tc);
   const int bm = tr * kTile, bn = tc * kTile;
   T *D = static_cast<T *>(mats[b]);
   const T *R = Rbuf + (size_t)b * kNB * ld;
@@ -732,12 +901,15 @@ __global__ __launch_bounds__(256, 2) void k_gj_update(
   const int trow = tid / LPR, tcol = (tid % LPR) * G::VEC;
   using VT = typename V16<T>::type;
   // tiles of column block p + 1 also go to the next step's column panel
-  T *Cn = (Cnext && bn == p0 + kNB) ? Cnext + (size_t)b * ld * kNB : nullptr;
-  if (bm == p0) {  // pivot rows: D[p, :] = R, no product needed
+  T *Cn = (!SYM && Cnext && bn == p0 + kNB) ? Cnext + (size_t)b * ld * kNB : nullptr;
+  if (bm == p0) {  // pivot rows: D[p, :] = R (SYM: -W^T left of the pivot), no product
+    const T sg = (SYM && bn < p0) ? T(-1) : T(1);
 #pragma unroll
     for (int q = 0; q < G::NQ; ++q) {
       const int row = bm + q * G::RPI + trow;
-      const VT v = ld16(R + (size_t)(row - p0) * ld + bn + tcol);
+      VT v = ld16(R + (size_t)(row - p0) * ld + bn + tcol);
+#pragma unroll
+      for (int e = 0; e < G::VEC; ++e) v[e] *= sg;
       st16(D + (size_t)row * ld + bn + tcol, v);
       if (Cn) st16(Cn + (size_t)row * kNB + tcol, v);
     }
@@ -747,6 +919,7 @@ __global__ __launch_bounds__(256, 2) void k_gj_update(
   acc.zero();
   mma_tile<T>(Cb + (size_t)bm * kNB, kNB, R + bn, ld, nullptr, kNB, As, Bs, acc);
   const bool pivcols = (bn + tcol >= p0) && (bn + tcol < p0 + kNB);
+  const bool plus = SYM && bn < p0;  // s_j = -1: the product is added
   const int wave = tid >> 6;
   constexpr int NH = G::NQ / 2;  // row passes per half
 #pragma unroll
@@ -771,7 +944,8 @@ __global__ __launch_bounds__(256, 2) void k_gj_update(
       const int lrow = q * G::RPI + trow;
       VT v;
 #pragma unroll
-      for (int e = 0; e < G::VEC; ++e) v[e] = (pivcols ? T(0) : dv[q][e]) - Xs[lrow][tcol + e];
+      for (int e = 0; e < G::VEC; ++e)
+        v[e] = (pivcols ? T(0) : dv[q][e]) + (plus ? Xs[lrow][tcol + e] : -Xs[lrow][tcol + e]);
       st16(D + (size_t)(bm + h * HR + lrow) * ld + bn + tcol, v);
       if (Cn) st16(Cn + (size_t)(bm + h * HR + lrow) * kNB + tcol, v);
     }
@@ -973,9 +1147,15 @@ GjStreams::~GjStreams() {
 // for Ur(p - 1) (which last wrote their tiles and read the buffers that
 // Ux(p) and panel(q) overwrite); Ur(p) waits for Ux(p - 1) (same reason);
 // panel(q) waits for Ux(p).  The last step updates all tiles on s.
+//
+// sym: the matrices are symmetric; the updates touch only the lower
+// triangle of tiles (about half the work, see k_gj_update), the panel
+// kernel forms C and W^T from it, and one last launch mirrors the lower
+// triangle of the (symmetric) inverse into the upper one.  The pivot
+// kernel is the same: W_q^T is the block q of its R operand.
 template <typename T>
 hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
-                     int any_sign, GjStreams &gs, hipStream_t s) {
+                     int any_sign, int sym, GjStreams &gs, hipStream_t s) {
   if (nmat <= 0) return hipSuccess;
   static_assert(kNB == kTile, "one pivot block per tile row");
   const int nt = ld / kTile;
@@ -1000,22 +1180,29 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
   };
   auto panel = [&](int p, hipEvent_t done) {
     const ProfSpan ps = prof_open(KK_GJ_PANEL);
-    hipExtLaunchKernelGGL(k_gj_panel<T>, dim3(nt, nmat), dim3(256), 0, s, ps.a,
-                          ps.b ? ps.b : done, 0, mats, PinvT, Rb[p & 1], Cb[p & 1], ld, p,
-                          p == 0 ? 1 : 0);
+    if (sym)
+      hipExtLaunchKernelGGL(k_gj_panel_sym<T>, dim3(nt, nmat), dim3(256), 0, s, ps.a,
+                            ps.b ? ps.b : done, 0, mats, PinvT, Rb[p & 1], Cb[p & 1], ld, p);
+    else
+      hipExtLaunchKernelGGL(k_gj_panel<T>, dim3(nt, nmat), dim3(256), 0, s, ps.a,
+                            ps.b ? ps.b : done, 0, mats, PinvT, Rb[p & 1], Cb[p & 1], ld, p,
+                            p == 0 ? 1 : 0);
     prof_close(ps, KK_GJ_PANEL, 2.0 * nmat * (double)kNB * kNB * std::max(M - kNB, 0));
     return ps.b ? ps.b : done;
   };
   auto update = [&](int p, int sel, hipStream_t st, hipEvent_t done) {
-    const int ntiles = sel_tiles(sel, nt);
-    // tiles that take a product (the pivot-row tiles are copies)
-    const double tiles = sel == kSelAll     ? mfma_tiles
+    const int ntiles = sym ? sel_tiles_sym(sel, nt) : sel_tiles(sel, nt);
+    // tiles that take a product (the pivot-row tiles are copies; the
+    // symmetric sets hold p + 1 of them outside the cross set)
+    const double tiles = sym ? (sel == kSelCross ? nt - 1.0 : ntiles - (p + 1.0))
+                         : sel == kSelAll   ? mfma_tiles
                          : sel == kSelCross ? 2.0 * nt - 3
                                             : (nt - 1.0) * (nt - 2);
-    T *Cn = sel == kSelCross ? Cb[(p + 1) & 1] : nullptr;
+    T *Cn = (!sym && sel == kSelCross) ? Cb[(p + 1) & 1] : nullptr;
     const ProfSpan ps = prof_open(KK_GJ_UPDATE);
-    hipExtLaunchKernelGGL(k_gj_update<T>, dim3(ntiles * nmat), dim3(256), 0, st, ps.a,
-                          ps.b ? ps.b : done, 0, mats, Rb[p & 1], Cb[p & 1], Cn, ld, p, sel);
+    hipExtLaunchKernelGGL(sym ? k_gj_update<T, true> : k_gj_update<T, false>,
+                          dim3(ntiles * nmat), dim3(256), 0, st, ps.a, ps.b ? ps.b : done, 0,
+                          mats, Rb[p & 1], Cb[p & 1], Cn, ld, p, sel);
     prof_close(ps, KK_GJ_UPDATE, mfma_tiles > 0 ? step_flops * tiles / mfma_tiles : 0.0);
     return ps.b ? ps.b : done;
   };
@@ -1024,6 +1211,8 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
   do {                                        \
     if ((e = (call)) != hipSuccess) return e; \
   } while (0)
+  if (sym && nreal > 0)
+    hipLaunchKernelGGL(k_sym_diag<T>, dim3(nreal, nmat), dim3(256), 0, s, mats, ld);
   pivot(0);
   hipEvent_t ev_panel = panel(0, gs.panel);
   hipEvent_t ev_rest[2] = {nullptr, nullptr}, ev_cross[2] = {nullptr, nullptr};
@@ -1044,6 +1233,9 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
       update(p, kSelAll, s, nullptr);
     }
   }
+  if (sym && nt > 1)
+    hipLaunchKernelGGL(k_mirror_lower<T>, dim3(nt * (nt - 1) / 2, nmat), dim3(256), 0, s, mats,
+                       ld);
 #undef GJCHK
   return hipGetLastError();
 }
@@ -1055,7 +1247,7 @@ hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int
   template void launch_gemm<T>(const GemmJob *, int, int, int, double, double, hipStream_t); \
   template void launch_gemm_rect<T>(const GemmJob *, int, int, int, int, int, int, double,     \
                                     double, hipStream_t);                                      \
-  template hipError_t gj_invert<T>(void *const *, int, int, int, void *, int *, int,        \
+  template hipError_t gj_invert<T>(void *const *, int, int, int, void *, int *, int, int,   \
                                    GjStreams &, hipStream_t);
 DDST_INST(float)
 DDST_INST(double)

@@ -175,11 +175,13 @@ static_assert(sizeof(ElimStatus) == 32, "ElimStatus is 32 bytes");
 // bytes (two R and two column panels, the pivot inverses); flag: device
 // ElimStatus: bad set to 1 when a pivot is non-finite, or non-positive
 // unless any_sign is non-zero, inv_max raised to the largest |entry| of
-// the inverted pivot blocks.  Everything is ordered before later work on s when the call
+// the inverted pivot blocks; sym non-zero: the matrices are symmetric and
+// only their lower triangle is eliminated (the inverse is mirrored at the
+// end).  Everything is ordered before later work on s when the call
 // returns.
 template <typename T>
 hipError_t gj_invert(void *const *mats, int nmat, int ld, int M, void *work, int *flag,
-                     int any_sign, GjStreams &gs, hipStream_t s);
+                     int any_sign, int sym, GjStreams &gs, hipStream_t s);
 // Bytes of Gauss-Jordan workspace for nmat matrices.
 inline size_t gj_workspace_bytes(int nmat, int ld, size_t esz) {
   return (size_t)nmat * kNB * ld * esz * 4 + (size_t)nmat * kNB * kNB * esz;
@@ -335,6 +337,7 @@ struct ddst_op {
   int *flag = nullptr;        // device ElimStatus (breakdown flag, pivot growth)
   double pivot_growth = 0;    // largest pivot growth seen by the last build
   int indefinite = 0;         // 1: negative pivots accepted (indefinite local problems)
+  int sym = 0;                // 1: symmetric operator, symmetric local eliminations
   // compressed forms (hodlr.hip: from the dense blocks; hbs.hip: from samples)
   ddst::Hodlr *hodlr = nullptr;
   ddst::Hbs *hbs = nullptr;

@@ -20,6 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "libddst.so")
 DDST_OK, DDST_ENOTCONV = 0, 1
 DDST_EINVAL, DDST_ENOMEM, DDST_EHIP, DDST_EBREAKDOWN, DDST_ERANK, DDST_ESTATE = -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
+ELIM_AUTO, ELIM_GENERAL = 0, 1
 TREE_BINARY, TREE_QUAD = 0, 1
 FACTOR_BF16, FACTOR_FP32, FACTOR_FP64 = 0, 1, 2
 APPLY_DENSE, APPLY_HODLR, APPLY_MATFREE, APPLY_HBS = 0, 1, 2, 3
@@ -43,7 +44,7 @@ class ProblemC(ctypes.Structure):
 class BuildOptsC(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("keep_factors", ctypes.c_int32),
                 ("transpose", ctypes.c_int32), ("skip_transfer", ctypes.c_int32),
-                ("indefinite", ctypes.c_int32)]
+                ("indefinite", ctypes.c_int32), ("elimination", ctypes.c_int32)]
 
 
 class CompressOptsC(ctypes.Structure):
@@ -75,7 +76,8 @@ class StatsC(ctypes.Structure):
                 ("t_adjoint_ms", ctypes.c_double), ("bytes_factors", ctypes.c_double),
                 ("bytes_transfer", ctypes.c_double), ("bytes_hodlr", ctypes.c_double),
                 ("max_rank", ctypes.c_int32), ("min_rank", ctypes.c_int32),
-                ("pivot_growth", ctypes.c_double)]
+                ("pivot_growth", ctypes.c_double), ("symmetric", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +87,7 @@ EXPORTS = ["ddst_build_transfer", "ddst_compress", "ddst_solve", "ddst_solve_man
            "ddst_release_factors", "ddst_destroy", "ddst_last_error", "ddst_op_info",
            "ddst_get_transfer", "ddst_apply", "ddst_loads", "ddst_get_factor",
            "ddst_get_center_inverse", "ddst_test_gemm", "ddst_test_invert",
+           "ddst_test_invert_sym",
            "ddst_profile_enable", "ddst_profile_select", "ddst_profile_read",
            "ddst_profile_busy", "ddst_compress_info", "ddst_gmres", "ddst_cond_est",
            "ddst_set_allocator", "ddst_build_stats", "ddst_apply_noalloc",
@@ -172,6 +175,7 @@ def load_library(path: str = _LIB_PATH):
     L.ddst_test_gemm.argtypes = [i32, i32, i32, vp, vp, vp, vp, ctypes.c_double,
                                  ctypes.c_double, vp]
     L.ddst_test_invert.argtypes = [i32, i32, i32, vp, vp]
+    L.ddst_test_invert_sym.argtypes = [i32, i32, i32, vp, vp]
     L.ddst_compress_info.argtypes = [vp, P(ctypes.c_double), P(i32), P(i32),
                                      P(ctypes.c_double)]
     L.ddst_profile_enable.argtypes = [i32]
@@ -230,11 +234,14 @@ class Operator:
 
     def __init__(self, dim, n, n_slabs, kappa=None, bvec=(0.0, 0.0, 0.0), c=None,
                  precision: str = "fp32", keep_factors: bool = True,
-                 transfer_blocks: bool = True, indefinite: bool = False):
+                 transfer_blocks: bool = True, indefinite: bool = False,
+                 symmetric_elimination: bool = True):
         """transfer_blocks=False: the matrix-free set-up (slab factors and
         interface blocks only); solves then apply S matrix-free.
         indefinite=True: accept negative pivots (indefinite, nonsingular local
-        problems); by default they are reported as DDST_EBREAKDOWN."""
+        problems); by default they are reported as DDST_EBREAKDOWN.
+        symmetric_elimination=False: the general elimination even when the
+        operator is symmetric (no convection)."""
         if not torch.cuda.is_available():
             raise RuntimeError("ddst needs a ROCm GPU; no device is visible")
         L = load_library()
@@ -247,7 +254,8 @@ class Operator:
                               (ctypes.c_double * 3)(*[float(v) for v in b[:3]]), _ptr(self._c))
         self.transfer_blocks = bool(transfer_blocks)
         opts = BuildOptsC(FP32 if precision == "fp32" else FP64, 1 if keep_factors else 0, 0,
-                          0 if transfer_blocks else 1, 1 if indefinite else 0)
+                          0 if transfer_blocks else 1, 1 if indefinite else 0,
+                          ELIM_AUTO if symmetric_elimination else ELIM_GENERAL)
         h = ctypes.c_void_p()
         _check(L.ddst_build_transfer(ctypes.byref(self._prob), ctypes.byref(opts), _stream(),
                                      ctypes.byref(h)))
@@ -259,10 +267,11 @@ class Operator:
 
     @classmethod
     def from_problem(cls, prob, precision="fp32", keep_factors=True, transfer_blocks=True,
-                     indefinite=False):
+                     indefinite=False, symmetric_elimination=True):
         return cls(prob.dim, prob.n, prob.n_slabs, kappa=prob.kappa, bvec=prob.bvec, c=prob.c,
                    precision=precision, keep_factors=keep_factors,
-                   transfer_blocks=transfer_blocks, indefinite=indefinite)
+                   transfer_blocks=transfer_blocks, indefinite=indefinite,
+                   symmetric_elimination=symmetric_elimination)
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -476,11 +485,14 @@ def kernel_gemm(A, B, C, bscale=None, alpha=1.0, beta=0.0):
     return C
 
 
-def kernel_invert(A):
-    """In-place batched Gauss-Jordan inversion with the build's kernels."""
+def kernel_invert(A, symmetric=False):
+    """In-place batched Gauss-Jordan inversion with the build's kernels
+    (symmetric=True: the symmetric elimination, which reads only the lower
+    triangle of each A_b)."""
     prec = FP32 if A.dtype == torch.float32 else FP64
     batch, ld, _ = A.shape
-    _check(load_library().ddst_test_invert(prec, ld, batch, _raw_ptr(A), _stream()))
+    f = load_library().ddst_test_invert_sym if symmetric else load_library().ddst_test_invert
+    _check(f(prec, ld, batch, _raw_ptr(A), _stream()))
     return A
 
 

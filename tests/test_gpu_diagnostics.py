@@ -209,6 +209,8 @@ def test_indefinite_transfer_blocks_match_oracle(dim, n, n_slabs, k2):
         worst = max(worst, np.abs(SL - refL).max() / scale, np.abs(SR - refR).max() / scale)
     print(f"  max rel block error {worst:.3e} pivot growth {op.build_stats()['pivot_growth']:.3e}")
     assert worst <= 1e-11  # the bar of the definite FP64 blocks; 6e-14-1.6e-12 observed
+    # indefinite local problems keep the general elimination
+    assert op.build_stats()["symmetric"] == 0
     op.close()
 
 

@@ -87,6 +87,41 @@ def test_gauss_jordan_inverse_nonsymmetric(dtype, ld, M):
     assert relerr(Ad.cpu().double(), ref) <= TOL[dtype] * 4
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("ld,M", [(128, 128), (256, 200), (512, 450), (640, 640)])
+def test_gauss_jordan_inverse_symmetric(dtype, ld, M):
+    """Symmetric elimination (lower triangle of tiles only, mirrored at the
+    end): SPD blocks with several look-ahead steps and a ragged last block;
+    the 128 x 128 tiles above the diagonal are overwritten with junk first
+    (the diagonal tiles are read in full), so the result can only be right
+    if the elimination never reads them.  Same bound as the general
+    elimination, and the inverse comes out symmetric off the diagonal
+    tiles."""
+    print(f"\n[gpu] kernel invert symmetric {dtype} ld={ld} M={M}", flush=True)
+    g = torch.Generator().manual_seed(M + 7)
+    batch = 3
+    A = torch.eye(ld, dtype=torch.float64).repeat(batch, 1, 1)
+    X = torch.randn(batch, M, M, generator=g, dtype=torch.float64)
+    A[:, :M, :M] = X @ X.transpose(1, 2) / M + 2.0 * torch.eye(M, dtype=torch.float64)
+    A = A.to(dtype)
+    ref = torch.linalg.inv(A.double())
+    junk = A.clone()
+    nt = ld // 128
+    for i in range(nt):
+        for j in range(i + 1, nt):
+            junk[:, i * 128:(i + 1) * 128, j * 128:(j + 1) * 128] = 1e3
+    Ad = junk.cuda()
+    ddst().kernel_invert(Ad, symmetric=True)
+    out = Ad.cpu().double()
+    assert relerr(out, ref) <= TOL[dtype] * 4
+    # tiles off the diagonal are exact mirrors
+    for i in range(nt):
+        for j in range(i):
+            a = out[:, i * 128:(i + 1) * 128, j * 128:(j + 1) * 128]
+            b = out[:, j * 128:(j + 1) * 128, i * 128:(i + 1) * 128]
+            assert torch.equal(a, b.transpose(1, 2))
+
+
 def test_gauss_jordan_breakdown_flag():
     print("\n[gpu] kernel invert breakdown", flush=True)
     A = torch.eye(128, dtype=torch.float64).repeat(2, 1, 1)

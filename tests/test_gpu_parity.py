@@ -96,6 +96,45 @@ def test_transfer_blocks(name, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["cfg1", "cfg3s", "cfg4s"])
+def test_symmetric_elimination_matches_general(name, precision):
+    """Symmetric operators (no convection) are eliminated on the lower
+    triangle only by default; the general elimination of the same operator
+    and the oracle's blocks agree with it to the same bound, and the
+    operator with convection keeps the general elimination."""
+    p = prob(name)
+    tol = 1e-11 if precision == "fp64" else fp32_block_tol(p)
+    banner(f"symmetric vs general elimination {name} {precision}")
+    dd = ddst()
+    op_s = dd.Operator.from_problem(p, precision=precision)
+    op_g = dd.Operator.from_problem(p, precision=precision, symmetric_elimination=False)
+    assert op_s.build_stats()["symmetric"] == 1
+    assert op_g.build_stats()["symmetric"] == 0
+    blocks = oracle(name, p).all_blocks()
+    scale = max(np.abs(B).max() for B in blocks.values())
+    e_sym = e_gen = e_both = 0.0
+    for j in range(1, p.n_ds + 1):
+        a = [t.cpu().numpy() for t in op_s.transfer(j)]
+        b = [t.cpu().numpy() for t in op_g.transfer(j)]
+        for side, jp in ((0, j - 1), (1, j + 1)):
+            ref = blocks.get((j, jp), np.zeros_like(a[side]))
+            e_sym = max(e_sym, np.abs(a[side] - ref).max() / scale)
+            e_gen = max(e_gen, np.abs(b[side] - ref).max() / scale)
+            e_both = max(e_both, np.abs(a[side] - b[side]).max() / scale)
+    print(f"  vs oracle: symmetric {e_sym:.3e}, general {e_gen:.3e}; between {e_both:.3e}")
+    assert e_sym <= tol and e_gen <= tol and e_both <= 2 * tol
+    # the interface inverses come out symmetric
+    for j in (1, p.n_ds):
+        Si = op_s.center_inverse(j).cpu().numpy()
+        assert np.abs(Si - Si.T).max() <= tol * np.abs(Si).max()
+    op_s.close()
+    op_g.close()
+    conv = dd.Operator.from_problem(prob("cfg2s"), precision=precision)
+    assert conv.build_stats()["symmetric"] == 0
+    conv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["cfg2s", "cfg4s"])
 def test_loads_and_apply(name, precision):
     p = prob(name)
