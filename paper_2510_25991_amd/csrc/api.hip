@@ -634,8 +634,9 @@ SolveWs carve_ws(ddst_op *op, int max_iter, int nr = 1) {
   o[9] = cv.take((size_t)(4 * max_iter + 16) * 8);
   o[10] = cv.take(part * 8);
   o[11] = cv.take(64 * 8);
-  // partial sums: up to max_iter + 2 interface-length dots, or one volume norm
-  o[12] = cv.take(std::max(dots_part_len(ifc, max_iter + 2), dots_part_len(vol, 1)) * 8);
+  // partial sums: up to 2 (max_iter + 2) interface-length dots (the lagged
+  // Arnoldi step's pass A), or one volume norm
+  o[12] = cv.take(std::max(dots_part_len(ifc, 2 * (max_iter + 2)), dots_part_len(vol, 1)) * 8);
   const size_t o_gm = cv.take(GmresDev::doubles(max_iter) * 8);
   const size_t o_zf = cv.take(vol * 8), o_zb = cv.take(vol * 8);
   const size_t o_mx = cv.take(ifc * 8), o_mv = cv.take(ifc * 8), o_mf = cv.take(ifc * 8);
@@ -875,8 +876,14 @@ void run_matfree(const ddst_op *op, const MatfreeTables &t, bool trans, const Ma
 // diag(S, ..., S) (one Krylov polynomial for all, inner products summed
 // over all: the "global" GMRES of several right-hand sides), so that each
 // product reads every block of S once for all of them.
+// Once the basis holds more than kLagBytes, each step orthogonalizes with
+// lagged reorthogonalization (launch_arnoldi_lagged: two passes over the
+// basis instead of four, one column of H finalized a step later); below
+// that, the classical twice-applied Gram-Schmidt step, whose fewer launches
+// cost less than the passes saved.
 // Returns the iterations used.
 constexpr int kGmresCheck = 8;
+constexpr size_t kLagBytes = (size_t)16 << 20;
 
 template <typename T>
 int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
@@ -915,9 +922,41 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
   GmresDev d = w.gm;
   int used = 0;
   double res = 1.0;
-  int checked = 0;  // iterations whose estimates were read back
+  int checked = 0;  // columns whose estimates were read back
+  int nfinal = 0;   // columns of H finalized by the steps enqueued so far
   int next_check = std::min(kGmresCheck, max_iter);
   double prev_res = 1.0;
+  auto lagged = [&](int k) { return (size_t)(k + 1) * len * 8 >= kLagBytes; };
+  // read back the estimates of the columns finalized since the last check
+  auto check = [&]() {
+    const int n = nfinal - checked;
+    if (n <= 0) return;
+    HIPCHK(hipMemcpyAsync(hh, d.res + 2 * (size_t)checked, (size_t)n * 16,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) {
+      res = hh[2 * i];
+      // stop at the tolerance or at a breakdown (the new direction
+      // vanished: the Krylov space is exhausted)
+      if (res <= tol || hh[2 * i + 1] != 0.0) {
+        used = checked + i + 1;
+        break;
+      }
+    }
+    if (used == 0) {
+      // next read-back: when the reduction rate seen over this window
+      // predicts the tolerance, at most kGmresCheck iterations ahead
+      int step = kGmresCheck;
+      if (res > 0.0 && res < prev_res) {
+        const double rate = std::log(res / prev_res) / n;  // per iteration, < 0
+        const double need = std::ceil(std::log(tol / res) / rate);
+        if (need < step) step = std::max(1, (int)need);
+      }
+      prev_res = res;
+      next_check = std::min(nfinal + step, max_iter);
+    }
+    checked = nfinal;
+  };
   for (int k = 0; k < max_iter && used == 0; ++k) {
     const double *vk = w.V + (size_t)k * len;
     if (form == DDST_APPLY_HODLR || form == DDST_APPLY_HBS) {
@@ -937,37 +976,24 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
       launch_gemv_many<T>(tab.at<GemvJob>(offs[k]), op->n_ds, op->ld, op->M, -1.0, nr, w.ifc,
                           w.part, s);
     }
-    launch_arnoldi_step(w.V, len, k, w.W, len, w.hd, w.V + (size_t)(k + 1) * len, w.dpart, d,
-                        beta, s);
-    if (k + 1 == next_check) {
-      const int n = k + 1 - checked;
-      HIPCHK(hipMemcpyAsync(hh, d.res + 2 * (size_t)checked, (size_t)n * 16,
-                            hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i < n; ++i) {
-        res = hh[2 * i];
-        // stop at the tolerance or at a breakdown (the new direction
-        // vanished: the Krylov space is exhausted)
-        if (res <= tol || hh[2 * i + 1] != 0.0) {
-          used = checked + i + 1;
-          break;
-        }
-      }
-      if (used == 0) {
-        // next read-back: when the reduction rate seen over this window
-        // predicts the tolerance, at most kGmresCheck iterations ahead
-        int step = kGmresCheck;
-        if (res > 0.0 && res < prev_res) {
-          const double rate = std::log(res / prev_res) / n;  // per iteration, < 0
-          const double need = std::ceil(std::log(tol / res) / rate);
-          if (need < step) step = std::max(1, (int)need);
-        }
-        prev_res = res;
-        next_check = std::min(k + 1 + step, max_iter);
-      }
-      checked = k + 1;
+    if (lagged(k)) {
+      launch_arnoldi_lagged(w.V, len, k, w.W, len, w.dpart, d, beta,
+                            (k >= 1 && !lagged(k - 1)) ? 1 : 0, 0, s);
+      nfinal = k;
+    } else {
+      launch_arnoldi_step(w.V, len, k, w.W, len, w.hd, w.V + (size_t)(k + 1) * len, w.dpart,
+                          d, beta, s);
+      nfinal = k + 1;
     }
+    if (nfinal >= next_check) check();
   }
+  if (used == 0 && nfinal < max_iter && max_iter > 0 && lagged(max_iter - 1)) {
+    // close the last column (its reorthogonalization coefficients)
+    launch_arnoldi_lagged(w.V, len, max_iter, nullptr, len, w.dpart, d, beta,
+                          (max_iter >= 1 && !lagged(max_iter - 1)) ? 1 : 0, 1, s);
+    nfinal = max_iter;
+  }
+  if (used == 0) check();
   if (used == 0) used = checked;
   launch_gmres_solution(d, used, x, w.V, len, s);
   HIPCHK(hipStreamSynchronize(s));

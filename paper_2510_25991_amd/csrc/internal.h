@@ -233,18 +233,39 @@ void launch_norm(const double *w, size_t len, double *out, double *part, hipStre
 // entries, from offset k (k + 3) / 2), Givens pairs, the rotated right-hand
 // side g and per-iteration residual estimates.
 __host__ __device__ inline size_t gmres_hoff(int k) { return (size_t)k * (k + 3) / 2; }
+// The unrotated Hessenberg matrix by rows (for products H a): row i holds
+// columns max(i - 1, 0) .. mi - 1, rows 0 .. mi.
+__host__ __device__ inline size_t gmres_roff(int i, int mi) {
+  return i == 0 ? 0 : (size_t)mi + (size_t)(i - 1) * (mi + 1) - (size_t)(i - 1) * i / 2;
+}
+__host__ __device__ inline size_t gmres_rix(int i, int j, int mi) {
+  return gmres_roff(i, mi) + (size_t)(j - (i > 0 ? i - 1 : 0));
+}
 struct GmresDev {
   double *H, *cs, *sn, *g, *res, *y;
+  // lagged reorthogonalization (launch_arnoldi_lagged): unrotated columns
+  // by rows, the provisional column of the previous step, coefficients and
+  // scalars of the current step, pass-A dot products, H a
+  double *Hraw, *prov, *cf, *sc, *dA, *dv;
+  int maxit;
   static size_t doubles(int max_iter) {
-    return gmres_hoff(max_iter) + 6 * (size_t)max_iter + 8;
+    return gmres_hoff(max_iter) + 6 * (size_t)max_iter + 8 + gmres_roff(max_iter + 1, max_iter) +
+           5 * (size_t)(max_iter + 2) + 16;
   }
   void carve(double *base, int max_iter) {
+    maxit = max_iter;
     H = base;
     cs = H + gmres_hoff(max_iter);
     sn = cs + max_iter;
     g = sn + max_iter;
     res = g + max_iter + 1;  // pairs (estimate, breakdown flag) per iteration
     y = res + 2 * (size_t)max_iter;
+    Hraw = y + max_iter + 8;
+    prov = Hraw + gmres_roff(max_iter + 1, max_iter);
+    cf = prov + (max_iter + 2);
+    dv = cf + (max_iter + 2);
+    dA = dv + (max_iter + 2);  // 2 (max_iter + 2)
+    sc = dA + 2 * (size_t)(max_iter + 2);  // 16
   }
 };
 // GMRES iteration k after the matvec w = S v_k: one Arnoldi step by
@@ -259,6 +280,23 @@ struct GmresDev {
 void launch_arnoldi_step(const double *V, size_t stride, int k, double *w, size_t len,
                          double *hd, double *vnext, double *part, GmresDev gd, double beta,
                          hipStream_t s);
+// GMRES iteration k with lagged reorthogonalization (two passes over the
+// basis instead of four).  V slots 0..k-1 hold the orthonormal q_0..q_{k-1};
+// slot k holds the candidate u (q_k after one Gram-Schmidt pass, normalized);
+// w = S u.  Pass A: a = Q^T u, |u|^2, b = Q^T w, u.w in one sweep; then
+// nu = |u - Q a|, column k - 1 of H is finalized (its provisional
+// coefficients plus rho a, subdiagonal rho nu) and rotated (res[2(k-1)]);
+// q_k = (u - Q a) / nu, and, with d = H a (S Q = Q H), the first pass of
+// S q_k = (w - [Q, q_k] d) / nu against [Q, q_k] gives the provisional
+// column h of step k and z = S q_k - [Q, q_k] h, formed from w, u and Q in
+// pass B (one sweep, which also writes q_k over u); slot k + 1 = z / |z|,
+// rho = |z|.  col_final: column k - 1 is already final (the previous step
+// was a classical one); finalize_only: only pass A for a and nu and the
+// finalization of column k - 1 (w unused), to close the last column.
+// part: dots_part_len(len, 2 (k + 1)).
+void launch_arnoldi_lagged(double *V, size_t stride, int k, double *w, size_t len,
+                           double *part, GmresDev gd, double beta, int col_final,
+                           int finalize_only, hipStream_t s);
 // y = R^{-1} g over the first k columns (one work-group), then x = V y.
 void launch_gmres_solution(GmresDev d, int k, double *x, const double *V, size_t len,
                            hipStream_t s);

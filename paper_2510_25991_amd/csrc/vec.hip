@@ -597,56 +597,156 @@ __global__ __launch_bounds__(256) void k_mgs_update_dots(double *__restrict__ w,
   chunk_dots(V2, stride, nvec2, ws, base, cn, part);
 }
 
-// Column k of H (two Gram-Schmidt passes summed, new norm hn) is rotated by
-// the k previous Givens rotations, a new rotation zeroes its subdiagonal
-// entry and is applied to g.  Called by every thread of one work-group: the
-// column and the rotations are staged in LDS (when they fit), so the serial
-// rotation chain of thread 0 reads no global memory.
+// Column j of H, staged in LDS cl[0..j+1] (cl[j+1] = hn, the subdiagonal
+// entry), is rotated by the j previous Givens rotations (cs, sn staged in
+// LDS), a new rotation zeroes its subdiagonal entry and is applied to g;
+// writes column j of d.H, the rotation, g and res[2j], res[2j+1].  All 256
+// threads of the work-group.  The rotations form the recurrence
+//   a_0 = c_0,  a_{i+1} = -sn_i a_i + cs_i c_{i+1},  c_i <- cs_i a_i + sn_i c_{i+1}
+// (c_j <- a_j before the new rotation): a first-order linear recurrence,
+// evaluated as a parallel prefix of affine maps x -> m x + b (each thread
+// composes the maps of a contiguous segment, the work-group scans the 256
+// segment maps, then each thread replays its segment from its prefix), so
+// the column costs O(j / 256 + log 256) steps instead of a serial chain of
+// j rotations.
 constexpr int kGivensLds = 2048;
+__device__ __forceinline__ void givens_column_lds(double *cl, const double *cs,
+                                                  const double *sn, int j, GmresDev d,
+                                                  double beta, double hn) {
+  __shared__ double sm[256], sb[256], co[kGivensLds + 1];
+  __shared__ double aj;
+  const int t = threadIdx.x;
+  const int seg = (j + 255) / 256;
+  const int i0 = min(t * seg, j), i1 = min(i0 + seg, j);
+  double m = 1.0, b = 0.0;
+  for (int i = i0; i < i1; ++i) {  // compose T_i after the segment so far
+    const double mi = -sn[i], bi = cs[i] * cl[i + 1];
+    b = mi * b + bi;
+    m = mi * m;
+  }
+  sm[t] = m;
+  sb[t] = b;
+  __syncthreads();
+  // inclusive scan over threads: P_t = S_t o ... o S_0
+  for (int off = 1; off < 256; off <<= 1) {
+    double pm = 1.0, pb = 0.0;
+    const bool has = t >= off;
+    if (has) {
+      pm = sm[t - off];
+      pb = sb[t - off];
+    }
+    __syncthreads();
+    if (has) {  // (S_t o P_{t-off}): m = m_t pm, b = m_t pb + b_t
+      const double mt = sm[t], bt = sb[t];
+      sm[t] = mt * pm;
+      sb[t] = mt * pb + bt;
+    }
+    __syncthreads();
+  }
+  // a at the start of this thread's segment: exclusive prefix applied to c_0
+  double a = cl[0];
+  if (t > 0) a = sm[t - 1] * cl[0] + sb[t - 1];
+  for (int i = i0; i < i1; ++i) {
+    const double bnext = cl[i + 1];
+    co[i] = cs[i] * a + sn[i] * bnext;
+    a = -sn[i] * a + cs[i] * bnext;
+  }
+  if (i1 == j && i0 < i1) aj = a;  // the thread that took the last step
+  if (j == 0 && t == 0) aj = cl[0];
+  __syncthreads();
+  double *col = d.H + gmres_hoff(j);
+  for (int i = t; i < j; i += 256) col[i] = co[i];
+  if (t == 0) {
+    const double av = aj;
+    const double r = hypot(av, hn);
+    const double ck = r > 0.0 ? av / r : 1.0;
+    const double sk = r > 0.0 ? hn / r : 0.0;
+    d.cs[j] = ck;
+    d.sn[j] = sk;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    const double gk = j == 0 ? beta : d.g[j];
+    d.g[j + 1] = -sk * gk;
+    d.g[j] = ck * gk;
+    d.res[2 * j] = fabs(d.g[j + 1]) / beta;
+    d.res[2 * j + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
+  }
+}
+
+// The same for a column too long for LDS (j + 2 > kGivensLds): thread 0 runs
+// the rotations serially on the column in global memory.
+__device__ __forceinline__ void givens_column_global(double *col, int j, GmresDev d,
+                                                     double beta, double hn) {
+  if (threadIdx.x == 0) {
+    col[j + 1] = hn;
+    double a = col[0];
+    for (int i = 0; i < j; ++i) {
+      const double bnext = col[i + 1];
+      col[i] = d.cs[i] * a + d.sn[i] * bnext;
+      a = -d.sn[i] * a + d.cs[i] * bnext;
+    }
+    const double r = hypot(a, hn);
+    const double ck = r > 0.0 ? a / r : 1.0;
+    const double sk = r > 0.0 ? hn / r : 0.0;
+    d.cs[j] = ck;
+    d.sn[j] = sk;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    const double gk = j == 0 ? beta : d.g[j];
+    d.g[j + 1] = -sk * gk;
+    d.g[j] = ck * gk;
+    d.res[2 * j] = fabs(d.g[j + 1]) / beta;
+    d.res[2 * j + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
+  }
+}
+
+// Column k of H from the two classical Gram-Schmidt passes (hd[0..k] +
+// hd[k+1..2k+1], new norm hn): kept unrotated in d.Hraw (for a later lagged
+// step, which multiplies by H), then rotated.  All threads of one work-group.
 __device__ __forceinline__ void gmres_givens_block(const double *__restrict__ hd, GmresDev d,
                                                    int k, double beta, double hn) {
   __shared__ double cl[kGivensLds + 2], cs[kGivensLds], sn[kGivensLds];
-  double *col = d.H + gmres_hoff(k);
-  const bool staged = k + 2 <= kGivensLds;
-  if (staged) {
-    for (int i = threadIdx.x; i <= k; i += blockDim.x) {
-      cl[i] = hd[i] + hd[k + 1 + i];
+  for (int i = threadIdx.x; i <= k + 1; i += blockDim.x) {
+    const double v = i <= k ? hd[i] + hd[k + 1 + i] : hn;
+    d.Hraw[gmres_rix(i, k, d.maxit)] = v;
+    if (k + 2 <= kGivensLds) {
+      cl[i] = v;
       if (i < k) {
         cs[i] = d.cs[i];
         sn[i] = d.sn[i];
       }
+    } else {
+      d.H[gmres_hoff(k) + i] = v;
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    double *c = staged ? cl : col;
-    const double *rc = staged ? cs : d.cs, *rs = staged ? sn : d.sn;
-    if (!staged)
-      for (int i = 0; i <= k; ++i) c[i] = hd[i] + hd[k + 1 + i];
-    c[k + 1] = hn;
-    double a = c[0];
-    for (int i = 0; i < k; ++i) {
-      const double bnext = c[i + 1];
-      c[i] = rc[i] * a + rs[i] * bnext;
-      a = -rs[i] * a + rc[i] * bnext;
+  __syncthreads();
+  if (k + 2 <= kGivensLds)
+    givens_column_lds(cl, cs, sn, k, d, beta, hn);
+  else
+    givens_column_global(d.H + gmres_hoff(k), k, d, beta, hn);
+}
+
+// Column j of H from d.Hraw (rows 0..j+1), rotated (the lagged steps).
+__device__ __forceinline__ void gmres_givens_raw(GmresDev d, int j, double beta) {
+  __shared__ double cl[kGivensLds + 2], cs[kGivensLds], sn[kGivensLds];
+  const double hn = d.Hraw[gmres_rix(j + 1, j, d.maxit)];
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
+    const double v = d.Hraw[gmres_rix(i, j, d.maxit)];
+    if (j + 2 <= kGivensLds) {
+      cl[i] = v;
+      if (i < j) {
+        cs[i] = d.cs[i];
+        sn[i] = d.sn[i];
+      }
+    } else {
+      d.H[gmres_hoff(j) + i] = v;
     }
-    const double r = hypot(a, c[k + 1]);
-    const double ck = r > 0.0 ? a / r : 1.0;
-    const double sk = r > 0.0 ? c[k + 1] / r : 0.0;
-    d.cs[k] = ck;
-    d.sn[k] = sk;
-    c[k] = r;
-    c[k + 1] = 0.0;
-    const double gk = k == 0 ? beta : d.g[k];
-    d.g[k + 1] = -sk * gk;
-    d.g[k] = ck * gk;
-    d.res[2 * k] = fabs(d.g[k + 1]) / beta;
-    d.res[2 * k + 1] = (hn > 0.0 && isfinite(hn)) ? 0.0 : 1.0;
   }
-  if (staged) {
-    __syncthreads();
-    for (int i = threadIdx.x; i <= k + 1; i += blockDim.x) col[i] = cl[i];
-  }
+  __syncthreads();
+  if (j + 2 <= kGivensLds)
+    givens_column_lds(cl, cs, sn, j, d, beta, hn);
+  else
+    givens_column_global(d.H + gmres_hoff(j), j, d, beta, hn);
 }
 
 // Last kernel of Arnoldi step k: dst = src / sqrt(sum of the nchunk partial
@@ -674,6 +774,194 @@ __global__ __launch_bounds__(256) void k_norm_scale_givens(const double *__restr
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < len) dst[e] = (d > 0.0) ? src[e] / d : 0.0;
   if (blockIdx.x == 0) gmres_givens_block(hd, gd, k, beta, d);
+}
+
+// ---- Arnoldi with lagged reorthogonalization (see launch_arnoldi_lagged) --
+
+// Pass A: partial dot products of the m = k + 1 slots of V (stride) with
+// u = slot k and with w (null: only those with u), per 256-element chunk:
+// part[chunk][i] = V_i . u, part[chunk][m + i] = V_i . w.  One wavefront per
+// basis vector, kDotVecs at a time, as chunk_dots.
+__global__ __launch_bounds__(256) void k_lag_dots(const double *__restrict__ V, size_t stride,
+                                                  int m, const double *__restrict__ w,
+                                                  size_t len, double *__restrict__ part) {
+  constexpr int E = kDotChunk / 64;
+  __shared__ double us[kDotChunk], zs[kDotChunk];
+  const size_t base = (size_t)blockIdx.x * kDotChunk;
+  const int cn = (int)min((size_t)kDotChunk, len - base);
+  const double *u = V + (size_t)(m - 1) * stride;
+  for (int e = threadIdx.x; e < kDotChunk; e += 256) {
+    us[e] = e < cn ? u[base + e] : 0.0;
+    zs[e] = (w && e < cn) ? w[base + e] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double uw[E], zw[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    uw[t] = us[lane + 64 * t];
+    zw[t] = zs[lane + 64 * t];
+  }
+  double *pc = part + (size_t)blockIdx.x * 2 * m;
+  for (int i0 = wave; i0 < m; i0 += 4 * kDotVecs) {
+    double su[kDotVecs], sz[kDotVecs];
+#pragma unroll
+    for (int q = 0; q < kDotVecs; ++q) su[q] = sz[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kDotVecs; ++q) {
+      const int i = i0 + 4 * q;
+      if (i < m) {
+        const double *v = V + (size_t)i * stride + base;
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+          const int e = lane + 64 * t;
+          const double x = v[e < cn ? e : cn - 1];
+          su[q] += x * uw[t];
+          sz[q] += x * zw[t];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kDotVecs; ++q) {
+      const int i = i0 + 4 * q;
+      const double ru = wave_sum(su[q]), rz = wave_sum(sz[q]);
+      if (lane == 0 && i < m) {
+        pc[i] = ru;
+        pc[m + i] = rz;
+      }
+    }
+  }
+}
+
+// nu = |u - Q a| = sqrt(|u|^2 - |a|^2) from the pass-A products (every
+// thread of the work-group gets it).
+__device__ __forceinline__ double lag_nu(const GmresDev &d, int k) {
+  __shared__ double sh[4], snu;
+  double t = 0.0;
+  for (int i = threadIdx.x; i < k; i += 256) t += d.dA[i] * d.dA[i];
+  t = block_sum(t, sh);
+  if (threadIdx.x == 0) {
+    const double nu2 = d.dA[k] - t;
+    snu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+  }
+  __syncthreads();
+  return snu;
+}
+
+// d = H a over rows 0..k (one wavefront per row, four rows per work-group),
+// with column k - 1 taken as finalized now (unless col_final: it is in
+// Hraw already): prov + rho a above the diagonal, rho nu below it; work-group
+// 0 stores that column in Hraw.
+__global__ __launch_bounds__(256) void k_lag_hmul(GmresDev d, int k, int col_final) {
+  const double nu = lag_nu(d, k);
+  const double *a = d.dA;
+  const double rho = d.sc[2];
+  const bool fin = k >= 1 && !col_final;
+  auto lastcol = [&](int i) { return i < k ? d.prov[i] + rho * a[i] : rho * nu; };
+  if (blockIdx.x == 0 && fin)
+    for (int i = threadIdx.x; i <= k; i += 256) d.Hraw[gmres_rix(i, k - 1, d.maxit)] = lastcol(i);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 4 + wave;
+  if (r > k) return;
+  const int j0 = r > 0 ? r - 1 : 0;
+  const int jend = fin ? k - 1 : k;  // stored columns [j0, jend)
+  const double *row = d.Hraw + gmres_roff(r, d.maxit) - j0;
+  double acc = 0.0;
+  for (int j = j0 + lane; j < jend; j += 64) acc += row[j] * a[j];
+  acc = wave_sum(acc);
+  if (lane == 0) d.dv[r] = acc + (fin ? lastcol(r) * a[k - 1] : 0.0);
+}
+
+// Coefficients of pass B (one work-group): with d = dv, b = Q^T w, gamma =
+// u.w, the provisional column h_i = (b_i - d_i) / nu (i < k), h_k =
+// ((gamma - a.b) / nu - d_k) / nu; e = d / nu + h; pass B forms
+// z = w / nu - Q f - g u with f = e[0:k] - e_k a / nu, g = e_k / nu.
+__global__ __launch_bounds__(256) void k_lag_coef(GmresDev d, int k) {
+  __shared__ double sh[4], sek;
+  const double nu = lag_nu(d, k);
+  const int m = k + 1;
+  const double *a = d.dA, *b = d.dA + m;
+  double t = 0.0;
+  for (int i = threadIdx.x; i < k; i += 256) t += a[i] * b[i];
+  t = block_sum(t, sh);
+  const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+  if (threadIdx.x == 0) {
+    const double hk = ((b[k] - t) * inv - d.dv[k]) * inv;
+    d.prov[k] = hk;
+    sek = d.dv[k] * inv + hk;
+    d.sc[0] = inv;
+    d.sc[1] = sek * inv;
+  }
+  __syncthreads();
+  const double ek = sek;
+  for (int i = threadIdx.x; i < k; i += 256) {
+    const double h = (b[i] - d.dv[i]) * inv;
+    d.prov[i] = h;
+    d.cf[i] = d.dv[i] * inv + h - ek * a[i] * inv;
+  }
+}
+
+// Pass B, per 256-element chunk: q_k = (u - Q a) / nu over slot k (u), w =
+// w / nu - Q f - g u, and the chunk's partial squared norm of the new w.
+__global__ __launch_bounds__(256) void k_lag_update(double *__restrict__ V, size_t stride, int k,
+                                                    double *__restrict__ w, size_t len,
+                                                    GmresDev d, double *__restrict__ part) {
+  __shared__ double sh[4];
+  const size_t e = (size_t)blockIdx.x * kDotChunk + threadIdx.x;
+  double zn = 0.0;
+  if (e < len) {
+    const double *a = d.dA, *f = d.cf;
+    const double *v = V + e;
+    double ta[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = 0;
+    for (; i + 8 <= k; i += 8)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double x = v[(size_t)(i + q) * stride];
+        ta[q] += x * a[i + q];
+        tf[q] += x * f[i + q];
+      }
+    for (; i < k; ++i) {
+      const double x = v[(size_t)i * stride];
+      ta[0] += x * a[i];
+      tf[0] += x * f[i];
+    }
+    const double sa = ((ta[0] + ta[1]) + (ta[2] + ta[3])) + ((ta[4] + ta[5]) + (ta[6] + ta[7]));
+    const double sf = ((tf[0] + tf[1]) + (tf[2] + tf[3])) + ((tf[4] + tf[5]) + (tf[6] + tf[7]));
+    const double inv = d.sc[0], g = d.sc[1];
+    double *uk = V + (size_t)k * stride + e;
+    const double u = *uk;
+    *uk = (u - sa) * inv;
+    zn = w[e] * inv - sf - g * u;
+    w[e] = zn;
+  }
+  const double s = block_sum(zn * zn, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// rho = |w| (every work-group sums the partials in the same order; the
+// first stores it), vnext = w / rho, and work-group 0 rotates column
+// givens_col of H (< 0: none) from Hraw, beside the others' scaling.
+__global__ __launch_bounds__(256) void k_lag_norm_scale(const double *__restrict__ part, int nchunk,
+                                                        const double *__restrict__ w,
+                                                        double *__restrict__ vnext, size_t len,
+                                                        GmresDev d, int givens_col, double beta) {
+  __shared__ double sh[1];
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += 64) s += part[c];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+      const double r = sqrt(s);
+      sh[0] = r;
+      if (blockIdx.x == 0 && len > 0) d.sc[2] = r;
+    }
+  }
+  __syncthreads();
+  const double r = sh[0];
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) vnext[e] = (r > 0.0) ? w[e] / r : 0.0;
+  if (blockIdx.x == 0 && givens_col >= 0) gmres_givens_raw(d, givens_col, beta);
 }
 
 // One work-group per vector sums its partials (strided, then a tree).
@@ -908,6 +1196,29 @@ void launch_arnoldi_step(const double *V, size_t stride, int k, double *w, size_
                      (const double *)(hd + nvec), -1.0, len, (const double *)nullptr, 1, part);
   hipLaunchKernelGGL(k_norm_scale_givens, dim3(nblk(len)), dim3(256), 0, s,
                      (const double *)part, nchunk, hd, (const double *)w, vnext, len, gd, k, beta);
+}
+
+void launch_arnoldi_lagged(double *V, size_t stride, int k, double *w, size_t len,
+                           double *part, GmresDev gd, double beta, int col_final,
+                           int finalize_only, hipStream_t s) {
+  const int m = k + 1;
+  const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
+  static_assert(kDotChunk == 256, "one element per thread in pass B");
+  hipLaunchKernelGGL(k_lag_dots, dim3(nchunk), dim3(256), 0, s, (const double *)V, stride, m,
+                     finalize_only ? (const double *)nullptr : (const double *)w, len, part);
+  hipLaunchKernelGGL(k_multidot_reduce, dim3(2 * m), dim3(256), 0, s, (const double *)part,
+                     nchunk, 2 * m, gd.dA, 0);
+  hipLaunchKernelGGL(k_lag_hmul, dim3((m + 3) / 4), dim3(256), 0, s, gd, k, col_final);
+  const int gcol = (k >= 1 && !col_final) ? k - 1 : -1;
+  if (finalize_only) {
+    hipLaunchKernelGGL(k_lag_norm_scale, dim3(1), dim3(256), 0, s, (const double *)part, 0,
+                       (const double *)nullptr, (double *)nullptr, (size_t)0, gd, gcol, beta);
+    return;
+  }
+  hipLaunchKernelGGL(k_lag_coef, dim3(1), dim3(256), 0, s, gd, k);
+  hipLaunchKernelGGL(k_lag_update, dim3(nchunk), dim3(256), 0, s, V, stride, k, w, len, gd, part);
+  hipLaunchKernelGGL(k_lag_norm_scale, dim3(nblk(len)), dim3(256), 0, s, (const double *)part,
+                     nchunk, (const double *)w, V + (size_t)m * stride, len, gd, gcol, beta);
 }
 
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s) {
