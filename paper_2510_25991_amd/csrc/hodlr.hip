@@ -61,6 +61,12 @@ struct Hodlr {
   size_t off_leaf[2] = {0, 0};
   int n_leaf[2] = {0, 0};
   size_t off_con = 0;        // byte offset of the Contrib table in `jobs`
+  // fused product (k_hodlr_apply_fused): one job per (interface, leaf
+  // cluster) holding every contribution to its rows, per direction
+  void *fjobs = nullptr;
+  size_t foff_con = 0;       // byte offset of the FContrib table in `fjobs`
+  size_t foff[2] = {0, 0};
+  int fn[2] = {0, 0};
   double *pbuf = nullptr;    // 2 * n_ds * ld doubles: permuted x and y
   double tol_used = 0;       // truncation tolerance after the precision floor
 };
@@ -79,6 +85,15 @@ struct Contrib {
   long long off_u, off_v;
   int trans;       // apply the transpose of the stored block
   int pad_;
+};
+// A contribution to the rows [r0, r1) of a leaf cluster: a dense leaf
+// (rank -1, rows x rows, row stride lds), or the rows roff .. roff + (r1 - r0)
+// of a low-rank block whose output side has rfull rows (U: rfull x rank
+// row-major, V^T: rank x n row-major; transposed: U^T x, then V^T rows).
+struct FContrib {
+  int in_iface, c0, c1, rank;
+  long long off_u, off_v;
+  int trans, roff, rfull, lds;
 };
 
 namespace {
@@ -495,7 +510,7 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, 
 
 struct LeafJob {
   const void *S;
-  int r0, n;
+  int r0, n, lds;  // lds: row stride in the store (n rounded up to 8; padding zero)
   long long off;
 };
 
@@ -504,57 +519,99 @@ __global__ void k_pack_leaf(const LeafJob *__restrict__ jobs, const int *__restr
                             int ld, F *__restrict__ store) {
   const LeafJob J = jobs[blockIdx.y];
   const T *S = static_cast<const T *>(J.S);
-  const size_t tot = (size_t)J.n * J.n;
+  const size_t tot = (size_t)J.n * J.lds;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
-    int gr = J.r0 + (int)(e / J.n), gc = J.r0 + (int)(e % J.n);
-    if (perm) { gr = perm[gr]; gc = perm[gc]; }
-    store[J.off + e] = FactorIO<F>::put((double)S[(size_t)gr * ld + gc]);
+    const int r = (int)(e / J.lds), c = (int)(e % J.lds);
+    double v = 0.0;
+    if (c < J.n) {
+      int gr = J.r0 + r, gc = J.r0 + c;
+      if (perm) { gr = perm[gr]; gc = perm[gc]; }
+      v = (double)S[(size_t)gr * ld + gc];
+    }
+    store[J.off + e] = FactorIO<F>::put(v);
   }
 }
 
 // ------------------------------------------------------------------- apply
-// y_out[rows] -= sum over contributions of B x_in[cols] (or B^T for trans),
-// x and y in cluster order, interface-major with stride ld.  Products are
-// accumulated in FP32 for BF16 / FP32 factors and in FP64 for FP64 ones.
+// Eight consecutive factors (16-byte aligned) as accumulation values.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename F, typename Acc>
+__device__ __forceinline__ void load8f(const F *p, Acc (&v)[8]) {
+  if constexpr (sizeof(F) == 2) {
+    const u32x4 q = *reinterpret_cast<const __attribute__((address_space(1))) u32x4 *>(gp(p));
+    const unsigned w[4] = {q[0], q[1], q[2], q[3]};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[2 * e] = (Acc)__uint_as_float(w[e] << 16);
+      v[2 * e + 1] = (Acc)__uint_as_float(w[e] & 0xffff0000u);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (Acc)FactorIO<F>::get(p[e]);
+  }
+}
+
+// y = x - S x (or x - S^T x) over the rows of one leaf cluster of one
+// interface per work-group, in one launch: the identity part, the dense
+// leaves of both neighbouring transfer blocks, and at every tree level the
+// low-rank blocks whose row cluster contains these rows (their t = V^T x
+// formed by each leaf work-group again: a few thousand entries).  Rows of a
+// work-group are disjoint from every other's, so there are no write races;
+// the last cluster of an interface also copies the padding (rows >= M).
 template <typename F>
-__global__ __launch_bounds__(256) void k_hodlr_apply(const LrJob *__restrict__ jobs,
-                                                     const Contrib *__restrict__ con,
-                                                     const F *__restrict__ store,
-                                                     const double *__restrict__ x,
-                                                     double *__restrict__ y, int ld) {
+__global__ __launch_bounds__(256) void k_hodlr_apply_fused(const LrJob *__restrict__ jobs,
+                                                           const FContrib *__restrict__ con,
+                                                           const F *__restrict__ store,
+                                                           const double *__restrict__ x,
+                                                           double *__restrict__ y, int ld, int M) {
   using Acc = typename std::conditional<std::is_same<F, double>::value, double, float>::type;
   __shared__ Acc t[128];
+  __shared__ Acc xs[128];
   const LrJob J = jobs[blockIdx.x];
   const int rows = J.r1 - J.r0;
+  const double *xo = x + (size_t)J.out_iface * ld;
   double *yo = y + (size_t)J.out_iface * ld + J.r0;
+  for (int r = threadIdx.x; r < rows; r += 256) yo[r] = xo[J.r0 + r];
+  if (J.r1 == M)
+    for (int r = M + threadIdx.x; r < ld; r += 256) y[(size_t)J.out_iface * ld + r] = xo[r];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int ci = 0; ci < J.count; ++ci) {
-    const Contrib C = con[J.first + ci];
+    const FContrib C = con[J.first + ci];
     const double *xin = x + (size_t)C.in_iface * ld + C.c0;
     const int ncol = C.c1 - C.c0;
-    if (C.rank < 0) {  // dense (square) leaf, stored row-major
+    if (C.rank < 0) {  // dense square leaf, row stride lds (padding zero)
       const F *Lf = store + C.off_u;
       if (!C.trans) {
-        // 16 lanes per row, four rows per wavefront at a time (coalesced row
-        // reads, independent loads, a 16-lane reduction per row)
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        // 16 lanes per row with 8 columns each (one 16-byte load of BF16),
+        // four rows per wavefront at a time; x staged per 128 columns
         const int sub = lane >> 4, l16 = lane & 15;
-        for (int r0 = 4 * wave; r0 < rows; r0 += 16) {
-          const int r = r0 + sub;
-          Acc acc = 0;
-          if (r < rows)
-            for (int c = l16; c < ncol; c += 16)
-              acc += (Acc)FactorIO<F>::get(Lf[(size_t)r * ncol + c]) * (Acc)xin[c];
+        for (int cb = 0; cb < ncol; cb += 128) {
+          const int cw = min(128, ncol - cb);
+          __syncthreads();
+          for (int c = threadIdx.x; c < 128; c += 256) xs[c] = c < cw ? (Acc)xin[cb + c] : Acc(0);
+          __syncthreads();
+          for (int r0 = 4 * wave; r0 < rows; r0 += 16) {
+            const int r = r0 + sub;
+            Acc acc = 0;
+            if (r < rows && 8 * l16 < cw) {
+              Acc v[8];
+              load8f<F, Acc>(Lf + (size_t)r * C.lds + cb + 8 * l16, v);
 #pragma unroll
-          for (int off = 8; off > 0; off >>= 1) acc += __shfl_down(acc, off, 16);
-          if (l16 == 0 && r < rows) yo[r] -= (double)acc;
+              for (int e = 0; e < 8; ++e) acc += v[e] * xs[8 * l16 + e];
+            }
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) acc += __shfl_down(acc, off, 16);
+            if (l16 == 0 && r < rows) yo[r] -= (double)acc;
+          }
         }
       } else {
         // one thread per row: column c of the leaf is contiguous over rows
         for (int r = threadIdx.x; r < rows; r += 256) {
           Acc acc = 0;
           for (int c = 0; c < ncol; ++c)
-            acc += (Acc)FactorIO<F>::get(Lf[(size_t)c * rows + r]) * (Acc)xin[c];
+            acc += (Acc)FactorIO<F>::get(Lf[(size_t)c * C.lds + r]) * (Acc)xin[c];
           yo[r] -= (double)acc;
         }
       }
@@ -562,8 +619,7 @@ __global__ __launch_bounds__(256) void k_hodlr_apply(const LrJob *__restrict__ j
       continue;
     }
     const int rk = C.rank;
-    // t = Vt x (or U^T x for the transpose): one wavefront per entry of t
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // t = V^T x (or U^T x for the transpose): one wavefront per entry of t
     for (int k = wave; k < rk; k += 4) {
       Acc acc = 0;
       if (!C.trans) {
@@ -579,14 +635,17 @@ __global__ __launch_bounds__(256) void k_hodlr_apply(const LrJob *__restrict__ j
       if (lane == 0) t[k] = acc;
     }
     __syncthreads();
+    // rows roff .. roff + rows of the block's output side
     for (int r = threadIdx.x; r < rows; r += 256) {
       Acc acc = 0;
+      const int rr = C.roff + r;
       if (!C.trans) {
-        const F *u = store + C.off_u + (size_t)r * rk;
+        const F *u = store + C.off_u + (size_t)rr * rk;
         for (int k = 0; k < rk; ++k) acc += (Acc)FactorIO<F>::get(u[k]) * t[k];
       } else {
         const F *v = store + C.off_v;
-        for (int k = 0; k < rk; ++k) acc += (Acc)FactorIO<F>::get(v[(size_t)k * rows + r]) * t[k];
+        for (int k = 0; k < rk; ++k)
+          acc += (Acc)FactorIO<F>::get(v[(size_t)k * C.rfull + rr]) * t[k];
       }
       yo[r] -= (double)acc;
     }
@@ -618,6 +677,7 @@ __global__ void k_copy_d(const double *__restrict__ s, double *__restrict__ d, s
 }
 
 inline unsigned nb(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
+inline size_t pad8(size_t n) { return (n + 7) & ~size_t(7); }
 
 // ----------------------------------------------------------- host helpers
 struct HipErr : std::runtime_error {
@@ -737,6 +797,7 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     if (H->d_perm) dev_free(H->d_perm);
     if (H->factors) dev_free(H->factors);
     if (H->jobs) dev_free(H->jobs);
+    if (H->fjobs) dev_free(H->fjobs);
     if (H->pbuf) dev_free(H->pbuf);
     delete H;
   };
@@ -840,7 +901,8 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
         b.level = -1;
         b.rank = -1;
         b.off_u = store_elems;
-        store_elems += (size_t)(b.r1 - b.r0) * (b.r1 - b.r0);
+        // rows padded to a multiple of 8 entries (16-byte factor loads)
+        store_elems += (size_t)(b.r1 - b.r0) * pad8(b.r1 - b.r0);
         H->blocks.push_back(b);
       }
     // ---- compress level by level (FP64 staging kept until packing)
@@ -1000,9 +1062,9 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
         D.kept[b] = 1;
         hb.rank = r;
         hb.off_u = store_elems;
-        store_elems += (size_t)(hb.r1 - hb.r0) * r;
+        store_elems += pad8((size_t)(hb.r1 - hb.r0) * r);
         hb.off_v = store_elems;
-        store_elems += (size_t)r * (hb.c1 - hb.c0);
+        store_elems += pad8((size_t)r * (hb.c1 - hb.c0));
         D.selofs.push_back((int)selall.size());
         for (int k = 0; k < r; ++k) selall.push_back(sv[k].second);
         H->max_rank = std::max(H->max_rank, r);
@@ -1038,7 +1100,8 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     F *store = static_cast<F *>(H->factors);
     std::vector<LeafJob> lj;
     for (const HBlock &b : H->blocks)
-      if (b.rank < 0) lj.push_back({Sptr(b.smat), b.r0, b.r1 - b.r0, (long long)b.off_u});
+      if (b.rank < 0)
+        lj.push_back({Sptr(b.smat), b.r0, b.r1 - b.r0, (int)pad8(b.r1 - b.r0), (long long)b.off_u});
     if (!lj.empty()) {
       const LeafJob *d = static_cast<const LeafJob *>(upload(lj, st, keep));
       hipLaunchKernelGGL((k_pack_leaf<T, F>), dim3(64, (unsigned)lj.size()), dim3(256), 0, st,
@@ -1123,6 +1186,53 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
     if (!con.empty())
       HCHK(hipMemcpyAsync(static_cast<unsigned char *>(H->jobs) + H->off_con, con.data(),
                           con.size() * sizeof(Contrib), hipMemcpyHostToDevice, st));
+    // ---- fused tables: every leaf job takes its own dense contributions and,
+    // at each level, those of the job whose row cluster contains its rows
+    // (their low-rank rows restricted to the leaf's)
+    std::vector<LrJob> fj;
+    std::vector<FContrib> fc;
+    for (int dir = 0; dir < 2; ++dir) {
+      H->foff[dir] = fj.size();
+      for (int li = 0; li < H->n_leaf[dir]; ++li) {
+        const LrJob &lf = jobs[H->off_leaf[dir] + li];
+        LrJob f{lf.out_iface, lf.r0, lf.r1, (int)fc.size(), 0};
+        auto add = [&](const LrJob &src, int roff, int rfull) {
+          for (int q = 0; q < src.count; ++q) {
+            const Contrib &c = con[src.first + q];
+            FContrib x{};
+            x.in_iface = c.in_iface;
+            x.c0 = c.c0;
+            x.c1 = c.c1;
+            x.rank = c.rank;
+            x.off_u = c.off_u;
+            x.off_v = c.off_v;
+            x.trans = c.trans;
+            x.roff = roff;
+            x.rfull = rfull;
+            x.lds = (int)pad8(c.c1 - c.c0);
+            fc.push_back(x);
+          }
+        };
+        add(lf, 0, lf.r1 - lf.r0);
+        for (int L = 0; L < H->nlev; ++L)
+          for (int q = 0; q < H->n_lr[dir][L]; ++q) {
+            const LrJob &lj = jobs[H->off_lr[dir][L] + q];
+            if (lj.out_iface == lf.out_iface && lj.r0 <= lf.r0 && lf.r1 <= lj.r1)
+              add(lj, lf.r0 - lj.r0, lj.r1 - lj.r0);
+          }
+        f.count = (int)fc.size() - f.first;
+        fj.push_back(f);
+      }
+      H->fn[dir] = (int)(fj.size() - H->foff[dir]);
+    }
+    const size_t bytes_fj = fj.size() * sizeof(LrJob);
+    H->foff_con = (bytes_fj + 255) & ~size_t(255);
+    HCHK(dev_malloc(&H->fjobs, H->foff_con + std::max<size_t>(fc.size(), 1) * sizeof(FContrib)));
+    if (!fj.empty())
+      HCHK(hipMemcpyAsync(H->fjobs, fj.data(), bytes_fj, hipMemcpyHostToDevice, st));
+    if (!fc.empty())
+      HCHK(hipMemcpyAsync(static_cast<unsigned char *>(H->fjobs) + H->foff_con, fc.data(),
+                          fc.size() * sizeof(FContrib), hipMemcpyHostToDevice, st));
     HCHK(hipStreamSynchronize(st));
     cleanup();
     if (H->min_rank > H->max_rank) H->min_rank = 0;
@@ -1144,6 +1254,7 @@ void hodlr_free(ddst_op *op) {
   if (H->d_perm) dev_free(H->d_perm);
   if (H->factors) dev_free(H->factors);
   if (H->jobs) dev_free(H->jobs);
+  if (H->fjobs) dev_free(H->fjobs);
   if (H->pbuf) dev_free(H->pbuf);
   delete H;
   op->hodlr = nullptr;
@@ -1188,9 +1299,6 @@ int hodlr_apply_jobs(const ddst_op *op, const double *x, double *y, int transpos
   Hodlr *H = op->hodlr;
   if (!H) return DDST_ESTATE;
   const int dir = transpose ? 1 : 0;
-  const LrJob *jobs = static_cast<const LrJob *>(H->jobs);
-  const Contrib *con = reinterpret_cast<const Contrib *>(
-      static_cast<const unsigned char *>(H->jobs) + H->off_con);
   const size_t len = (size_t)op->n_ds * op->ld;
   const bool perm = H->d_perm != nullptr;
   double *xp = perm ? H->pbuf : nullptr;
@@ -1199,27 +1307,29 @@ int hodlr_apply_jobs(const ddst_op *op, const double *x, double *y, int transpos
     hipLaunchKernelGGL(k_permute, dim3(nb(op->ld), op->n_ds), dim3(256), 0, s, x, xp, H->d_perm,
                        op->M, op->ld, 0);
   const double *xi = perm ? xp : x;
-  hipLaunchKernelGGL(k_copy_d, dim3(nb(len)), dim3(256), 0, s, xi, yp, len);
-  auto launch = [&](size_t first, int count) {
-    if (count <= 0) return;
+  const int nj = H->fn[dir];
+  prof_begin(KK_GEMV, s);
+  if (nj == 0) {  // one interface: no transfer blocks, S = I
+    hipLaunchKernelGGL(k_copy_d, dim3(nb(len)), dim3(256), 0, s, xi, yp, len);
+  } else {
+    const LrJob *fj = static_cast<const LrJob *>(H->fjobs) + H->foff[dir];
+    const FContrib *fc = reinterpret_cast<const FContrib *>(
+        static_cast<const unsigned char *>(H->fjobs) + H->foff_con);
     switch (H->dtype) {
       case DDST_FACTOR_BF16:
-        hipLaunchKernelGGL(k_hodlr_apply<unsigned short>, dim3(count), dim3(256), 0, s,
-                           jobs + first, con, static_cast<const unsigned short *>(H->factors), xi,
-                           yp, op->ld);
+        hipLaunchKernelGGL(k_hodlr_apply_fused<unsigned short>, dim3(nj), dim3(256), 0, s, fj, fc,
+                           static_cast<const unsigned short *>(H->factors), xi, yp, op->ld,
+                           op->M);
         break;
       case DDST_FACTOR_FP32:
-        hipLaunchKernelGGL(k_hodlr_apply<float>, dim3(count), dim3(256), 0, s, jobs + first, con,
-                           static_cast<const float *>(H->factors), xi, yp, op->ld);
+        hipLaunchKernelGGL(k_hodlr_apply_fused<float>, dim3(nj), dim3(256), 0, s, fj, fc,
+                           static_cast<const float *>(H->factors), xi, yp, op->ld, op->M);
         break;
       default:
-        hipLaunchKernelGGL(k_hodlr_apply<double>, dim3(count), dim3(256), 0, s, jobs + first,
-                           con, static_cast<const double *>(H->factors), xi, yp, op->ld);
+        hipLaunchKernelGGL(k_hodlr_apply_fused<double>, dim3(nj), dim3(256), 0, s, fj, fc,
+                           static_cast<const double *>(H->factors), xi, yp, op->ld, op->M);
     }
-  };
-  prof_begin(KK_GEMV, s);
-  launch(H->off_leaf[dir], H->n_leaf[dir]);
-  for (int L = 0; L < H->nlev; ++L) launch(H->off_lr[dir][L], H->n_lr[dir][L]);
+  }
   prof_end(KK_GEMV, s, (double)H->bytes);
   if (perm)
     hipLaunchKernelGGL(k_permute, dim3(nb(op->ld), op->n_ds), dim3(256), 0, s, yp, y, H->d_perm,
