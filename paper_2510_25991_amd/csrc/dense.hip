@@ -105,17 +105,37 @@ struct Split3 {
   bf16x8 h, m, l;
 };
 // Parts of eight FP32 values (x[j] = h[j] + m[j] + l[j] to 2^-26 relative).
+// Pairs are rounded together (one packed conversion gives two BF16 values
+// in one register); the FP32 value of a part is its BF16 bits moved to the
+// upper half (a shift for the low element, a mask for the high one), so a
+// pair costs three conversions, two shifts, two masks and four
+// subtractions.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned cvt_pk(float a, float b) {
+  const f32x2 v = {a, b};
+  const bf16x2 p = __builtin_convertvector(v, bf16x2);
+  return __builtin_bit_cast(unsigned, p);
+}
+__device__ __forceinline__ float lo_f(unsigned p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float hi_f(unsigned p) { return __uint_as_float(p & 0xffff0000u); }
 __device__ __forceinline__ void split8(const float (&x)[8], Split3 &s) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 h, m, l;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const __bf16 h = (__bf16)x[j];
-    const float r = x[j] - (float)h;
-    const __bf16 m = (__bf16)r;
-    const float r2 = r - (float)m;
-    s.h[j] = h;
-    s.m[j] = m;
-    s.l[j] = (__bf16)r2;
+  for (int j = 0; j < 4; ++j) {
+    const float x0 = x[2 * j], x1 = x[2 * j + 1];
+    const unsigned hp = cvt_pk(x0, x1);
+    const float r0 = x0 - lo_f(hp), r1 = x1 - hi_f(hp);
+    const unsigned mp = cvt_pk(r0, r1);
+    const float q0 = r0 - lo_f(mp), q1 = r1 - hi_f(mp);
+    h[j] = hp;
+    m[j] = mp;
+    l[j] = cvt_pk(q0, q1);
   }
+  s.h = __builtin_bit_cast(bf16x8, h);
+  s.m = __builtin_bit_cast(bf16x8, m);
+  s.l = __builtin_bit_cast(bf16x8, l);
 }
 __device__ __forceinline__ f32x4 mfma_x6(const Split3 &a, const Split3 &b, f32x4 c) {
   c = mfma_bf16(a.l, b.h, c);
