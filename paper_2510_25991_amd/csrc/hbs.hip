@@ -52,8 +52,11 @@ struct HbsNodeDev {
   int lo;          // leaves: first cluster-order index
   int roff;        // offset of the node's rank entries in its level's hat vector
   int coff;        // offset of its children's entries in the next level's hat vector
+  int ldr, ldn;    // stored row lengths of U, V and of D (r, n rounded up to 8)
   int pad_;
   long long fU, fV, fD;  // element offsets (within one block) of U, V (n x r), D (n x n)
+                         // in the FP64 compression output (unpadded rows)
+  long long pU, pV, pD;  // the same in the stored factors (rows of ldr, ldn entries)
 };
 
 struct Hbs {
@@ -62,7 +65,8 @@ struct Hbs {
   std::vector<int> nhat;                    // hat entries per level (sum of ranks)
   std::vector<size_t> hoff;                 // per-level offset in one block's hat vector
   size_t hat_per_block = 0;
-  size_t block_elems = 0, root_off = 0;     // factor elements per block; root D offset
+  size_t block_elems = 0, root_off = 0;     // FP64 compression output per block; root D offset
+  size_t stored_elems = 0;                  // stored factor elements per block (padded rows)
   std::vector<int> perm;
   int *d_perm = nullptr;
   void *factors = nullptr;
@@ -497,29 +501,102 @@ __device__ __forceinline__ int blk_in(int b, int trans) {
   return trans ? (a ? s + 1 : s) : (a ? s : s + 1);
 }
 
-// out[c] (c < cols) += sum_i M[i][c] v[i] (i < rows): threads along c.
+// Stored factors: every row of U, V (r entries) and D (n entries) starts on
+// an 8-element boundary (rows padded with zeros to ldr and ldn entries), so
+// a thread reads eight entries of a row with 16-byte loads (one for BF16).
 template <typename F>
-__device__ __forceinline__ void col_dot(const F *M, int ldm, int rows, int cols, const double *v,
-                                        double *out) {
-  for (int c = threadIdx.x; c < cols; c += WG) {
-    double t = 0.0;
-    for (int i = 0; i < rows; ++i) t += FIO<F>::get(M[(size_t)i * ldm + c]) * v[i];
-    out[c] += t;
+__device__ __forceinline__ void load8(const F *p, double (&v)[8]) {
+  if constexpr (sizeof(F) == 2) {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 q = *reinterpret_cast<const __attribute__((address_space(1))) u32x4 *>(gp(p));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[2 * e] = (double)__uint_as_float(q[e] << 16);
+      v[2 * e + 1] = (double)__uint_as_float(q[e] & 0xffff0000u);
+    }
+  } else if constexpr (sizeof(F) == 4) {
+    const auto a = ld16(p), c = ld16(p + 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = (double)a[e];
+      v[4 + e] = (double)c[e];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const auto a = ld16(p + 2 * q);
+      v[2 * q] = a[0];
+      v[2 * q + 1] = a[1];
+    }
   }
 }
-// out[i] (i < rows) += sum_c M[i][c] v[c]: sixteen lanes along each row.
+
+// smallest power of two >= n (n <= 32 here)
+__device__ __forceinline__ int pow2_ge(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// out[i] += sum_c A[i][c] v[c] (i < rows, c < cols; rows of A padded to lda,
+// a multiple of 8): a group of lp lanes per row, eight entries per lane and
+// load, the row's partial sums reduced across the group.  Called by all
+// threads with the same arguments.
 template <typename F>
-__device__ __forceinline__ void row_dot(const F *M, int ldm, int rows, int cols, const double *v,
+__device__ __forceinline__ void mv_rows(const F *A, int lda, int rows, int cols, const double *v,
                                         double *out) {
-  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
-  for (int i0 = 0; i0 < rows; i0 += WG / 16) {
+  const int nch = (cols + 7) >> 3;
+  const int lp = pow2_ge(nch);
+  const int g = threadIdx.x / lp, l = threadIdx.x % lp, G = WG / lp;
+  for (int i0 = 0; i0 < rows; i0 += G) {
     const int i = i0 + g;
     double t = 0.0;
     if (i < rows)
-      for (int c = l; c < cols; c += 16) t += FIO<F>::get(M[(size_t)i * ldm + c]) * v[c];
-    for (int off = 8; off > 0; off >>= 1) t += __shfl_xor(t, off, 16);
+      for (int ch = l; ch < nch; ch += lp) {
+        double a[8];
+        load8(A + (size_t)i * lda + 8 * ch, a);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (8 * ch + e < cols) t += a[e] * v[8 * ch + e];
+      }
+    for (int off = lp >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off);
     if (i < rows && l == 0) out[i] += t;
   }
+}
+
+// out[c] += sum_i B[i][c] v[i] (i < rows, c < cols): lane l of a group of lp
+// takes columns 8 l .. 8 l + 7 of the rows g, g + G, ...; a column's partial
+// sums are reduced across the wavefront's groups by shuffles and across the
+// four wavefronts through red.  Called by all threads with the same
+// arguments; out is complete on return.
+template <typename F>
+__device__ __forceinline__ void mv_cols(const F *B, int ldb, int rows, int cols, const double *v,
+                                        double *out, double (*red)[kMaxN]) {
+  const int nch = (cols + 7) >> 3;
+  const int lp = pow2_ge(nch);
+  const int g = threadIdx.x / lp, l = threadIdx.x % lp, G = WG / lp;
+  double t[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) t[e] = 0.0;
+  if (l < nch)
+    for (int i = g; i < rows; i += G) {
+      double a[8];
+      load8(B + (size_t)i * ldb + 8 * l, a);
+      const double vi = v[i];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t[e] += a[e] * vi;
+    }
+  for (int off = lp; off < 64; off <<= 1)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] += __shfl_xor(t[e], off);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane < lp && l < nch)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (8 * l + e < cols) red[w][8 * l + e] = t[e];
+  __syncthreads();
+  for (int c = threadIdx.x; c < cols; c += WG) out[c] += red[0][c] + red[1][c] + red[2][c] + red[3][c];
+  __syncthreads();
 }
 
 // Up, leaf level: xh[b][L][t] = B^T x_in[perm[lo..lo+n)] (B = V, or U if trans).
@@ -530,16 +607,14 @@ __global__ __launch_bounds__(WG) void k_hbs_up_leaf(const HbsNodeDev *__restrict
                                                     const double *__restrict__ x, int ld,
                                                     double *__restrict__ hat, size_t hstride,
                                                     size_t hoff, int trans) {
-  __shared__ double v[kMaxN], out[kMaxN];
+  __shared__ double v[kMaxN], out[kMaxN], red[WG / 64][kMaxN];
   const HbsNodeDev N = nodes[blockIdx.x];
   const int b = blockIdx.y;
   const double *xin = x + (size_t)(blk_in(b, trans) - 1) * ld;
   for (int i = threadIdx.x; i < N.n; i += WG) v[i] = xin[perm ? perm[N.lo + i] : N.lo + i];
   for (int c = threadIdx.x; c < N.r; c += WG) out[c] = 0.0;
   __syncthreads();
-  const F *B = fac + b * bstride + (trans ? N.fU : N.fV);
-  col_dot(B, N.r, N.n, N.r, v, out);
-  __syncthreads();
+  mv_cols(fac + b * bstride + (trans ? N.pU : N.pV), N.ldr, N.n, N.r, v, out, red);
   double *h = hat + b * hstride + hoff + N.roff;
   for (int c = threadIdx.x; c < N.r; c += WG) h[c] = out[c];
 }
@@ -550,42 +625,41 @@ __global__ __launch_bounds__(WG) void k_hbs_up(const HbsNodeDev *__restrict__ no
                                                const F *__restrict__ fac, size_t bstride,
                                                double *__restrict__ hat, size_t hstride,
                                                size_t hoff, size_t hoff_child, int trans) {
-  __shared__ double v[kMaxN], out[kMaxN];
+  __shared__ double v[kMaxN], out[kMaxN], red[WG / 64][kMaxN];
   const HbsNodeDev N = nodes[blockIdx.x];
   const int b = blockIdx.y;
   const double *in = hat + b * hstride + hoff_child + N.coff;
   for (int i = threadIdx.x; i < N.n; i += WG) v[i] = in[i];
   for (int c = threadIdx.x; c < N.r; c += WG) out[c] = 0.0;
   __syncthreads();
-  const F *B = fac + b * bstride + (trans ? N.fU : N.fV);
-  col_dot(B, N.r, N.n, N.r, v, out);
-  __syncthreads();
+  mv_cols(fac + b * bstride + (trans ? N.pU : N.pV), N.ldr, N.n, N.r, v, out, red);
   double *h = hat + b * hstride + hoff + N.roff;
   for (int c = threadIdx.x; c < N.r; c += WG) h[c] = out[c];
 }
 
 // Root: yh[b][1] = D_root xh[b][1] (or D_root^T).
 template <typename F>
-__global__ __launch_bounds__(WG) void k_hbs_root(const F *__restrict__ fac, size_t bstride,
-                                                 size_t root_off, int n0, double *__restrict__ hat,
-                                                 size_t hstride, size_t hoff_x, size_t hoff_y,
-                                                 int trans) {
-  __shared__ double v[kMaxN], out[kMaxN];
+__global__ __launch_bounds__(WG) void k_hbs_root(const HbsNodeDev *__restrict__ root,
+                                                 const F *__restrict__ fac, size_t bstride,
+                                                 double *__restrict__ hat, size_t hstride,
+                                                 size_t hoff_x, size_t hoff_y, int trans) {
+  __shared__ double v[kMaxN], out[kMaxN], red[WG / 64][kMaxN];
+  const HbsNodeDev R = root[0];
   const int b = blockIdx.x;
   const double *in = hat + b * hstride + hoff_x;
-  for (int i = threadIdx.x; i < n0; i += WG) {
+  for (int i = threadIdx.x; i < R.n; i += WG) {
     v[i] = in[i];
     out[i] = 0.0;
   }
   __syncthreads();
-  const F *D = fac + b * bstride + root_off;
+  const F *D = fac + b * bstride + R.pD;
   if (trans)
-    col_dot(D, n0, n0, n0, v, out);
+    mv_cols(D, R.ldn, R.n, R.n, v, out, red);
   else
-    row_dot(D, n0, n0, n0, v, out);
+    mv_rows(D, R.ldn, R.n, R.n, v, out);
   __syncthreads();
   double *o = hat + b * hstride + hoff_y;
-  for (int i = threadIdx.x; i < n0; i += WG) o[i] = out[i];
+  for (int i = threadIdx.x; i < R.n; i += WG) o[i] = out[i];
 }
 
 // Down, internal level d: yh[b][d+1][children] = B' yh[b][d][t] + D xh[b][d+1][children]
@@ -596,7 +670,7 @@ __global__ __launch_bounds__(WG) void k_hbs_down(const HbsNodeDev *__restrict__ 
                                                  double *__restrict__ hat, size_t hstride,
                                                  size_t hoff_xc, size_t hoff_y, size_t hoff_yc,
                                                  int trans) {
-  __shared__ double vy[kMaxN], vx[kMaxN], out[kMaxN];
+  __shared__ double vy[kMaxN], vx[kMaxN], out[kMaxN], red[WG / 64][kMaxN];
   const HbsNodeDev N = nodes[blockIdx.x];
   const int b = blockIdx.y;
   double *hb = hat + b * hstride;
@@ -606,27 +680,29 @@ __global__ __launch_bounds__(WG) void k_hbs_down(const HbsNodeDev *__restrict__ 
     out[i] = 0.0;
   }
   __syncthreads();
-  const F *B = fac + b * bstride + (trans ? N.fV : N.fU);
-  const F *D = fac + b * bstride + N.fD;
-  row_dot(B, N.r, N.n, N.r, vy, out);
+  const F *fb = fac + b * bstride;
+  mv_rows(fb + (trans ? N.pV : N.pU), N.ldr, N.n, N.r, vy, out);
   __syncthreads();
   if (trans)
-    col_dot(D, N.n, N.n, N.n, vx, out);
+    mv_cols(fb + N.pD, N.ldn, N.n, N.n, vx, out, red);
   else
-    row_dot(D, N.n, N.n, N.n, vx, out);
+    mv_rows(fb + N.pD, N.ldn, N.n, N.n, vx, out);
   __syncthreads();
   for (int i = threadIdx.x; i < N.n; i += WG) hb[hoff_yc + N.coff + i] = out[i];
 }
 
 // Leaves: for output interface jo (blockIdx.y + 1) and leaf t,
-//   y_jo[perm] = x_jo[perm] - sum over its blocks (B' yh + D x_in[perm]).
+//   y_jo[perm] = x_jo[perm] - sum over its blocks (B' yh + D x_in[perm]);
+// without a basis (a single cluster) the leaf is the root and only D is
+// applied.  The first leaf's work-group also copies the padding entries
+// (M .. ld - 1) of y_jo from x_jo.
 template <typename F>
 __global__ __launch_bounds__(WG) void k_hbs_leaf_out(
     const HbsNodeDev *__restrict__ nodes, const F *__restrict__ fac, size_t bstride,
-    const int *__restrict__ perm, const double *__restrict__ x, double *__restrict__ y, int ld,
-    int n_ds, const double *__restrict__ hat, size_t hstride, size_t hoff_y, int has_basis,
-    size_t dsel, int trans) {
-  __shared__ double vy[kMaxN], vx[kMaxN], out[kMaxN];
+    const int *__restrict__ perm, const double *__restrict__ x, double *__restrict__ y, int M,
+    int ld, int n_ds, const double *__restrict__ hat, size_t hstride, size_t hoff_y,
+    int has_basis, int trans) {
+  __shared__ double vy[kMaxN], vx[kMaxN], out[kMaxN], red[WG / 64][kMaxN];
   const HbsNodeDev N = nodes[blockIdx.x];
   const int jo = blockIdx.y + 1;
   for (int i = threadIdx.x; i < N.n; i += WG) out[i] = 0.0;
@@ -651,14 +727,13 @@ __global__ __launch_bounds__(WG) void k_hbs_leaf_out(
     __syncthreads();
     const F *fb = fac + b * bstride;
     if (has_basis) {
-      row_dot(fb + (trans ? N.fV : N.fU), N.r, N.n, N.r, vy, out);
+      mv_rows(fb + (trans ? N.pV : N.pU), N.ldr, N.n, N.r, vy, out);
       __syncthreads();
     }
-    const F *D = fb + (has_basis ? (size_t)N.fD : dsel);
     if (trans)
-      col_dot(D, N.n, N.n, N.n, vx, out);
+      mv_cols(fb + N.pD, N.ldn, N.n, N.n, vx, out, red);
     else
-      row_dot(D, N.n, N.n, N.n, vx, out);
+      mv_rows(fb + N.pD, N.ldn, N.n, N.n, vx, out);
   }
   __syncthreads();
   const double *xo = x + (size_t)(jo - 1) * ld;
@@ -667,18 +742,29 @@ __global__ __launch_bounds__(WG) void k_hbs_leaf_out(
     const int p = perm ? perm[N.lo + i] : N.lo + i;
     yo[p] = xo[p] - out[i];
   }
+  if (blockIdx.x == 0)
+    for (int c = M + threadIdx.x; c < ld; c += WG) yo[c] = xo[c];
 }
 
-// padding entries (>= M) of y copied from x
-__global__ void k_copy_padding(const double *__restrict__ x, double *__restrict__ y, int M,
-                               int ld, int n_ds) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int w = ld - M;
-  if (w <= 0 || e >= (size_t)n_ds * w) return;
-  const size_t j = e / w, c = M + e % w;
-  y[j * ld + c] = x[j * ld + c];
+// Stored factors from the FP64 compression output: job (j, b) copies one
+// matrix (rows x cols, contiguous rows at src) of block b to rows padded to
+// ldd entries at dst, converted to F.  The padding is cleared beforehand.
+struct HbsPack {
+  long long src, dst;
+  int rows, cols, ldd, pad_;
+};
+template <typename F>
+__global__ void k_pack_hbs(const HbsPack *__restrict__ jobs, const double *__restrict__ src,
+                           size_t sblock, F *__restrict__ dst, size_t dblock) {
+  const HbsPack J = jobs[blockIdx.x];
+  const double *s = src + blockIdx.y * sblock + J.src;
+  F *d = dst + blockIdx.y * dblock + J.dst;
+  const int tot = J.rows * J.cols;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int i = e / J.cols, c = e % J.cols;
+    d[(size_t)i * J.ldd + c] = FIO<F>::put(s[e]);
+  }
 }
-
 }  // namespace
 
 // ------------------------------------------------------------- host side
@@ -922,7 +1008,7 @@ int hbs_compress(ddst_op *op, int k, int q, int leaf, int dtype, const double *o
     H->perm = perm;
     // node tables: factor offsets per block, hat offsets per level
     H->lv.assign(L + 1, {});
-    size_t off = 0;
+    size_t off = 0, poff = 0;
     H->nhat.assign(L + 1, 0);
     for (int d = L; d >= 1; --d) {
       int roff = 0, coff = 0;
@@ -941,6 +1027,14 @@ int hbs_compress(ddst_op *op, int k, int q, int leaf, int dtype, const double *o
         off += (size_t)N.n * N.r;
         N.fD = (long long)off;
         off += (size_t)N.n * N.n;
+        N.ldr = (N.r + 7) / 8 * 8;
+        N.ldn = (N.n + 7) / 8 * 8;
+        N.pU = (long long)poff;
+        poff += (size_t)N.n * N.ldr;
+        N.pV = (long long)poff;
+        poff += (size_t)N.n * N.ldr;
+        N.pD = (long long)poff;
+        poff += (size_t)N.n * N.ldn;
         H->lv[d].push_back(N);
       }
       H->nhat[d] = roff;
@@ -953,9 +1047,13 @@ int hbs_compress(ddst_op *op, int k, int q, int leaf, int dtype, const double *o
       H->root_off = off;
       R.fD = (long long)off;
       off += (size_t)R.n * R.n;
+      R.ldn = (R.n + 7) / 8 * 8;
+      R.pD = (long long)poff;
+      poff += (size_t)R.n * R.ldn;
       H->lv[0].push_back(R);
     }
     H->block_elems = (off + 63) / 64 * 64;
+    H->stored_elems = (poff + 63) / 64 * 64;
     // hat vector layout per block: x^ then y^ for every level 1..L
     H->hoff.assign(2 * (L + 1), 0);
     size_t h = 0;
@@ -987,7 +1085,7 @@ int hbs_compress(ddst_op *op, int k, int q, int leaf, int dtype, const double *o
     if (H->nblk > 0 && dev_malloc((void **)&H->hat, (size_t)H->nblk * H->hat_per_block * 8) != hipSuccess)
       throw std::bad_alloc();
     const size_t esz = dtype == DDST_FACTOR_BF16 ? 2 : dtype == DDST_FACTOR_FP32 ? 4 : 8;
-    H->bytes = (size_t)H->nblk * H->block_elems * esz;
+    H->bytes = (size_t)H->nblk * H->stored_elems * esz;
     if (H->nblk == 0) {
       BCHK(hipStreamSynchronize(st));
       return DDST_OK;
@@ -1144,15 +1242,35 @@ int hbs_compress(ddst_op *op, int k, int q, int leaf, int dtype, const double *o
     }
     // ---- pack
     if (dev_malloc(&H->factors, std::max<size_t>(H->bytes, 16)) != hipSuccess) throw std::bad_alloc();
-    const size_t tot = (size_t)nb * H->block_elems;
-    if (dtype == DDST_FACTOR_BF16)
-      hipLaunchKernelGGL(k_pack_factors<unsigned short>, dim3(nblk1(tot)), dim3(256), 0, st, F64,
-                         tot, static_cast<unsigned short *>(H->factors));
-    else if (dtype == DDST_FACTOR_FP32)
-      hipLaunchKernelGGL(k_pack_factors<float>, dim3(nblk1(tot)), dim3(256), 0, st, F64, tot,
-                         static_cast<float *>(H->factors));
-    else
-      BCHK(hipMemcpyAsync(H->factors, F64, tot * 8, hipMemcpyDeviceToDevice, st));
+    BCHK(hipMemsetAsync(H->factors, 0, H->bytes, st));
+    {
+      std::vector<HbsPack> pk;
+      for (int d = 0; d <= L; ++d)
+        for (const HbsNodeDev &N : H->lv[d]) {
+          if (d >= 1) {
+            pk.push_back({N.fU, N.pU, N.n, N.r, N.ldr, 0});
+            pk.push_back({N.fV, N.pV, N.n, N.r, N.ldr, 0});
+          }
+          pk.push_back({N.fD, N.pD, N.n, N.n, N.ldn, 0});
+        }
+      BMem pt(pk.size() * sizeof(HbsPack));
+      BCHK(hipMemcpyAsync(pt.p, pk.data(), pk.size() * sizeof(HbsPack), hipMemcpyHostToDevice,
+                          st));
+      const dim3 grid((unsigned)pk.size(), (unsigned)nb);
+      const HbsPack *pj = pt.as<HbsPack>();
+      const size_t sb = H->block_elems, db = H->stored_elems;
+      if (dtype == DDST_FACTOR_BF16)
+        hipLaunchKernelGGL(k_pack_hbs<unsigned short>, grid, dim3(256), 0, st, pj, F64, sb,
+                           static_cast<unsigned short *>(H->factors), db);
+      else if (dtype == DDST_FACTOR_FP32)
+        hipLaunchKernelGGL(k_pack_hbs<float>, grid, dim3(256), 0, st, pj, F64, sb,
+                           static_cast<float *>(H->factors), db);
+      else
+        hipLaunchKernelGGL(k_pack_hbs<double>, grid, dim3(256), 0, st, pj, F64, sb,
+                           static_cast<double *>(H->factors), db);
+      BCHK(hipGetLastError());
+      BCHK(hipStreamSynchronize(st));  // the job table
+    }
     BCHK(hipEventRecord(e2, st));
     BCHK(hipEventSynchronize(e2));
     float ms1 = 0, ms2 = 0;
@@ -1180,7 +1298,7 @@ void hbs_apply_t(const ddst_op *op, const double *x, double *y, int trans, hipSt
     return reinterpret_cast<const HbsNodeDev *>(static_cast<const unsigned char *>(H->nodes) +
                                                 H->node_off[d]);
   };
-  const size_t bs = H->block_elems, hs = H->hat_per_block;
+  const size_t bs = H->stored_elems, hs = H->hat_per_block;
   if (nb == 0) {
     BCHK(hipMemcpyAsync(y, x, (size_t)op->n_ds * ld * 8, hipMemcpyDeviceToDevice, st));
     return;
@@ -1193,25 +1311,20 @@ void hbs_apply_t(const ddst_op *op, const double *x, double *y, int trans, hipSt
       hipLaunchKernelGGL(k_hbs_up<F>, dim3((unsigned)H->lv[d].size(), nb), dim3(WG), 0, st,
                          nodes(d), fac, bs, H->hat, hs, H->hoff[2 * d], H->hoff[2 * (d + 1)],
                          trans);
-    hipLaunchKernelGGL(k_hbs_root<F>, dim3(nb), dim3(WG), 0, st, fac, bs, H->root_off,
-                       H->lv[0][0].n, H->hat, hs, H->hoff[2], H->hoff[3], trans);
+    hipLaunchKernelGGL(k_hbs_root<F>, dim3(nb), dim3(WG), 0, st, nodes(0), fac, bs, H->hat, hs,
+                       H->hoff[2], H->hoff[3], trans);
     for (int d = 1; d <= L - 1; ++d)
       hipLaunchKernelGGL(k_hbs_down<F>, dim3((unsigned)H->lv[d].size(), nb), dim3(WG), 0, st,
                          nodes(d), fac, bs, H->hat, hs, H->hoff[2 * (d + 1)], H->hoff[2 * d + 1],
                          H->hoff[2 * (d + 1) + 1], trans);
     hipLaunchKernelGGL(k_hbs_leaf_out<F>, dim3(nl, op->n_ds), dim3(WG), 0, st, nodes(L), fac, bs,
-                       H->d_perm, x, y, ld, op->n_ds, H->hat, hs, H->hoff[2 * L + 1], 1,
-                       (size_t)0, trans);
+                       H->d_perm, x, y, op->M, ld, op->n_ds, H->hat, hs, H->hoff[2 * L + 1], 1,
+                       trans);
   } else {
     // a single cluster: the root block is the whole transfer block
     hipLaunchKernelGGL(k_hbs_leaf_out<F>, dim3(1, op->n_ds), dim3(WG), 0, st, nodes(0), fac, bs,
-                       H->d_perm, x, y, ld, op->n_ds, H->hat, hs, (size_t)0, 0, H->root_off,
-                       trans);
+                       H->d_perm, x, y, op->M, ld, op->n_ds, H->hat, hs, (size_t)0, 0, trans);
   }
-  const int w = ld - op->M;
-  if (w > 0)
-    hipLaunchKernelGGL(k_copy_padding, dim3(nblk1((size_t)op->n_ds * w)), dim3(256), 0, st, x, y,
-                       op->M, ld, op->n_ds);
 }
 
 int hbs_apply(const ddst_op *op, const double *x, double *y, int transpose, hipStream_t st) {

@@ -112,9 +112,11 @@ def test_hbs_matches_oracle_hbs(name, k, leaf):
     fo = {key: (lambda v, t, h=h: ohbs.apply(h, v, t)) for key, h in Ho.items()}
     fd_ = {key: (lambda v, t, B=B: (B.T if t else B) @ v) for key, B in dense.items()}
     x = rng.standard_normal(p.n_ds * p.M)
+    xg = torch.tensor(x, device="cuda")
+    y64 = {}
     for trans in (False, True):
-        yg = op.apply(torch.tensor(x, device="cuda"), transpose=trans,
-                      which="hbs").cpu().numpy().ravel()
+        yg = op.apply(xg, transpose=trans, which="hbs").cpu().numpy().ravel()
+        y64[trans] = yg
         yo = k_apply(p, fo, x, trans)
         yd = k_apply(p, fd_, x, trans)
         e_go, e_od, e_gd = rel(yg, yo), rel(yo, yd), rel(yg, yd)
@@ -123,6 +125,17 @@ def test_hbs_matches_oracle_hbs(name, k, leaf):
               f"sample {info['sample_ms']:.1f} ms, compress {info['compress_ms']:.1f} ms")
         assert e_go <= 1e-9
         assert e_gd <= 2 * e_od + 1e-12
+    # the same form stored in FP32 and BF16 (rows padded to 8 entries in the
+    # stored factors): the products differ from the FP64 one by the factors'
+    # rounding only (2^-24, 2^-9 relative per entry); a misplaced row or
+    # entry would be O(1)
+    for dt, bound in (("fp32", 1e-5), ("bf16", 5e-2)):
+        op.compress_hbs(rank=k, oversample=10, leaf=leaf, factor_dtype=dt, omega=Om, psi=Ps)
+        for trans in (False, True):
+            yq = op.apply(xg, transpose=trans, which="hbs").cpu().numpy().ravel()
+            e = rel(yq, y64[trans])
+            print(f"  {dt} factors, transpose={trans}: vs FP64 factors {e:.3e}")
+            assert e <= bound
     op.close()
 
 
