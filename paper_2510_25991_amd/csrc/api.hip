@@ -881,9 +881,17 @@ void run_matfree(const ddst_op *op, const MatfreeTables &t, bool trans, const Ma
 // basis instead of four, one column of H finalized a step later); below
 // that, the classical twice-applied Gram-Schmidt step, whose fewer launches
 // cost less than the passes saved.
+// When the tolerance is at least kBasis32Tol the basis is stored in FP32
+// (half the bytes of the passes over it, which dominate long runs): each
+// q_j is rounded once when it is final (2^-24 relative), while the candidate
+// vector the operator is applied to and every sum stay FP64 (the candidate
+// in a separate FP64 vector after the FP32 slots).  The Arnoldi relation and
+// the solution x = V y then hold to about 1e-7 relative, far below such a
+// tolerance; an inner solve of iterative refinement at 1e-4 is the case.
 // Returns the iterations used.
 constexpr int kGmresCheck = 8;
 constexpr size_t kLagBytes = (size_t)16 << 20;
+constexpr double kBasis32Tol = 1e-6;
 
 template <typename T>
 int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, double *x, double tol,
@@ -899,13 +907,24 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
   launch_fill(x, 0.0, len, s);
   *relres = 0.0;
   if (!(beta > 0.0)) return 0;
-  launch_scale_by_inv(w.V, rhs, w.nrm, len, s);
+  // FP32 basis: (max_iter + 1) FP32 slots, then the FP64 candidate (the
+  // region holds max_iter + 1 FP64 slots, so both fit for max_iter >= 2)
+  const bool b32 = tol >= kBasis32Tol && max_iter >= 2 && len >= 64;
+  float *V32 = reinterpret_cast<float *>(w.V);
+  double *ucur =
+      b32 ? reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(w.V) +
+                                       ((size_t)(max_iter + 1) * len * 4 + 255) / 256 * 256)
+          : nullptr;
+  launch_scale_by_inv(b32 ? ucur : w.V, rhs, w.nrm, len, s);
+  if (b32) launch_to_float(V32, ucur, len, s);
+  // operator input of step k: slot k, or the FP64 candidate
+  auto vin = [&](int k) -> double * { return b32 ? ucur : w.V + (size_t)k * len; };
   // matvec tables for every basis vector
   JobTable tab;
   std::vector<size_t> offs(max_iter);
   if (form == DDST_APPLY_DENSE)
     for (int k = 0; k < max_iter; ++k)
-      offs[k] = tab.add(interface_jobs(op, w.V + (size_t)k * len, w.W, trans));
+      offs[k] = (b32 && k > 0) ? offs[0] : tab.add(interface_jobs(op, vin(k), w.W, trans));
   tab.upload(s);
   std::vector<MatfreeTables> mf(form == DDST_APPLY_MATFREE ? nr : 0);
   std::vector<MatfreeBufs> mb;
@@ -926,7 +945,7 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
   int nfinal = 0;   // columns of H finalized by the steps enqueued so far
   int next_check = std::min(kGmresCheck, max_iter);
   double prev_res = 1.0;
-  auto lagged = [&](int k) { return (size_t)(k + 1) * len * 8 >= kLagBytes; };
+  auto lagged = [&](int k) { return (size_t)(k + 1) * len * (b32 ? 4 : 8) >= kLagBytes; };
   // read back the estimates of the columns finalized since the last check
   auto check = [&]() {
     const int n = nfinal - checked;
@@ -958,7 +977,7 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
     checked = nfinal;
   };
   for (int k = 0; k < max_iter && used == 0; ++k) {
-    const double *vk = w.V + (size_t)k * len;
+    const double *vk = vin(k);
     if (form == DDST_APPLY_HODLR || form == DDST_APPLY_HBS) {
       for (int v = 0; v < nr; ++v) {
         const size_t oi = (size_t)v * w.ifc;
@@ -977,25 +996,43 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
                           w.part, s);
     }
     if (lagged(k)) {
-      launch_arnoldi_lagged(w.V, len, k, w.W, len, w.dpart, d, beta,
-                            (k >= 1 && !lagged(k - 1)) ? 1 : 0, 0, s);
+      const int cf = (k >= 1 && !lagged(k - 1)) ? 1 : 0;
+      if (b32)
+        launch_arnoldi_lagged<float>(V32, len, k, ucur, w.W, ucur, len, w.dpart, d, beta, cf, 0,
+                                     s);
+      else
+        launch_arnoldi_lagged<double>(w.V, len, k, w.V + (size_t)k * len, w.W,
+                                      w.V + (size_t)(k + 1) * len, len, w.dpart, d, beta, cf, 0,
+                                      s);
       nfinal = k;
     } else {
-      launch_arnoldi_step(w.V, len, k, w.W, len, w.hd, w.V + (size_t)(k + 1) * len, w.dpart,
-                          d, beta, s);
+      if (b32)
+        launch_arnoldi_step<float>(V32, len, k, w.W, len, w.hd, ucur, V32 + (size_t)(k + 1) * len,
+                                   w.dpart, d, beta, s);
+      else
+        launch_arnoldi_step<double>(w.V, len, k, w.W, len, w.hd, w.V + (size_t)(k + 1) * len,
+                                    nullptr, w.dpart, d, beta, s);
       nfinal = k + 1;
     }
     if (nfinal >= next_check) check();
   }
   if (used == 0 && nfinal < max_iter && max_iter > 0 && lagged(max_iter - 1)) {
     // close the last column (its reorthogonalization coefficients)
-    launch_arnoldi_lagged(w.V, len, max_iter, nullptr, len, w.dpart, d, beta,
-                          (max_iter >= 1 && !lagged(max_iter - 1)) ? 1 : 0, 1, s);
+    const int cf = (max_iter >= 1 && !lagged(max_iter - 1)) ? 1 : 0;
+    if (b32)
+      launch_arnoldi_lagged<float>(V32, len, max_iter, ucur, nullptr, nullptr, len, w.dpart, d,
+                                   beta, cf, 1, s);
+    else
+      launch_arnoldi_lagged<double>(w.V, len, max_iter, w.V + (size_t)max_iter * len, nullptr,
+                                    nullptr, len, w.dpart, d, beta, cf, 1, s);
     nfinal = max_iter;
   }
   if (used == 0) check();
   if (used == 0) used = checked;
-  launch_gmres_solution(d, used, x, w.V, len, s);
+  if (b32)
+    launch_gmres_solution<float>(d, used, x, V32, len, s);
+  else
+    launch_gmres_solution<double>(d, used, x, w.V, len, s);
   HIPCHK(hipStreamSynchronize(s));
   *relres = res;
   return used;

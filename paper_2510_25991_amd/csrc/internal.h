@@ -226,8 +226,13 @@ void launch_axpy(double *y, const double *x, double a, size_t len, hipStream_t s
 void launch_fill(double *y, double v, size_t len, hipStream_t s);
 // part: at least dots_part_len(len, nvec) doubles of workspace
 inline size_t dots_part_len(size_t len, int nvec) { return ((len + 255) / 256) * (size_t)nvec; }
-void launch_mgs_update(double *w, const double *V, size_t stride, int nvec,
+// w += sign V h over nvec basis vectors of stride `stride` (FP64 or FP32
+// storage, FP64 arithmetic)
+template <typename B>
+void launch_mgs_update(double *w, const B *V, size_t stride, int nvec,
                        const double *h, double sign, size_t len, hipStream_t s);
+// dst = src rounded to FP32
+void launch_to_float(float *dst, const double *src, size_t len, hipStream_t s);
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s);
 // GMRES state on the device: packed Hessenberg columns (column k, k + 2
 // entries, from offset k (k + 3) / 2), Givens pairs, the rotated right-hand
@@ -269,37 +274,43 @@ struct GmresDev {
   }
 };
 // GMRES iteration k after the matvec w = S v_k: one Arnoldi step by
-// classical Gram-Schmidt applied twice (FP64), V the k + 1 basis vectors of
-// stride `stride`,
+// classical Gram-Schmidt applied twice (FP64 arithmetic), V the k + 1 basis
+// vectors of stride `stride` (stored in FP64 or FP32),
 //   h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; vnext = w / |w|
+// (vnext in FP64; with an FP32 basis also rounded into vslot, slot k + 1;
+// vslot null otherwise, vnext being slot k + 1 itself)
 // (hd[0..k] = h1, hd[k+1 .. 2k+1] = h2, hd[2k+2] = |w|), then column k of H
 // from them: previous rotations applied, the new one formed, g updated;
 // res[2k] = |g[k+1]| / beta, res[2k+1] = 1 when the new norm is not
 // positive and finite (breakdown: the Krylov space is exhausted; a zero norm
 // makes the estimate exactly 0), else 0.  part: dots_part_len(len, k + 1).
-void launch_arnoldi_step(const double *V, size_t stride, int k, double *w, size_t len,
-                         double *hd, double *vnext, double *part, GmresDev gd, double beta,
+template <typename B>
+void launch_arnoldi_step(const B *V, size_t stride, int k, double *w, size_t len, double *hd,
+                         double *vnext, float *vslot, double *part, GmresDev gd, double beta,
                          hipStream_t s);
 // GMRES iteration k with lagged reorthogonalization (two passes over the
-// basis instead of four).  V slots 0..k-1 hold the orthonormal q_0..q_{k-1};
-// slot k holds the candidate u (q_k after one Gram-Schmidt pass, normalized);
-// w = S u.  Pass A: a = Q^T u, |u|^2, b = Q^T w, u.w in one sweep; then
+// basis instead of four).  V slots 0..k-1 hold the orthonormal q_0..q_{k-1}
+// (FP64 or FP32 storage); u (FP64: slot k itself with an FP64 basis, else a
+// separate vector) holds the candidate (q_k after one Gram-Schmidt pass,
+// normalized); w = S u.  Pass A: a = Q^T u, |u|^2, b = Q^T w, u.w in one sweep; then
 // nu = |u - Q a|, column k - 1 of H is finalized (its provisional
 // coefficients plus rho a, subdiagonal rho nu) and rotated (res[2(k-1)]);
 // q_k = (u - Q a) / nu, and, with d = H a (S Q = Q H), the first pass of
 // S q_k = (w - [Q, q_k] d) / nu against [Q, q_k] gives the provisional
 // column h of step k and z = S q_k - [Q, q_k] h, formed from w, u and Q in
-// pass B (one sweep, which also writes q_k over u); slot k + 1 = z / |z|,
+// pass B (one sweep, which also writes q_k into slot k); unext = z / |z|
+// (FP64: slot k + 1, or the separate candidate vector, overwriting u),
 // rho = |z|.  col_final: column k - 1 is already final (the previous step
 // was a classical one); finalize_only: only pass A for a and nu and the
 // finalization of column k - 1 (w unused), to close the last column.
 // part: dots_part_len(len, 2 (k + 1)).
-void launch_arnoldi_lagged(double *V, size_t stride, int k, double *w, size_t len,
-                           double *part, GmresDev gd, double beta, int col_final,
-                           int finalize_only, hipStream_t s);
+template <typename B>
+void launch_arnoldi_lagged(B *V, size_t stride, int k, const double *u, double *w,
+                           double *unext, size_t len, double *part, GmresDev gd, double beta,
+                           int col_final, int finalize_only, hipStream_t s);
 // y = R^{-1} g over the first k columns (one work-group), then x = V y.
-void launch_gmres_solution(GmresDev d, int k, double *x, const double *V, size_t len,
-                           hipStream_t s);
+template <typename B>
+void launch_gmres_solution(GmresDev d, int k, double *x, const B *V, size_t len, hipStream_t s);
 void launch_scale_by_inv(double *dst, const double *src, const double *nrm, size_t len,
                          hipStream_t s);
 void launch_cell_gradient(const double *u, const double *lam, const double *g, int dim,

@@ -509,7 +509,8 @@ constexpr int kDotVecs = 8;  // basis vectors per wavefront and round
 // Each wavefront takes kDotVecs vectors at a time with independent sums,
 // their loads issued together (entries past the chunk re-read its last element
 // and meet a zero of ws).
-__device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t stride,
+template <typename B>
+__device__ __forceinline__ void chunk_dots(const B *__restrict__ V, size_t stride,
                                            int nvec, const double *ws, size_t base, int cn,
                                            double *__restrict__ part) {
   constexpr int E = kDotChunk / 64;  // entries per lane
@@ -535,11 +536,11 @@ __device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t 
     for (int u = 0; u < kDotVecs; ++u) {
       const int i = i0 + 4 * u;
       if (i < nvec) {
-        const double *v = V + (size_t)i * stride + base;
+        const B *v = V + (size_t)i * stride + base;
 #pragma unroll
         for (int t = 0; t < E; ++t) {
           const int e = lane + 64 * t;
-          s[u] += v[e < cn ? e : cn - 1] * wv[t];
+          s[u] += (double)v[e < cn ? e : cn - 1] * wv[t];
         }
       }
     }
@@ -552,7 +553,8 @@ __device__ __forceinline__ void chunk_dots(const double *__restrict__ V, size_t 
   }
 }
 
-__global__ __launch_bounds__(256) void k_multidot_part(const double *__restrict__ V, size_t stride,
+template <typename B>
+__global__ __launch_bounds__(256) void k_multidot_part(const B *__restrict__ V, size_t stride,
                                                        int nvec, const double *__restrict__ w,
                                                        size_t len, double *__restrict__ part) {
   __shared__ double ws[kDotChunk];
@@ -567,12 +569,13 @@ __global__ __launch_bounds__(256) void k_multidot_part(const double *__restrict_
 // partial dot products of the updated chunk for the next pass (V2 = V,
 // nvec2 = nvec) or its partial squared norm (V2 null, nvec2 = 1): the two
 // kernels of the classical scheme that touch the same chunk, fused.
+template <typename B>
 __global__ __launch_bounds__(256) void k_mgs_update_dots(double *__restrict__ w,
-                                                         const double *__restrict__ V,
+                                                         const B *__restrict__ V,
                                                          size_t stride, int nvec,
                                                          const double *__restrict__ h,
                                                          double sign, size_t len,
-                                                         const double *__restrict__ V2,
+                                                         const B *__restrict__ V2,
                                                          int nvec2, double *__restrict__ part) {
   __shared__ double ws[kDotChunk];
   const size_t base = (size_t)blockIdx.x * kDotChunk;
@@ -581,13 +584,13 @@ __global__ __launch_bounds__(256) void k_mgs_update_dots(double *__restrict__ w,
   double we = 0.0;
   if (e < cn) {
     // eight independent partial sums: eight basis-vector loads in flight
-    const double *v = V + base + e;
+    const B *v = V + base + e;
     double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int i = 0;
     for (; i + 8 <= nvec; i += 8)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] += v[(size_t)(i + u) * stride] * h[i + u];
-    for (; i < nvec; ++i) t[0] += v[(size_t)i * stride] * h[i];
+      for (int u = 0; u < 8; ++u) t[u] += (double)v[(size_t)(i + u) * stride] * h[i + u];
+    for (; i < nvec; ++i) t[0] += (double)v[(size_t)i * stride] * h[i];
     const double sum = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
     we = w[base + e] + sign * sum;
     w[base + e] = we;
@@ -750,13 +753,15 @@ __device__ __forceinline__ void gmres_givens_raw(GmresDev d, int j, double beta)
 }
 
 // Last kernel of Arnoldi step k: dst = src / sqrt(sum of the nchunk partial
-// squared norms), every work-group summing the partials in the same order;
-// the first one stores the norm in hd and then applies the Givens rotations
-// (column k of H from hd), concurrently with the others' scaling.
+// squared norms) (and its FP32 rounding in slot, if given), every
+// work-group summing the partials in the same order; the first one stores
+// the norm in hd and then applies the Givens rotations (column k of H from
+// hd), concurrently with the others' scaling.
 __global__ __launch_bounds__(256) void k_norm_scale_givens(const double *__restrict__ part,
                                                            int nchunk, double *__restrict__ hd,
                                                            const double *__restrict__ src,
-                                                           double *__restrict__ dst, size_t len,
+                                                           double *__restrict__ dst,
+                                                           float *__restrict__ slot, size_t len,
                                                            GmresDev gd, int k, double beta) {
   __shared__ double sh[1];
   if (threadIdx.x < 64) {
@@ -772,24 +777,31 @@ __global__ __launch_bounds__(256) void k_norm_scale_givens(const double *__restr
   __syncthreads();
   const double d = sh[0];
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < len) dst[e] = (d > 0.0) ? src[e] / d : 0.0;
+  if (e < len) {
+    const double v = (d > 0.0) ? src[e] / d : 0.0;
+    dst[e] = v;
+    if (slot) slot[e] = (float)v;
+  }
   if (blockIdx.x == 0) gmres_givens_block(hd, gd, k, beta, d);
 }
 
 // ---- Arnoldi with lagged reorthogonalization (see launch_arnoldi_lagged) --
 
-// Pass A: partial dot products of the m = k + 1 slots of V (stride) with
-// u = slot k and with w (null: only those with u), per 256-element chunk:
-// part[chunk][i] = V_i . u, part[chunk][m + i] = V_i . w.  One wavefront per
-// basis vector, kDotVecs at a time, as chunk_dots.
-__global__ __launch_bounds__(256) void k_lag_dots(const double *__restrict__ V, size_t stride,
-                                                  int m, const double *__restrict__ w,
-                                                  size_t len, double *__restrict__ part) {
+// Pass A: partial dot products of the m - 1 basis vectors Q (V, stride) and
+// of the candidate u with u and with w (null: only those with u), per
+// 256-element chunk: part[chunk][i] = V_i . u, part[chunk][m + i] = V_i . w
+// (i < m - 1), part[chunk][m - 1] = u . u, part[chunk][2 m - 1] = u . w.
+// One wavefront per basis vector, kDotVecs at a time, as chunk_dots; the
+// products of u come from the chunk staged in LDS.
+template <typename B>
+__global__ __launch_bounds__(256) void k_lag_dots(const B *__restrict__ V, size_t stride, int m,
+                                                  const double *__restrict__ u,
+                                                  const double *__restrict__ w, size_t len,
+                                                  double *__restrict__ part) {
   constexpr int E = kDotChunk / 64;
   __shared__ double us[kDotChunk], zs[kDotChunk];
   const size_t base = (size_t)blockIdx.x * kDotChunk;
   const int cn = (int)min((size_t)kDotChunk, len - base);
-  const double *u = V + (size_t)(m - 1) * stride;
   for (int e = threadIdx.x; e < kDotChunk; e += 256) {
     us[e] = e < cn ? u[base + e] : 0.0;
     zs[e] = (w && e < cn) ? w[base + e] : 0.0;
@@ -803,19 +815,34 @@ __global__ __launch_bounds__(256) void k_lag_dots(const double *__restrict__ V, 
     zw[t] = zs[lane + 64 * t];
   }
   double *pc = part + (size_t)blockIdx.x * 2 * m;
-  for (int i0 = wave; i0 < m; i0 += 4 * kDotVecs) {
+  if (wave == 0) {
+    double su = 0.0, sz = 0.0;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      su += uw[t] * uw[t];
+      sz += uw[t] * zw[t];
+    }
+    su = wave_sum(su);
+    sz = wave_sum(sz);
+    if (lane == 0) {
+      pc[m - 1] = su;
+      pc[2 * m - 1] = sz;
+    }
+  }
+  const int nq = m - 1;
+  for (int i0 = wave; i0 < nq; i0 += 4 * kDotVecs) {
     double su[kDotVecs], sz[kDotVecs];
 #pragma unroll
     for (int q = 0; q < kDotVecs; ++q) su[q] = sz[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < kDotVecs; ++q) {
       const int i = i0 + 4 * q;
-      if (i < m) {
-        const double *v = V + (size_t)i * stride + base;
+      if (i < nq) {
+        const B *v = V + (size_t)i * stride + base;
 #pragma unroll
         for (int t = 0; t < E; ++t) {
           const int e = lane + 64 * t;
-          const double x = v[e < cn ? e : cn - 1];
+          const double x = (double)v[e < cn ? e : cn - 1];
           su[q] += x * uw[t];
           sz[q] += x * zw[t];
         }
@@ -825,7 +852,7 @@ __global__ __launch_bounds__(256) void k_lag_dots(const double *__restrict__ V, 
     for (int q = 0; q < kDotVecs; ++q) {
       const int i = i0 + 4 * q;
       const double ru = wave_sum(su[q]), rz = wave_sum(sz[q]);
-      if (lane == 0 && i < m) {
+      if (lane == 0 && i < nq) {
         pc[i] = ru;
         pc[m + i] = rz;
       }
@@ -901,9 +928,12 @@ __global__ __launch_bounds__(256) void k_lag_coef(GmresDev d, int k) {
   }
 }
 
-// Pass B, per 256-element chunk: q_k = (u - Q a) / nu over slot k (u), w =
+// Pass B, per 256-element chunk: q_k = (u - Q a) / nu into slot k of V, w =
 // w / nu - Q f - g u, and the chunk's partial squared norm of the new w.
-__global__ __launch_bounds__(256) void k_lag_update(double *__restrict__ V, size_t stride, int k,
+// u may be slot k itself (an FP64 basis): each element is read before it is
+// overwritten, by the same thread.
+template <typename B>
+__global__ __launch_bounds__(256) void k_lag_update(B *V, size_t stride, int k, const double *u,
                                                     double *__restrict__ w, size_t len,
                                                     GmresDev d, double *__restrict__ part) {
   __shared__ double sh[4];
@@ -911,28 +941,27 @@ __global__ __launch_bounds__(256) void k_lag_update(double *__restrict__ V, size
   double zn = 0.0;
   if (e < len) {
     const double *a = d.dA, *f = d.cf;
-    const double *v = V + e;
+    const B *v = V + e;
     double ta[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int i = 0;
     for (; i + 8 <= k; i += 8)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const double x = v[(size_t)(i + q) * stride];
+        const double x = (double)v[(size_t)(i + q) * stride];
         ta[q] += x * a[i + q];
         tf[q] += x * f[i + q];
       }
     for (; i < k; ++i) {
-      const double x = v[(size_t)i * stride];
+      const double x = (double)v[(size_t)i * stride];
       ta[0] += x * a[i];
       tf[0] += x * f[i];
     }
     const double sa = ((ta[0] + ta[1]) + (ta[2] + ta[3])) + ((ta[4] + ta[5]) + (ta[6] + ta[7]));
     const double sf = ((tf[0] + tf[1]) + (tf[2] + tf[3])) + ((tf[4] + tf[5]) + (tf[6] + tf[7]));
     const double inv = d.sc[0], g = d.sc[1];
-    double *uk = V + (size_t)k * stride + e;
-    const double u = *uk;
-    *uk = (u - sa) * inv;
-    zn = w[e] * inv - sf - g * u;
+    const double ue = u[e];
+    V[(size_t)k * stride + e] = (B)((ue - sa) * inv);
+    zn = w[e] * inv - sf - g * ue;
     w[e] = zn;
   }
   const double s = block_sum(zn * zn, sh);
@@ -977,13 +1006,19 @@ __global__ __launch_bounds__(256) void k_multidot_reduce(const double *__restric
   if (threadIdx.x == 0) out[i] = take_sqrt ? sqrt(s) : s;
 }
 
-__global__ void k_mgs_update(double *__restrict__ w, const double *__restrict__ V, size_t stride,
+template <typename B>
+__global__ void k_mgs_update(double *__restrict__ w, const B *__restrict__ V, size_t stride,
                              int nvec, const double *__restrict__ h, double sign, size_t len) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= len) return;
   double s = 0.0;
-  for (int i = 0; i < nvec; ++i) s += V[(size_t)i * stride + e] * h[i];
+  for (int i = 0; i < nvec; ++i) s += (double)V[(size_t)i * stride + e] * h[i];
   w[e] += sign * s;
+}
+
+__global__ void k_to_float(float *__restrict__ dst, const double *__restrict__ src, size_t len) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) dst[e] = (float)src[e];
 }
 
 __global__ void k_scale_by_inv(double *__restrict__ dst, const double *__restrict__ src,
@@ -1169,42 +1204,60 @@ void launch_fill(double *y, double v, size_t len, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(len)), dim3(256), 0, s, y, v, len);
 }
 
-void launch_mgs_update(double *w, const double *V, size_t stride, int nvec, const double *h,
+template <typename B>
+void launch_mgs_update(double *w, const B *V, size_t stride, int nvec, const double *h,
                        double sign, size_t len, hipStream_t s) {
-  hipLaunchKernelGGL(k_mgs_update, dim3(nblk(len)), dim3(256), 0, s, w, V, stride, nvec, h,
+  hipLaunchKernelGGL(k_mgs_update<B>, dim3(nblk(len)), dim3(256), 0, s, w, V, stride, nvec, h,
                      sign, len);
 }
+template void launch_mgs_update<double>(double *, const double *, size_t, int, const double *,
+                                        double, size_t, hipStream_t);
+template void launch_mgs_update<float>(double *, const float *, size_t, int, const double *,
+                                       double, size_t, hipStream_t);
 
-void launch_arnoldi_step(const double *V, size_t stride, int k, double *w, size_t len,
-                         double *hd, double *vnext, double *part, GmresDev gd, double beta,
+void launch_to_float(float *dst, const double *src, size_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_float, dim3(nblk(len)), dim3(256), 0, s, dst, src, len);
+}
+
+template <typename B>
+void launch_arnoldi_step(const B *V, size_t stride, int k, double *w, size_t len, double *hd,
+                         double *vnext, float *vslot, double *part, GmresDev gd, double beta,
                          hipStream_t s) {
   const int nvec = k + 1;
   const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
   static_assert(kDotChunk == 256, "one element per thread in the fused update");
   // pass 1: h1 = V^T w
-  hipLaunchKernelGGL(k_multidot_part, dim3(nchunk), dim3(256), 0, s, V, stride, nvec,
+  hipLaunchKernelGGL(k_multidot_part<B>, dim3(nchunk), dim3(256), 0, s, V, stride, nvec,
                      (const double *)w, len, part);
   hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(256), 0, s, (const double *)part,
                      nchunk, nvec, hd, 0);
   // w -= V h1, then pass 2 partials
-  hipLaunchKernelGGL(k_mgs_update_dots, dim3(nchunk), dim3(256), 0, s, w, V, stride, nvec,
+  hipLaunchKernelGGL(k_mgs_update_dots<B>, dim3(nchunk), dim3(256), 0, s, w, V, stride, nvec,
                      (const double *)hd, -1.0, len, V, nvec, part);
   hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(256), 0, s, (const double *)part,
                      nchunk, nvec, hd + nvec, 0);
   // w -= V h2, then partial squared norms; v_next = w / |w| and the rotations
-  hipLaunchKernelGGL(k_mgs_update_dots, dim3(nchunk), dim3(256), 0, s, w, V, stride, nvec,
-                     (const double *)(hd + nvec), -1.0, len, (const double *)nullptr, 1, part);
+  hipLaunchKernelGGL(k_mgs_update_dots<B>, dim3(nchunk), dim3(256), 0, s, w, V, stride, nvec,
+                     (const double *)(hd + nvec), -1.0, len, (const B *)nullptr, 1, part);
   hipLaunchKernelGGL(k_norm_scale_givens, dim3(nblk(len)), dim3(256), 0, s,
-                     (const double *)part, nchunk, hd, (const double *)w, vnext, len, gd, k, beta);
+                     (const double *)part, nchunk, hd, (const double *)w, vnext, vslot, len, gd,
+                     k, beta);
 }
+template void launch_arnoldi_step<double>(const double *, size_t, int, double *, size_t,
+                                          double *, double *, float *, double *, GmresDev,
+                                          double, hipStream_t);
+template void launch_arnoldi_step<float>(const float *, size_t, int, double *, size_t, double *,
+                                         double *, float *, double *, GmresDev, double,
+                                         hipStream_t);
 
-void launch_arnoldi_lagged(double *V, size_t stride, int k, double *w, size_t len,
-                           double *part, GmresDev gd, double beta, int col_final,
-                           int finalize_only, hipStream_t s) {
+template <typename B>
+void launch_arnoldi_lagged(B *V, size_t stride, int k, const double *u, double *w,
+                           double *unext, size_t len, double *part, GmresDev gd, double beta,
+                           int col_final, int finalize_only, hipStream_t s) {
   const int m = k + 1;
   const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
   static_assert(kDotChunk == 256, "one element per thread in pass B");
-  hipLaunchKernelGGL(k_lag_dots, dim3(nchunk), dim3(256), 0, s, (const double *)V, stride, m,
+  hipLaunchKernelGGL(k_lag_dots<B>, dim3(nchunk), dim3(256), 0, s, (const B *)V, stride, m, u,
                      finalize_only ? (const double *)nullptr : (const double *)w, len, part);
   hipLaunchKernelGGL(k_multidot_reduce, dim3(2 * m), dim3(256), 0, s, (const double *)part,
                      nchunk, 2 * m, gd.dA, 0);
@@ -1216,15 +1269,22 @@ void launch_arnoldi_lagged(double *V, size_t stride, int k, double *w, size_t le
     return;
   }
   hipLaunchKernelGGL(k_lag_coef, dim3(1), dim3(256), 0, s, gd, k);
-  hipLaunchKernelGGL(k_lag_update, dim3(nchunk), dim3(256), 0, s, V, stride, k, w, len, gd, part);
+  hipLaunchKernelGGL(k_lag_update<B>, dim3(nchunk), dim3(256), 0, s, V, stride, k, u, w, len, gd,
+                     part);
   hipLaunchKernelGGL(k_lag_norm_scale, dim3(nblk(len)), dim3(256), 0, s, (const double *)part,
-                     nchunk, (const double *)w, V + (size_t)m * stride, len, gd, gcol, beta);
+                     nchunk, (const double *)w, unext, len, gd, gcol, beta);
 }
+template void launch_arnoldi_lagged<double>(double *, size_t, int, const double *, double *,
+                                            double *, size_t, double *, GmresDev, double, int,
+                                            int, hipStream_t);
+template void launch_arnoldi_lagged<float>(float *, size_t, int, const double *, double *,
+                                           double *, size_t, double *, GmresDev, double, int,
+                                           int, hipStream_t);
 
 void launch_norm(const double *w, size_t len, double *out, double *part, hipStream_t s) {
   const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
-  hipLaunchKernelGGL(k_multidot_part, dim3(nchunk), dim3(256), 0, s, (const double *)nullptr,
-                     (size_t)0, 1, w, len, part);
+  hipLaunchKernelGGL(k_multidot_part<double>, dim3(nchunk), dim3(256), 0, s,
+                     (const double *)nullptr, (size_t)0, 1, w, len, part);
   hipLaunchKernelGGL(k_multidot_reduce, dim3(1), dim3(256), 0, s, part, nchunk, 1, out, 1);
 }
 
@@ -1246,12 +1306,16 @@ __global__ __launch_bounds__(256) void k_gmres_backsub(GmresDev d, int k) {
 }  // namespace
 
 
-void launch_gmres_solution(GmresDev d, int k, double *x, const double *V, size_t len,
-                           hipStream_t s) {
+template <typename B>
+void launch_gmres_solution(GmresDev d, int k, double *x, const B *V, size_t len, hipStream_t s) {
   if (k <= 0) return;
   hipLaunchKernelGGL(k_gmres_backsub, dim3(1), dim3(256), 0, s, d, k);
-  launch_mgs_update(x, V, len, k, d.y, 1.0, len, s);
+  launch_mgs_update<B>(x, V, len, k, d.y, 1.0, len, s);
 }
+template void launch_gmres_solution<double>(GmresDev, int, double *, const double *, size_t,
+                                            hipStream_t);
+template void launch_gmres_solution<float>(GmresDev, int, double *, const float *, size_t,
+                                           hipStream_t);
 
 void launch_scale_by_inv(double *dst, const double *src, const double *nrm, size_t len,
                          hipStream_t s) {
