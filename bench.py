@@ -416,9 +416,13 @@ def large_leg(dd, torch, name):
     """One end-to-end run of a large workload by two routes: the dense
     transfer blocks compressed as HODLR (the workload's definition), and the
     sampled construction without dense blocks compressed as HBS (the paper's
-    Algorithm 1).  FP32 build, BF16 factors, FP64 refinement to a predicted
-    relative error of 1e-9; times from the host clock around the calls (inputs
-    resident in HBM), the library's own phase times beside them."""
+    Algorithm 1).  FP32 build, FP64 refinement to a predicted relative error
+    of 1e-9; times from the host clock around the calls (inputs resident in
+    HBM), the library's own phase times beside them.  Compressed factors in
+    FP32 for the 2D oscillatory workload, whose near-resonant conditioning
+    turns the BF16 factors' rounding into 5 (HODLR) and 7 (HBS) refinement
+    passes against 4 with FP32 factors (twice the compressed bytes, a few
+    hundred MiB); BF16 for the 3D workload (3 to 4 passes either way)."""
     from problems import make_config
     p = make_config(name)
     t = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device="cuda")
@@ -439,6 +443,8 @@ def large_leg(dd, torch, name):
     out = {"workload": f"{p.dim}D {name} {p.n}^{p.dim}, {p.n_slabs} slabs, M={p.M}, N_ds={p.n_ds}",
            "N": p.N, "s_build_nominal_flops": F_build}
     opts = dd.SolveOptions(tol=1e-9, max_iter=3000, max_outer=12)
+    fdt = "fp32" if p.dim == 2 else "bf16"
+    out["factor_dtype"] = fdt
     for route in ("dense_hodlr", "sampled_hbs"):
         print(f"[bench] {name} route {route}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -451,11 +457,11 @@ def large_leg(dd, torch, name):
         if route == "dense_hodlr":
             flops[route] = inv + chain
             info = op.compress(tol=1e-8 if p.dim == 2 else 1e-7, leaf=128, oversample=10,
-                               max_rank=118, factor_dtype="bf16")
+                               max_rank=118, factor_dtype=fdt)
             o = dataclasses_replace(opts, use_hodlr=True)
         else:
             k = 32 if p.dim == 2 else 64
-            info = op.compress_hbs(rank=k, oversample=10, factor_dtype="bf16", seed=11)
+            info = op.compress_hbs(rank=k, oversample=10, factor_dtype=fdt, seed=11)
             o = dataclasses_replace(opts, use_hbs=True)
             smp = (4 * (p.n_slabs - 2) * steps + 2 * (p.n_ds - 1) + p.n_ds) * 2.0 * p.M ** 2 * (
                 3 * k + 10)

@@ -147,13 +147,23 @@ struct BlockGemmJob {
   const double *W;    // Omega (shared) or this block's Q
 };
 
-template <typename T>
+// Work-group tile: TM rows of op(B) x SC columns (SC >= s), k in steps of
+// GK; thread (tr, tc) accumulates rows 4 tr .. 4 tr + 3 and columns
+// 8 tc .. 8 tc + 7 (32 FP64 sums), reading four op(B) and eight W values
+// from LDS per k (16-byte reads).  Global reads are contiguous along S's
+// rows (trans 0: along k; trans 1: along the output rows) and along W's
+// contiguous index; a tile is staged through registers while the previous
+// one is multiplied.
+template <typename T, int SC>
 __global__ __launch_bounds__(256) void k_block_gemm(const BlockGemmJob *__restrict__ jobs,
                                                     const int *__restrict__ perm, int ld, int s,
                                                     int trans) {
-  constexpr int TM = 64, TK = 32;
-  __shared__ double Bs[TK][TM + 1];   // op(B) tile, k-major
-  __shared__ double Ws[TK][129];      // W tile (k x s <= 128)
+  constexpr int GK = 16;
+  constexpr int NTC = SC / 8, NTR = 256 / NTC, TM = 4 * NTR;
+  constexpr int BP = TM + 2, WP = SC + 2;  // LDS rows (16-byte aligned)
+  constexpr int NB = TM * GK / 256, NW = (GK * SC + 255) / 256;
+  __shared__ __align__(16) double Bs[GK][BP];
+  __shared__ __align__(16) double Ws[GK][WP];
   const BlockGemmJob J = jobs[blockIdx.y];
   const T *S = static_cast<const T *>(J.S);
   const int mrows = trans ? J.n : J.m;  // rows of op(B)
@@ -161,44 +171,107 @@ __global__ __launch_bounds__(256) void k_block_gemm(const BlockGemmJob *__restri
   const int row0 = blockIdx.x * TM;
   if (row0 >= mrows) return;
   const int tid = threadIdx.x;
-  // each thread: rows (tid % 64), columns k = tid/64 + 4*q, q < s/4
-  const int tr = tid & 63, tc = tid >> 6;
-  double acc[32];
+  const int tr = tid % NTR, tc = tid / NTR;
+  double rb[NB], rw[NW];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-  for (int k0 = 0; k0 < kdim; k0 += TK) {
-    __syncthreads();
-    for (int e = tid; e < TK * TM; e += 256) {
-      const int kk = e / TM, ii = e % TM;
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      // trans 0: k fastest (along a row of S); trans 1: the output row fastest
+      const int kk = trans ? e / TM : e % GK, ii = trans ? e % TM : e / GK;
       const int i = row0 + ii, k = k0 + kk;
       double v = 0.0;
       if (i < mrows && k < kdim) {
         const int br = trans ? k : i, bc = trans ? i : k;  // entry B[br][bc]
         int gr = J.r0 + br, gc = J.c0 + bc;
-        if (perm) { gr = perm[gr]; gc = perm[gc]; }
+        if (perm) {
+          gr = perm[gr];
+          gc = perm[gc];
+        }
         v = (double)S[(size_t)gr * ld + gc];
       }
-      Bs[kk][ii] = v;
+      rb[q] = v;
     }
-    for (int e = tid; e < TK * s; e += 256) {
-      const int kk = e / s, q = e % s, k = k0 + kk;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const int e = tid + 256 * q;
       double v = 0.0;
-      if (k < kdim) v = trans ? J.W[(size_t)q * kdim + k] : J.W[(size_t)k * s + q];
-      Ws[kk][q] = v;
+      if (e < GK * SC) {
+        // Omega row-major (n x s): q fastest; Q column-major (kdim x s): k fastest
+        const int kk = trans ? e % GK : e / SC, c = trans ? e / GK : e % SC;
+        const int k = k0 + kk;
+        if (k < kdim && c < s) v = trans ? J.W[(size_t)c * kdim + k] : J.W[(size_t)k * s + c];
+      }
+      rw[q] = v;
+    }
+  };
+  double acc[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[a][c] = 0.0;
+  load(0);
+  for (int k0 = 0; k0 < kdim; k0 += GK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = trans ? e / TM : e % GK, ii = trans ? e % TM : e / GK;
+      Bs[kk][ii] = rb[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const int e = tid + 256 * q;
+      if (e < GK * SC) {
+        const int kk = trans ? e % GK : e / SC, c = trans ? e / GK : e % SC;
+        Ws[kk][c] = rw[q];
+      }
     }
     __syncthreads();
-    for (int kk = 0; kk < TK; ++kk) {
-      const double b = Bs[kk][tr];
+    if (k0 + GK < kdim) load(k0 + GK);
+#pragma unroll 4
+    for (int kk = 0; kk < GK; ++kk) {
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      const d2 b01 = *reinterpret_cast<const d2 *>(&Bs[kk][4 * tr]);
+      const d2 b23 = *reinterpret_cast<const d2 *>(&Bs[kk][4 * tr + 2]);
+      const double bv[4] = {b01[0], b01[1], b23[0], b23[1]};
+      double wv[8];
 #pragma unroll
-      for (int q = 0; q < 32; ++q)
-        if (tc + 4 * q < s) acc[q] += b * Ws[kk][tc + 4 * q];
+      for (int c = 0; c < 4; ++c) {
+        const d2 w2 = *reinterpret_cast<const d2 *>(&Ws[kk][8 * tc + 2 * c]);
+        wv[2 * c] = w2[0];
+        wv[2 * c + 1] = w2[1];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[a][c] += bv[a] * wv[c];
     }
   }
-  const int i = row0 + tr;
-  if (i < mrows)
 #pragma unroll
-    for (int q = 0; q < 32; ++q)
-      if (tc + 4 * q < s) J.C[(size_t)(tc + 4 * q) * mrows + i] = acc[q];
+  for (int c = 0; c < 8; ++c) {
+    const int q = 8 * tc + c;
+    if (q >= s) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = row0 + 4 * tr + a;
+      if (i < mrows) J.C[(size_t)q * mrows + i] = acc[a][c];
+    }
+  }
+}
+template <typename T>
+void launch_block_gemm(const BlockGemmJob *jobs, int nbk, int rows_max, const int *perm, int ld,
+                       int s, int trans, hipStream_t st) {
+  // tile widths 32, 64, 128 columns: 256, 128, 64 rows
+  if (s <= 32)
+    hipLaunchKernelGGL((k_block_gemm<T, 32>), dim3((rows_max + 255) / 256, nbk), dim3(256), 0, st,
+                       jobs, perm, ld, s, trans);
+  else if (s <= 64)
+    hipLaunchKernelGGL((k_block_gemm<T, 64>), dim3((rows_max + 127) / 128, nbk), dim3(256), 0, st,
+                       jobs, perm, ld, s, trans);
+  else
+    hipLaunchKernelGGL((k_block_gemm<T, 128>), dim3((rows_max + 63) / 64, nbk), dim3(256), 0, st,
+                       jobs, perm, ld, s, trans);
 }
 
 // --------------------------------------------------- Householder QR + form Q
@@ -228,9 +301,15 @@ __device__ __forceinline__ double qr_wave_sum(double v) {
   return v;  // lane 0 holds the sum
 }
 
-__global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__ jobs, int s) {
+// kQrThreads threads (16 wavefronts) per block: the elimination streams the
+// trailing columns once per column, so it runs at the latency-bound
+// bandwidth of one CU; more wavefronts keep more loads in flight.
+constexpr int kQrThreads = 1024;
+constexpr int kQrWaves = kQrThreads / 64;
+__global__ __launch_bounds__(kQrThreads) void k_householder_q(const QrJob *__restrict__ jobs,
+                                                              int s) {
   __shared__ double tau[128];
-  __shared__ double sh[8];
+  __shared__ double sh[kQrWaves];
   __shared__ double dots[128];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const QrJob J = jobs[blockIdx.x];
@@ -240,7 +319,7 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
   for (int j = 0; j < kmax; ++j) {
     double *a = A + (size_t)j * m;
     double part = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < m; i += 256) part += a[i] * a[i];
+    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) part += a[i] * a[i];
     const double sig = block_reduce_sum(part, sh);
     const double x0 = a[j];
     double beta, t, scale;
@@ -256,7 +335,7 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
       scale = 1.0 / v0;
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < m; i += 256) a[i] *= scale;  // v (v_0 = 1)
+    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) a[i] *= scale;  // v (v_0 = 1)
     if (threadIdx.x == 0) {
       a[j] = beta;
       tau[j] = t;
@@ -264,7 +343,7 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
     __syncthreads();
     // apply H_j = I - t v v^T to the remaining columns: one wavefront per
     // column for the dot products (no work-group barrier per column)
-    for (int c = j + 1 + wave; c < s; c += 4) {
+    for (int c = j + 1 + wave; c < s; c += kQrWaves) {
       const double *ac = A + (size_t)c * m;
       double p2 = 0.0;
       for (int i = j + 1 + lane; i < m; i += 64) p2 += a[i] * ac[i];
@@ -275,13 +354,13 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
     for (int c = j + 1; c < s; ++c) {
       double *ac = A + (size_t)c * m;
       const double w = t * dots[c];
-      for (int i = j + 1 + threadIdx.x; i < m; i += 256) ac[i] -= w * a[i];
+      for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) ac[i] -= w * a[i];
       if (threadIdx.x == 0) ac[j] -= w;
     }
     __syncthreads();
   }
   if (J.R) {  // R: the upper triangle left by the elimination
-    for (int e = threadIdx.x; e < s * s; e += 256) {
+    for (int e = threadIdx.x; e < s * s; e += kQrThreads) {
       const int i = e % s, c = e / s;
       J.R[e] = (i <= c && i < kmax) ? A[(size_t)c * m + i] : 0.0;
     }
@@ -292,7 +371,7 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
     const double t = tau[j];
     double *a = A + (size_t)j * m;
     // columns c > j currently hold Q's columns (rows >= j+1 meaningful, rows <= j set)
-    for (int c = j + 1 + wave; c < s; c += 4) {
+    for (int c = j + 1 + wave; c < s; c += kQrWaves) {
       const double *ac = A + (size_t)c * m;
       double p2 = 0.0;
       for (int i = j + 1 + lane; i < m; i += 64) p2 += a[i] * ac[i];
@@ -303,19 +382,19 @@ __global__ __launch_bounds__(256) void k_householder_q(const QrJob *__restrict__
     for (int c = j + 1; c < s; ++c) {
       double *ac = A + (size_t)c * m;
       const double w = t * dots[c];
-      for (int i = j + 1 + threadIdx.x; i < m; i += 256) ac[i] -= w * a[i];
+      for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) ac[i] -= w * a[i];
       if (threadIdx.x == 0) ac[j] = -w;
     }
     __syncthreads();
     // column j: H_j e_j = e_j - t v
-    for (int i = j + 1 + threadIdx.x; i < m; i += 256) a[i] = -t * a[i];
+    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) a[i] = -t * a[i];
     if (threadIdx.x == 0) a[j] = 1.0 - t;
-    for (int i = threadIdx.x; i < j; i += 256) a[i] = 0.0;
+    for (int i = threadIdx.x; i < j; i += kQrThreads) a[i] = 0.0;
     __syncthreads();
   }
   // columns beyond min(s, m) (only when m < s): zero
   for (int c = kmax; c < s; ++c)
-    for (int i = threadIdx.x; i < m; i += 256) A[(size_t)c * m + i] = 0.0;
+    for (int i = threadIdx.x; i < m; i += kQrThreads) A[(size_t)c * m + i] = 0.0;
 }
 
 // -------------------------------------------------- one-sided Jacobi SVD
@@ -1010,12 +1089,10 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       const JacJob *djac = static_cast<const JacJob *>(upload(jac, st, keep));
       const QrJob *dqx = static_cast<const QrJob *>(upload(qx, st, keep));
       const DenseGemmJob *drot = static_cast<const DenseGemmJob *>(upload(rot, st, keep));
-      hipLaunchKernelGGL(k_block_gemm<T>, dim3((mmax + 63) / 64, nbk), dim3(256), 0, st, dgy,
-                         d_perm, op->ld, s, 0);
-      hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(256), 0, st, dqr, s);
-      hipLaunchKernelGGL(k_block_gemm<T>, dim3((nmax + 63) / 64, nbk), dim3(256), 0, st, dgx,
-                         d_perm, op->ld, s, 1);
-      hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(256), 0, st, dqx, s);
+      launch_block_gemm<T>(dgy, nbk, mmax, d_perm, op->ld, s, 0, st);
+      hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(kQrThreads), 0, st, dqr, s);
+      launch_block_gemm<T>(dgx, nbk, nmax, d_perm, op->ld, s, 1, st);
+      hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(kQrThreads), 0, st, dqx, s);
       double *dsig = static_cast<double *>(D.sig->p);
       if (s <= 32)
         hipLaunchKernelGGL(k_jacobi<32>, dim3(nbk), dim3(256), 0, st, djac, s, 30, dsig);
