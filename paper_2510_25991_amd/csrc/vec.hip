@@ -789,38 +789,35 @@ __global__ __launch_bounds__(256) void k_norm_scale_givens(const double *__restr
 
 // Pass A: partial dot products of the m - 1 basis vectors Q (V, stride) and
 // of the candidate u with u and with w (null: only those with u), per
-// 256-element chunk: part[chunk][i] = V_i . u, part[chunk][m + i] = V_i . w
-// (i < m - 1), part[chunk][m - 1] = u . u, part[chunk][2 m - 1] = u . w.
-// One wavefront per basis vector, kDotVecs at a time, as chunk_dots; the
-// products of u come from the chunk staged in LDS.
+// kLagChunk-element chunk: part[chunk][i] = V_i . u, part[chunk][m + i] =
+// V_i . w (i < m - 1), part[chunk][m - 1] = u . u, part[chunk][2 m - 1] =
+// u . w.  Work-group (chunk, g) takes the chunk of u and w (in LDS) and the
+// kLagGroup basis vectors g kLagGroup ..: each wavefront 8 of them, four at
+// a time with their loads issued together, 32 entries per lane and vector
+// before one reduction per product; group 0 also forms the products of u.
+constexpr int kLagChunk = 2048, kLagGroup = 32;
 template <typename B>
 __global__ __launch_bounds__(256) void k_lag_dots(const B *__restrict__ V, size_t stride, int m,
                                                   const double *__restrict__ u,
                                                   const double *__restrict__ w, size_t len,
                                                   double *__restrict__ part) {
-  constexpr int E = kDotChunk / 64;
-  __shared__ double us[kDotChunk], zs[kDotChunk];
-  const size_t base = (size_t)blockIdx.x * kDotChunk;
-  const int cn = (int)min((size_t)kDotChunk, len - base);
-  for (int e = threadIdx.x; e < kDotChunk; e += 256) {
+  constexpr int E = kLagChunk / 64;  // entries per lane and vector
+  __shared__ double us[kLagChunk], zs[kLagChunk];
+  const size_t base = (size_t)blockIdx.x * kLagChunk;
+  const int cn = (int)min((size_t)kLagChunk, len - base);
+  for (int e = threadIdx.x; e < kLagChunk; e += 256) {
     us[e] = e < cn ? u[base + e] : 0.0;
     zs[e] = (w && e < cn) ? w[base + e] : 0.0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double uw[E], zw[E];
-#pragma unroll
-  for (int t = 0; t < E; ++t) {
-    uw[t] = us[lane + 64 * t];
-    zw[t] = zs[lane + 64 * t];
-  }
   double *pc = part + (size_t)blockIdx.x * 2 * m;
-  if (wave == 0) {
+  if (blockIdx.y == 0 && wave == 0) {
     double su = 0.0, sz = 0.0;
-#pragma unroll
     for (int t = 0; t < E; ++t) {
-      su += uw[t] * uw[t];
-      sz += uw[t] * zw[t];
+      const double x = us[lane + 64 * t];
+      su += x * x;
+      sz += x * zs[lane + 64 * t];
     }
     su = wave_sum(su);
     sz = wave_sum(sz);
@@ -830,27 +827,34 @@ __global__ __launch_bounds__(256) void k_lag_dots(const B *__restrict__ V, size_
     }
   }
   const int nq = m - 1;
-  for (int i0 = wave; i0 < nq; i0 += 4 * kDotVecs) {
-    double su[kDotVecs], sz[kDotVecs];
+  const int i0 = blockIdx.y * kLagGroup + wave;
+#pragma unroll 1
+  for (int h = 0; h < kLagGroup / 4; h += 4) {
+    // vectors i0 + 4 (h + q), q < 4
+    double su[4] = {0.0, 0.0, 0.0, 0.0}, sz[4] = {0.0, 0.0, 0.0, 0.0};
+    const B *v[4];
 #pragma unroll
-    for (int q = 0; q < kDotVecs; ++q) su[q] = sz[q] = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int i = min(i0 + 4 * (h + q), max(nq - 1, 0));
+      v[q] = V + (size_t)i * stride + base;
+    }
+    if (i0 + 4 * h < nq) {
+#pragma unroll 4
+      for (int t = 0; t < E; ++t) {
+        const int e = lane + 64 * t;
+        const int el = e < cn ? e : cn - 1;
+        const double a = us[e], c = zs[e];
 #pragma unroll
-    for (int q = 0; q < kDotVecs; ++q) {
-      const int i = i0 + 4 * q;
-      if (i < nq) {
-        const B *v = V + (size_t)i * stride + base;
-#pragma unroll
-        for (int t = 0; t < E; ++t) {
-          const int e = lane + 64 * t;
-          const double x = (double)v[e < cn ? e : cn - 1];
-          su[q] += x * uw[t];
-          sz[q] += x * zw[t];
+        for (int q = 0; q < 4; ++q) {
+          const double x = (double)v[q][el];
+          su[q] += x * a;
+          sz[q] += x * c;
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < kDotVecs; ++q) {
-      const int i = i0 + 4 * q;
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + 4 * (h + q);
       const double ru = wave_sum(su[q]), rz = wave_sum(sz[q]);
       if (lane == 0 && i < nq) {
         pc[i] = ru;
@@ -1257,10 +1261,12 @@ void launch_arnoldi_lagged(B *V, size_t stride, int k, const double *u, double *
   const int m = k + 1;
   const int nchunk = (int)((len + kDotChunk - 1) / kDotChunk);
   static_assert(kDotChunk == 256, "one element per thread in pass B");
-  hipLaunchKernelGGL(k_lag_dots<B>, dim3(nchunk), dim3(256), 0, s, (const B *)V, stride, m, u,
-                     finalize_only ? (const double *)nullptr : (const double *)w, len, part);
+  const int nlchunk = (int)((len + kLagChunk - 1) / kLagChunk);
+  const int ngroup = std::max((m - 1 + kLagGroup - 1) / kLagGroup, 1);
+  hipLaunchKernelGGL(k_lag_dots<B>, dim3(nlchunk, ngroup), dim3(256), 0, s, (const B *)V, stride,
+                     m, u, finalize_only ? (const double *)nullptr : (const double *)w, len, part);
   hipLaunchKernelGGL(k_multidot_reduce, dim3(2 * m), dim3(256), 0, s, (const double *)part,
-                     nchunk, 2 * m, gd.dA, 0);
+                     nlchunk, 2 * m, gd.dA, 0);
   hipLaunchKernelGGL(k_lag_hmul, dim3((m + 3) / 4), dim3(256), 0, s, gd, k, col_final);
   const int gcol = (k >= 1 && !col_final) ? k - 1 : -1;
   if (finalize_only) {
