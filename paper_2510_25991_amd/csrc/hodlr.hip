@@ -148,7 +148,7 @@ struct BlockGemmJob {
 };
 
 // Work-group tile: TM rows of op(B) x SC columns (SC >= s), k in steps of
-// GK; thread (tr, tc) accumulates rows 4 tr .. 4 tr + 3 and columns
+// GK (8 or 16); thread (tr, tc) accumulates rows 4 tr .. 4 tr + 3 and columns
 // 8 tc .. 8 tc + 7 (32 FP64 sums), reading four op(B) and eight W values
 // from LDS per k (16-byte reads).  Global reads are contiguous along S's
 // rows (trans 0: along k; trans 1: along the output rows) and along W's
@@ -158,7 +158,7 @@ template <typename T, int SC>
 __global__ __launch_bounds__(256) void k_block_gemm(const BlockGemmJob *__restrict__ jobs,
                                                     const int *__restrict__ perm, int ld, int s,
                                                     int trans) {
-  constexpr int GK = 16;
+  constexpr int GK = SC == 32 ? 8 : 16;  // the 256-row tile: 8 staged values per thread
   constexpr int NTC = SC / 8, NTR = 256 / NTC, TM = 4 * NTR;
   constexpr int BP = TM + 2, WP = SC + 2;  // LDS rows (16-byte aligned)
   constexpr int NB = TM * GK / 256, NW = (GK * SC + 255) / 256;
@@ -293,6 +293,7 @@ struct QrJob {
   double *A;  // m x s column-major
   int m;
   double *R;  // optional: receives R (s x s, column-major, zero below the diagonal)
+  double *Qs; // m x s scratch (Q is formed here, then copied over A)
 };
 
 __device__ __forceinline__ double qr_wave_sum(double v) {
@@ -301,63 +302,194 @@ __device__ __forceinline__ double qr_wave_sum(double v) {
   return v;  // lane 0 holds the sum
 }
 
-// kQrThreads threads (16 wavefronts) per block: the elimination streams the
-// trailing columns once per column, so it runs at the latency-bound
-// bandwidth of one CU; more wavefronts keep more loads in flight.
+// Blocked Householder QR, one work-group of kQrThreads per block.  Panels of
+// kQb columns are factored column by column (each reflector applied to the
+// panel's later columns only); the panel's reflectors H_j = I - tau_j v_j
+// v_j^T (v_j: 1 at row j, stored below the diagonal of A) then act on the
+// trailing columns together as H_{j0+b-1} ... H_{j0} = I - V T^T V^T (compact
+// WY form: V the panel's reflectors, T upper triangular from their Gram
+// matrix and tau), in two passes over the trailing columns: d_c = V^T a_c
+// (a wavefront per trailing column group, each lane holding the panel's
+// entries of one row of a 64-row chunk), then a_c -= V (T^T d_c) (a thread
+// per row, its kQb reflector entries in registers).  The trailing columns are
+// streamed twice per panel instead of three times per column.  Q = H_0 ...
+// H_{k-1} [I; 0] is formed the same way in Qs, panels in reverse order
+// (I - V T V^T on the columns from the panel's first on), and copied over A.
 constexpr int kQrThreads = 1024;
 constexpr int kQrWaves = kQrThreads / 64;
+constexpr int kQb = 8;
+constexpr int kQrMaxS = 128;
+static_assert(kQrMaxS % kQb == 0, "whole panels");
+
+// v_j's entry in row i (j < m): 1 on the diagonal, A below it, 0 above
+__device__ __forceinline__ double qr_vent(const double *A, int m, int j, int i) {
+  return i > j ? A[(size_t)j * m + i] : (i == j ? 1.0 : 0.0);
+}
+
+// X[:, c] -= V_p (M d_c) for the columns c0 <= c < s of X (m x s, rows >=
+// j0 only; V_p: the reflectors j0 .. j0 + jb - 1 stored in A), with d_c =
+// V_p^T X[:, c] and M = T^T (apply H_{j0+jb-1} ... H_{j0}) or T (apply
+// H_{j0} ... H_{j0+jb-1}).  All threads of the work-group; ends with a
+// barrier.  dl: kQb x kQrMaxS doubles of LDS.
+template <bool TRANS>
+__device__ void qr_apply_panel(const double *A, double *X, int m, int s, int j0, int jb, int c0,
+                               const double (*T)[kQb], double (*dl)[kQrMaxS]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nc = s - c0;
+  // pass 1: wavefront w takes the columns c0 + w, c0 + w + kQrWaves, ...,
+  // four at a time (register budget of 1024-thread work-groups)
+  constexpr int CPW = kQrMaxS / kQrWaves;  // columns per wavefront, at most
+  constexpr int CH = 4;
+  for (int u0 = 0; u0 < CPW; u0 += CH) {
+    if (c0 + wave + kQrWaves * u0 >= s) break;  // wave-uniform
+    double t[CH][kQb];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+#pragma unroll
+      for (int p = 0; p < kQb; ++p) t[u][p] = 0.0;
+    for (int i0 = j0; i0 < m; i0 += 64) {
+      const int i = i0 + lane;
+      double v[kQb];
+#pragma unroll
+      for (int p = 0; p < kQb; ++p) v[p] = (p < jb && i < m) ? qr_vent(A, m, j0 + p, i) : 0.0;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int c = c0 + wave + kQrWaves * (u0 + u);
+        if (c < s) {
+          const double x = i < m ? X[(size_t)c * m + i] : 0.0;
+#pragma unroll
+          for (int p = 0; p < kQb; ++p) t[u][p] += v[p] * x;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int c = c0 + wave + kQrWaves * (u0 + u);
+#pragma unroll
+      for (int p = 0; p < kQb; ++p) {
+        const double r = qr_wave_sum(t[u][p]);
+        if (lane == 0 && c < s && p < jb) dl[p][c] = r;
+      }
+    }
+  }
+  __syncthreads();
+  // w_c = M d_c, in place (a thread per column)
+  for (int c = c0 + threadIdx.x; c < s; c += kQrThreads) {
+    double w[kQb];
+#pragma unroll
+    for (int q = 0; q < kQb; ++q) {
+      double acc = 0.0;
+      if (q < jb)
+        for (int p = 0; p < jb; ++p) acc += (TRANS ? T[p][q] : T[q][p]) * dl[p][c];
+      w[q] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < kQb; ++q)
+      if (q < jb) dl[q][c] = w[q];
+  }
+  __syncthreads();
+  // pass 2: X[i][c] -= sum_p v_p[i] w_c[p], a thread per row
+  if (nc > 0)
+    for (int i = j0 + threadIdx.x; i < m; i += kQrThreads) {
+      double v[kQb];
+#pragma unroll
+      for (int p = 0; p < kQb; ++p) v[p] = p < jb ? qr_vent(A, m, j0 + p, i) : 0.0;
+      for (int c = c0; c < s; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int p = 0; p < kQb; ++p) acc += v[p] * dl[p][c];
+        X[(size_t)c * m + i] -= acc;
+      }
+    }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kQrThreads) void k_householder_q(const QrJob *__restrict__ jobs,
                                                               int s) {
-  __shared__ double tau[128];
+  __shared__ double tau[kQrMaxS];
   __shared__ double sh[kQrWaves];
-  __shared__ double dots[128];
+  __shared__ double dots[kQrMaxS];
+  __shared__ double G[kQb][kQb];
+  __shared__ double Tm[kQrMaxS / kQb][kQb][kQb];  // T of every panel
+  __shared__ double dl[kQb][kQrMaxS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const QrJob J = jobs[blockIdx.x];
   double *A = J.A;
   const int m = J.m;
   const int kmax = min(s, m);
-  for (int j = 0; j < kmax; ++j) {
-    double *a = A + (size_t)j * m;
-    double part = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) part += a[i] * a[i];
-    const double sig = block_reduce_sum(part, sh);
-    const double x0 = a[j];
-    double beta, t, scale;
-    if (sig == 0.0) {
-      t = 0.0;
-      beta = x0;
-      scale = 0.0;
-    } else {
-      const double mu = sqrt(x0 * x0 + sig);
-      beta = (x0 <= 0.0) ? mu : -mu;   // beta = -sign(x0) |x|
-      const double v0 = x0 - beta;
-      t = (beta - x0) / beta;
-      scale = 1.0 / v0;
+  for (int j0 = 0; j0 < kmax; j0 += kQb) {
+    const int jb = min(kQb, kmax - j0);
+    // the panel, column by column
+    for (int j = j0; j < j0 + jb; ++j) {
+      double *a = A + (size_t)j * m;
+      double part = 0.0;
+      for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) part += a[i] * a[i];
+      const double sig = block_reduce_sum(part, sh);
+      const double x0 = a[j];
+      double beta, t, scale;
+      if (sig == 0.0) {
+        t = 0.0;
+        beta = x0;
+        scale = 0.0;
+      } else {
+        const double mu = sqrt(x0 * x0 + sig);
+        beta = (x0 <= 0.0) ? mu : -mu;  // beta = -sign(x0) |x|
+        const double v0 = x0 - beta;
+        t = (beta - x0) / beta;
+        scale = 1.0 / v0;
+      }
+      __syncthreads();
+      for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) a[i] *= scale;  // v (v_0 = 1)
+      if (threadIdx.x == 0) {
+        a[j] = beta;
+        tau[j] = t;
+      }
+      __syncthreads();
+      // H_j on the panel's later columns: a wavefront per column for the dots
+      for (int c = j + 1 + wave; c < j0 + jb; c += kQrWaves) {
+        const double *ac = A + (size_t)c * m;
+        double p2 = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) p2 += a[i] * ac[i];
+        p2 = qr_wave_sum(p2);
+        if (lane == 0) dots[c] = p2 + ac[j];
+      }
+      __syncthreads();
+      for (int c = j + 1; c < j0 + jb; ++c) {
+        double *ac = A + (size_t)c * m;
+        const double w = t * dots[c];
+        for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) ac[i] -= w * a[i];
+        if (threadIdx.x == 0) ac[j] -= w;
+      }
+      __syncthreads();
+    }
+    // Gram of the panel's reflectors, G[p][q] = v_p . v_q (p < q): v_q is 1
+    // in row j0 + q and zero above it
+    for (int pq = wave; pq < jb * jb; pq += kQrWaves) {
+      const int p = pq / jb, q = pq % jb;
+      if (p >= q) continue;
+      const double *ap = A + (size_t)(j0 + p) * m, *aq = A + (size_t)(j0 + q) * m;
+      double g = 0.0;
+      for (int i = j0 + q + 1 + lane; i < m; i += 64) g += ap[i] * aq[i];
+      g = qr_wave_sum(g);
+      if (lane == 0) G[p][q] = g + ap[j0 + q];
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) a[i] *= scale;  // v (v_0 = 1)
+    // T: T[q][q] = tau_q, T[0:q][q] = -tau_q T[0:q][0:q] G[0:q][q], zero below
+    double (*T)[kQb] = Tm[j0 / kQb];
     if (threadIdx.x == 0) {
-      a[j] = beta;
-      tau[j] = t;
+      for (int q = 0; q < kQb; ++q) {
+        const double tq = q < jb ? tau[j0 + q] : 0.0;
+        for (int p = 0; p < q; ++p) {
+          double acc = 0.0;
+          for (int r = p; r < q; ++r) acc += T[p][r] * G[r][q];
+          T[p][q] = q < jb ? -tq * acc : 0.0;
+        }
+        T[q][q] = tq;
+        for (int p = q + 1; p < kQb; ++p) T[p][q] = 0.0;
+      }
     }
     __syncthreads();
-    // apply H_j = I - t v v^T to the remaining columns: one wavefront per
-    // column for the dot products (no work-group barrier per column)
-    for (int c = j + 1 + wave; c < s; c += kQrWaves) {
-      const double *ac = A + (size_t)c * m;
-      double p2 = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) p2 += a[i] * ac[i];
-      p2 = qr_wave_sum(p2);
-      if (lane == 0) dots[c] = p2 + ac[j];
-    }
-    __syncthreads();
-    for (int c = j + 1; c < s; ++c) {
-      double *ac = A + (size_t)c * m;
-      const double w = t * dots[c];
-      for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) ac[i] -= w * a[i];
-      if (threadIdx.x == 0) ac[j] -= w;
-    }
-    __syncthreads();
+    if (j0 + jb < s) qr_apply_panel<true>(A, A, m, s, j0, jb, j0 + jb, T, dl);
   }
   if (J.R) {  // R: the upper triangle left by the elimination
     for (int e = threadIdx.x; e < s * s; e += kQrThreads) {
@@ -366,35 +498,19 @@ __global__ __launch_bounds__(kQrThreads) void k_householder_q(const QrJob *__res
     }
     __syncthreads();
   }
-  // form Q = H_0 ... H_{k-1} [I; 0] backwards, in place (v_j below the diagonal)
-  for (int j = kmax - 1; j >= 0; --j) {
-    const double t = tau[j];
-    double *a = A + (size_t)j * m;
-    // columns c > j currently hold Q's columns (rows >= j+1 meaningful, rows <= j set)
-    for (int c = j + 1 + wave; c < s; c += kQrWaves) {
-      const double *ac = A + (size_t)c * m;
-      double p2 = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) p2 += a[i] * ac[i];
-      p2 = qr_wave_sum(p2);  // row j of column c is 0
-      if (lane == 0) dots[c] = p2;
-    }
-    __syncthreads();
-    for (int c = j + 1; c < s; ++c) {
-      double *ac = A + (size_t)c * m;
-      const double w = t * dots[c];
-      for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) ac[i] -= w * a[i];
-      if (threadIdx.x == 0) ac[j] = -w;
-    }
-    __syncthreads();
-    // column j: H_j e_j = e_j - t v
-    for (int i = j + 1 + threadIdx.x; i < m; i += kQrThreads) a[i] = -t * a[i];
-    if (threadIdx.x == 0) a[j] = 1.0 - t;
-    for (int i = threadIdx.x; i < j; i += kQrThreads) a[i] = 0.0;
-    __syncthreads();
+  // Q = H_0 ... H_{k-1} [I; 0] in Qs (columns beyond min(s, m), when m < s: 0)
+  double *Q = J.Qs;
+  for (size_t e = threadIdx.x; e < (size_t)m * s; e += kQrThreads) {
+    const int c = (int)(e / m), i = (int)(e % m);
+    Q[e] = (i == c && c < kmax) ? 1.0 : 0.0;
   }
-  // columns beyond min(s, m) (only when m < s): zero
-  for (int c = kmax; c < s; ++c)
-    for (int i = threadIdx.x; i < m; i += kQrThreads) A[(size_t)c * m + i] = 0.0;
+  __syncthreads();
+  const int np = (kmax + kQb - 1) / kQb;
+  for (int pn = np - 1; pn >= 0; --pn) {
+    const int j0 = pn * kQb, jb = min(kQb, kmax - j0);
+    qr_apply_panel<false>(A, Q, m, s, j0, jb, j0, Tm[pn], dl);
+  }
+  for (size_t e = threadIdx.x; e < (size_t)m * s; e += kQrThreads) A[e] = Q[e];
 }
 
 // -------------------------------------------------- one-sided Jacobi SVD
@@ -574,11 +690,13 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob *__restrict__ jobs, 
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot_u + tot_v;
        e += (size_t)gridDim.x * blockDim.x) {
     if (e < tot_u) {
-      const int i = (int)(e / J.rank), k = (int)(e % J.rank);
-      const int col = J.sel[k];
+      // U[i][k] = (Q V)[i][sel[k]]: consecutive threads take consecutive rows
+      // of Q (column-major) for the same column of V
+      const int k = (int)(e / J.m), i = (int)(e % J.m);
+      const double *vk = J.V + (size_t)J.sel[k] * s;
       double v = 0.0;
-      for (int q = 0; q < s; ++q) v += J.Q[(size_t)q * J.m + i] * J.V[(size_t)col * s + q];
-      store[J.off_u + e] = FactorIO<F>::put(v);
+      for (int q = 0; q < s; ++q) v += J.Q[(size_t)q * J.m + i] * vk[q];
+      store[J.off_u + (size_t)i * J.rank + k] = FactorIO<F>::put(v);
     } else {
       const size_t f = e - tot_u;
       const int k = (int)(f / J.n), c = (int)(f % J.n);
@@ -1062,6 +1180,8 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       D.XR = new DMem(totX * 8); keep.push_back(D.XR);
       D.sig = new DMem((size_t)nbk * s * 8); keep.push_back(D.sig);
       DMem om((size_t)nmax * s * 8);
+      DMem qsm(std::max(totY, totX) * 8);  // Q of each QR is formed here (one QR at a time)
+      double *qs = static_cast<double *>(qsm.p);
       hipLaunchKernelGGL(k_gaussian, dim3(nb((size_t)nmax * s)), dim3(256), 0, st,
                          static_cast<double *>(om.p), nmax, s, (unsigned long long)o.seed, (int)L);
       std::vector<BlockGemmJob> gy, gx;
@@ -1076,10 +1196,10 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
         double *Rb = static_cast<double *>(D.R->p) + (size_t)b * s * s;
         gy.push_back({Sptr(hb.smat), hb.r0, hb.c0, m, n, Yb, static_cast<double *>(om.p)});
         gx.push_back({Sptr(hb.smat), hb.r0, hb.c0, m, n, Xb, Yb});
-        qr.push_back({Yb, m, nullptr});
+        qr.push_back({Yb, m, nullptr, qs + D.offY[b]});
         // X = Q2 R: the Jacobi rotations run on the s x s R instead of the
         // n x s X (same singular values and rotations), then X J = Q2 (R J)
-        qx.push_back({Xb, n, Rb});
+        qx.push_back({Xb, n, Rb, qs + D.offX[b]});
         jac.push_back({Rb, static_cast<double *>(D.V->p) + (size_t)b * s * s, s});
         rot.push_back({Xb, Rb, static_cast<double *>(D.XR->p) + D.offX[b], n});
       }
@@ -1197,8 +1317,12 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
         H->blocks.push_back(hb);
       }
       if (pj.empty()) continue;
+      size_t most = 1;  // entries of the largest job: one per thread
+      for (const PackJob &j : pj)
+        most = std::max(most, (size_t)j.m * j.rank + (size_t)j.rank * j.n);
+      const unsigned gx = (unsigned)std::min<size_t>((most + 255) / 256, 4096);
       const PackJob *d = static_cast<const PackJob *>(upload(pj, st, keep));
-      hipLaunchKernelGGL(k_pack<F>, dim3(32, (unsigned)pj.size()), dim3(256), 0, st, d, D.s,
+      hipLaunchKernelGGL(k_pack<F>, dim3(gx, (unsigned)pj.size()), dim3(256), 0, st, d, D.s,
                          store);
     }
     HCHK(hipGetLastError());
