@@ -419,10 +419,11 @@ def large_leg(dd, torch, name):
     Algorithm 1).  FP32 build, FP64 refinement to a predicted relative error
     of 1e-9; times from the host clock around the calls (inputs resident in
     HBM), the library's own phase times beside them.  Compressed factors in
-    FP32 for the 2D oscillatory workload, whose near-resonant conditioning
-    turns the BF16 factors' rounding into 5 (HODLR) and 7 (HBS) refinement
-    passes against 4 with FP32 factors (twice the compressed bytes, a few
-    hundred MiB); BF16 for the 3D workload (3 to 4 passes either way)."""
+    BF16 (the workloads' definition).  For the 2D oscillatory workload, whose
+    near-resonant conditioning turns the BF16 factors' rounding into 5
+    (HODLR) and 7 (HBS) refinement passes, each route is also compressed
+    again with FP32 factors and solved (4 passes): `fp32_factors`, timed as
+    the route's set-up plus that compression and solve."""
     from problems import make_config
     p = make_config(name)
     t = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device="cuda")
@@ -443,7 +444,7 @@ def large_leg(dd, torch, name):
     out = {"workload": f"{p.dim}D {name} {p.n}^{p.dim}, {p.n_slabs} slabs, M={p.M}, N_ds={p.n_ds}",
            "N": p.N, "s_build_nominal_flops": F_build}
     opts = dd.SolveOptions(tol=1e-9, max_iter=3000, max_outer=12)
-    fdt = "fp32" if p.dim == 2 else "bf16"
+    fdt = "bf16"
     out["factor_dtype"] = fdt
     for route in ("dense_hodlr", "sampled_hbs"):
         print(f"[bench] {name} route {route}", file=sys.stderr, flush=True)
@@ -452,6 +453,8 @@ def large_leg(dd, torch, name):
         t0 = time.perf_counter()
         op = dd.Operator(p.dim, p.n, p.n_slabs, kappa=kap, bvec=p.bvec, c=c, precision="fp32",
                          transfer_blocks=(route == "dense_hodlr"))
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
         sym = bool(op.build_stats()["symmetric"])
         inv = n_inv * (1.0 if sym else 2.0) * M3
         if route == "dense_hodlr":
@@ -472,8 +475,29 @@ def large_leg(dd, torch, name):
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         bs = op.build_stats()
-        op.close()
         del u
+        v32 = None
+        if p.dim == 2:
+            # the same route with FP32 compressed factors
+            t1 = time.perf_counter()
+            if route == "dense_hodlr":
+                i32 = op.compress(tol=1e-8, leaf=128, oversample=10, max_rank=118,
+                                  factor_dtype="fp32")
+            else:
+                i32 = op.compress_hbs(rank=k, oversample=10, factor_dtype="fp32", seed=11)
+            torch.cuda.synchronize()
+            t_c = time.perf_counter() - t1
+            u32, _, s32 = op.solve(f, opts=o, want_gamma=False, allow_notconv=True)
+            torch.cuda.synchronize()
+            t_s = time.perf_counter() - t1 - t_c
+            del u32
+            tot32 = t_setup + t_c + t_s
+            v32 = {"total_s": round(tot32, 3), "dof_per_s": round(p.N / tot32, 1),
+                   "compress_s": round(t_c, 3), "solve_ms": round(s32["t_solve_ms"], 1),
+                   "outer_iters": s32["outer_iters"], "gmres_iters": s32["gmres_iters"],
+                   "fd_residual_rel": s32["residual_rel"],
+                   "converged": bool(s32["status"] == 0), "compressed_bytes": i32["bytes"]}
+        op.close()
         bt = bs["t_build_ms"] / 1e3
         r = {"total_s": round(total, 3), "dof_per_s": round(p.N / total, 1),
              "build_ms": round(bs["t_build_ms"], 1),
@@ -500,6 +524,8 @@ def large_leg(dd, torch, name):
                       "compress_ms": round(info["compress_ms"], 1), "rank": info["rank"],
                       "build_tflops": round(flops[route] / (bt + info["sample_ms"] / 1e3) / 1e12,
                                             2)})
+        if v32 is not None:
+            r["fp32_factors"] = v32
         out[route] = r
         torch.cuda.empty_cache()
     return out
