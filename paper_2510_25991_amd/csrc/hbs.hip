@@ -599,24 +599,59 @@ __device__ __forceinline__ void mv_cols(const F *B, int ldb, int rows, int cols,
   __syncthreads();
 }
 
-// Up, leaf level: xh[b][L][t] = B^T x_in[perm[lo..lo+n)] (B = V, or U if trans).
+// out[c] = sum_i B[i][c] v[i] (i < rows, c < cols) by one wavefront: lane
+// l of a group of lp takes the 8-column chunk l of the rows g, g + G, ...;
+// the groups' partial sums are reduced by shuffles.
 template <typename F>
-__global__ __launch_bounds__(WG) void k_hbs_up_leaf(const HbsNodeDev *__restrict__ nodes,
-                                                    const F *__restrict__ fac, size_t bstride,
-                                                    const int *__restrict__ perm,
-                                                    const double *__restrict__ x, int ld,
-                                                    double *__restrict__ hat, size_t hstride,
-                                                    size_t hoff, int trans) {
-  __shared__ double v[kMaxN], out[kMaxN], red[WG / 64][kMaxN];
-  const HbsNodeDev N = nodes[blockIdx.x];
-  const int b = blockIdx.y;
-  const double *xin = x + (size_t)(blk_in(b, trans) - 1) * ld;
-  for (int i = threadIdx.x; i < N.n; i += WG) v[i] = xin[perm ? perm[N.lo + i] : N.lo + i];
-  for (int c = threadIdx.x; c < N.r; c += WG) out[c] = 0.0;
+__device__ __forceinline__ void wave_mv_cols(const F *B, int ldb, int rows, int cols,
+                                             const double *v, double *out) {
+  const int lane = threadIdx.x & 63;
+  const int nch = (cols + 7) >> 3;
+  const int lp = pow2_ge(nch);
+  const int g = lane / lp, l = lane % lp, G = 64 / lp;
+  double t[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) t[e] = 0.0;
+  if (l < nch)
+    for (int i = g; i < rows; i += G) {
+      double a[8];
+      load8(B + (size_t)i * ldb + 8 * l, a);
+      const double vi = v[i];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t[e] += a[e] * vi;
+    }
+  for (int off = lp; off < 64; off <<= 1)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] += __shfl_xor(t[e], off);
+  if (lane < lp && l < nch)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (8 * l + e < cols) out[8 * l + e] = t[e];
+}
+
+// Up, leaf level, four leaves per work-group (one per wavefront):
+// xh[b][L][t] = B^T x_in[perm[lo..lo+n)] (B = V, or U if trans).
+template <typename F>
+__global__ __launch_bounds__(WG) void k_hbs_up_leaf4(const HbsNodeDev *__restrict__ nodes, int nl,
+                                                     const F *__restrict__ fac, size_t bstride,
+                                                     const int *__restrict__ perm,
+                                                     const double *__restrict__ x, int ld,
+                                                     double *__restrict__ hat, size_t hstride,
+                                                     size_t hoff, int trans) {
+  __shared__ double v[WG / 64][kMaxN];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (WG / 64) + w, b = blockIdx.y;
+  const bool has = t < nl;
+  HbsNodeDev N{};
+  if (has) {
+    N = nodes[t];
+    const double *xin = x + (size_t)(blk_in(b, trans) - 1) * ld;
+    for (int i = lane; i < N.n; i += 64) v[w][i] = xin[perm ? perm[N.lo + i] : N.lo + i];
+  }
   __syncthreads();
-  mv_cols(fac + b * bstride + (trans ? N.pU : N.pV), N.ldr, N.n, N.r, v, out, red);
-  double *h = hat + b * hstride + hoff + N.roff;
-  for (int c = threadIdx.x; c < N.r; c += WG) h[c] = out[c];
+  if (has)
+    wave_mv_cols(fac + b * bstride + (trans ? N.pU : N.pV), N.ldr, N.n, N.r, v[w],
+                 hat + b * hstride + hoff + N.roff);
 }
 
 // Up, internal level: xh[b][d][t] = B^T xh[b][d+1][children].
@@ -1305,8 +1340,9 @@ void hbs_apply_t(const ddst_op *op, const double *x, double *y, int trans, hipSt
   }
   if (L >= 1) {
     const unsigned nl = (unsigned)H->lv[L].size();
-    hipLaunchKernelGGL(k_hbs_up_leaf<F>, dim3(nl, nb), dim3(WG), 0, st, nodes(L), fac, bs,
-                       H->d_perm, x, ld, H->hat, hs, H->hoff[2 * L], trans);
+    hipLaunchKernelGGL(k_hbs_up_leaf4<F>, dim3((nl + WG / 64 - 1) / (WG / 64), nb), dim3(WG), 0,
+                       st, nodes(L), (int)nl, fac, bs, H->d_perm, x, ld, H->hat, hs,
+                       H->hoff[2 * L], trans);
     for (int d = L - 1; d >= 1; --d)
       hipLaunchKernelGGL(k_hbs_up<F>, dim3((unsigned)H->lv[d].size(), nb), dim3(WG), 0, st,
                          nodes(d), fac, bs, H->hat, hs, H->hoff[2 * d], H->hoff[2 * (d + 1)],
