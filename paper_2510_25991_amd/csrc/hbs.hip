@@ -726,21 +726,50 @@ __global__ __launch_bounds__(WG) void k_hbs_down(const HbsNodeDev *__restrict__ 
   for (int i = threadIdx.x; i < N.n; i += WG) hb[hoff_yc + N.coff + i] = out[i];
 }
 
+// out[i] = sum_c A[i][c] v[c] (i < rows, c < cols) by one wavefront: a
+// group of lp lanes per row, eight entries per lane and load, the row's
+// partial sums reduced by shuffles.
+template <typename F>
+__device__ __forceinline__ void wave_mv_rows(const F *A, int lda, int rows, int cols,
+                                             const double *v, double *out) {
+  const int lane = threadIdx.x & 63;
+  const int nch = (cols + 7) >> 3;
+  const int lp = pow2_ge(nch);
+  const int g = lane / lp, l = lane % lp, G = 64 / lp;
+  for (int i0 = 0; i0 < rows; i0 += G) {
+    const int i = i0 + g;
+    double t = 0.0;
+    if (i < rows)
+      for (int ch = l; ch < nch; ch += lp) {
+        double a[8];
+        load8(A + (size_t)i * lda + 8 * ch, a);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (8 * ch + e < cols) t += a[e] * v[8 * ch + e];
+      }
+    for (int off = lp >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (i < rows && l == 0) out[i] = t;
+  }
+}
+
 // Leaves: for output interface jo (blockIdx.y + 1) and leaf t,
-//   y_jo[perm] = x_jo[perm] - sum over its blocks (B' yh + D x_in[perm]);
-// without a basis (a single cluster) the leaf is the root and only D is
-// applied.  The first leaf's work-group also copies the padding entries
-// (M .. ld - 1) of y_jo from x_jo.
+//   y_jo[perm] = x_jo[perm] - sum over its blocks (B' yh + D x_in[perm])
+// (B' = U, or V if trans; D or D^T); without a basis (a single cluster) the
+// leaf is the root and only D is applied.  Wavefront 2 q + h takes block q's
+// basis product (h = 0) or dense product (h = 1) into its own LDS slice;
+// the slices are summed after one barrier.  The first leaf's work-group also
+// copies the padding entries (M .. ld - 1) of y_jo from x_jo.
 template <typename F>
 __global__ __launch_bounds__(WG) void k_hbs_leaf_out(
     const HbsNodeDev *__restrict__ nodes, const F *__restrict__ fac, size_t bstride,
     const int *__restrict__ perm, const double *__restrict__ x, double *__restrict__ y, int M,
     int ld, int n_ds, const double *__restrict__ hat, size_t hstride, size_t hoff_y,
     int has_basis, int trans) {
-  __shared__ double vy[kMaxN], vx[kMaxN], out[kMaxN], red[WG / 64][kMaxN];
+  static_assert(WG == 256, "four wavefronts: two products for each of two blocks");
+  __shared__ double vin[4][kMaxN], part[4][kMaxN];
   const HbsNodeDev N = nodes[blockIdx.x];
   const int jo = blockIdx.y + 1;
-  for (int i = threadIdx.x; i < N.n; i += WG) out[i] = 0.0;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // blocks writing to jo: non-transposed S_{jo,jo-1} (b = 2(jo-2)) and
   // S_{jo,jo+1} (b = 2(jo-1)+1); transposed S_{jo+1,jo} (b = 2(jo-1)) and
   // S_{jo-1,jo} (b = 2(jo-2)+1)
@@ -752,30 +781,37 @@ __global__ __launch_bounds__(WG) void k_hbs_leaf_out(
     if (jo <= n_ds - 1) bl[nb++] = 2 * (jo - 1);
     if (jo >= 2) bl[nb++] = 2 * (jo - 2) + 1;
   }
-  for (int q = 0; q < nb; ++q) {
-    const int b = bl[q];
-    const double *xin = x + (size_t)(blk_in(b, trans) - 1) * ld;
-    __syncthreads();
-    for (int i = threadIdx.x; i < N.n; i += WG) vx[i] = xin[perm ? perm[N.lo + i] : N.lo + i];
-    if (has_basis)
-      for (int c = threadIdx.x; c < N.r; c += WG) vy[c] = hat[b * hstride + hoff_y + N.roff + c];
-    __syncthreads();
-    const F *fb = fac + b * bstride;
-    if (has_basis) {
-      mv_rows(fb + (trans ? N.pV : N.pU), N.ldr, N.n, N.r, vy, out);
-      __syncthreads();
+  const int q = w >> 1, h = w & 1;
+  const bool act = q < nb && (h == 1 || has_basis);
+  int b = 0;
+  if (act) {
+    b = bl[q];
+    if (h == 0) {
+      for (int c = lane; c < N.r; c += 64) vin[w][c] = hat[b * hstride + hoff_y + N.roff + c];
+    } else {
+      const double *xin = x + (size_t)(blk_in(b, trans) - 1) * ld;
+      for (int i = lane; i < N.n; i += 64) vin[w][i] = xin[perm ? perm[N.lo + i] : N.lo + i];
     }
-    if (trans)
-      mv_cols(fb + N.pD, N.ldn, N.n, N.n, vx, out, red);
+  }
+  __syncthreads();
+  if (act) {
+    const F *fb = fac + b * bstride;
+    if (h == 0)
+      wave_mv_rows(fb + (trans ? N.pV : N.pU), N.ldr, N.n, N.r, vin[w], part[w]);
+    else if (trans)
+      wave_mv_cols(fb + N.pD, N.ldn, N.n, N.n, vin[w], part[w]);
     else
-      mv_rows(fb + N.pD, N.ldn, N.n, N.n, vx, out);
+      wave_mv_rows(fb + N.pD, N.ldn, N.n, N.n, vin[w], part[w]);
   }
   __syncthreads();
   const double *xo = x + (size_t)(jo - 1) * ld;
   double *yo = y + (size_t)(jo - 1) * ld;
   for (int i = threadIdx.x; i < N.n; i += WG) {
+    double s = 0.0;
+    for (int u = 0; u < 4; ++u)
+      if ((u >> 1) < nb && ((u & 1) == 1 || has_basis)) s += part[u][i];
     const int p = perm ? perm[N.lo + i] : N.lo + i;
-    yo[p] = xo[p] - out[i];
+    yo[p] = xo[p] - s;
   }
   if (blockIdx.x == 0)
     for (int c = M + threadIdx.x; c < ld; c += WG) yo[c] = xo[c];
