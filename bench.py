@@ -421,9 +421,11 @@ def large_leg(dd, torch, name):
     HBM), the library's own phase times beside them.  Compressed factors in
     BF16 (the workloads' definition).  For the 2D oscillatory workload, whose
     near-resonant conditioning turns the BF16 factors' rounding into 5
-    (HODLR) and 7 (HBS) refinement passes, each route is also compressed
-    again with FP32 factors and solved (4 passes): `fp32_factors`, timed as
-    the route's set-up plus that compression and solve."""
+    (HODLR) and 7 (HBS) refinement passes, each route is also solved again
+    with the FP32 Krylov basis (the solve option basis_fp32: `fp32_basis`,
+    timed as the route's set-up, compression and that solve) and compressed
+    again with FP32 factors and solved (4 passes, FP64 basis: `fp32_factors`,
+    timed as the route's set-up plus that compression and solve)."""
     from problems import make_config
     p = make_config(name)
     t = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device="cuda")
@@ -476,8 +478,18 @@ def large_leg(dd, torch, name):
         total = time.perf_counter() - t0
         bs = op.build_stats()
         del u
-        v32 = None
+        v32 = vb32 = None
         if p.dim == 2:
+            # the same form, FP32 Krylov basis
+            ob = dataclasses_replace(o, basis_fp32=True)
+            ub, _, sb = op.solve(f, opts=ob, want_gamma=False, allow_notconv=True)
+            torch.cuda.synchronize()
+            del ub
+            tb = total - st["t_solve_ms"] / 1e3 + sb["t_solve_ms"] / 1e3
+            vb32 = {"total_s": round(tb, 3), "dof_per_s": round(p.N / tb, 1),
+                    "solve_ms": round(sb["t_solve_ms"], 1), "outer_iters": sb["outer_iters"],
+                    "gmres_iters": sb["gmres_iters"], "fd_residual_rel": sb["residual_rel"],
+                    "converged": bool(sb["status"] == 0)}
             # the same route with FP32 compressed factors
             t1 = time.perf_counter()
             if route == "dense_hodlr":
@@ -524,6 +536,8 @@ def large_leg(dd, torch, name):
                       "compress_ms": round(info["compress_ms"], 1), "rank": info["rank"],
                       "build_tflops": round(flops[route] / (bt + info["sample_ms"] / 1e3) / 1e12,
                                             2)})
+        if vb32 is not None:
+            r["fp32_basis"] = vb32
         if v32 is not None:
             r["fp32_factors"] = v32
         out[route] = r

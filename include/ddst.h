@@ -148,6 +148,12 @@ typedef struct {
   int32_t use_hbs;          /* 1: apply S through the HBS form of
                                ddst_compress_hbs (exclusive with use_hodlr and
                                matrix_free)                                    */
+  int32_t basis_fp32;       /* 1: GMRES passes whose tolerance is >= 1e-6 keep
+                               the finalized Krylov vectors in FP32 (the
+                               operator's input and every sum stay FP64; half
+                               the bytes of the Gram-Schmidt passes); 0 (the
+                               default): FP64 basis                            */
+  int32_t reserved_;
 } ddst_solve_opts_t;
 
 typedef struct {

@@ -603,6 +603,7 @@ struct SolveWs {
   GmresDev gm;               // device GMRES state
   size_t vol, ifc;           // one right-hand side's volume / interface length
   int nr;                    // right-hand sides held (vectors nr * vol, nr * ifc)
+  bool basis32 = false;      // FP32 Krylov basis allowed (ddst_solve_opts_t::basis_fp32)
 };
 
 void ensure_ws(ddst_op *op, size_t bytes) {
@@ -881,7 +882,8 @@ void run_matfree(const ddst_op *op, const MatfreeTables &t, bool trans, const Ma
 // basis instead of four, one column of H finalized a step later); below
 // that, the classical twice-applied Gram-Schmidt step, whose fewer launches
 // cost less than the passes saved.
-// When the tolerance is at least kBasis32Tol the basis is stored in FP32
+// When the caller allows it (basis_fp32) and the tolerance is at least
+// kBasis32Tol the basis is stored in FP32
 // (half the bytes of the passes over it, which dominate long runs): each
 // q_j is rounded once when it is final (2^-24 relative), while the candidate
 // vector the operator is applied to and every sum stay FP64 (the candidate
@@ -909,7 +911,7 @@ int gmres_cycle(ddst_op *op, SolveWs &w, const void *G, const double *rhs, doubl
   if (!(beta > 0.0)) return 0;
   // FP32 basis: (max_iter + 1) FP32 slots, then the FP64 candidate (the
   // region holds max_iter + 1 FP64 slots, so both fit for max_iter >= 2)
-  const bool b32 = tol >= kBasis32Tol && max_iter >= 2 && len >= 64;
+  const bool b32 = w.basis32 && tol >= kBasis32Tol && max_iter >= 2 && len >= 64;
   float *V32 = reinterpret_cast<float *>(w.V);
   double *ucur =
       b32 ? reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(w.V) +
@@ -1282,6 +1284,8 @@ ddst_solve_opts_t solve_defaults(const ddst_op *op) {
   o.matrix_free = 0;
   o.restart = 0;
   o.use_hbs = 0;
+  o.basis_fp32 = 0;
+  o.reserved_ = 0;
   return o;
 }
 
@@ -1293,6 +1297,8 @@ int check_solve_opts(const ddst_solve_opts_t &o) {
   if ((o.use_hodlr != 0 && o.use_hodlr != 1) || (o.matrix_free != 0 && o.matrix_free != 1) ||
       (o.use_hbs != 0 && o.use_hbs != 1))
     return fail(DDST_EINVAL, "use_hodlr, use_hbs and matrix_free must be 0 or 1");
+  if (o.basis_fp32 != 0 && o.basis_fp32 != 1)
+    return fail(DDST_EINVAL, "basis_fp32 must be 0 or 1");
   if (o.use_hodlr + o.matrix_free + o.use_hbs > 1)
     return fail(DDST_EINVAL, "use_hodlr, use_hbs and matrix_free are exclusive");
   if (o.restart < 0 || o.restart > o.max_iter)
@@ -1314,6 +1320,7 @@ int solve_impl(ddst_op *op, const double *f, const double *g, const ddst_solve_o
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, s));
   SolveWs w = carve_ws(op, o.max_iter, nr);
+  w.basis32 = o.basis_fp32 != 0;
   RefineOut ro;
   const int status = refine<T>(op, op->G, f, g, false, o, w, ro, s);
   if (u_vol)
@@ -1369,6 +1376,7 @@ int adjoint_impl(ddst_op *op, const double *u_vol, const double *g, const double
     G = tmp.p;
   }
   SolveWs w = carve_ws(op, o.max_iter);
+  w.basis32 = o.basis_fp32 != 0;
   RefineOut ro;
   const int status = refine<T>(op, G, gbar, nullptr, true, o, w, ro, s);
   launch_cell_gradient(u_vol, w.X, g, op->dim, op->n, op->M, op->ld, op->h, dkappa, s);

@@ -58,7 +58,8 @@ class SolveOptsC(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("use_hodlr", ctypes.c_int32), ("matrix_free", ctypes.c_int32),
-                ("restart", ctypes.c_int32), ("use_hbs", ctypes.c_int32)]
+                ("restart", ctypes.c_int32), ("use_hbs", ctypes.c_int32),
+                ("basis_fp32", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class HbsOptsC(ctypes.Structure):
@@ -227,6 +228,7 @@ class SolveOptions:
     matrix_free: bool = False              # apply S by sweeps with the stored factors
     restart: int = 0                       # 0: unrestarted GMRES; k: restart every k
     use_hbs: bool = False                  # apply S through the sampled HBS form
+    basis_fp32: bool = False               # FP32 Krylov basis for passes at tol >= 1e-6
 
 
 class Operator:
@@ -301,7 +303,8 @@ class Operator:
         # an operator without transfer blocks applies S matrix-free
         mf = o.matrix_free or not (self.transfer_blocks or o.use_hodlr or o.use_hbs)
         return SolveOptsC(o.tol, inner, o.max_iter, o.max_outer, 1 if o.use_hodlr else 0,
-                          1 if mf else 0, int(o.restart), 1 if o.use_hbs else 0)
+                          1 if mf else 0, int(o.restart), 1 if o.use_hbs else 0,
+                          1 if o.basis_fp32 else 0, 0)
 
     def solve(self, f=None, g=None, opts: Optional[SolveOptions] = None, want_gamma=True,
               allow_notconv=False):

@@ -180,12 +180,21 @@ def test_full_size_cfg3_hodlr():
     bw = float(np.abs(r).max() / (nA * np.abs(x).max()))
     print(f"  scaled FD residual {bw:.3e}")
     assert bw <= 1e-10
+    # the same solve with the FP32 Krylov basis (inner passes at 1e-4; both
+    # the classical and the lagged Gram-Schmidt steps run with it)
+    u2, _, st2 = op.solve(p.f, opts=dd.SolveOptions(tol=1e-9, max_iter=3000, max_outer=10,
+                                                     use_hodlr=True, basis_fp32=True))
+    print(f"  FP32 basis: status {st2['status']} outer {st2['outer_iters']} gmres "
+          f"{st2['gmres_iters']}")
+    assert st2["status"] == 0
+    x2 = u2.cpu().numpy().ravel()
     op.close()
     # the backward error does not bound the forward error of this
     # near-resonant operator: compare with the oracle's global direct solve
-    err = rel(x, global_reference("cfg3", p))
-    print(f"  rel err vs global direct {err:.3e}")
-    assert err <= 1e-8
+    ref = global_reference("cfg3", p)
+    err, err2 = rel(x, ref), rel(x2, ref)
+    print(f"  rel err vs global direct {err:.3e} (FP32 basis {err2:.3e})")
+    assert err <= 1e-8 and err2 <= 1e-8
 
 
 @pytest.mark.parametrize("name,rank", [("cfg3", 32), ("cfg4", 64)])
