@@ -1210,6 +1210,7 @@ int compress_impl(ddst_op *op, const ddst_compress_opts_t &o, hipStream_t st, in
       const QrJob *dqx = static_cast<const QrJob *>(upload(qx, st, keep));
       const DenseGemmJob *drot = static_cast<const DenseGemmJob *>(upload(rot, st, keep));
       launch_block_gemm<T>(dgy, nbk, mmax, d_perm, op->ld, s, 0, st);
+      if (s > kQrMaxS) throw std::logic_error("sample count above the QR kernel's column limit");
       hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(kQrThreads), 0, st, dqr, s);
       launch_block_gemm<T>(dgx, nbk, nmax, d_perm, op->ld, s, 1, st);
       hipLaunchKernelGGL(k_householder_q, dim3(nbk), dim3(kQrThreads), 0, st, dqx, s);
